@@ -1,0 +1,326 @@
+"""Seeded synthetic workloads: geometry, initial fields and parameters.
+
+This module only builds input data (masks, wall temperatures, initial
+temperature / mass-fraction / velocity fields, chemistry parameters).  It
+holds none of the method's arithmetic and is shared, as plain data, by the
+GPU library's tests and benchmark and by the CPU oracle.
+
+The workloads stand in for the paper's cases (Sec. IV): a 2-D channel flame
+(IV.A), a pseudo 2-D burner with staggered cylinders (IV.B) and random 3-D
+sphere packings (IV.C).  The paper's own geometry, the BFER-2 mechanism and
+Cantera data are not available, so a one-step synthetic mechanism with the
+same structure (fuel + oxidiser -> product, inert diluent) is used.
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass, field
+
+import numpy as np
+
+FACES = ("periodic", "wall", "inflow", "outflow", "wall_adiabatic")
+FLUID, SOLID_ISOTHERMAL, SOLID_ADIABATIC = 0, 1, 2
+
+# Four-species one-step mixture.  Mass stoichiometry F + 4 O -> 5 P, molar
+# masses chosen so that moles (and the mixture molar mass) are unchanged by
+# reaction; q = 3e4 K per unit fuel mass fraction so that the stoichiometric
+# unburnt mixture at 300 K burns to 1800 K.
+W4 = (16.0, 32.0, 80.0 / 3.0, 28.0)
+Y_UNBURNT_STOICH = (0.05, 0.2, 0.0, 0.75)
+Y_BURNT_STOICH = (0.0, 0.0, 0.25, 0.75)
+Y_UNBURNT_LEAN = (0.04, 0.2, 0.0, 0.76)
+Y_BURNT_LEAN = (0.0, 0.04, 0.2, 0.76)
+W_REF = 28.0
+DT_PHYS_CHANNEL = 7.5e-8  # s, time step of the channel cases (Sec. IV.A)
+DT_PHYS_BURNER = 1.0e-7   # s, time step of the burner / porous cases (Sec. IV.B)
+
+
+@dataclass
+class Reaction:
+    reactants: list
+    A: float
+    b: float
+    Ta: float
+    nu: list
+    q: float
+
+
+@dataclass
+class Problem:
+    name: str
+    lattice: int
+    nx: int
+    ny: int
+    nz: int
+    faces: tuple
+    face_T: tuple
+    tau: float
+    prandtl: float
+    dt_phys: float
+    T_ref: float
+    W_ref: float
+    W: tuple
+    reactions: list
+    u_in: tuple
+    T_in: float
+    Y_in: tuple
+    mask: np.ndarray
+    wall_T: np.ndarray
+    T0: np.ndarray
+    Y0: np.ndarray
+    u0: np.ndarray | None = None
+    Ph0: np.ndarray | None = None
+    omega3: float = 1.0
+    omega4: float = 1.0
+    eq_discrete: bool = False
+    chem_substeps_max: int = 1
+    T_u: float = 300.0
+    T_b: float = 1800.0
+    steps: int = 0
+    notes: dict = field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def n_species(self) -> int:
+        return len(self.W)
+
+    @property
+    def n_fluid(self) -> int:
+        return int(np.count_nonzero(self.mask == FLUID))
+
+    def replace(self, **kw) -> "Problem":
+        return dataclasses.replace(self, **kw)
+
+
+def one_step_reaction(A: float = 1e9, Ta: float = 15000.0, b: float = 0.0) -> Reaction:
+    return Reaction(reactants=[0, 1], A=A, b=b, Ta=Ta, nu=[-1.0, -4.0, 5.0, 0.0], q=3.0e4)
+
+
+def _tanh_blend(x, x0, width, lo, hi):
+    th = 0.5 * (1.0 + np.tanh((x - x0) / width))
+    return th, lo + (hi - lo) * th
+
+
+def _front_fields(shape, xcoord, x0, width, T_lo, T_hi, Y_lo, Y_hi):
+    """tanh front along x: theta = (1 + tanh((x - x0)/width))/2."""
+    th, T = _tanh_blend(xcoord, x0, width, T_lo, T_hi)
+    T = np.broadcast_to(T, shape).astype(np.float64).copy()
+    th = np.broadcast_to(th, shape)
+    Y = np.stack([(1.0 - th) * Y_lo[k] + th * Y_hi[k] for k in range(len(Y_lo))])
+    return T, np.ascontiguousarray(Y, dtype=np.float64)
+
+
+def channel_flame(nx: int = 256, ny: int = 64, steps: int = 2000, front_x: float = 64.0,
+                  width: float = 4.0, wall_T: float = 300.0, adiabatic: bool = False,
+                  name: str = "channel_flame_256x64") -> Problem:
+    """2-D channel flame, D2Q9: rows y=0 and y=ny-1 solid (isothermal at
+    wall_T, or adiabatic), periodic in x, fluid at rest, tanh front from
+    300 K / unburnt stoichiometric mixture to 1800 K / burnt mixture at
+    x = front_x (width 4 cells).  tau = 0.6, Pr = 0.7, A = 1e9 1/s,
+    Ta = 15000 K, dt = 7.5e-8 s."""
+    shape = (1, ny, nx)
+    mask = np.zeros(shape, dtype=np.uint8)
+    solid = SOLID_ADIABATIC if adiabatic else SOLID_ISOTHERMAL
+    mask[:, 0, :] = solid
+    mask[:, ny - 1, :] = solid
+    x = np.arange(nx, dtype=np.float64)[None, None, :]
+    T0, Y0 = _front_fields(shape, x, front_x, width, 300.0, 1800.0,
+                           Y_UNBURNT_STOICH, Y_BURNT_STOICH)
+    wT = np.full(shape, wall_T, dtype=np.float64)
+    T0[mask != FLUID] = wall_T
+    return Problem(
+        name=name, lattice=9, nx=nx, ny=ny, nz=1,
+        faces=("periodic",) * 6, face_T=(300.0,) * 6,
+        tau=0.6, prandtl=0.7, dt_phys=DT_PHYS_CHANNEL, T_ref=300.0, W_ref=W_REF,
+        W=W4, reactions=[one_step_reaction()],
+        u_in=(0.0, 0.0, 0.0), T_in=300.0, Y_in=Y_UNBURNT_STOICH,
+        mask=mask, wall_T=wT, T0=T0, Y0=Y0, steps=steps,
+        notes={"wall": "adiabatic" if adiabatic else "isothermal %.1f K" % wall_T},
+    )
+
+
+def _periodic_delta(a, c, n):
+    d = np.abs(a - c)
+    return np.minimum(d, n - d)
+
+
+def cylinder_burner(nx: int = 2048, ny: int = 512, radius: float = 20.0, pitch: int = 64,
+                    x_begin: int = 256, x_end: int = 1792, wall_T: float = 400.0,
+                    u_in: float = 0.02, front_x: float = 1024.0, steps: int = 20000,
+                    name: str | None = None) -> Problem:
+    """Pseudo 2-D porous burner, D2Q9: staggered cylinders of `radius` on a
+    `pitch` lattice (columns every `pitch` cells over [x_begin, x_end),
+    centres y = pitch/2 + pitch*j + (pitch/2)(col mod 2), periodic in y),
+    isothermal at wall_T; lean inflow (Y = 0.04/0.2/0/0.76, 300 K, u_in)
+    at -x, outflow at +x; fluid at rest with a tanh front at front_x and
+    the lean burnt state downstream."""
+    shape = (1, ny, nx)
+    mask = np.zeros(shape, dtype=np.uint8)
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    for col, cx in enumerate(range(x_begin, x_end, pitch)):
+        for j in range(ny // pitch):
+            cy = pitch // 2 + pitch * j + (pitch // 2) * (col % 2)
+            cy %= ny
+            inside = (xx - cx) ** 2 + _periodic_delta(yy, cy, ny) ** 2 <= radius * radius
+            mask[0][inside] = SOLID_ISOTHERMAL
+    x = np.arange(nx, dtype=np.float64)[None, None, :]
+    T0, Y0 = _front_fields(shape, x, front_x, 4.0, 300.0, 1500.0, Y_UNBURNT_LEAN, Y_BURNT_LEAN)
+    T0[mask != FLUID] = wall_T
+    return Problem(
+        name=name or "cylinder_burner_%dx%d" % (nx, ny), lattice=9, nx=nx, ny=ny, nz=1,
+        faces=("inflow", "outflow", "periodic", "periodic", "periodic", "periodic"),
+        face_T=(300.0,) * 6, tau=0.6, prandtl=0.7, dt_phys=DT_PHYS_BURNER, T_ref=300.0,
+        W_ref=W_REF, W=W4, reactions=[one_step_reaction()],
+        u_in=(u_in, 0.0, 0.0), T_in=300.0, Y_in=Y_UNBURNT_LEAN,
+        mask=mask, wall_T=np.full(shape, wall_T), T0=T0, Y0=Y0, steps=steps,
+        T_u=300.0, T_b=1500.0,
+    )
+
+
+def sphere_packing_mask(nx, ny, nz, porosity, radius_lo, radius_hi, seed, margin=16,
+                        max_spheres=1_000_000):
+    """Overlapping spheres with centres uniform in x in [margin, nx-margin)
+    and over the periodic y, z extent, radii uniform in [radius_lo,
+    radius_hi] (a single value when equal), added until the voxel porosity
+    of the packed slab x in [margin, nx-margin) is <= porosity.  A cell is
+    solid when its centre is within the radius (periodic in y and z, cut
+    at the slab ends)."""
+    rng = np.random.default_rng(seed)
+    solid = np.zeros((nz, ny, nx), dtype=bool)
+    x0, x1 = margin, nx - margin
+    total = (x1 - x0) * ny * nz
+    nsolid = 0
+    spheres = []
+    for _ in range(max_spheres):
+        if 1.0 - nsolid / total <= porosity:
+            break
+        cx = rng.uniform(x0, x1)
+        cy = rng.uniform(0, ny)
+        cz = rng.uniform(0, nz)
+        r = radius_lo if radius_hi == radius_lo else rng.uniform(radius_lo, radius_hi)
+        spheres.append((cx, cy, cz, r))
+        ri = int(np.ceil(r))
+        xs = np.arange(max(x0, int(np.floor(cx - ri))), min(x1, int(np.ceil(cx + ri)) + 1))
+        ys = np.arange(int(np.floor(cy - ri)), int(np.ceil(cy + ri)) + 1)
+        zs = np.arange(int(np.floor(cz - ri)), int(np.ceil(cz + ri)) + 1)
+        if xs.size == 0:
+            continue
+        dz = (zs - cz)[:, None, None] ** 2
+        dy = (ys - cy)[None, :, None] ** 2
+        dx = (xs - cx)[None, None, :] ** 2
+        inside = dz + dy + dx <= r * r
+        zi = (zs % nz)[:, None, None]
+        yi = (ys % ny)[None, :, None]
+        xi = xs[None, None, :]
+        zi, yi, xi = np.broadcast_arrays(zi, yi, xi)
+        zi, yi, xi = zi[inside], yi[inside], xi[inside]
+        new = ~solid[zi, yi, xi]
+        # repeated (wrapped) coordinates in one sphere are counted once
+        lin = np.unique((zi[new] * ny + yi[new]) * nx + xi[new])
+        solid.reshape(-1)[lin] = True
+        nsolid += lin.size
+    return solid, spheres
+
+
+def _three_d_front(shape, nx, front_x, T_lo, T_hi, Y_lo, Y_hi):
+    x = np.arange(nx, dtype=np.float64)[None, None, :]
+    return _front_fields(shape, x, front_x, 4.0, T_lo, T_hi, Y_lo, Y_hi)
+
+
+def porous_3d(nx: int = 256, ny: int = 256, nz: int = 256, porosity: float = 0.80,
+              radius: float = 8.0, seed: int = 2304, wall_T: float = 350.0, u_in: float = 0.01,
+              front_x: float | None = None, margin: int = 16, steps: int = 5000,
+              name: str | None = None) -> Problem:
+    """3-D random porous medium, D3Q27: overlapping spheres of `radius`
+    (seeded) to `porosity`, solid isothermal at wall_T, stoichiometric
+    inflow at -x (u_in, 300 K), outflow at +x, periodic in y and z; tanh
+    front at front_x (default nx/2) with burnt gas downstream."""
+    shape = (nz, ny, nx)
+    solid, _ = sphere_packing_mask(nx, ny, nz, porosity, radius, radius, seed, margin)
+    mask = np.where(solid, SOLID_ISOTHERMAL, FLUID).astype(np.uint8)
+    T0, Y0 = _three_d_front(shape, nx, nx / 2 if front_x is None else front_x, 300.0, 1800.0,
+                            Y_UNBURNT_STOICH, Y_BURNT_STOICH)
+    T0[solid] = wall_T
+    return Problem(
+        name=name or "porous3d_%dx%dx%d" % (nx, ny, nz), lattice=27, nx=nx, ny=ny, nz=nz,
+        faces=("inflow", "outflow", "periodic", "periodic", "periodic", "periodic"),
+        face_T=(300.0,) * 6, tau=0.6, prandtl=0.7, dt_phys=DT_PHYS_BURNER, T_ref=300.0,
+        W_ref=W_REF, W=W4, reactions=[one_step_reaction()],
+        u_in=(u_in, 0.0, 0.0), T_in=300.0, Y_in=Y_UNBURNT_STOICH,
+        mask=mask, wall_T=np.full(shape, wall_T), T0=T0, Y0=Y0, steps=steps,
+        notes={"seed": seed, "porosity_target": porosity},
+    )
+
+
+def synthetic_mechanism(n_species: int = 9, n_reactions: int = 20, seed: int = 2305,
+                        log10A=(6.0, 13.0), Ta=(5000.0, 25000.0), b=(-1.0, 1.0),
+                        q=(0.0, 3.0e4)) -> list:
+    """Seeded synthetic mechanism: per reaction two distinct reactants and
+    one or two distinct products among the species; mass coefficients:
+    reactants lose fractions that sum to 1 over the reactants, products gain
+    the same total, so that the coefficients sum to zero."""
+    rng = np.random.default_rng(seed)
+    rx = []
+    for _ in range(n_reactions):
+        perm = rng.permutation(n_species)
+        reac = [int(perm[0]), int(perm[1])]
+        nprod = int(rng.integers(1, 3))
+        prods = [int(p) for p in perm[2:2 + nprod]]
+        nu = [0.0] * n_species
+        a = float(rng.uniform(0.2, 0.8))
+        nu[reac[0]] = -a
+        nu[reac[1]] = -(1.0 - a)
+        if nprod == 1:
+            nu[prods[0]] = 1.0
+        else:
+            c = float(rng.uniform(0.2, 0.8))
+            nu[prods[0]] = c
+            nu[prods[1]] = 1.0 - c
+        rx.append(Reaction(reactants=reac, A=float(10.0 ** rng.uniform(*log10A)),
+                           b=float(rng.uniform(*b)), Ta=float(rng.uniform(*Ta)), nu=nu,
+                           q=float(rng.uniform(*q))))
+    return rx
+
+
+def porous_3d_mech(nx: int = 512, ny: int = 256, nz: int = 256, porosity: float = 0.85,
+                   radius=(6.0, 12.0), seed: int = 2306, mech_seed: int = 2305,
+                   wall_T: float = 350.0, u_in: float = 0.01, margin: int = 16,
+                   steps: int = 2000, substeps_max: int = 64, name: str | None = None) -> Problem:
+    """3-D porous medium with a synthetic 9-species / 20-reaction mechanism
+    (all molar masses 28, so the mixture molar mass is constant)."""
+    ns = 9
+    shape = (nz, ny, nx)
+    solid, _ = sphere_packing_mask(nx, ny, nz, porosity, radius[0], radius[1], seed, margin)
+    mask = np.where(solid, SOLID_ISOTHERMAL, FLUID).astype(np.uint8)
+    Y_lo = (0.05, 0.2) + (0.0,) * 6 + (0.75,)
+    Y_hi = (0.0, 0.0) + (0.05, 0.05, 0.05, 0.05, 0.0, 0.05) + (0.75,)
+    T0, Y0 = _three_d_front(shape, nx, nx / 2, 300.0, 1800.0, Y_lo, Y_hi)
+    T0[solid] = wall_T
+    return Problem(
+        name=name or "porous3d_mech_%dx%dx%d" % (nx, ny, nz), lattice=27, nx=nx, ny=ny, nz=nz,
+        faces=("inflow", "outflow", "periodic", "periodic", "periodic", "periodic"),
+        face_T=(300.0,) * 6, tau=0.6, prandtl=0.7, dt_phys=DT_PHYS_BURNER, T_ref=300.0,
+        W_ref=28.0, W=(28.0,) * ns, reactions=synthetic_mechanism(ns, 20, mech_seed),
+        u_in=(u_in, 0.0, 0.0), T_in=300.0, Y_in=Y_lo,
+        mask=mask, wall_T=np.full(shape, wall_T), T0=T0, Y0=Y0, steps=steps,
+        chem_substeps_max=substeps_max, notes={"seed": seed, "mech_seed": mech_seed},
+    )
+
+
+def named(name: str) -> Problem:
+    """The five standard workloads by short name."""
+    if name == "channel":
+        return channel_flame()
+    if name == "burner":
+        return cylinder_burner()
+    if name == "porous":
+        return porous_3d()
+    if name == "porous_mech":
+        return porous_3d_mech()
+    if name == "channel_adjoint":
+        return channel_flame(nx=1024, ny=256, steps=500, front_x=64.0,
+                             name="channel_flame_1024x256")
+    raise KeyError(name)

@@ -1,0 +1,572 @@
+"""Pins of the FP64 oracle against closed forms, exact invariants, textbook
+reductions and brute-force recurrences (not against itself).
+
+Each test names the passage of arXiv:2304.05657 it pins.  Runs on CPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2304_05657_amd import workloads as W
+
+CS2 = 1.0 / 3.0
+
+
+# ---------------------------------------------------------------- lattice
+@pytest.mark.parametrize("Q", [9, 27])
+def test_lattice_isotropy(oracle_mod, Q):
+    """Sec. II.B: first-neighbour lattices with third-order quadrature."""
+    c, w = oracle_mod.single.lattice(Q)
+    D = 2 if Q == 9 else 3
+    assert np.isclose(w.sum(), 1.0, rtol=0, atol=1e-15)
+    assert np.allclose(w @ c, 0.0, atol=1e-16)
+    for a in range(D):
+        for b in range(D):
+            assert np.isclose((w * c[:, a] * c[:, b]).sum(), CS2 * (a == b), atol=1e-15)
+    # fourth-order isotropy: cs^4 (d_ab d_cd + d_ac d_bd + d_ad d_bc)
+    for a in range(D):
+        for b in range(D):
+            for cc in range(D):
+                for d in range(D):
+                    want = CS2 ** 2 * ((a == b) * (cc == d) + (a == cc) * (b == d) + (a == d) * (b == cc))
+                    got = (w * c[:, a] * c[:, b] * c[:, cc] * c[:, d]).sum()
+                    assert np.isclose(got, want, atol=1e-15)
+    if Q == 27:
+        assert np.isclose((w * c[:, 0] ** 2 * c[:, 1] ** 2 * c[:, 2] ** 2).sum(), CS2 ** 3, atol=1e-16)
+    # opposite direction is Q-1-i
+    assert np.array_equal(c[::-1], -c)
+
+
+# ------------------------------------------------------------ equilibria
+@pytest.mark.parametrize("Q", [9, 27])
+def test_equilibrium_moments(oracle_mod, Q):
+    """Sec. II.B Eqs. (10), (12), (13): moments of the discrete equilibria."""
+    c, w = oracle_mod.single.lattice(Q)
+    D = 2 if Q == 9 else 3
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        rho = rng.uniform(0.2, 1.5)
+        u = np.zeros(3)
+        u[:D] = rng.uniform(-0.1, 0.1, D)
+        Ph = rng.uniform(-0.05, 0.05)
+        feq = oracle_mod.single.feq(Q, rho, u)
+        assert np.isclose(feq.sum(), rho, rtol=1e-14)
+        assert np.allclose(feq @ c, rho * u, atol=1e-15)
+        for a in range(D):
+            for b in range(D):
+                want = rho * (CS2 * (a == b) + u[a] * u[b])
+                assert np.isclose((feq * c[:, a] * c[:, b]).sum(), want, atol=1e-15)
+        geq = oracle_mod.single.geq(Q, Ph, rho, u)
+        assert np.isclose(geq.sum(), Ph, atol=1e-15)
+        assert np.allclose(geq @ c / CS2, rho * u, atol=1e-15)
+        # at rest with P_h = 0 the pressure-based equilibrium vanishes
+        assert np.allclose(oracle_mod.single.geq(Q, 0.0, rho, np.zeros(3)), 0.0, atol=1e-16)
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_source_moments(oracle_mod, Q):
+    """Sec. II.B Eq. (9): sum Xi = cs^2 u.grad(rho) + rho cs^2 Lambda and
+    sum c Xi = 0 (first moments of f^eq/rho and of w)."""
+    c, w = oracle_mod.single.lattice(Q)
+    D = 2 if Q == 9 else 3
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        rho = rng.uniform(0.2, 1.5)
+        u = np.zeros(3)
+        u[:D] = rng.uniform(-0.1, 0.1, D)
+        gr = np.zeros(3)
+        gr[:D] = rng.uniform(-0.2, 0.2, D)
+        Lam = rng.uniform(-0.01, 0.01)
+        xi = oracle_mod.single.source_xi(Q, rho, u, gr, Lam)
+        assert np.isclose(xi.sum(), CS2 * u @ gr + rho * CS2 * Lam, atol=1e-16)
+        assert np.allclose(xi @ c, 0.0, atol=1e-16)
+
+
+# ------------------------------------------------------------- collision
+def _params(oracle_mod, Q, **kw):
+    prob = W.channel_flame(nx=8, ny=6) if Q == 9 else W.porous_3d(8, 8, 8, porosity=1.0, margin=2)
+    p = oracle_mod.oracle.make_params(prob)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _random_cell(Q, rng, D):
+    rho = rng.uniform(0.3, 1.2)
+    u = np.zeros(3)
+    u[:D] = rng.uniform(-0.08, 0.08, D)
+    g = rng.normal(0.0, 0.01, Q)
+    return rho, u, g
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_central_moments_maxwellian_at_rest(oracle_mod, Q):
+    """Sec. II.C Eq. (21): central moments of f^eq/rho at u = 0 equal the
+    Maxwellian ones (1, 0, cs^2 per axis with exponent 2)."""
+    c, w = oracle_mod.single.lattice(Q)
+    kap = oracle_mod.single.central_moments(Q, w, np.zeros(3))
+    for j in range(Q):
+        p = c[j] + 1
+        if Q == 9:
+            p = p.copy()
+            p[2] = 0
+        want = 0.0 if np.any(p == 1) else CS2 ** int(np.sum(p == 2))
+        assert np.isclose(kap[j], want, atol=1e-16)
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_collision_zero_rates_is_identity(oracle_mod, Q):
+    """With every rate 0 the collision returns g + Xi (Eq. 14 with Eq. 19):
+    the inverse central-moment transform undoes the forward one."""
+    D = 2 if Q == 9 else 3
+    p = _params(oracle_mod, Q, tau=1e300, omega3=0.0, omega4=0.0)
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        rho, u, g = _random_cell(Q, rng, D)
+        xi = rng.normal(0, 1e-3, Q)
+        gs = oracle_mod.single.collide(p, g, xi, rho, u)
+        assert np.allclose(gs, g + xi, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_collision_conserves_mass_and_momentum(oracle_mod, Q):
+    """Orders 0 and 1 are not relaxed: sum g* = sum g + sum Xi and
+    sum c g* = sum c g + sum c Xi."""
+    c, w = oracle_mod.single.lattice(Q)
+    D = 2 if Q == 9 else 3
+    p = _params(oracle_mod, Q, tau=0.6, omega3=1.0, omega4=1.0)
+    rng = np.random.default_rng(4)
+    for _ in range(5):
+        rho, u, g = _random_cell(Q, rng, D)
+        xi = rng.normal(0, 1e-3, Q)
+        gs = oracle_mod.single.collide(p, g, xi, rho, u)
+        assert np.isclose(gs.sum(), g.sum() + xi.sum(), atol=1e-15)
+        assert np.allclose(gs @ c, g @ c + xi @ c, atol=1e-15)
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_collision_full_relaxation_hits_targets(oracle_mod, Q):
+    """With all rates 1 the post-collision shifted distribution has exactly
+    the Maxwellian central moments of orders >= 2."""
+    c, w = oracle_mod.single.lattice(Q)
+    D = 2 if Q == 9 else 3
+    p = _params(oracle_mod, Q, tau=1.0, omega3=1.0, omega4=1.0)
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        rho, u, g = _random_cell(Q, rng, D)
+        # make u the true mean velocity of f' (Xi = 0)
+        u = np.zeros(3)
+        u[:D] = (g @ c)[:D] / (rho * CS2)
+        xi = np.zeros(Q)
+        gs = oracle_mod.single.collide(p, g, xi, rho, u)
+        f = g / (rho * CS2)
+        pi = f.sum()
+        hs = gs / (rho * CS2) + w * (1.0 - pi)
+        kap = oracle_mod.single.central_moments(Q, hs, u)
+        for j in range(Q):
+            e = c[j] + 1
+            if Q == 9:
+                e = e.copy()
+                e[2] = 0
+            want = 0.0 if np.any(e == 1) else CS2 ** int(np.sum(e == 2))
+            assert np.isclose(kap[j], want, atol=2e-15), (j, kap[j], want)
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_collision_reduces_to_srt(oracle_mod, Q):
+    """Eq. (11): with discrete-equilibrium targets, every rate 1/tau and
+    Xi = 0 the collision is the single-relaxation-time operator
+    g* = g - (g - g^eq)/tau, g^eq = w (P_h - rho cs^2) + cs^2 f^eq."""
+    c, w = oracle_mod.single.lattice(Q)
+    D = 2 if Q == 9 else 3
+    tau = 0.73
+    p = _params(oracle_mod, Q, tau=tau, omega3=1.0 / tau, omega4=1.0 / tau, eq_discrete=1)
+    rng = np.random.default_rng(6)
+    for _ in range(5):
+        rho, _, g = _random_cell(Q, rng, D)
+        u = (g @ c) / (rho * CS2)
+        Ph = g.sum()
+        cu = c @ u
+        feq = w * rho * (1 + cu / CS2 + cu ** 2 / (2 * CS2 ** 2) - (u @ u) / (2 * CS2))
+        geq = w * (Ph - rho * CS2) + CS2 * feq
+        want = g - (g - geq) / tau
+        gs = oracle_mod.single.collide(p, g, np.zeros(Q), rho, u)
+        assert np.allclose(gs, want, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_chmrt_equals_discrete_targets_at_rest(oracle_mod, Q):
+    """At u = 0 the Maxwellian targets coincide with those of f^eq/rho."""
+    D = 2 if Q == 9 else 3
+    rng = np.random.default_rng(7)
+    pa = _params(oracle_mod, Q, tau=0.6)
+    pb = _params(oracle_mod, Q, tau=0.6, eq_discrete=1)
+    for _ in range(3):
+        rho, _, g = _random_cell(Q, rng, D)
+        xi = rng.normal(0, 1e-3, Q)
+        a = oracle_mod.single.collide(pa, g, xi, rho, np.zeros(3))
+        b = oracle_mod.single.collide(pb, g, xi, rho, np.zeros(3))
+        assert np.allclose(a, b, rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------- finite differences
+def test_fd_operators_exact_on_polynomials(oracle_mod):
+    """Sec. II.D: 4th-order central D1 is exact up to degree 4, D2 up to
+    degree 5 (unit spacing)."""
+    x = np.arange(-2, 3, dtype=np.float64)
+    for deg in range(6):
+        a = 0.3 + 0.1 * deg
+        phi = (x + a) ** deg
+        if deg <= 4:
+            want = deg * a ** (deg - 1) if deg >= 1 else 0.0
+            assert np.isclose(oracle_mod.single.d1(phi), want, atol=1e-13)
+        want2 = deg * (deg - 1) * a ** (deg - 2) if deg >= 2 else 0.0
+        assert np.isclose(oracle_mod.single.d2(phi), want2, atol=1e-13)
+
+
+def test_weno3_linear_and_order(oracle_mod):
+    """Sec. II.D: the WENO3 derivative is exact on linear data for both
+    upwind directions and third-order accurate on smooth data."""
+    x = np.arange(-2, 3, dtype=np.float64)
+    for slope in (-2.0, 0.5, 3.0):
+        phi = 1.0 + slope * x
+        for u in (1.0, -1.0, 0.0):
+            assert np.isclose(oracle_mod.single.weno3(phi, u), slope, atol=1e-12)
+    errs = []
+    hs = [0.1, 0.05, 0.025, 0.0125]
+    x0 = 0.3  # a point where sin' != 0
+    for h in hs:
+        phi = np.sin(x0 + h * x)
+        errs.append(abs(oracle_mod.single.weno3(phi, 1.0) / h - math.cos(x0)))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert min(orders[1:]) > 2.7, orders
+
+
+# -------------------------------------------------------------- chemistry
+def test_chemistry_rate_and_invariants(oracle_mod):
+    """One-step Arrhenius source per lattice step:
+    r = A dt T^b exp(-Ta/T) Y_F Y_O; sum of species sources is 0 and
+    T + q Y_F is unchanged (q = 3e4 K)."""
+    prob = W.channel_flame(nx=8, ny=6)
+    p = oracle_mod.oracle.make_params(prob)
+    for T in (300.0, 900.0, 1800.0, 2200.0):
+        Y = np.array(W.Y_UNBURNT_STOICH)
+        sT, sY = oracle_mod.single.chemistry(p, T, Y)
+        r = 1e9 * 7.5e-8 * math.exp(-15000.0 / T) * Y[0] * Y[1]
+        assert np.isclose(-sY[0], r, rtol=1e-14)
+        assert np.isclose(sY.sum(), 0.0, atol=1e-18 + 1e-15 * r)
+        assert np.isclose(sT + 3e4 * sY[0], 0.0, atol=1e-12 * max(sT, 1e-30))
+
+
+def test_chemistry_substeps_reduce_to_euler_when_slow(oracle_mod):
+    """Sub-cycling (cap > 1) is one plain Euler step when k dt < 0.1."""
+    prob = W.channel_flame(nx=8, ny=6)
+    p1 = oracle_mod.oracle.make_params(prob)
+    p8 = oracle_mod.oracle.make_params(prob, chem_substeps_max=8)
+    Y = np.array(W.Y_UNBURNT_STOICH)
+    a = oracle_mod.single.chemistry(p1, 1200.0, Y)
+    b = oracle_mod.single.chemistry(p8, 1200.0, Y)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+def test_chemistry_substeps_converge(oracle_mod):
+    """For a stiff rate the sub-cycled source approaches the exact solution
+    of dY_F/dt = -k Y_F Y_O over one step (lean mixture, Y_O = 4 Y_F + c
+    holds exactly), and more sub-steps get closer."""
+    prob = W.channel_flame(nx=8, ny=6)
+    prob = prob.replace(reactions=[W.Reaction([0, 1], 2e9, 0.0, 0.0, [-1.0, -4.0, 5.0, 0.0], 0.0)])
+    Y = np.array(W.Y_UNBURNT_LEAN)
+    k = 2e9 * 7.5e-8
+    F0, O0 = Y[0], Y[1]
+    cc = O0 - 4 * F0
+    F1 = cc * F0 / ((4 * F0 + cc) * math.exp(k * cc) - 4 * F0)
+    errs = []
+    for cap in (100, 400, 1600):
+        p = oracle_mod.oracle.make_params(prob, chem_substeps_max=cap)
+        _, sY = oracle_mod.single.chemistry(p, 1500.0, Y)
+        errs.append(abs(Y[0] + sY[0] - F1) / F0)
+    assert errs[2] < 2e-3 and errs[0] > errs[1] > errs[2], errs
+
+
+# ------------------------------------------------------- whole-step pins
+def _uniform_problem(nx, ny, T=300.0, Y=(0.5, 0.5), Wk=(28.0, 28.0), faces=None, lattice=9, nz=1,
+                     reactions=None):
+    shape = (nz, ny, nx)
+    ns = len(Y)
+    Y0 = np.stack([np.full(shape, Y[k]) for k in range(ns)])
+    return W.Problem(
+        name="uniform", lattice=lattice, nx=nx, ny=ny, nz=nz,
+        faces=faces or ("periodic",) * 6, face_T=(300.0,) * 6, tau=0.6, prandtl=0.7,
+        dt_phys=7.5e-8, T_ref=300.0, W_ref=28.0, W=Wk, reactions=reactions or [],
+        u_in=(0.0, 0.0, 0.0), T_in=T, Y_in=Y, mask=np.zeros(shape, np.uint8),
+        wall_T=np.full(shape, 300.0), T0=np.full(shape, T), Y0=Y0)
+
+
+def test_rest_state_stays_zero(oracle_mod):
+    """At rest with P_h = 0 and uniform scalars g = 0 is a fixed point."""
+    prob = _uniform_problem(12, 10)
+    prob.mask[0, 0, :] = 1
+    prob.mask[0, 4:6, 3:6] = 2
+    o = oracle_mod.Oracle(prob)
+    o.step(20)
+    # zero up to the round-off of the Maxwellian targets (1/3 is inexact)
+    assert np.abs(o.pops()).max() < 1e-15
+
+
+def test_taylor_green_decay(oracle_mod):
+    """Sec. II.B: the LB recovers Navier-Stokes with nu = cs^2 (tau - 1/2):
+    a Taylor-Green vortex decays as exp(-2 nu k^2 t)."""
+    n = 32
+    U0 = 0.01
+    k = 2 * math.pi / n
+    prob = _uniform_problem(n, n)
+    x = np.arange(n) + 0.0
+    X, Yy = np.meshgrid(x, x, indexing="xy")
+    u0 = np.zeros((3, 1, n, n))
+    u0[0, 0] = U0 * np.sin(k * X) * np.cos(k * Yy)
+    u0[1, 0] = -U0 * np.cos(k * X) * np.sin(k * Yy)
+    Ph0 = (-0.25 * U0 ** 2 * (np.cos(2 * k * X) + np.cos(2 * k * Yy)))[None]
+    prob = prob.replace(u0=u0, Ph0=Ph0)
+    o = oracle_mod.Oracle(prob)
+    nu = CS2 * (0.6 - 0.5)
+    basis = np.sin(k * X) * np.cos(k * Yy)
+    a0 = (o.fields()["u"][0, 0] * basis).sum() / (basis * basis).sum()
+    m0 = o.diagnostics()["mom"]
+    steps = 300
+    o.step(steps)
+    a1 = (o.fields()["u"][0, 0] * basis).sum() / (basis * basis).sum()
+    rate = -math.log(a1 / a0) / steps
+    assert abs(rate / (2 * nu * k * k) - 1.0) < 1e-2, rate / (2 * nu * k * k)
+    # total momentum of a periodic box is conserved
+    # (sum over 1024 cells of |rho u| ~ 10: round-off level 1e-12)
+    d = o.diagnostics()
+    assert np.allclose(d["mom"], m0, rtol=0, atol=1e-11)
+
+
+def _poiseuille_error(oracle_mod, H):
+    prob = _uniform_problem(2, H + 2)
+    prob.mask[0, 0, :] = 2
+    prob.mask[0, H + 1, :] = 2
+    nu = CS2 * 0.1
+    umax = 0.005
+    F = umax * 2 * nu * 4 / H ** 2  # rho = 1 at 300 K, W = 28
+    o = oracle_mod.Oracle(prob, body_force=(F, 0.0, 0.0))
+    o.step(int(4 * H * H / nu))
+    u = o.fields()["u"][0, 0, 1:H + 1, 0]
+    y = np.arange(1, H + 1)
+    exact = F / (2 * nu) * (y - 0.5) * (H + 0.5 - y)
+    return np.abs(u - exact).max() / exact.max()
+
+
+@pytest.mark.slow
+def test_poiseuille_profile(oracle_mod):
+    """Half-way bounce-back (Eq. 28) with walls half-way between cells:
+    body-force-driven channel flow converges to the parabola, 2nd order."""
+    e8 = _poiseuille_error(oracle_mod, 8)
+    e16 = _poiseuille_error(oracle_mod, 16)
+    assert e16 < 1e-2, e16
+    assert e8 / e16 > 3.0, (e8, e16)
+
+
+def test_species_fourier_mode_exact(oracle_mod):
+    """Sec. II.D: explicit Euler + 4th-order central diffusion multiplies a
+    Fourier mode of a passive species (uniform rho, u = 0) by
+    G = 1 + alpha (-2 cos 2k + 32 cos k - 30)/12 per step, exactly."""
+    n = 32
+    kk = 2 * math.pi * 3 / n
+    prob = _uniform_problem(n, 4)
+    x = np.arange(n)
+    Y0 = np.zeros((2, 1, 4, n))
+    Y0[0] = 0.5 + 0.1 * np.cos(kk * x)[None, None, :]
+    Y0[1] = 1.0 - Y0[0]
+    prob = prob.replace(Y0=Y0)
+    o = oracle_mod.Oracle(prob)
+    alpha = CS2 * 0.1 / 0.7
+    G = 1 + alpha * (-2 * math.cos(2 * kk) + 32 * math.cos(kk) - 30) / 12
+    steps = 50
+    o.step(steps)
+    Y = o.fields()["Y"][0, 0, 0]
+    want = 0.5 + 0.1 * G ** steps * np.cos(kk * x)
+    assert np.allclose(Y, want, rtol=0, atol=1e-13)
+
+
+def _conduction_error(oracle_mod, H, steps):
+    T1, T2 = 300.0, 600.0
+    prob = _uniform_problem(4, H + 2)
+    prob.mask[0, 0, :] = 1
+    prob.mask[0, H + 1, :] = 1
+    prob.wall_T[0, 0, :] = T1
+    prob.wall_T[0, H + 1, :] = T2
+    y = np.arange(H + 2)
+    T0 = T1 + (T2 - T1) * (y - 0.5) / H
+    prob.T0[0] = T0[:, None]
+    o = oracle_mod.Oracle(prob)
+    o.step(steps)
+    T = o.fields()["T"][0, 1:H + 1, 0]
+    s = (y[1:H + 1] - 0.5) / H
+    exact = T1 * (T2 / T1) ** s
+    return np.abs(T - exact).max() / (T2 - T1)
+
+
+def test_isothermal_walls_steady_conduction(oracle_mod):
+    """Sec. III.B ghost nodes (Eq. 34) with directly reconstructed density:
+    steady conduction between walls at T1, T2 (rho alpha grad T constant,
+    rho ~ 1/T) converges to T1 (T2/T1)^s, s = (y - 1/2)/H, 2nd order."""
+    e8 = _conduction_error(oracle_mod, 8, 3000)
+    e16 = _conduction_error(oracle_mod, 16, 12000)
+    assert e16 < 2e-3, e16
+    assert e8 / e16 > 3.0, (e8, e16)
+
+
+def test_adiabatic_walls_keep_uniform_state(oracle_mod):
+    """Neumann (adiabatic) ghosts: a uniform temperature stays uniform."""
+    prob = _uniform_problem(10, 8, T=700.0)
+    prob.mask[0, 0, :] = 2
+    prob.mask[0, 7, :] = 2
+    prob.mask[0, 3:5, 4] = 2
+    o = oracle_mod.Oracle(prob)
+    o.step(30)
+    f = o.fields()
+    fl = prob.mask[0] == 0
+    assert np.allclose(f["T"][0][fl], 700.0, rtol=1e-14, atol=0)
+    assert np.abs(o.pops()).max() < 1e-15
+
+
+def test_zero_d_reactor_brute_force(oracle_mod):
+    """Homogeneous periodic box with reaction: T, Y and P_h follow the
+    scalar recurrence T+=q r, Y+=nu r, S+=rho cs^2 Lambda,
+    P_h = S + rho cs^2 Lambda / 2 (Eqs. 6, 9, 13a at u = 0)."""
+    prob = W.channel_flame(nx=4, ny=4)
+    prob.mask[:] = 0
+    Yu = np.array(W.Y_UNBURNT_STOICH)
+    prob = prob.replace(T0=np.full((1, 4, 4), 1500.0),
+                        Y0=np.stack([np.full((1, 4, 4), v) for v in Yu]))
+    o = oracle_mod.Oracle(prob)
+    T, Y, S = 1500.0, Yu.copy(), 0.0
+    Wk = np.array(W.W4)
+    for n in range(40):
+        f = o.fields()
+        Wm = 1.0 / (Y / Wk).sum()
+        rho = (300.0 / T) * Wm / 28.0
+        r = 1e9 * 7.5e-8 * math.exp(-15000.0 / T) * Y[0] * Y[1]
+        srcY = np.array([-1.0, -4.0, 5.0, 0.0]) * r
+        srcT = 3e4 * r
+        Lam = srcT / T + ((Wm / Wk) * srcY).sum()
+        Ph = S + 0.5 * rho * CS2 * Lam
+        assert np.allclose(f["T"], T, rtol=1e-12)
+        assert np.allclose(f["Y"][:, 0, 0, 0], Y, rtol=1e-11, atol=1e-15)
+        assert np.allclose(f["Ph"], Ph, rtol=1e-9, atol=1e-15)
+        T += srcT
+        Y = Y + srcY
+        S += rho * CS2 * Lam
+        o.step(1)
+
+
+def test_population_mass_budget(oracle_mod):
+    """Bounce-back conserves the populations: in a box closed by walls and
+    periodic faces sum g^{n+1} - sum g^n = sum Xi^n (Eq. 8)."""
+    prob = W.channel_flame(nx=64, ny=16, front_x=20.0)
+    o = oracle_mod.Oracle(prob)
+    o.step(5)
+    for _ in range(5):
+        d0 = o.diagnostics()
+        o.step(1)
+        d1 = o.diagnostics()
+        scale = abs(d0["sum_xi"]) + abs(d0["sum_g"])
+        assert abs(d1["sum_g"] - d0["sum_g"] - d0["sum_xi"]) < 1e-12 * scale
+
+
+def test_channel_species_sum_and_symmetry(oracle_mod):
+    """Eq. (26): with the correction, sum_k Y_k stays 1 to round-off; the
+    channel is mirror-symmetric about its mid-plane."""
+    prob = W.channel_flame(nx=64, ny=16, front_x=20.0)
+    o = oracle_mod.Oracle(prob)
+    o.step(200)
+    d = o.diagnostics()
+    assert d["max_sumY_err"] < 1e-14
+    f = o.fields()
+    for key in ("T", "Ph"):
+        a = f[key][0]
+        assert np.abs(a - a[::-1, :]).max() <= 1e-12 * np.abs(a).max()
+    uy = f["u"][1, 0]
+    assert np.abs(uy + uy[::-1, :]).max() <= 1e-12 * np.abs(f["u"]).max()
+
+
+def test_uniform_inflow_outflow_channel(oracle_mod):
+    """Inlet (Eq. 31) and outlet (Eq. 32): a uniform stream entering at
+    u_in through a periodic channel stays at u_in (the outlet weights sum
+    to one, the inlet imposes the equilibrium momentum flux)."""
+    uin = 0.02
+    prob = _uniform_problem(24, 6, faces=("inflow", "outflow", "periodic", "periodic", "periodic", "periodic"))
+    prob = prob.replace(u_in=(uin, 0.0, 0.0), T_in=300.0, Y_in=(0.5, 0.5))
+    u0 = np.zeros((3, 1, 6, 24))
+    u0[0] = uin
+    prob = prob.replace(u0=u0)
+    o = oracle_mod.Oracle(prob)
+    o.step(400)
+    u = o.fields()["u"]
+    assert np.abs(u[0] - uin).max() < 2e-3 * uin
+    assert np.abs(u[1]).max() < 1e-12
+
+
+# ------------------------------------------------------------ D3Q27 pins
+def test_taylor_green_decay_3d(oracle_mod):
+    """D3Q27: a z-invariant Taylor-Green vortex decays as exp(-2 nu k^2 t)."""
+    n, nz = 16, 4
+    U0 = 0.01
+    k = 2 * math.pi / n
+    prob = _uniform_problem(n, n, lattice=27, nz=nz)
+    x = np.arange(n) + 0.0
+    X, Yy = np.meshgrid(x, x, indexing="xy")
+    u0 = np.zeros((3, nz, n, n))
+    u0[0] = U0 * np.sin(k * X) * np.cos(k * Yy)
+    u0[1] = -U0 * np.cos(k * X) * np.sin(k * Yy)
+    Ph0 = np.broadcast_to(-0.25 * U0 ** 2 * (np.cos(2 * k * X) + np.cos(2 * k * Yy)), (nz, n, n)).copy()
+    prob = prob.replace(u0=u0, Ph0=Ph0)
+    o = oracle_mod.Oracle(prob)
+    nu = CS2 * 0.1
+    basis = np.sin(k * X) * np.cos(k * Yy)
+    a0 = (o.fields()["u"][0, 0] * basis).sum() / (basis * basis).sum()
+    steps = 100
+    o.step(steps)
+    f = o.fields()
+    a1 = (f["u"][0, 0] * basis).sum() / (basis * basis).sum()
+    rate = -math.log(a1 / a0) / steps
+    assert abs(rate / (2 * nu * k * k) - 1.0) < 3e-2, rate / (2 * nu * k * k)
+    assert np.abs(f["u"][2]).max() < 1e-12 * U0
+    assert np.abs(f["u"][0] - f["u"][0, :1]).max() < 1e-12 * U0
+
+
+def test_species_fourier_mode_exact_3d(oracle_mod):
+    """D3Q27 grid: the passive-species Fourier-mode factor along z."""
+    n = 16
+    kk = 2 * math.pi * 2 / n
+    prob = _uniform_problem(4, 4, lattice=27, nz=n)
+    z = np.arange(n)
+    Y0 = np.zeros((2, n, 4, 4))
+    Y0[0] = 0.5 + 0.1 * np.cos(kk * z)[:, None, None]
+    Y0[1] = 1.0 - Y0[0]
+    prob = prob.replace(Y0=Y0)
+    o = oracle_mod.Oracle(prob)
+    alpha = CS2 * 0.1 / 0.7
+    G = 1 + alpha * (-2 * math.cos(2 * kk) + 32 * math.cos(kk) - 30) / 12
+    o.step(20)
+    Y = o.fields()["Y"][0, :, 1, 2]
+    assert np.allclose(Y, 0.5 + 0.1 * G ** 20 * np.cos(kk * z), rtol=0, atol=1e-13)
+
+
+def test_population_mass_budget_3d(oracle_mod):
+    """D3Q27 with a sphere and a burning front in a closed periodic box:
+    sum g^{n+1} - sum g^n = sum Xi^n."""
+    prob = W.porous_3d(16, 10, 10, porosity=0.97, radius=3.0, margin=4, front_x=8.0)
+    prob = prob.replace(faces=("periodic",) * 6)
+    o = oracle_mod.Oracle(prob)
+    o.step(3)
+    for _ in range(3):
+        d0 = o.diagnostics()
+        o.step(1)
+        d1 = o.diagnostics()
+        scale = abs(d0["sum_xi"]) + abs(d0["sum_g"])
+        assert abs(d1["sum_g"] - d0["sum_g"] - d0["sum_xi"]) < 1e-12 * scale
+    assert o.diagnostics()["max_sumY_err"] < 1e-14
