@@ -317,7 +317,8 @@ double lbo_weno3(const double *phi5, double u)
 /* source sum_j nu_jk r_j and the temperature source sum_j q_j r_j, all */
 /* per lattice step.  With chem_substeps_max > 1 the source over one    */
 /* step is integrated with N explicit sub-steps, N = ceil(max_j k_j/0.1)*/
-/* capped at chem_substeps_max (one sub-step is the plain Euler source).*/
+/* capped at chem_substeps_max (one sub-step is the plain Euler source);*/
+/* each sub-step is scaled down if it would drive a Y_k below zero.     */
 /* ------------------------------------------------------------------ */
 static double rate_coeff(const lbo_reaction *r, double dt_phys, double T)
 {
@@ -359,9 +360,19 @@ void lbo_chemistry(const lbo_params *p, double T, const double *Y,
                 incY[k] += r->nu[k] * rr;
             incT += r->q * rr;
         }
-        dT += incT;
+        /* positivity limiter (reading for stiff mechanisms): scale the    */
+        /* sub-step so that no mass fraction is consumed below zero; it is */
+        /* 1, i.e. plain explicit Euler, whenever nothing would go negative */
+        double lam = 1.0;
         for (int k = 0; k < ns; ++k)
-            dY[k] += incY[k];
+            if (incY[k] < 0.0 && Yc[k] + incY[k] < 0.0) {
+                double l = (Yc[k] > 0.0 ? Yc[k] : 0.0) / (-incY[k]);
+                if (l < lam)
+                    lam = l;
+            }
+        dT += lam * incT;
+        for (int k = 0; k < ns; ++k)
+            dY[k] += lam * incY[k];
     }
     *src_T = dT;
     for (int k = 0; k < ns; ++k)
