@@ -1,0 +1,204 @@
+/*
+ * lbfd.h -- C ABI of the MI355X (gfx950) coupled lattice-Boltzmann /
+ * finite-difference time step for low-Mach reacting flow, after
+ * Hosseini & Thevenin, "Towards pore-scale simulation of combustion in
+ * porous media using a low-Mach hybrid lattice Boltzmann/finite difference
+ * solver", arXiv:2304.05657.
+ *
+ * One step advances, on one GPU, the pressure-based lattice-Boltzmann
+ * populations g_i (Sec. II.B: LB equation with the source Xi_i, central-
+ * moment multiple-relaxation-time collision of Sec. II.C, D2Q9 or D3Q27)
+ * and the temperature T and species mass fractions Y_k by explicit Euler
+ * finite differences (Sec. II.D: WENO3 convection with the mass-conserving
+ * correction, fourth-order central diffusion, Arrhenius sources), with the
+ * boundary treatment of Sec. III: half-way bounce-back at walls and
+ * obstacles, velocity inlet, non-reflecting outlet, ghost-node isothermal
+ * (Dirichlet) or adiabatic (Neumann) walls.
+ *
+ * Conventions
+ *  - Lattice units: dr = dt = 1, cs^2 = 1/3.
+ *  - A box of nx * ny * nz cells (nz = 1 for D2Q9); cell (x, y, z) has the
+ *    linear index (z*ny + y)*nx + x.  Multi-component host arrays are
+ *    component-major: u[d*N + cell], Y[k*N + cell].
+ *  - Faces are ordered -x, +x, -y, +y, -z, +z.
+ *  - Density in lattice units: rho = (T_ref / T) * (W / W_ref) with the
+ *    mixture molar mass W = 1 / sum_k (Y_k / W_k) (ideal gas at uniform
+ *    thermodynamic pressure, Sec. II.A).
+ *  - alpha = D_k = cs^2 (tau - 1/2) / prandtl (unity Lewis numbers).
+ *
+ * Ownership: every input pointer is caller-owned and only read during the
+ * call (copied to the device).  A context owns all of its device memory
+ * until lbfd_destroy.  Output pointers are caller-owned host buffers.
+ *
+ * Errors: every function returns LBFD_OK (0) or a negative code; nothing
+ * aborts or throws across the ABI.  lbfd_last_error() returns a message
+ * for the last failure on the calling thread.
+ */
+#ifndef LBFD_H
+#define LBFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBFD_OK = 0,
+    LBFD_EINVAL = -1,     /* invalid argument or configuration */
+    LBFD_ENOMEM = -2,     /* device or host allocation failed */
+    LBFD_EDEVICE = -3,    /* a HIP runtime call failed */
+    LBFD_ENONFINITE = -4, /* a periodic check found NaN/Inf in the state */
+    LBFD_ESTATE = -5      /* state blob does not match the context */
+};
+
+enum { LBFD_D2Q9 = 9, LBFD_D3Q27 = 27 };
+
+/* Storage and arithmetic of the step.
+ *  FP64: populations, T, Y stored and computed in double.
+ *  MIXED_FP32: populations stored in float as deviations scaled by the
+ *    lattice weight, g_i / (w_i cs^2); T, Y stored in float; collision and
+ *    finite differences in float; Arrhenius source and reductions in double.
+ *  MIXED_FP16: as MIXED_FP32 with the populations stored in IEEE half
+ *    (round to nearest even). */
+enum { LBFD_FP64 = 0, LBFD_MIXED_FP32 = 1, LBFD_MIXED_FP16 = 2 };
+
+/* Face kinds.  WALL: isothermal no-slip wall at face_T (bounce-back, and a
+ * Dirichlet ghost for T).  WALL_ADIABATIC: no-slip, Neumann ghost for T.
+ * INFLOW: velocity inlet at u_in with Dirichlet T_in, Y_in (Eq. 31).
+ * OUTFLOW: non-reflecting zero-gradient outlet (Eq. 32); only the x faces
+ * may be OUTFLOW. */
+enum {
+    LBFD_FACE_PERIODIC = 0,
+    LBFD_FACE_WALL = 1,
+    LBFD_FACE_INFLOW = 2,
+    LBFD_FACE_OUTFLOW = 3,
+    LBFD_FACE_WALL_ADIABATIC = 4
+};
+
+/* Cell mask values: solids are no-slip obstacles (half-way bounce-back);
+ * isothermal solids hold their wall_T, adiabatic ones impose zero normal
+ * gradient on T. */
+enum { LBFD_FLUID = 0, LBFD_SOLID_ISOTHERMAL = 1, LBFD_SOLID_ADIABATIC = 2 };
+
+#define LBFD_MAX_SPECIES 16
+#define LBFD_MAX_REACTIONS 32
+
+/* One irreversible reaction (Arrhenius law on mass fractions):
+ * per lattice step the progress is r = A dt_phys T^b exp(-Ta/T) prod Y_r
+ * over the n_react reactant indices; species k changes by nu_mass[k] r and
+ * T by q_over_cp r.  sum_k nu_mass[k] must be 0 (checked to 1e-12). */
+typedef struct {
+    int n_react;
+    int react[4];
+    double A;      /* [1/s] */
+    double b;      /* temperature exponent */
+    double Ta;     /* activation temperature Ea/R [K] */
+    double nu_mass[LBFD_MAX_SPECIES];
+    double q_over_cp; /* [K per unit progress] */
+} lbfd_reaction;
+
+typedef struct {
+    int lattice;             /* LBFD_D2Q9 (nz must be 1) or LBFD_D3Q27 */
+    int nx, ny, nz;
+    int precision;           /* LBFD_FP64 / LBFD_MIXED_FP32 / LBFD_MIXED_FP16 */
+    int face[6];
+    double face_T[6];        /* temperature of WALL faces [K] */
+    double tau;              /* relaxation time (> 1/2); nu = cs^2 (tau - 1/2) */
+    double prandtl;          /* alpha = nu / prandtl */
+    double dt_phys;          /* physical time step of the Arrhenius law [s] */
+    double T_ref, W_ref;     /* density scale */
+    int n_species;           /* 1..LBFD_MAX_SPECIES (builds: 2, 4 and 9) */
+    double W[LBFD_MAX_SPECIES];
+    int n_reactions;         /* 0..LBFD_MAX_REACTIONS */
+    const lbfd_reaction *rxn;
+    double u_in[3], T_in, Y_in[LBFD_MAX_SPECIES]; /* INFLOW state */
+    double omega3, omega4;   /* rates of 3rd- and >=4th-order central moments */
+    int chem_substeps_max;   /* <= 1: one Euler source step; else sub-cycled */
+    int check_every;         /* steps between NaN/Inf checks; 0 = never */
+    double T_u, T_b;         /* progress variable theta = (T-T_u)/(T_b-T_u) */
+} lbfd_params;
+
+/* Diagnostics of the state at one level (plain sums over fluid cells in
+ * double precision):
+ *  sum_g     sum_i g_i                  sum_xi   sum_i Xi_i
+ *  mom       sum_i c_i g_i / cs^2       max_abs_sumY_minus_1
+ *  nonfinite fluid cells with a NaN/Inf T, Y_k or g_i (skipped in the rest)
+ *  sum_theta sum of the progress variable
+ *  hrr_idx, hrr_max  cell (first in index order) and value of the largest
+ *            per-step temperature source
+ *  wall_q    per fluid cell and axis side whose first neighbour is an
+ *            isothermal solid or wall face: 2 alpha rho(T_w, Y) (T - T_w)
+ *  fuel_rate sum of the per-step consumption of species 0
+ *  step      level the diagnostics refer to */
+typedef struct {
+    double sum_g, sum_xi, mom[3], max_abs_sumY_minus_1;
+    int64_t nonfinite;
+    double sum_theta;
+    int64_t hrr_idx;
+    double hrr_max, wall_q, fuel_rate;
+    int64_t step;
+} lbfd_diag;
+
+typedef struct lbfd_ctx lbfd_ctx;
+
+/* Create a context on the current HIP device.  mask [N] (uint8), wall_T
+ * [N] (temperature of isothermal solid cells; NULL = 300 K), T0 [N],
+ * Y0 [n_species*N] (sum 1 in fluid cells, checked to 1e-12), u0 [dim*N]
+ * or NULL (rest), Ph0 [N] or NULL (0).  The initial populations are the
+ * pressure-based equilibrium g_i = w_i (P_h - rho cs^2) + cs^2 f_i^eq
+ * (Eq. 12).  hip_stream: a hipStream_t on which all work of the context is
+ * queued (NULL: the null stream).  On success *out receives the context. */
+int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T,
+              const double *T0, const double *Y0, const double *u0,
+              const double *Ph0, void *hip_stream, lbfd_ctx **out);
+
+/* Queue nsteps coupled steps (asynchronous).  Every check_every levels
+ * the step also reduces the diagnostics; a non-finite value is reported
+ * by the next lbfd_sync. */
+int lbfd_step(lbfd_ctx *c, int64_t nsteps);
+
+/* Wait for queued work.  Returns LBFD_ENONFINITE if a periodic check saw
+ * a non-finite value (lbfd_last_error names the level). */
+int lbfd_sync(lbfd_ctx *c);
+
+/* Current level (number of steps taken). */
+int64_t lbfd_level(const lbfd_ctx *c);
+
+/* Macroscopic fields at the current level into host buffers (any may be
+ * NULL): rho [N], u [dim*N] (Eq. 13b), T [N], Y [n_species*N],
+ * Ph [N] (Eq. 13a, including the rho cs^2 Lambda / 2 term).  Always double.
+ * Non-fluid cells report rho = u = Ph = 0 and their stored T, Y.
+ * Synchronous. */
+int lbfd_read_fields(lbfd_ctx *c, double *rho, double *u, double *T,
+                     double *Y, double *Ph);
+
+/* Diagnostics of the current level (synchronous). */
+int lbfd_diagnostics(lbfd_ctx *c, lbfd_diag *d);
+
+/* Replace the wall temperature of isothermal solid cells (host [N]). */
+int lbfd_set_wall_temperature(lbfd_ctx *c, const double *wall_T);
+
+/* Checkpoint: the whole state (populations, scalars, outlet buffer,
+ * level) as an opaque blob of lbfd_state_size bytes.  Restoring it into a
+ * context created with the same parameters and geometry resumes the run
+ * bit for bit.  LBFD_ESTATE if the blob does not fit the context. */
+int lbfd_state_size(const lbfd_ctx *c, size_t *bytes);
+int lbfd_save_state(lbfd_ctx *c, void *blob, size_t bytes);
+int lbfd_load_state(lbfd_ctx *c, const void *blob, size_t bytes);
+
+/* Measured duration of the step kernels: queue nsteps steps bracketed by
+ * HIP events on the context stream, wait, and return the elapsed
+ * milliseconds in *ms. */
+int lbfd_time_steps(lbfd_ctx *c, int64_t nsteps, double *ms);
+
+void lbfd_destroy(lbfd_ctx *c);
+
+const char *lbfd_strerror(int code);
+const char *lbfd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

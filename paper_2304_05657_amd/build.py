@@ -1,0 +1,89 @@
+"""Build liblbfd.so (gfx950) in-tree with hipcc.
+
+Every HIP source is compiled to an object under ``_build/`` (in parallel,
+one translation unit per kernel configuration) and linked into
+``paper_2304_05657_amd/liblbfd.so``.  ``python -m paper_2304_05657_amd.build``
+rebuilds what changed; ``--force`` rebuilds everything.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import glob
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(ROOT, "_build", "lbfd")
+LIB = os.path.join(PKG, "liblbfd.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+# Packed FP32 instructions are disabled (-packed-fp32-ops): plain float code
+# is kept on the scalar-lane VALU path.
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-I", os.path.join(ROOT, "include")]
+
+
+def sources() -> list[str]:
+    return ([os.path.join(CSRC, "lbfd_api.hip"), os.path.join(CSRC, "lbfd_dispatch.hip")]
+            + sorted(glob.glob(os.path.join(CSRC, "inst", "*.hip"))))
+
+
+def _headers() -> list[str]:
+    return glob.glob(os.path.join(CSRC, "*.h")) + [os.path.join(ROOT, "include", "lbfd.h")]
+
+
+def _obj(src: str) -> str:
+    rel = os.path.relpath(src, CSRC).replace(os.sep, "_")
+    return os.path.join(BUILD, rel + ".o")
+
+
+def _compile(src: str) -> tuple[str, int, str]:
+    obj = _obj(src)
+    tmp = obj + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode == 0:
+        os.replace(tmp, obj)
+    out = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
+                    if "packed-fp32-ops" not in l and l.strip())
+    return src, r.returncode, out
+
+
+def build(force: bool = False, jobs: int | None = None, verbose: bool = True) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    hdr_mtime = max(os.path.getmtime(h) for h in _headers())
+    todo = []
+    for s in sources():
+        o = _obj(s)
+        if force or not os.path.exists(o) or os.path.getmtime(o) < max(os.path.getmtime(s), hdr_mtime):
+            todo.append(s)
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    failed = []
+    if todo:
+        with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+            for src, rc, out in ex.map(_compile, todo):
+                if verbose:
+                    print("[lbfd build] %s %s" % ("ok  " if rc == 0 else "FAIL", os.path.relpath(src, ROOT)),
+                          flush=True)
+                if out and (rc != 0 or verbose):
+                    print(out, flush=True)
+                if rc != 0:
+                    failed.append(src)
+    if failed:
+        raise RuntimeError("hipcc failed for: " + ", ".join(failed))
+    objs = [_obj(s) for s in sources()]
+    if force or todo or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(o) for o in objs):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+        os.replace(tmp, LIB)
+        if verbose:
+            print("[lbfd build] linked %s" % os.path.relpath(LIB, ROOT), flush=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(force="--force" in sys.argv)

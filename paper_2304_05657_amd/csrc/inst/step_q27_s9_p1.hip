@@ -1,0 +1,6 @@
+// Explicit instantiation of the step and init kernels for D3Q27, 9 species, precision 1.
+#include "../lbfd_kernels.h"
+
+namespace lbfd {
+LBFD_INSTANTIATE(27, 9, 1)
+}

@@ -1,0 +1,529 @@
+// lbfd_api.hip -- host side of the C ABI declared in include/lbfd.h:
+// validation, device memory, the step loop on the caller's stream,
+// read-back, diagnostics, checkpoints.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "lbfd_internal.h"
+
+using namespace lbfd;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(LBFD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+constexpr double kCs2 = 1.0 / 3.0;
+constexpr uint32_t kMagic = 0x4c424644u;  // "LBFD"
+
+struct StateHeader {
+    uint32_t magic;
+    int32_t lattice, n_species, precision, nx, ny, nz;
+    int64_t level;
+    uint64_t pop_bytes, sc_bytes, outlet_bytes;
+};
+
+size_t pop_elem_size(int prec) { return prec == LBFD_FP64 ? 8 : prec == LBFD_MIXED_FP32 ? 4 : 2; }
+size_t sc_elem_size(int prec) { return prec == LBFD_FP64 ? 8 : 4; }
+
+double mixture_density(const lbfd_params &p, double T, const double *Y)
+{
+    double s = 0.0;
+    for (int k = 0; k < p.n_species; ++k) s += Y[k] / p.W[k];
+    return (p.T_ref / T) * ((1.0 / s) / p.W_ref);
+}
+
+}  // namespace
+
+struct lbfd_ctx {
+    lbfd_params p;
+    lbfd_reaction rx[LBFD_MAX_REACTIONS];
+    int Q, D, nsp, prec;
+    long long N;
+    hipStream_t stream;
+    void *pop[2] = {nullptr, nullptr};
+    void *sc[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint8_t *mask = nullptr;
+    double *wall_T = nullptr;
+    double *outlet = nullptr;
+    size_t outlet_n = 0;
+    double *fields = nullptr;
+    double *partials = nullptr;
+    int nblocks = 0;
+    double *diag_dev = nullptr;
+    long long *bad_dev = nullptr;
+    lbfd_reaction *rx_dev = nullptr;
+    int64_t level = 0;
+    dim3 grid, block;
+    KParams base;
+};
+
+static void free_ctx(lbfd_ctx *c)
+{
+    if (!c) return;
+    void *ptrs[] = {c->pop[0], c->pop[1], c->sc[0], c->sc[1], c->mask, c->wall_T, c->outlet,
+                    c->fields, c->partials, c->diag_dev, c->bad_dev, c->rx_dev};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    delete c;
+}
+
+static int validate(const lbfd_params *p, const uint8_t *mask, const double *T0, const double *Y0)
+{
+    if (!p || !mask || !T0 || !Y0) return fail(LBFD_EINVAL, "null argument");
+    if (p->lattice != LBFD_D2Q9 && p->lattice != LBFD_D3Q27) return fail(LBFD_EINVAL, "lattice must be 9 or 27");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBFD_EINVAL, "grid sizes must be positive");
+    if (p->lattice == LBFD_D2Q9 && p->nz != 1) return fail(LBFD_EINVAL, "D2Q9 needs nz == 1");
+    if (p->precision < LBFD_FP64 || p->precision > LBFD_MIXED_FP16) return fail(LBFD_EINVAL, "bad precision");
+    if (p->n_species < 1 || p->n_species > LBFD_MAX_SPECIES) return fail(LBFD_EINVAL, "bad species count");
+    if (!supported(p->lattice, p->n_species, p->precision))
+        return fail(LBFD_EINVAL, "no kernel built for lattice %d, %d species, precision %d", p->lattice,
+                    p->n_species, p->precision);
+    if (!(p->tau > 0.5)) return fail(LBFD_EINVAL, "tau must exceed 1/2");
+    if (!(p->prandtl > 0.0)) return fail(LBFD_EINVAL, "prandtl must be positive");
+    const int D = p->lattice == LBFD_D2Q9 ? 2 : 3;
+    const double alpha = kCs2 * (p->tau - 0.5) / p->prandtl;
+    if (alpha > (D == 2 ? 3.0 / 16.0 : 1.0 / 8.0))
+        return fail(LBFD_EINVAL, "diffusivity %g above the explicit stability bound", alpha);
+    for (int f = 0; f < 6; ++f) {
+        if (p->face[f] < LBFD_FACE_PERIODIC || p->face[f] > LBFD_FACE_WALL_ADIABATIC)
+            return fail(LBFD_EINVAL, "bad face kind on face %d", f);
+        if (p->face[f] == LBFD_FACE_OUTFLOW && f >= 2) return fail(LBFD_EINVAL, "only x faces may be OUTFLOW");
+        if (D == 2 && f >= 4 && p->face[f] != LBFD_FACE_PERIODIC)
+            return fail(LBFD_EINVAL, "z faces of a D2Q9 box must be periodic");
+    }
+    if (p->n_reactions < 0 || p->n_reactions > LBFD_MAX_REACTIONS) return fail(LBFD_EINVAL, "bad reaction count");
+    if (p->n_reactions > 0 && !p->rxn) return fail(LBFD_EINVAL, "null reaction array");
+    for (int j = 0; j < p->n_reactions; ++j) {
+        const lbfd_reaction &r = p->rxn[j];
+        if (r.n_react < 0 || r.n_react > 4) return fail(LBFD_EINVAL, "reaction %d: bad reactant count", j);
+        for (int m = 0; m < r.n_react; ++m)
+            if (r.react[m] < 0 || r.react[m] >= p->n_species)
+                return fail(LBFD_EINVAL, "reaction %d: bad reactant index", j);
+        double s = 0.0;
+        for (int k = 0; k < p->n_species; ++k) s += r.nu_mass[k];
+        if (std::fabs(s) > 1e-12) return fail(LBFD_EINVAL, "reaction %d does not conserve mass", j);
+    }
+    for (int k = 0; k < p->n_species; ++k)
+        if (!(p->W[k] > 0.0)) return fail(LBFD_EINVAL, "molar masses must be positive");
+    if (!(p->T_ref > 0.0) || !(p->W_ref > 0.0)) return fail(LBFD_EINVAL, "T_ref, W_ref must be positive");
+    if (p->check_every < 0) return fail(LBFD_EINVAL, "check_every must be >= 0");
+    const long long N = (long long)p->nx * p->ny * p->nz;
+    long long nfluid = 0;
+    for (long long i = 0; i < N; ++i) {
+        if (mask[i] > LBFD_SOLID_ADIABATIC) return fail(LBFD_EINVAL, "bad mask value at cell %lld", i);
+        if (mask[i] != LBFD_FLUID) continue;
+        ++nfluid;
+        double s = 0.0;
+        for (int k = 0; k < p->n_species; ++k) s += Y0[k * N + i];
+        if (std::fabs(s - 1.0) > 1e-12) return fail(LBFD_EINVAL, "mass fractions do not sum to 1 at cell %lld", i);
+        if (!(T0[i] > 0.0)) return fail(LBFD_EINVAL, "temperature must be positive at cell %lld", i);
+    }
+    if (nfluid == 0) return fail(LBFD_EINVAL, "no fluid cell");
+    return LBFD_OK;
+}
+
+static KParams make_kparams(const lbfd_ctx *c)
+{
+    const lbfd_params &p = c->p;
+    KParams k;
+    memset(&k, 0, sizeof(k));
+    k.nx = p.nx;
+    k.ny = p.ny;
+    k.nz = p.nz;
+    k.N = c->N;
+    for (int f = 0; f < 6; ++f) {
+        k.face[f] = p.face[f];
+        k.face_T[f] = p.face_T[f];
+    }
+    k.mask = c->mask;
+    k.wall_T = c->wall_T;
+    k.outlet = c->outlet;
+    k.fields = c->fields;
+    k.partials = c->partials;
+    k.rx = c->rx_dev;
+    k.n_rx = p.n_reactions;
+    k.chem_substeps_max = p.chem_substeps_max;
+    k.omega2 = 1.0 / p.tau;
+    k.omega3 = p.omega3;
+    k.omega4 = p.omega4;
+    k.alpha = kCs2 * (p.tau - 0.5) / p.prandtl;
+    k.dt_phys = p.dt_phys;
+    k.T_ref = p.T_ref;
+    k.W_ref = p.W_ref;
+    for (int s = 0; s < c->nsp; ++s) {
+        k.invW[s] = 1.0 / p.W[s];
+        k.Y_in[s] = p.Y_in[s];
+    }
+    for (int d = 0; d < 3; ++d) k.u_in[d] = p.u_in[d];
+    k.T_in = p.T_in;
+    k.rho_in = mixture_density(p, p.T_in, p.Y_in);
+    k.T_u = p.T_u;
+    k.T_b = p.T_b;
+    return k;
+}
+
+// Convert and upload a double host array into a device scalar buffer.
+static int upload_scalars(lbfd_ctx *c, void *dst, const double *T0, const double *Y0)
+{
+    const long long N = c->N;
+    const size_t n = (size_t)(1 + c->nsp) * N;
+    if (c->prec == LBFD_FP64) {
+        HIP_TRY(hipMemcpy(dst, T0, N * sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy((double *)dst + N, Y0, (size_t)c->nsp * N * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> tmp(n);
+        for (long long i = 0; i < N; ++i) tmp[i] = (float)T0[i];
+        for (size_t i = 0; i < (size_t)c->nsp * N; ++i) tmp[N + i] = (float)Y0[i];
+        HIP_TRY(hipMemcpy(dst, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice));
+    }
+    return LBFD_OK;
+}
+
+extern "C" {
+
+int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, const double *T0,
+              const double *Y0, const double *u0, const double *Ph0, void *hip_stream, lbfd_ctx **out)
+{
+    if (!out) return fail(LBFD_EINVAL, "null output pointer");
+    *out = nullptr;
+    int rc = validate(p, mask, T0, Y0);
+    if (rc) return rc;
+    lbfd_ctx *c = new (std::nothrow) lbfd_ctx();
+    if (!c) return fail(LBFD_ENOMEM, "host allocation failed");
+    c->p = *p;
+    for (int j = 0; j < p->n_reactions; ++j) c->rx[j] = p->rxn[j];
+    c->p.rxn = nullptr;
+    c->Q = p->lattice;
+    c->D = p->lattice == LBFD_D2Q9 ? 2 : 3;
+    c->nsp = p->n_species;
+    c->prec = p->precision;
+    c->N = (long long)p->nx * p->ny * p->nz;
+    c->stream = (hipStream_t)hip_stream;
+    const long long N = c->N;
+    const size_t pop_bytes = (size_t)c->Q * N * pop_elem_size(c->prec);
+    const size_t sc_bytes = (size_t)(1 + c->nsp) * N * sc_elem_size(c->prec);
+    c->outlet_n = (size_t)2 * c->Q * p->ny * p->nz;
+    if (c->D == 2) {
+        c->block = dim3(64, 4, 1);
+    } else {
+        c->block = dim3(64, 2, 2);
+    }
+    c->grid = dim3((p->nx + c->block.x - 1) / c->block.x, (p->ny + c->block.y - 1) / c->block.y,
+                   (p->nz + c->block.z - 1) / c->block.z);
+    c->nblocks = c->grid.x * c->grid.y * c->grid.z;
+
+#define ALLOC(ptr, bytes)                                                          \
+    do {                                                                           \
+        if (hipMalloc((void **)&(ptr), (bytes)) != hipSuccess) {                   \
+            free_ctx(c);                                                           \
+            return fail(LBFD_ENOMEM, "hipMalloc of %zu bytes failed", (size_t)(bytes)); \
+        }                                                                          \
+    } while (0)
+    ALLOC(c->pop[0], pop_bytes);
+    ALLOC(c->pop[1], pop_bytes);
+    ALLOC(c->sc[0], sc_bytes);
+    ALLOC(c->sc[1], sc_bytes);
+    ALLOC(c->mask, N);
+    ALLOC(c->wall_T, N * sizeof(double));
+    ALLOC(c->outlet, c->outlet_n * sizeof(double));
+    ALLOC(c->partials, (size_t)c->nblocks * kNDiag * sizeof(double));
+    ALLOC(c->diag_dev, kNDiag * sizeof(double));
+    ALLOC(c->bad_dev, sizeof(long long));
+    ALLOC(c->rx_dev, sizeof(lbfd_reaction) * LBFD_MAX_REACTIONS);
+#undef ALLOC
+
+#define TRY_OR_FREE(expr)            \
+    do {                             \
+        int r_ = (expr);             \
+        if (r_) {                    \
+            free_ctx(c);             \
+            return r_;               \
+        }                            \
+    } while (0)
+#define HIP_OR_FREE(expr)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            free_ctx(c);                                                               \
+            return fail(LBFD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+        }                                                                              \
+    } while (0)
+    HIP_OR_FREE(hipMemset(c->pop[0], 0, pop_bytes));
+    HIP_OR_FREE(hipMemset(c->pop[1], 0, pop_bytes));
+    HIP_OR_FREE(hipMemset(c->outlet, 0, c->outlet_n * sizeof(double)));
+    HIP_OR_FREE(hipMemcpy(c->mask, mask, N, hipMemcpyHostToDevice));
+    {
+        std::vector<double> wt;
+        const double *src = wall_T;
+        if (!src) {
+            wt.assign(N, 300.0);
+            src = wt.data();
+        }
+        HIP_OR_FREE(hipMemcpy(c->wall_T, src, N * sizeof(double), hipMemcpyHostToDevice));
+    }
+    long long minus1 = -1;
+    HIP_OR_FREE(hipMemcpy(c->bad_dev, &minus1, sizeof(minus1), hipMemcpyHostToDevice));
+    if (p->n_reactions > 0)
+        HIP_OR_FREE(hipMemcpy(c->rx_dev, c->rx, sizeof(lbfd_reaction) * p->n_reactions, hipMemcpyHostToDevice));
+    TRY_OR_FREE(upload_scalars(c, c->sc[0], T0, Y0));
+    TRY_OR_FREE(upload_scalars(c, c->sc[1], T0, Y0));
+
+    c->base = make_kparams(c);
+    double *u0_dev = nullptr, *Ph0_dev = nullptr;
+    if (u0) {
+        HIP_OR_FREE(hipMalloc((void **)&u0_dev, (size_t)c->D * N * sizeof(double)));
+        HIP_OR_FREE(hipMemcpy(u0_dev, u0, (size_t)c->D * N * sizeof(double), hipMemcpyHostToDevice));
+    }
+    if (Ph0) {
+        HIP_OR_FREE(hipMalloc((void **)&Ph0_dev, N * sizeof(double)));
+        HIP_OR_FREE(hipMemcpy(Ph0_dev, Ph0, N * sizeof(double), hipMemcpyHostToDevice));
+    }
+    KParams k = c->base;
+    k.sc_in = c->sc[0];
+    k.pop_out = c->pop[0];
+    hipError_t e = launch_init(c->Q, c->nsp, c->prec, k, u0_dev, Ph0_dev, c->grid, c->block, c->stream);
+    hipError_t e2 = hipStreamSynchronize(c->stream);
+    if (u0_dev) (void)hipFree(u0_dev);
+    if (Ph0_dev) (void)hipFree(Ph0_dev);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        free_ctx(c);
+        return fail(LBFD_EDEVICE, "init kernel failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+#undef TRY_OR_FREE
+#undef HIP_OR_FREE
+    c->cur = 0;
+    c->level = 0;
+    *out = c;
+    return LBFD_OK;
+}
+
+int lbfd_step(lbfd_ctx *c, int64_t nsteps)
+{
+    if (!c || nsteps < 0) return fail(LBFD_EINVAL, "bad arguments");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        KParams k = c->base;
+        k.pop_in = c->pop[c->cur];
+        k.pop_out = c->pop[1 - c->cur];
+        k.sc_in = c->sc[c->cur];
+        k.sc_out = c->sc[1 - c->cur];
+        const bool check = c->p.check_every > 0 && (c->level % c->p.check_every) == 0;
+        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, check ? kModeStepDiag : kModeStep, k, c->grid, c->block,
+                            c->stream));
+        if (check) HIP_TRY(launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream));
+        c->cur ^= 1;
+        c->level += 1;
+    }
+    return LBFD_OK;
+}
+
+int lbfd_sync(lbfd_ctx *c)
+{
+    if (!c) return fail(LBFD_EINVAL, "null context");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    long long bad = -1;
+    HIP_TRY(hipMemcpy(&bad, c->bad_dev, sizeof(bad), hipMemcpyDeviceToHost));
+    if (bad >= 0) return fail(LBFD_ENONFINITE, "non-finite values in the state at level %lld", bad);
+    return LBFD_OK;
+}
+
+int64_t lbfd_level(const lbfd_ctx *c) { return c ? c->level : -1; }
+
+// Evaluate the current level without advancing it: fields and diagnostics.
+static int evaluate(lbfd_ctx *c)
+{
+    if (!c->fields) {
+        if (hipMalloc((void **)&c->fields, (size_t)5 * c->N * sizeof(double)) != hipSuccess) {
+            c->fields = nullptr;
+            return fail(LBFD_ENOMEM, "hipMalloc of the field buffer failed");
+        }
+        c->base.fields = c->fields;
+    }
+    KParams k = c->base;
+    k.pop_in = c->pop[c->cur];
+    k.sc_in = c->sc[c->cur];
+    HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeFields, k, c->grid, c->block, c->stream));
+    HIP_TRY(launch_finalize(c->partials, c->nblocks, c->diag_dev, nullptr, c->level, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LBFD_OK;
+}
+
+int lbfd_read_fields(lbfd_ctx *c, double *rho, double *u, double *T, double *Y, double *Ph)
+{
+    if (!c) return fail(LBFD_EINVAL, "null context");
+    int rc = evaluate(c);
+    if (rc) return rc;
+    const long long N = c->N;
+    if (rho) HIP_TRY(hipMemcpy(rho, c->fields, N * sizeof(double), hipMemcpyDeviceToHost));
+    if (u) HIP_TRY(hipMemcpy(u, c->fields + N, (size_t)c->D * N * sizeof(double), hipMemcpyDeviceToHost));
+    if (Ph) HIP_TRY(hipMemcpy(Ph, c->fields + 4 * N, N * sizeof(double), hipMemcpyDeviceToHost));
+    if (T || Y) {
+        const size_t n = (size_t)(1 + c->nsp) * N;
+        if (c->prec == LBFD_FP64) {
+            if (T) HIP_TRY(hipMemcpy(T, c->sc[c->cur], N * sizeof(double), hipMemcpyDeviceToHost));
+            if (Y)
+                HIP_TRY(hipMemcpy(Y, (double *)c->sc[c->cur] + N, (size_t)c->nsp * N * sizeof(double),
+                                  hipMemcpyDeviceToHost));
+        } else {
+            std::vector<float> tmp(n);
+            HIP_TRY(hipMemcpy(tmp.data(), c->sc[c->cur], n * sizeof(float), hipMemcpyDeviceToHost));
+            if (T)
+                for (long long i = 0; i < N; ++i) T[i] = tmp[i];
+            if (Y)
+                for (size_t i = 0; i < (size_t)c->nsp * N; ++i) Y[i] = tmp[N + i];
+        }
+    }
+    return LBFD_OK;
+}
+
+int lbfd_diagnostics(lbfd_ctx *c, lbfd_diag *d)
+{
+    if (!c || !d) return fail(LBFD_EINVAL, "null argument");
+    int rc = evaluate(c);
+    if (rc) return rc;
+    double a[kNDiag];
+    HIP_TRY(hipMemcpy(a, c->diag_dev, sizeof(a), hipMemcpyDeviceToHost));
+    d->sum_g = a[kSumG];
+    d->sum_xi = a[kSumXi];
+    d->mom[0] = a[kMomX];
+    d->mom[1] = a[kMomY];
+    d->mom[2] = a[kMomZ];
+    d->max_abs_sumY_minus_1 = a[kMaxY];
+    d->nonfinite = (int64_t)a[kNonfinite];
+    d->sum_theta = a[kTheta];
+    d->hrr_idx = a[kHrrIdx] < 1e299 ? (int64_t)a[kHrrIdx] : -1;
+    d->hrr_max = a[kHrrMax];
+    d->wall_q = a[kWallQ];
+    d->fuel_rate = a[kFuel];
+    d->step = c->level;
+    return LBFD_OK;
+}
+
+int lbfd_set_wall_temperature(lbfd_ctx *c, const double *wall_T)
+{
+    if (!c || !wall_T) return fail(LBFD_EINVAL, "null argument");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(c->wall_T, wall_T, c->N * sizeof(double), hipMemcpyHostToDevice));
+    return LBFD_OK;
+}
+
+static void state_sizes(const lbfd_ctx *c, size_t *pop, size_t *sc, size_t *outl)
+{
+    *pop = (size_t)c->Q * c->N * pop_elem_size(c->prec);
+    *sc = (size_t)(1 + c->nsp) * c->N * sc_elem_size(c->prec);
+    *outl = c->outlet_n * sizeof(double);
+}
+
+int lbfd_state_size(const lbfd_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return fail(LBFD_EINVAL, "null argument");
+    size_t a, b, o;
+    state_sizes(c, &a, &b, &o);
+    *bytes = sizeof(StateHeader) + a + b + o;
+    return LBFD_OK;
+}
+
+int lbfd_save_state(lbfd_ctx *c, void *blob, size_t bytes)
+{
+    size_t need;
+    int rc = lbfd_state_size(c, &need);
+    if (rc) return rc;
+    if (!blob || bytes < need) return fail(LBFD_EINVAL, "state buffer too small (%zu < %zu)", bytes, need);
+    size_t a, b, o;
+    state_sizes(c, &a, &b, &o);
+    StateHeader h = {kMagic, c->Q, c->nsp, c->prec, c->p.nx, c->p.ny, c->p.nz, c->level, a, b, o};
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    char *q = (char *)blob;
+    memcpy(q, &h, sizeof(h));
+    HIP_TRY(hipMemcpy(q + sizeof(h), c->pop[c->cur], a, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(q + sizeof(h) + a, c->sc[c->cur], b, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(q + sizeof(h) + a + b, c->outlet, o, hipMemcpyDeviceToHost));
+    return LBFD_OK;
+}
+
+int lbfd_load_state(lbfd_ctx *c, const void *blob, size_t bytes)
+{
+    size_t need;
+    int rc = lbfd_state_size(c, &need);
+    if (rc) return rc;
+    if (!blob || bytes < need) return fail(LBFD_ESTATE, "state blob too small");
+    StateHeader h;
+    memcpy(&h, blob, sizeof(h));
+    size_t a, b, o;
+    state_sizes(c, &a, &b, &o);
+    if (h.magic != kMagic || h.lattice != c->Q || h.n_species != c->nsp || h.precision != c->prec ||
+        h.nx != c->p.nx || h.ny != c->p.ny || h.nz != c->p.nz || h.pop_bytes != a || h.sc_bytes != b ||
+        h.outlet_bytes != o)
+        return fail(LBFD_ESTATE, "state blob does not match this context");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const char *q = (const char *)blob;
+    HIP_TRY(hipMemcpy(c->pop[c->cur], q + sizeof(h), a, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->sc[c->cur], q + sizeof(h) + a, b, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->outlet, q + sizeof(h) + a + b, o, hipMemcpyHostToDevice));
+    c->level = h.level;
+    return LBFD_OK;
+}
+
+int lbfd_time_steps(lbfd_ctx *c, int64_t nsteps, double *ms)
+{
+    if (!c || !ms || nsteps < 0) return fail(LBFD_EINVAL, "bad arguments");
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    HIP_TRY(hipEventRecord(a, c->stream));
+    int rc = lbfd_step(c, nsteps);
+    HIP_TRY(hipEventRecord(b, c->stream));
+    HIP_TRY(hipEventSynchronize(b));
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = t;
+    return rc;
+}
+
+void lbfd_destroy(lbfd_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_ctx(c);
+}
+
+const char *lbfd_strerror(int code)
+{
+    switch (code) {
+    case LBFD_OK: return "ok";
+    case LBFD_EINVAL: return "invalid argument";
+    case LBFD_ENOMEM: return "out of memory";
+    case LBFD_EDEVICE: return "HIP runtime error";
+    case LBFD_ENONFINITE: return "non-finite state";
+    case LBFD_ESTATE: return "state blob mismatch";
+    default: return "unknown error";
+    }
+}
+
+const char *lbfd_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// Internal interface between the C-ABI layer (lbfd_api.hip) and the gfx950
+// kernels (lbfd_step.hip).  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lbfd.h"
+
+namespace lbfd {
+
+constexpr int kMaxSp = LBFD_MAX_SPECIES;
+constexpr int kNDiag = 12;  // per-block partial diagnostics, see DiagSlot
+constexpr int kBlock = 256;
+
+// Slots of the per-block and final diagnostics arrays (double).
+enum DiagSlot {
+    kSumG = 0, kSumXi = 1, kMomX = 2, kMomY = 3, kMomZ = 4, kMaxY = 5,
+    kNonfinite = 6, kTheta = 7, kHrrMax = 8, kHrrIdx = 9, kWallQ = 10, kFuel = 11
+};
+
+// Kind of what a neighbour coordinate lands on.
+enum NbKind { kFluid = 0, kIso = 1, kAdia = 2, kInflow = 3, kOutflow = 4 };
+
+// Everything a step kernel reads; passed by value (kernarg segment, read
+// through the scalar cache).
+struct KParams {
+    int nx, ny, nz;
+    long long N;
+    int face[6];
+    double face_T[6];
+    const uint8_t *mask;
+    const double *wall_T;
+    const void *pop_in;   // post-collision populations of the previous level
+    void *pop_out;        // post-collision populations of this level
+    const void *sc_in;    // [1 + n_species][N]: T then Y_k
+    void *sc_out;
+    double *outlet;       // [2 x faces][Q][ny*nz] post-streaming outlet populations
+    double *fields;       // [5][N]: rho, u_x, u_y, u_z, P_h  (fields mode)
+    double *partials;     // [blocks][kNDiag]  (diagnostics modes)
+    const lbfd_reaction *rx;
+    int n_rx;
+    int chem_substeps_max;
+    double omega2, omega3, omega4, alpha;
+    double dt_phys;
+    double T_ref, W_ref;
+    double invW[kMaxSp];
+    double u_in[3], T_in, Y_in[kMaxSp], rho_in;
+    double T_u, T_b;
+};
+
+// Kernel modes.
+enum { kModeStep = 0, kModeStepDiag = 1, kModeFields = 2 };
+
+// Launchers (lbfd_step.hip).  Return hipSuccess or the launch error.
+hipError_t launch_step(int Q, int nsp, int prec, int mode, const KParams &kp,
+                       dim3 grid, dim3 block, hipStream_t s);
+hipError_t launch_init(int Q, int nsp, int prec, const KParams &kp, const double *u0,
+                       const double *Ph0, dim3 grid, dim3 block, hipStream_t s);
+hipError_t launch_finalize(const double *partials, int nblocks, double *out,
+                           long long *first_bad, long long level, hipStream_t s);
+bool supported(int Q, int nsp, int prec);
+
+}  // namespace lbfd

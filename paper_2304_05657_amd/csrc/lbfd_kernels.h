@@ -1,0 +1,803 @@
+#pragma once
+// lbfd_kernels.h -- templates of the fused coupled step for gfx950: pull-scheme lattice-Boltzmann streaming
+// with boundary conditions, finite-difference advection-diffusion-reaction
+// of T and Y_k with ghost nodes, source Xi, central-moment collision, and
+// explicit Euler update -- one thread per cell, one kernel per step.
+//
+// Method: Hosseini & Thevenin, arXiv:2304.05657, Secs. II-III.  The step
+// order (all terms at level n) and the readings of the paper's silent or
+// garbled passages are those stated in include/lbfd.h and the design notes.
+//
+// Storage (structure of arrays, x fastest):
+//   populations  pop[i][cell]   post-collision values g*_i of the previous
+//                               level; FP64: g itself, mixed: g/(w_i cs^2)
+//   scalars      sc[0][cell] = T, sc[1+k][cell] = Y_k
+//   outlet       post-streaming values of the populations that enter
+//                through an outflow face, per face cell (double)
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "lbfd_internal.h"
+
+#include <type_traits>
+
+namespace lbfd {
+
+constexpr double kCs2 = 1.0 / 3.0;
+
+// ---------------------------------------------------------------- lattice
+template <int Q>
+struct Lat {
+    static constexpr int D = (Q == 9) ? 2 : 3;
+    __host__ __device__ static constexpr int cx(int i) { return i % 3 - 1; }
+    __host__ __device__ static constexpr int cy(int i) { return (i / 3) % 3 - 1; }
+    __host__ __device__ static constexpr int cz(int i) { return Q == 9 ? 0 : i / 9 - 1; }
+    __host__ __device__ static constexpr int c(int i, int d) { return d == 0 ? cx(i) : d == 1 ? cy(i) : cz(i); }
+    __host__ __device__ static constexpr double w(int i)
+    {
+        // textbook weights by |c|^2
+        return Q == 9 ? (cx(i) * cx(i) + cy(i) * cy(i) == 0   ? 4.0 / 9.0
+                         : cx(i) * cx(i) + cy(i) * cy(i) == 1 ? 1.0 / 9.0
+                                                              : 1.0 / 36.0)
+                      : (cx(i) * cx(i) + cy(i) * cy(i) + cz(i) * cz(i) == 0   ? 8.0 / 27.0
+                         : cx(i) * cx(i) + cy(i) * cy(i) + cz(i) * cz(i) == 1 ? 2.0 / 27.0
+                         : cx(i) * cx(i) + cy(i) * cy(i) + cz(i) * cz(i) == 2 ? 1.0 / 54.0
+                                                                              : 1.0 / 216.0);
+    }
+};
+
+// ------------------------------------------------------------- precision
+template <int PREC> struct Prec;
+template <> struct Prec<LBFD_FP64> { using calc = double; using pop = double; using scal = double; };
+template <> struct Prec<LBFD_MIXED_FP32> { using calc = float; using pop = float; using scal = float; };
+template <> struct Prec<LBFD_MIXED_FP16> { using calc = float; using pop = __half; using scal = float; };
+
+// Populations: FP64 stores g; mixed stores g / (w_i cs^2) (deviation from
+// the lattice weights, scaled to comparable magnitude across directions).
+template <int Q, int PREC, int I>
+__device__ __forceinline__ typename Prec<PREC>::calc pop_load(const void *base, long long N, long long idx)
+{
+    if constexpr (PREC == LBFD_FP64) {
+        return ((const double *)base)[I * N + idx];
+    } else if constexpr (PREC == LBFD_MIXED_FP32) {
+        constexpr float s = (float)(Lat<Q>::w(I) * kCs2);
+        return ((const float *)base)[I * N + idx] * s;
+    } else {
+        constexpr float s = (float)(Lat<Q>::w(I) * kCs2);
+        return __half2float(((const __half *)base)[I * N + idx]) * s;
+    }
+}
+
+template <int Q, int PREC, int I>
+__device__ __forceinline__ void pop_store(void *base, long long N, long long idx, typename Prec<PREC>::calc v)
+{
+    if constexpr (PREC == LBFD_FP64) {
+        ((double *)base)[I * N + idx] = v;
+    } else if constexpr (PREC == LBFD_MIXED_FP32) {
+        constexpr float s = (float)(1.0 / (Lat<Q>::w(I) * kCs2));
+        ((float *)base)[I * N + idx] = v * s;
+    } else {
+        constexpr float s = (float)(1.0 / (Lat<Q>::w(I) * kCs2));
+        ((__half *)base)[I * N + idx] = __float2half_rn(v * s);
+    }
+}
+
+// compile-time loop
+template <int B, int E, class F>
+__device__ __forceinline__ void sfor(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+
+// ------------------------------------------------------------- geometry
+struct Nb {
+    int kind;
+    int face;
+    long long idx;
+    double Tw;
+};
+
+__device__ __forceinline__ int wrapc(int v, int n)
+{
+    if ((unsigned)v < (unsigned)n) return v;
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// What sits at (x, y, z): periodic faces wrap; outside any other face the
+// point is that face (walls before inflow before outflow, lower axis and
+// face first); inside, the mask decides.
+__device__ __forceinline__ Nb classify(const KParams &P, int x, int y, int z)
+{
+    int q[3] = {x, y, z};
+    const int n[3] = {P.nx, P.ny, P.nz};
+    int best_face = -1, best_rank = 99;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if ((unsigned)q[d] >= (unsigned)n[d]) {
+            int f = 2 * d + (q[d] >= n[d] ? 1 : 0);
+            int kind = P.face[f];
+            if (kind == LBFD_FACE_PERIODIC) {
+                q[d] = wrapc(q[d], n[d]);
+            } else {
+                int rank = (kind == LBFD_FACE_WALL || kind == LBFD_FACE_WALL_ADIABATIC) ? 0
+                         : kind == LBFD_FACE_INFLOW ? 1 : 2;
+                if (rank < best_rank) {
+                    best_rank = rank;
+                    best_face = f;
+                }
+            }
+        }
+    }
+    Nb r;
+    r.idx = 0;
+    r.Tw = 0.0;
+    r.face = best_face;
+    if (best_face >= 0) {
+        int kind = P.face[best_face];
+        r.kind = kind == LBFD_FACE_WALL ? kIso : kind == LBFD_FACE_WALL_ADIABATIC ? kAdia
+               : kind == LBFD_FACE_INFLOW ? kInflow : kOutflow;
+        r.Tw = P.face_T[best_face];
+        return r;
+    }
+    r.idx = ((long long)q[2] * P.ny + q[1]) * P.nx + q[0];
+    uint8_t m = P.mask[r.idx];
+    r.kind = m == LBFD_FLUID ? kFluid : m == LBFD_SOLID_ISOTHERMAL ? kIso : kAdia;
+    if (r.kind == kIso) r.Tw = P.wall_T[r.idx];
+    return r;
+}
+
+__device__ __forceinline__ long long outlet_index(const KParams &P, int face, int i, int Q, int y, int z)
+{
+    return ((long long)((face & 1) * Q + i) * P.nz + z) * P.ny + y;
+}
+
+// Post-streaming population i of fluid cell (x, y, z) at the current level
+// from the post-collision buffer: pull from r - c_i; half-way bounce-back
+// from a solid or wall; velocity inlet (Eq. 31 in g units:
+// g*_opp + 2 w_i rho_in c_i.u_in); outlet value kept in the outlet buffer.
+template <int Q, int PREC, int I>
+__device__ __forceinline__ typename Prec<PREC>::calc gather(const KParams &P, int x, int y, int z, long long idx)
+{
+    using C = typename Prec<PREC>::calc;
+    using L = Lat<Q>;
+    constexpr int OPP = Q - 1 - I;
+    if constexpr (I == (Q - 1) / 2) {
+        return pop_load<Q, PREC, I>(P.pop_in, P.N, idx);  // rest population
+    } else {
+        Nb s = classify(P, x - L::cx(I), y - L::cy(I), z - L::cz(I));
+        if (s.kind == kFluid) return pop_load<Q, PREC, I>(P.pop_in, P.N, s.idx);
+        if (s.kind == kInflow) {
+            double cu = L::cx(I) * P.u_in[0] + L::cy(I) * P.u_in[1] + L::cz(I) * P.u_in[2];
+            return pop_load<Q, PREC, OPP>(P.pop_in, P.N, idx) + (C)(2.0 * L::w(I) * P.rho_in * cu);
+        }
+        if (s.kind == kOutflow) {
+            int sign = (s.face & 1) ? 1 : -1;
+            Nb in = classify(P, x - sign, y, z);
+            if (in.kind == kFluid) return (C)P.outlet[outlet_index(P, s.face, I, Q, y, z)];
+        }
+        return pop_load<Q, PREC, OPP>(P.pop_in, P.N, idx);
+    }
+}
+
+// ------------------------------------------------------------ scalars
+template <int NSP, class C>
+struct Pt {
+    C T, rho;
+    C Y[NSP];
+};
+
+template <int NSP, class C>
+__device__ __forceinline__ C density(const KParams &P, C T, const C *Y)
+{
+    C s = 0;
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) s += Y[k] * (C)P.invW[k];
+    return ((C)P.T_ref / T) * (((C)1 / s) / (C)P.W_ref);
+}
+
+template <int NSP, int PREC>
+__device__ __forceinline__ void load_point(const KParams &P, long long idx, Pt<NSP, typename Prec<PREC>::calc> &o)
+{
+    using S = typename Prec<PREC>::scal;
+    const S *sc = (const S *)P.sc_in;
+    o.T = sc[idx];
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) o.Y[k] = sc[(1 + k) * P.N + idx];
+    o.rho = density<NSP>(P, o.T, o.Y);
+}
+
+// Ghost value across the wall `w` from the image point (Sec. III.B):
+// Dirichlet 2 phi_B - phi(I) for T at isothermal walls and for T, Y at the
+// inlet; Neumann phi(I) otherwise (walls are impermeable); the density
+// ghost is reconstructed directly from its wall value.
+template <int NSP, class C>
+__device__ __forceinline__ void ghost(const KParams &P, const Nb &w, const Pt<NSP, C> &img, Pt<NSP, C> &o)
+{
+    if (w.kind == kIso) {
+        C Tw = (C)w.Tw;
+        o.T = (C)2 * Tw - img.T;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) o.Y[k] = img.Y[k];
+        o.rho = (C)2 * density<NSP>(P, Tw, img.Y) - img.rho;
+    } else if (w.kind == kInflow) {
+        o.T = (C)2 * (C)P.T_in - img.T;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) o.Y[k] = (C)2 * (C)P.Y_in[k] - img.Y[k];
+        o.rho = (C)2 * (C)P.rho_in - img.rho;
+    } else {
+        o = img;
+    }
+}
+
+// Values at p + m e_d, m = -2..2 (slot m+2), ghosts included; `near` is
+// set when a non-fluid point lies within two cells on either side.
+template <int NSP, int PREC, bool DIAG>
+__device__ __forceinline__ void axis_stencil(const KParams &P, int x, int y, int z, int d,
+                                             const Pt<NSP, typename Prec<PREC>::calc> &ctr,
+                                             Pt<NSP, typename Prec<PREC>::calc> (&st)[5], bool &near,
+                                             double &wallq)
+{
+    using C = typename Prec<PREC>::calc;
+    st[2] = ctr;
+#pragma unroll
+    for (int sg = -1; sg <= 1; sg += 2) {
+        int o1 = 2 + sg, o2 = 2 + 2 * sg;
+        int q1[3] = {x, y, z}, q2[3] = {x, y, z}, qm[3] = {x, y, z};
+        q1[d] += sg;
+        q2[d] += 2 * sg;
+        qm[d] -= sg;
+        Nb c1 = classify(P, q1[0], q1[1], q1[2]);
+        if (c1.kind != kFluid) {
+            near = true;
+            if constexpr (DIAG) {
+                if (c1.kind == kIso)
+                    wallq += 2.0 * P.alpha * (double)density<NSP>(P, (C)c1.Tw, ctr.Y) *
+                             ((double)ctr.T - c1.Tw);
+            }
+            ghost<NSP>(P, c1, ctr, st[o1]);
+            Nb cm = classify(P, qm[0], qm[1], qm[2]);
+            Pt<NSP, C> img;
+            if (cm.kind == kFluid)
+                load_point<NSP, PREC>(P, cm.idx, img);
+            else
+                img = ctr;
+            ghost<NSP>(P, c1, img, st[o2]);
+        } else {
+            load_point<NSP, PREC>(P, c1.idx, st[o1]);
+            Nb c2 = classify(P, q2[0], q2[1], q2[2]);
+            if (c2.kind != kFluid) {
+                near = true;
+                ghost<NSP>(P, c2, st[o1], st[o2]);
+            } else {
+                load_point<NSP, PREC>(P, c2.idx, st[o2]);
+            }
+        }
+    }
+}
+
+// fourth-order central first and second derivatives (Sec. II.D)
+template <class C>
+__device__ __forceinline__ C d1(C a, C b, C c, C d, C e)
+{
+    return ((a - (C)8 * b) + ((C)8 * d - e)) * (C)(1.0 / 12.0);
+}
+template <class C>
+__device__ __forceinline__ C d2(C a, C b, C c, C d, C e)
+{
+    return ((C)16 * (b + d) - (a + e) - (C)30 * c) * (C)(1.0 / 12.0);
+}
+
+// WENO3 (Jiang-Shu, eps = 1e-6) value at the face between b and c from
+// the side of b; a is the far upwind point.  The normalised weight of the
+// one-sided candidate is e1^2 / (e1^2 + 2 e0^2), e_r = eps + beta_r.
+template <class C>
+__device__ __forceinline__ C weno_face(C a, C b, C c)
+{
+    const C eps = (C)1e-6;
+    C q0 = (C)1.5 * b - (C)0.5 * a;
+    C q1 = (C)0.5 * (b + c);
+    C e0 = eps + (b - a) * (b - a);
+    C e1 = eps + (c - b) * (c - b);
+    C e0s = e0 * e0, e1s = e1 * e1;
+    C w0 = e1s / (e1s + (C)2 * e0s);
+    return q1 + w0 * (q0 - q1);
+}
+
+template <class C>
+__device__ __forceinline__ C weno3(C m2, C m1, C c0, C p1, C p2, C u)
+{
+    if (u >= (C)0) return weno_face(m1, c0, p1) - weno_face(m2, m1, c0);
+    return weno_face(p2, p1, c0) - weno_face(p1, c0, m1);
+}
+
+// ------------------------------------------------------------ chemistry
+// Arrhenius source over one step in double precision (per reaction
+// r = A dt T^b exp(-Ta/T) prod Y_react; species nu_k r, temperature q r):
+// one explicit Euler step, or, with chem_substeps_max > 1, N sub-steps
+// with N = ceil(max_j k_j / 0.1) capped at chem_substeps_max; a sub-step
+// that would consume a mass fraction below zero is scaled down.
+__device__ __forceinline__ double rate_coeff(const lbfd_reaction &r, double dt, double T)
+{
+    return r.A * dt * pow(T, r.b) * exp(-r.Ta / T);
+}
+
+template <int NSP>
+__device__ __forceinline__ void chemistry(const KParams &P, double T, const double (&Y)[NSP], double &srcT,
+                                          double (&srcY)[NSP])
+{
+    int nsub = 1;
+    if (P.chem_substeps_max > 1) {
+        double kmax = 0.0;
+        for (int j = 0; j < P.n_rx; ++j) kmax = fmax(kmax, rate_coeff(P.rx[j], P.dt_phys, T));
+        double want = ceil(kmax / 0.1);
+        nsub = want < 1.0 ? 1 : want > (double)P.chem_substeps_max ? P.chem_substeps_max : (int)want;
+    }
+    double dT = 0.0, dY[NSP];
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) dY[k] = 0.0;
+    for (int s = 0; s < nsub; ++s) {
+        double Tc = T + dT;
+        double Yc[NSP];
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) Yc[k] = Y[k] + dY[k];
+        double incT = 0.0, incY[NSP];
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) incY[k] = 0.0;
+        for (int j = 0; j < P.n_rx; ++j) {
+            const lbfd_reaction &r = P.rx[j];
+            double rr = rate_coeff(r, P.dt_phys, Tc) / nsub;
+            for (int m = 0; m < r.n_react; ++m) {
+                int kr = r.react[m];
+                double yv = 0.0;
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) yv = (k == kr) ? Yc[k] : yv;
+                rr *= yv;
+            }
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) incY[k] += r.nu_mass[k] * rr;
+            incT += r.q_over_cp * rr;
+        }
+        // positivity limiter: scale the sub-step so that no mass fraction
+        // is consumed below zero (1, i.e. plain Euler, otherwise)
+        double lam = 1.0;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k)
+            if (incY[k] < 0.0 && Yc[k] + incY[k] < 0.0) lam = fmin(lam, fmax(Yc[k], 0.0) / (-incY[k]));
+        dT += lam * incT;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) dY[k] += lam * incY[k];
+    }
+    srcT = dT;
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) srcY[k] = dY[k];
+}
+
+// ------------------------------------------------- central-moment transform
+// Central moments about u (Sec. II.C, Eq. 21) of the 3 x 3 (x 3) cube of
+// populations, one axis at a time.  Along a line with velocities -1, 0, 1
+// holding (a, b, d): m0 = a+b+d, m1 = (d-a) - u m0,
+// m2 = (a+d) + 2u(a-d) + u^2 m0.  Moment (p, q, r) lands at p + 3q + 9r.
+template <class C>
+__device__ __forceinline__ void cm_fwd_line(C &a, C &b, C &d, C u)
+{
+    C m0 = a + b + d;
+    C m1 = (d - a) - u * m0;
+    C m2 = (a + d) + (C)2 * u * (a - d) + u * u * m0;
+    a = m0;
+    b = m1;
+    d = m2;
+}
+
+// exact inverse of cm_fwd_line
+template <class C>
+__device__ __forceinline__ void cm_inv_line(C &a, C &b, C &d, C u)
+{
+    C m0 = a, m1 = b, m2 = d;
+    C uu = u * u;
+    a = (C)0.5 * (m0 * (uu - u) + m1 * ((C)2 * u - (C)1) + m2);
+    b = m0 * ((C)1 - uu) - (C)2 * u * m1 - m2;
+    d = (C)0.5 * (m0 * (uu + u) + m1 * ((C)2 * u + (C)1) + m2);
+}
+
+template <int Q, class C>
+__device__ __forceinline__ void central_fwd(C (&h)[Q], const C (&u)[3])
+{
+#pragma unroll
+    for (int l = 0; l < Q / 3; ++l) cm_fwd_line(h[3 * l], h[3 * l + 1], h[3 * l + 2], u[0]);
+#pragma unroll
+    for (int zp = 0; zp < Q / 9; ++zp)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) cm_fwd_line(h[9 * zp + p], h[9 * zp + p + 3], h[9 * zp + p + 6], u[1]);
+    if constexpr (Q == 27) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) cm_fwd_line(h[r], h[r + 9], h[r + 18], u[2]);
+    }
+}
+
+template <int Q, class C>
+__device__ __forceinline__ void central_inv(C (&h)[Q], const C (&u)[3])
+{
+    if constexpr (Q == 27) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) cm_inv_line(h[r], h[r + 9], h[r + 18], u[2]);
+    }
+#pragma unroll
+    for (int zp = 0; zp < Q / 9; ++zp)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) cm_inv_line(h[9 * zp + p], h[9 * zp + p + 3], h[9 * zp + p + 6], u[1]);
+#pragma unroll
+    for (int l = 0; l < Q / 3; ++l) cm_inv_line(h[3 * l], h[3 * l + 1], h[3 * l + 2], u[0]);
+}
+
+// Relax toward the Maxwellian central moments at temperature cs^2: orders
+// 0-1 kept, order 2 at 1/tau, order 3 at omega3, higher at omega4.
+template <int Q, class C>
+__device__ __forceinline__ void relax(C (&k)[Q], C om2, C om3, C om4)
+{
+    sfor<0, Q>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        constexpr int p = j % 3, q = (j / 3) % 3, r = (Q == 27) ? j / 9 : 0;
+        constexpr int order = p + q + r;
+        if constexpr (order >= 2) {
+            constexpr bool odd = (p == 1) || (q == 1) || (r == 1);
+            constexpr int n2 = (p == 2) + (q == 2) + (r == 2);
+            constexpr double tgt = odd ? 0.0 : (n2 == 1 ? kCs2 : n2 == 2 ? kCs2 * kCs2 : kCs2 * kCs2 * kCs2);
+            C om = order == 2 ? om2 : order == 3 ? om3 : om4;
+            k[j] = k[j] - om * (k[j] - (C)tgt);
+        }
+    });
+}
+
+// ------------------------------------------------------------ reductions
+__device__ __forceinline__ void diag_combine(double (&a)[kNDiag], const double *b)
+{
+    a[kSumG] += b[kSumG];
+    a[kSumXi] += b[kSumXi];
+    a[kMomX] += b[kMomX];
+    a[kMomY] += b[kMomY];
+    a[kMomZ] += b[kMomZ];
+    a[kMaxY] = fmax(a[kMaxY], b[kMaxY]);
+    a[kNonfinite] += b[kNonfinite];
+    a[kTheta] += b[kTheta];
+    if (b[kHrrMax] > a[kHrrMax] || (b[kHrrMax] == a[kHrrMax] && b[kHrrIdx] < a[kHrrIdx])) {
+        a[kHrrMax] = b[kHrrMax];
+        a[kHrrIdx] = b[kHrrIdx];
+    }
+    a[kWallQ] += b[kWallQ];
+    a[kFuel] += b[kFuel];
+}
+
+__device__ __forceinline__ void diag_identity(double (&a)[kNDiag])
+{
+#pragma unroll
+    for (int s = 0; s < kNDiag; ++s) a[s] = 0.0;
+    a[kHrrMax] = -INFINITY;
+    a[kHrrIdx] = 1e300;
+}
+
+// Block reduction (wave64 butterflies, then the waves in order) of the
+// per-thread diagnostics; thread 0 writes the block's partial.
+__device__ __forceinline__ void block_reduce_diag(double (&a)[kNDiag], double *out)
+{
+    __shared__ double red[kBlock / 64][kNDiag];
+    const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        double b[kNDiag];
+#pragma unroll
+        for (int s = 0; s < kNDiag; ++s) b[s] = __shfl_xor(a[s], off, 64);
+        diag_combine(a, b);
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int s = 0; s < kNDiag; ++s) red[wave][s] = a[s];
+    __syncthreads();
+    if (tid == 0) {
+        const int nw = (blockDim.x * blockDim.y * blockDim.z + 63) / 64;
+        for (int w = 1; w < nw; ++w) diag_combine(a, red[w]);
+#pragma unroll
+        for (int s = 0; s < kNDiag; ++s) out[s] = a[s];
+    }
+}
+
+// ------------------------------------------------------------ step kernel
+template <int Q, int NSP, int PREC, int MODE>
+__global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
+{
+    using L = Lat<Q>;
+    using C = typename Prec<PREC>::calc;
+    using S = typename Prec<PREC>::scal;
+    constexpr int D = L::D;
+    constexpr bool DIAG = MODE != kModeStep;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z * blockDim.z + threadIdx.z;
+    const bool inbox = x < P.nx && y < P.ny && z < P.nz;
+    const long long idx = inbox ? ((long long)z * P.ny + y) * P.nx + x : 0;
+    const bool active = inbox && P.mask[idx] == LBFD_FLUID;
+    double acc[kNDiag];
+    if constexpr (DIAG) diag_identity(acc);
+
+    if (active) {
+        // streaming with boundary conditions (pull)
+        C g[Q];
+        sfor<0, Q>([&](auto I) { g[decltype(I)::value] = gather<Q, PREC, decltype(I)::value>(P, x, y, z, idx); });
+        Pt<NSP, C> ctr;
+        load_point<NSP, PREC>(P, idx, ctr);
+        const C rho = ctr.rho;
+
+        // moments: sum g and sum c g (Eq. 13)
+        C sg = 0, m[3] = {0, 0, 0};
+        sfor<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            sg += g[i];
+            if constexpr (L::cx(i) == 1) m[0] += g[i];
+            if constexpr (L::cx(i) == -1) m[0] -= g[i];
+            if constexpr (L::cy(i) == 1) m[1] += g[i];
+            if constexpr (L::cy(i) == -1) m[1] -= g[i];
+            if constexpr (L::cz(i) == 1) m[2] += g[i];
+            if constexpr (L::cz(i) == -1) m[2] -= g[i];
+        });
+        const C inv_rc = (C)1 / (rho * (C)kCs2);
+        const C u[3] = {m[0] * inv_rc, m[1] * inv_rc, m[2] * inv_rc};
+        const C inv_rho = (C)1 / rho;
+
+        // finite differences per axis with ghost nodes (Sec. II.D, III.B)
+        C diffT = 0, CT = 0, grad[3] = {0, 0, 0};
+        C diffY[NSP], CY[NSP];
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) diffY[k] = CY[k] = 0;
+        double wallq = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            Pt<NSP, C> st[5];
+            bool near = false;
+            axis_stencil<NSP, PREC, DIAG>(P, x, y, z, d, ctr, st, near, wallq);
+            const C d1r = d1(st[0].rho, st[1].rho, st[2].rho, st[3].rho, st[4].rho);
+            grad[d] = d1r;
+            const C ud = u[d];
+            diffT += d2(st[0].T, st[1].T, st[2].T, st[3].T, st[4].T) +
+                     d1r * d1(st[0].T, st[1].T, st[2].T, st[3].T, st[4].T) * inv_rho;
+            const C cT = near ? (C)0.5 * (st[3].T - st[1].T) : weno3(st[0].T, st[1].T, st[2].T, st[3].T, st[4].T, ud);
+            CT += ud * cT;
+            C cY[NSP], sumc = 0;
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) {
+                diffY[k] += d2(st[0].Y[k], st[1].Y[k], st[2].Y[k], st[3].Y[k], st[4].Y[k]) +
+                            d1r * d1(st[0].Y[k], st[1].Y[k], st[2].Y[k], st[3].Y[k], st[4].Y[k]) * inv_rho;
+                cY[k] = near ? (C)0.5 * (st[3].Y[k] - st[1].Y[k])
+                             : weno3(st[0].Y[k], st[1].Y[k], st[2].Y[k], st[3].Y[k], st[4].Y[k], ud);
+                sumc += cY[k];
+            }
+            // mass-conserving correction of the convection (Eq. 26)
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) CY[k] += ud * (cY[k] - ctr.Y[k] * sumc);
+        }
+        const C alpha = (C)P.alpha;
+        diffT *= alpha;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) diffY[k] *= alpha;
+
+        // Arrhenius source (double)
+        double Yd[NSP], srcT, srcY[NSP];
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) Yd[k] = (double)ctr.Y[k];
+        chemistry<NSP>(P, (double)ctr.T, Yd, srcT, srcY);
+
+        // material derivatives, Lambda (Eq. 6), Euler update, P_h (Eq. 13a)
+        const C DtT = diffT + (C)srcT;
+        C DtY[NSP], invW = 0;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) {
+            DtY[k] = diffY[k] + (C)srcY[k];
+            invW += ctr.Y[k] * (C)P.invW[k];
+        }
+        const C Wm = (C)1 / invW;
+        C Lam = DtT / ctr.T;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) Lam += (Wm * (C)P.invW[k]) * DtY[k];
+        const C Tn = ctr.T - CT + DtT;
+        C Yn[NSP];
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) Yn[k] = ctr.Y[k] - CY[k] + DtY[k];
+        const C Ph = sg + (C)0.5 * rho * (C)kCs2 * Lam;
+
+        // source Xi_i (Eq. 9) and pre-conditioned populations (Eq. 19)
+        const C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        C xi[Q], h[Q], pi = 0, sxi = 0;
+        const C half_inv = (C)0.5 * inv_rc;
+        sfor<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr C wi = (C)L::w(i);
+            const C cu = (C)L::cx(i) * u[0] + (C)L::cy(i) * u[1] + (C)L::cz(i) * u[2];
+            const C feq_r = wi * ((C)1 + (C)3 * cu + (C)4.5 * cu * cu - (C)1.5 * uu);
+            const C proj = ((C)L::cx(i) - u[0]) * grad[0] + ((C)L::cy(i) - u[1]) * grad[1] +
+                           ((C)L::cz(i) - u[2]) * grad[2];
+            xi[i] = (C)kCs2 * (feq_r - wi) * proj + wi * rho * (C)kCs2 * Lam;
+            sxi += xi[i];
+            h[i] = g[i] * inv_rc + xi[i] * half_inv;
+            pi += h[i];
+        });
+        // unit-mass shift, central-moment relaxation, shift back (Eq. 14)
+        const C sh = (C)1 - pi;
+        sfor<0, Q>([&](auto I) { h[decltype(I)::value] += (C)L::w(decltype(I)::value) * sh; });
+        central_fwd<Q>(h, u);
+        relax<Q>(h, (C)P.omega2, (C)P.omega3, (C)P.omega4);
+        central_inv<Q>(h, u);
+        const C rc = rho * (C)kCs2;
+        sfor<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            h[i] = rc * (h[i] - (C)L::w(i) * sh) + (C)0.5 * xi[i];
+        });
+
+        if constexpr (DIAG) {
+            bool bad = !isfinite((double)ctr.T);
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) bad |= !isfinite((double)ctr.Y[k]);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) bad |= !isfinite((double)g[i]);
+            if (bad) {
+                acc[kNonfinite] = 1.0;
+            } else {
+                double sy = 0.0;
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) sy += (double)ctr.Y[k];
+                acc[kSumG] = (double)sg;
+                acc[kSumXi] = (double)sxi;
+                acc[kMomX] = (double)m[0] * 3.0;
+                acc[kMomY] = (double)m[1] * 3.0;
+                acc[kMomZ] = (double)m[2] * 3.0;
+                acc[kMaxY] = fabs(sy - 1.0);
+                acc[kTheta] = ((double)ctr.T - P.T_u) / (P.T_b - P.T_u);
+                acc[kHrrMax] = srcT;
+                acc[kHrrIdx] = (double)idx;
+                acc[kWallQ] = wallq;
+                acc[kFuel] = -srcY[0];
+            }
+        }
+
+        if constexpr (MODE != kModeFields) {
+            sfor<0, Q>([&](auto I) { pop_store<Q, PREC, decltype(I)::value>(P.pop_out, P.N, idx, h[decltype(I)::value]); });
+            S *so = (S *)P.sc_out;
+            so[idx] = (S)Tn;
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) so[(1 + k) * P.N + idx] = (S)Yn[k];
+            // outlet (Eq. 32): g_i(r) <- g_i(r-n)(cs - u.n) + g_i(r)(1 - cs + u.n)
+            // for the populations entering through the face, with the
+            // post-streaming values and velocity of this level
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                if (P.face[f] != LBFD_FACE_OUTFLOW || x != (f ? P.nx - 1 : 0)) continue;
+                const int sign = f ? 1 : -1;
+                Nb in = classify(P, x - sign, y, z);
+                if (in.kind != kFluid) continue;
+                const C cs = (C)0.57735026918962576451;
+                const C un = (C)sign * u[0];
+                sfor<0, Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    if constexpr (L::cx(i) != 0) {
+                        if (L::cx(i) == -sign) {
+                            Nb s = classify(P, x - L::cx(i), y - L::cy(i), z - L::cz(i));
+                            if (s.kind == kOutflow && s.face == f) {
+                                C G = gather<Q, PREC, i>(P, x - sign, y, z, in.idx);
+                                P.outlet[outlet_index(P, f, i, Q, y, z)] =
+                                    (double)(G * (cs - un) + g[i] * ((C)1 - cs + un));
+                            }
+                        }
+                    }
+                });
+            }
+        } else {
+            P.fields[idx] = (double)rho;
+            P.fields[P.N + idx] = (double)u[0];
+            P.fields[2 * P.N + idx] = (double)u[1];
+            P.fields[3 * P.N + idx] = (double)u[2];
+            P.fields[4 * P.N + idx] = (double)Ph;
+        }
+    } else if constexpr (MODE == kModeFields) {
+        if (inbox)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) P.fields[c * P.N + idx] = 0.0;
+    }
+
+    if constexpr (DIAG) {
+        const long long blk = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+        block_reduce_diag(acc, P.partials + blk * kNDiag);
+    }
+}
+
+// ------------------------------------------------------------ init kernel
+// g^0 = w (P_h0 - rho cs^2) + cs^2 f^eq(rho, u0) (Eq. 12), scattered into
+// the post-collision buffer so that the first gather returns it (inverse
+// of the pull, the inlet and the bounce-back rules); populations entering
+// through an outlet are written to the outlet buffer.
+template <int Q, int NSP, int PREC>
+__global__ void __launch_bounds__(kBlock) init_kernel(const KParams P, const double *u0, const double *Ph0)
+{
+    using L = Lat<Q>;
+    using S = typename Prec<PREC>::scal;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z * blockDim.z + threadIdx.z;
+    if (x >= P.nx || y >= P.ny || z >= P.nz) return;
+    const long long idx = ((long long)z * P.ny + y) * P.nx + x;
+    if (P.mask[idx] != LBFD_FLUID) return;
+    const S *sc = (const S *)P.sc_in;
+    double T = (double)sc[idx], Y[NSP];
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) Y[k] = (double)sc[(1 + k) * P.N + idx];
+    const double rho = density<NSP>(P, T, Y);
+    double u[3] = {0.0, 0.0, 0.0};
+    if (u0)
+        for (int d = 0; d < L::D; ++d) u[d] = u0[d * P.N + idx];
+    const double ph = Ph0 ? Ph0[idx] : 0.0;
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    sfor<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int opp = Q - 1 - i;
+        const double cu = L::cx(i) * u[0] + L::cy(i) * u[1] + L::cz(i) * u[2];
+        const double feq = L::w(i) * rho * (1.0 + cu / kCs2 + cu * cu / (2.0 * kCs2 * kCs2) - uu / (2.0 * kCs2));
+        const double g0 = L::w(i) * (ph - rho * kCs2) + kCs2 * feq;
+        using C = typename Prec<PREC>::calc;
+        if constexpr (i == (Q - 1) / 2) {
+            pop_store<Q, PREC, i>(P.pop_out, P.N, idx, (C)g0);
+        } else {
+            Nb s = classify(P, x - L::cx(i), y - L::cy(i), z - L::cz(i));
+            if (s.kind == kFluid) {
+                pop_store<Q, PREC, i>(P.pop_out, P.N, s.idx, (C)g0);
+            } else if (s.kind == kInflow) {
+                const double ci = L::cx(i) * P.u_in[0] + L::cy(i) * P.u_in[1] + L::cz(i) * P.u_in[2];
+                pop_store<Q, PREC, opp>(P.pop_out, P.N, idx, (C)(g0 - 2.0 * L::w(i) * P.rho_in * ci));
+            } else if (s.kind == kOutflow) {
+                const int sign = (s.face & 1) ? 1 : -1;
+                Nb in = classify(P, x - sign, y, z);
+                if (in.kind == kFluid)
+                    P.outlet[outlet_index(P, s.face, i, Q, y, z)] = g0;
+                else
+                    pop_store<Q, PREC, opp>(P.pop_out, P.N, idx, (C)g0);
+            } else {
+                pop_store<Q, PREC, opp>(P.pop_out, P.N, idx, (C)g0);
+            }
+        }
+    });
+}
+
+// ------------------------------------------------------------ launchers
+// Instantiated once per configuration in inst/*.hip (explicit
+// instantiation), declared extern in the dispatcher.
+template <int Q, int NSP, int PREC>
+hipError_t launch_step_t(int mode, const KParams &kp, dim3 grid, dim3 block, hipStream_t s)
+{
+    switch (mode) {
+    case kModeStep: step_kernel<Q, NSP, PREC, kModeStep><<<grid, block, 0, s>>>(kp); break;
+    case kModeStepDiag: step_kernel<Q, NSP, PREC, kModeStepDiag><<<grid, block, 0, s>>>(kp); break;
+    default: step_kernel<Q, NSP, PREC, kModeFields><<<grid, block, 0, s>>>(kp); break;
+    }
+    return hipGetLastError();
+}
+
+template <int Q, int NSP, int PREC>
+hipError_t launch_init_t(const KParams &kp, const double *u0, const double *Ph0, dim3 grid, dim3 block,
+                         hipStream_t s)
+{
+    init_kernel<Q, NSP, PREC><<<grid, block, 0, s>>>(kp, u0, Ph0);
+    return hipGetLastError();
+}
+
+// (lattice, species, precision) combinations built into the library
+#define LBFD_FOR_CONFIGS(X) \
+    X(9, 2, 0) X(9, 4, 0) X(9, 9, 0) X(27, 2, 0) X(27, 4, 0) X(27, 9, 0) \
+    X(9, 2, 1) X(9, 4, 1) X(9, 9, 1) X(27, 2, 1) X(27, 4, 1) X(27, 9, 1) \
+    X(9, 4, 2) X(27, 4, 2) X(27, 9, 2)
+
+#define LBFD_INSTANTIATE(q, n, p) \
+    template hipError_t launch_step_t<q, n, p>(int, const KParams &, dim3, dim3, hipStream_t); \
+    template hipError_t launch_init_t<q, n, p>(const KParams &, const double *, const double *, dim3, dim3, \
+                                               hipStream_t);
+
+}  // namespace lbfd

@@ -1,0 +1,247 @@
+"""Thin ctypes binding of ``liblbfd.so`` (C ABI in ``include/lbfd.h``).
+
+Argument marshalling only: every part of the step runs in the library's
+HIP kernels.  The library must have been built (``python -m
+paper_2304_05657_amd.build``); if it is missing or cannot be loaded the
+import of :class:`Solver` fails loudly -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbfd.so")
+
+MAX_SPECIES = 16
+MAX_REACTIONS = 32
+FP64, MIXED_FP32, MIXED_FP16 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "fp16": MIXED_FP16}
+FACE_CODES = {"periodic": 0, "wall": 1, "inflow": 2, "outflow": 3, "wall_adiabatic": 4}
+ERRORS = {0: "LBFD_OK", -1: "LBFD_EINVAL", -2: "LBFD_ENOMEM", -3: "LBFD_EDEVICE",
+          -4: "LBFD_ENONFINITE", -5: "LBFD_ESTATE"}
+
+EXPORTS = ("lbfd_init", "lbfd_step", "lbfd_sync", "lbfd_level", "lbfd_read_fields",
+           "lbfd_diagnostics", "lbfd_set_wall_temperature", "lbfd_state_size",
+           "lbfd_save_state", "lbfd_load_state", "lbfd_time_steps", "lbfd_destroy",
+           "lbfd_strerror", "lbfd_last_error")
+
+
+class LbfdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (ERRORS.get(code, code), msg))
+        self.code = code
+
+
+class Reaction(C.Structure):
+    _fields_ = [("n_react", C.c_int), ("react", C.c_int * 4), ("A", C.c_double),
+                ("b", C.c_double), ("Ta", C.c_double), ("nu_mass", C.c_double * MAX_SPECIES),
+                ("q_over_cp", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("lattice", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("precision", C.c_int), ("face", C.c_int * 6), ("face_T", C.c_double * 6),
+        ("tau", C.c_double), ("prandtl", C.c_double), ("dt_phys", C.c_double),
+        ("T_ref", C.c_double), ("W_ref", C.c_double), ("n_species", C.c_int),
+        ("W", C.c_double * MAX_SPECIES), ("n_reactions", C.c_int),
+        ("rxn", C.POINTER(Reaction)), ("u_in", C.c_double * 3), ("T_in", C.c_double),
+        ("Y_in", C.c_double * MAX_SPECIES), ("omega3", C.c_double), ("omega4", C.c_double),
+        ("chem_substeps_max", C.c_int), ("check_every", C.c_int),
+        ("T_u", C.c_double), ("T_b", C.c_double),
+    ]
+
+
+class Diag(C.Structure):
+    _fields_ = [("sum_g", C.c_double), ("sum_xi", C.c_double), ("mom", C.c_double * 3),
+                ("max_abs_sumY_minus_1", C.c_double), ("nonfinite", C.c_int64),
+                ("sum_theta", C.c_double), ("hrr_idx", C.c_int64), ("hrr_max", C.c_double),
+                ("wall_q", C.c_double), ("fuel_rate", C.c_double), ("step", C.c_int64)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load liblbfd.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liblbfd.so is not built (run python -m paper_2304_05657_amd.build); "
+                          "the GPU library has no CPU fallback")
+    lib = C.CDLL(LIB_PATH)
+    vp, dp = C.c_void_p, C.POINTER(C.c_double)
+    lib.lbfd_init.argtypes = [C.POINTER(Params), vp, dp, dp, dp, dp, dp, vp, C.POINTER(vp)]
+    lib.lbfd_step.argtypes = [vp, C.c_int64]
+    lib.lbfd_sync.argtypes = [vp]
+    lib.lbfd_level.argtypes = [vp]
+    lib.lbfd_level.restype = C.c_int64
+    lib.lbfd_read_fields.argtypes = [vp, dp, dp, dp, dp, dp]
+    lib.lbfd_diagnostics.argtypes = [vp, C.POINTER(Diag)]
+    lib.lbfd_set_wall_temperature.argtypes = [vp, dp]
+    lib.lbfd_state_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+    lib.lbfd_save_state.argtypes = [vp, vp, C.c_size_t]
+    lib.lbfd_load_state.argtypes = [vp, vp, C.c_size_t]
+    lib.lbfd_time_steps.argtypes = [vp, C.c_int64, dp]
+    lib.lbfd_destroy.argtypes = [vp]
+    lib.lbfd_destroy.restype = None
+    lib.lbfd_strerror.argtypes = [C.c_int]
+    lib.lbfd_strerror.restype = C.c_char_p
+    lib.lbfd_last_error.argtypes = []
+    lib.lbfd_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(lib, rc):
+    if rc != 0:
+        raise LbfdError(rc, lib.lbfd_last_error().decode())
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_params(prob, precision="fp64", check_every: int = 0):
+    """Marshal a workloads.Problem into lbfd_params (+ the reaction array
+    that must stay alive while the params are used)."""
+    p = Params()
+    p.lattice = prob.lattice
+    p.nx, p.ny, p.nz = prob.nx, prob.ny, prob.nz
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    for f in range(6):
+        p.face[f] = FACE_CODES[prob.faces[f]]
+        p.face_T[f] = prob.face_T[f]
+    p.tau, p.prandtl, p.dt_phys = prob.tau, prob.prandtl, prob.dt_phys
+    p.T_ref, p.W_ref = prob.T_ref, prob.W_ref
+    p.n_species = len(prob.W)
+    for k, v in enumerate(prob.W):
+        p.W[k] = v
+    rx = (Reaction * max(1, len(prob.reactions)))()
+    for j, r in enumerate(prob.reactions):
+        rx[j].n_react = len(r.reactants)
+        for m, k in enumerate(r.reactants):
+            rx[j].react[m] = k
+        rx[j].A, rx[j].b, rx[j].Ta, rx[j].q_over_cp = r.A, r.b, r.Ta, r.q
+        for k, v in enumerate(r.nu):
+            rx[j].nu_mass[k] = v
+    p.n_reactions = len(prob.reactions)
+    p.rxn = C.cast(rx, C.POINTER(Reaction))
+    for d in range(3):
+        p.u_in[d] = prob.u_in[d]
+    p.T_in = prob.T_in
+    for k, v in enumerate(prob.Y_in):
+        p.Y_in[k] = v
+    p.omega3, p.omega4 = prob.omega3, prob.omega4
+    p.chem_substeps_max = prob.chem_substeps_max
+    p.check_every = check_every
+    p.T_u, p.T_b = prob.T_u, prob.T_b
+    if prob.eq_discrete:
+        raise ValueError("the GPU library relaxes toward Maxwellian central moments only")
+    return p, rx
+
+
+class Solver:
+    """One GPU context: ``Solver(problem, precision='fp64').step(n)``.
+
+    ``stream`` is a raw hipStream_t handle (int); by default the current
+    torch stream of the current device is used when torch is importable,
+    else the null stream."""
+
+    def __init__(self, prob, precision="fp64", check_every: int = 0, stream=None):
+        lib = load_library()
+        if stream is None:
+            stream = _torch_stream()
+        self.prob = prob
+        self.precision = precision
+        self._params, self._rx = make_params(prob, precision, check_every)
+        N = prob.N
+        self.N = N
+        self.nsp = len(prob.W)
+        self.dim = 2 if prob.lattice == 9 else 3
+        mask = np.ascontiguousarray(prob.mask, dtype=np.uint8).reshape(-1)
+        wall_T = np.ascontiguousarray(prob.wall_T, dtype=np.float64).reshape(-1)
+        T0 = np.ascontiguousarray(prob.T0, dtype=np.float64).reshape(-1)
+        Y0 = np.ascontiguousarray(prob.Y0, dtype=np.float64).reshape(-1)
+        u0 = None if prob.u0 is None else np.ascontiguousarray(
+            np.asarray(prob.u0, dtype=np.float64)[: self.dim]).reshape(-1)
+        Ph0 = None if prob.Ph0 is None else np.ascontiguousarray(prob.Ph0, dtype=np.float64).reshape(-1)
+        h = C.c_void_p()
+        rc = lib.lbfd_init(C.byref(self._params), mask.ctypes.data, _dp(wall_T), _dp(T0), _dp(Y0),
+                           _dp(u0), _dp(Ph0), C.c_void_p(stream or 0), C.byref(h))
+        _check(lib, rc)
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.lbfd_destroy(h)
+            self._h = None
+
+    __del__ = close
+
+    @property
+    def level(self) -> int:
+        return int(self._lib.lbfd_level(self._h))
+
+    def step(self, n: int = 1):
+        _check(self._lib, self._lib.lbfd_step(self._h, int(n)))
+
+    def sync(self):
+        _check(self._lib, self._lib.lbfd_sync(self._h))
+
+    def time_steps(self, n: int) -> float:
+        ms = C.c_double()
+        _check(self._lib, self._lib.lbfd_time_steps(self._h, int(n), C.byref(ms)))
+        return ms.value
+
+    def fields(self) -> dict:
+        pr = self.prob
+        shp = (pr.nz, pr.ny, pr.nx)
+        N = self.N
+        rho, T, Ph = np.empty(N), np.empty(N), np.empty(N)
+        u = np.empty(self.dim * N)
+        Y = np.empty(self.nsp * N)
+        _check(self._lib, self._lib.lbfd_read_fields(self._h, _dp(rho), _dp(u), _dp(T), _dp(Y), _dp(Ph)))
+        u3 = np.zeros((3,) + shp)
+        u3[: self.dim] = u.reshape((self.dim,) + shp)
+        return {"rho": rho.reshape(shp), "u": u3, "T": T.reshape(shp),
+                "Y": Y.reshape((self.nsp,) + shp), "Ph": Ph.reshape(shp)}
+
+    def diagnostics(self) -> dict:
+        d = Diag()
+        _check(self._lib, self._lib.lbfd_diagnostics(self._h, C.byref(d)))
+        return {"sum_g": d.sum_g, "sum_xi": d.sum_xi, "mom": np.array(list(d.mom)),
+                "max_sumY_err": d.max_abs_sumY_minus_1, "nonfinite": int(d.nonfinite),
+                "sum_theta": d.sum_theta, "hrr_idx": int(d.hrr_idx), "hrr_max": d.hrr_max,
+                "wall_q": d.wall_q, "fuel_rate": d.fuel_rate, "step": int(d.step)}
+
+    def set_wall_temperature(self, wall_T):
+        a = np.ascontiguousarray(wall_T, dtype=np.float64).reshape(-1)
+        _check(self._lib, self._lib.lbfd_set_wall_temperature(self._h, _dp(a)))
+
+    def save_state(self) -> bytes:
+        n = C.c_size_t()
+        _check(self._lib, self._lib.lbfd_state_size(self._h, C.byref(n)))
+        buf = (C.c_char * n.value)()
+        _check(self._lib, self._lib.lbfd_save_state(self._h, buf, n))
+        return bytes(buf)
+
+    def load_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(self._lib, self._lib.lbfd_load_state(self._h, buf, len(blob)))
+
+
+def _torch_stream():
+    try:
+        import torch
+    except ImportError:
+        return 0
+    if not torch.cuda.is_available():
+        return 0
+    return int(torch.cuda.current_stream().cuda_stream)
