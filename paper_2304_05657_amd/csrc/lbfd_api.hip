@@ -66,6 +66,10 @@ struct lbfd_ctx {
     void *sc[2] = {nullptr, nullptr};
     int cur = 0;
     uint8_t *mask = nullptr;
+    uint8_t *code = nullptr;
+    int *boundary = nullptr;
+    long long n_boundary = 0;
+    int nblocks_interior = 0;
     double *wall_T = nullptr;
     double *outlet = nullptr;
     size_t outlet_n = 0;
@@ -83,7 +87,7 @@ struct lbfd_ctx {
 static void free_ctx(lbfd_ctx *c)
 {
     if (!c) return;
-    void *ptrs[] = {c->pop[0], c->pop[1], c->sc[0], c->sc[1], c->mask, c->wall_T, c->outlet,
+    void *ptrs[] = {c->pop[0], c->pop[1], c->sc[0], c->sc[1], c->mask, c->code, c->boundary, c->wall_T, c->outlet,
                     c->fields, c->partials, c->diag_dev, c->bad_dev, c->rx_dev};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -145,6 +149,52 @@ static int validate(const lbfd_params *p, const uint8_t *mask, const double *T0,
     return LBFD_OK;
 }
 
+// Cell codes: solid; interior fluid when every pull source (the 3^D - 1
+// neighbours) and every finite-difference point (+-1, +-2 along each axis)
+// lies inside the box without wrapping and is fluid; boundary fluid
+// otherwise.  Returns the boundary cells in increasing index order.
+static void classify_cells(const lbfd_params &p, const uint8_t *mask, std::vector<uint8_t> &code,
+                           std::vector<int> &boundary)
+{
+    const int D = p.lattice == LBFD_D2Q9 ? 2 : 3;
+    const long long N = (long long)p.nx * p.ny * p.nz;
+    const long long sy = p.nx, sz = (long long)p.nx * p.ny;
+    code.assign(N, kCodeSolid);
+    boundary.clear();
+    int off[40][3];
+    int no = 0;
+    for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx)
+                if (dx || dy || dz) {
+                    off[no][0] = dx;
+                    off[no][1] = dy;
+                    off[no][2] = dz;
+                    ++no;
+                }
+    for (int d = 0; d < D; ++d)
+        for (int s2 = -2; s2 <= 2; s2 += 4) {
+            off[no][0] = off[no][1] = off[no][2] = 0;
+            off[no][d] = s2;
+            ++no;
+        }
+    for (int z = 0; z < p.nz; ++z)
+        for (int y = 0; y < p.ny; ++y)
+            for (int x = 0; x < p.nx; ++x) {
+                const long long i = z * sz + y * sy + x;
+                if (mask[i] != LBFD_FLUID) continue;
+                bool interior = true;
+                for (int o = 0; o < no && interior; ++o) {
+                    const int qx = x + off[o][0], qy = y + off[o][1], qz = z + off[o][2];
+                    if (qx < 0 || qx >= p.nx || qy < 0 || qy >= p.ny || qz < 0 || qz >= p.nz ||
+                        mask[qz * sz + qy * sy + qx] != LBFD_FLUID)
+                        interior = false;
+                }
+                code[i] = interior ? kCodeInterior : kCodeBoundary;
+                if (!interior) boundary.push_back((int)i);
+            }
+}
+
 static KParams make_kparams(const lbfd_ctx *c)
 {
     const lbfd_params &p = c->p;
@@ -159,6 +209,10 @@ static KParams make_kparams(const lbfd_ctx *c)
         k.face_T[f] = p.face_T[f];
     }
     k.mask = c->mask;
+    k.code = c->code;
+    k.boundary = c->boundary;
+    k.n_boundary = c->n_boundary;
+    k.boundary_partial_offset = c->nblocks_interior;
     k.wall_T = c->wall_T;
     k.outlet = c->outlet;
     k.fields = c->fields;
@@ -173,6 +227,7 @@ static KParams make_kparams(const lbfd_ctx *c)
     k.dt_phys = p.dt_phys;
     k.T_ref = p.T_ref;
     k.W_ref = p.W_ref;
+    k.T_ref_over_W_ref = p.T_ref / p.W_ref;
     for (int s = 0; s < c->nsp; ++s) {
         k.invW[s] = 1.0 / p.W[s];
         k.Y_in[s] = p.Y_in[s];
@@ -233,7 +288,16 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     }
     c->grid = dim3((p->nx + c->block.x - 1) / c->block.x, (p->ny + c->block.y - 1) / c->block.y,
                    (p->nz + c->block.z - 1) / c->block.z);
-    c->nblocks = c->grid.x * c->grid.y * c->grid.z;
+    if (c->N >= (1LL << 29)) {
+        delete c;
+        return fail(LBFD_EINVAL, "box too large (at most 2^29 cells: 32-bit byte offsets per field)");
+    }
+    std::vector<uint8_t> code;
+    std::vector<int> boundary;
+    classify_cells(*p, mask, code, boundary);
+    c->n_boundary = (long long)boundary.size();
+    c->nblocks_interior = c->grid.x * c->grid.y * c->grid.z;
+    c->nblocks = c->nblocks_interior + (int)((c->n_boundary + kBlock - 1) / kBlock);
 
 #define ALLOC(ptr, bytes)                                                          \
     do {                                                                           \
@@ -247,6 +311,8 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     ALLOC(c->sc[0], sc_bytes);
     ALLOC(c->sc[1], sc_bytes);
     ALLOC(c->mask, N);
+    ALLOC(c->code, N);
+    ALLOC(c->boundary, sizeof(int) * (boundary.empty() ? 1 : boundary.size()));
     ALLOC(c->wall_T, N * sizeof(double));
     ALLOC(c->outlet, c->outlet_n * sizeof(double));
     ALLOC(c->partials, (size_t)c->nblocks * kNDiag * sizeof(double));
@@ -275,6 +341,9 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     HIP_OR_FREE(hipMemset(c->pop[1], 0, pop_bytes));
     HIP_OR_FREE(hipMemset(c->outlet, 0, c->outlet_n * sizeof(double)));
     HIP_OR_FREE(hipMemcpy(c->mask, mask, N, hipMemcpyHostToDevice));
+    HIP_OR_FREE(hipMemcpy(c->code, code.data(), N, hipMemcpyHostToDevice));
+    if (!boundary.empty())
+        HIP_OR_FREE(hipMemcpy(c->boundary, boundary.data(), sizeof(int) * boundary.size(), hipMemcpyHostToDevice));
     {
         std::vector<double> wt;
         const double *src = wall_T;

@@ -19,6 +19,10 @@ enum DiagSlot {
     kNonfinite = 6, kTheta = 7, kHrrMax = 8, kHrrIdx = 9, kWallQ = 10, kFuel = 11
 };
 
+// Per-cell geometry code: solid, interior fluid (every pull source and
+// finite-difference point is an in-box fluid cell), boundary fluid.
+enum CellCode { kCodeSolid = 0, kCodeInterior = 1, kCodeBoundary = 2 };
+
 // Kind of what a neighbour coordinate lands on.
 enum NbKind { kFluid = 0, kIso = 1, kAdia = 2, kInflow = 3, kOutflow = 4 };
 
@@ -30,6 +34,10 @@ struct KParams {
     int face[6];
     double face_T[6];
     const uint8_t *mask;
+    const uint8_t *code;        // CellCode per cell
+    const int *boundary;        // boundary fluid cells, increasing index
+    long long n_boundary;
+    long long boundary_partial_offset;  // first partial slot of the boundary kernel
     const double *wall_T;
     const void *pop_in;   // post-collision populations of the previous level
     void *pop_out;        // post-collision populations of this level
@@ -43,7 +51,7 @@ struct KParams {
     int chem_substeps_max;
     double omega2, omega3, omega4, alpha;
     double dt_phys;
-    double T_ref, W_ref;
+    double T_ref, W_ref, T_ref_over_W_ref;
     double invW[kMaxSp];
     double u_in[3], T_in, Y_in[kMaxSp], rho_in;
     double T_u, T_b;

@@ -52,33 +52,53 @@ template <> struct Prec<LBFD_FP64> { using calc = double; using pop = double; us
 template <> struct Prec<LBFD_MIXED_FP32> { using calc = float; using pop = float; using scal = float; };
 template <> struct Prec<LBFD_MIXED_FP16> { using calc = float; using pop = __half; using scal = float; };
 
+// Loads and stores at a 32-bit byte offset from a uniform base pointer
+// (base in scalar registers, one 32-bit offset register per access; every
+// buffer is below 4 GiB, checked at init).
+template <class T>
+__device__ __forceinline__ T ldo(const void *base, uint32_t byte_off)
+{
+    return *(const T *)((const char *)base + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void sto(void *base, uint32_t byte_off, T v)
+{
+    *(T *)((char *)base + byte_off) = v;
+}
+
 // Populations: FP64 stores g; mixed stores g / (w_i cs^2) (deviation from
 // the lattice weights, scaled to comparable magnitude across directions).
 template <int Q, int PREC, int I>
-__device__ __forceinline__ typename Prec<PREC>::calc pop_load(const void *base, long long N, long long idx)
+__device__ __forceinline__ typename Prec<PREC>::calc pop_load(const void *base, long long N, uint32_t idx)
 {
+    using T = typename Prec<PREC>::pop;
+    const char *b = (const char *)base + (size_t)I * (size_t)N * sizeof(T);
+    const uint32_t off = idx * (uint32_t)sizeof(T);
     if constexpr (PREC == LBFD_FP64) {
-        return ((const double *)base)[I * N + idx];
+        return ldo<double>(b, off);
     } else if constexpr (PREC == LBFD_MIXED_FP32) {
         constexpr float s = (float)(Lat<Q>::w(I) * kCs2);
-        return ((const float *)base)[I * N + idx] * s;
+        return ldo<float>(b, off) * s;
     } else {
         constexpr float s = (float)(Lat<Q>::w(I) * kCs2);
-        return __half2float(((const __half *)base)[I * N + idx]) * s;
+        return __half2float(ldo<__half>(b, off)) * s;
     }
 }
 
 template <int Q, int PREC, int I>
-__device__ __forceinline__ void pop_store(void *base, long long N, long long idx, typename Prec<PREC>::calc v)
+__device__ __forceinline__ void pop_store(void *base, long long N, uint32_t idx, typename Prec<PREC>::calc v)
 {
+    using T = typename Prec<PREC>::pop;
+    char *b = (char *)base + (size_t)I * (size_t)N * sizeof(T);
+    const uint32_t off = idx * (uint32_t)sizeof(T);
     if constexpr (PREC == LBFD_FP64) {
-        ((double *)base)[I * N + idx] = v;
+        sto<double>(b, off, v);
     } else if constexpr (PREC == LBFD_MIXED_FP32) {
         constexpr float s = (float)(1.0 / (Lat<Q>::w(I) * kCs2));
-        ((float *)base)[I * N + idx] = v * s;
+        sto<float>(b, off, v * s);
     } else {
         constexpr float s = (float)(1.0 / (Lat<Q>::w(I) * kCs2));
-        ((__half *)base)[I * N + idx] = __float2half_rn(v * s);
+        sto<__half>(b, off, __float2half_rn(v * s));
     }
 }
 
@@ -196,17 +216,19 @@ __device__ __forceinline__ C density(const KParams &P, C T, const C *Y)
     C s = 0;
 #pragma unroll
     for (int k = 0; k < NSP; ++k) s += Y[k] * (C)P.invW[k];
-    return ((C)P.T_ref / T) * (((C)1 / s) / (C)P.W_ref);
+    return (C)P.T_ref_over_W_ref / (T * s);
 }
 
 template <int NSP, int PREC>
 __device__ __forceinline__ void load_point(const KParams &P, long long idx, Pt<NSP, typename Prec<PREC>::calc> &o)
 {
     using S = typename Prec<PREC>::scal;
-    const S *sc = (const S *)P.sc_in;
-    o.T = sc[idx];
+    const char *sc = (const char *)P.sc_in;
+    const size_t fstride = (size_t)P.N * sizeof(S);
+    const uint32_t off = (uint32_t)idx * (uint32_t)sizeof(S);
+    o.T = ldo<S>(sc, off);
 #pragma unroll
-    for (int k = 0; k < NSP; ++k) o.Y[k] = sc[(1 + k) * P.N + idx];
+    for (int k = 0; k < NSP; ++k) o.Y[k] = ldo<S>(sc + (size_t)(1 + k) * fstride, off);
     o.rho = density<NSP>(P, o.T, o.Y);
 }
 
@@ -246,10 +268,10 @@ __device__ __forceinline__ void axis_stencil(const KParams &P, int x, int y, int
 #pragma unroll
     for (int sg = -1; sg <= 1; sg += 2) {
         int o1 = 2 + sg, o2 = 2 + 2 * sg;
-        int q1[3] = {x, y, z}, q2[3] = {x, y, z}, qm[3] = {x, y, z};
-        q1[d] += sg;
-        q2[d] += 2 * sg;
-        qm[d] -= sg;
+        const int ox = d == 0, oy = d == 1, oz = d == 2;
+        const int q1[3] = {x + sg * ox, y + sg * oy, z + sg * oz};
+        const int q2[3] = {x + 2 * sg * ox, y + 2 * sg * oy, z + 2 * sg * oz};
+        const int qm[3] = {x - sg * ox, y - sg * oy, z - sg * oz};
         Nb c1 = classify(P, q1[0], q1[1], q1[2]);
         if (c1.kind != kFluid) {
             near = true;
@@ -322,7 +344,8 @@ __device__ __forceinline__ C weno3(C m2, C m1, C c0, C p1, C p2, C u)
 // that would consume a mass fraction below zero is scaled down.
 __device__ __forceinline__ double rate_coeff(const lbfd_reaction &r, double dt, double T)
 {
-    return r.A * dt * pow(T, r.b) * exp(-r.Ta / T);
+    const double tb = r.b == 0.0 ? 1.0 : pow(T, r.b);
+    return r.A * dt * tb * exp(-r.Ta / T);
 }
 
 template <int NSP>
@@ -506,7 +529,12 @@ __device__ __forceinline__ void block_reduce_diag(double (&a)[kNDiag], double *o
 }
 
 // ------------------------------------------------------------ step kernel
-template <int Q, int NSP, int PREC, int MODE>
+// FAST = true: the interior kernel -- a 2-D/3-D grid over the box whose
+// threads work only on interior fluid cells (every pull source and every
+// finite-difference point in the box and fluid), with plain offset loads.
+// FAST = false: the boundary kernel -- a 1-D grid over the list of the
+// other fluid cells, with the general geometry logic.
+template <int Q, int NSP, int PREC, int MODE, bool FAST>
 __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
 {
     using L = Lat<Q>;
@@ -514,21 +542,76 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
     using S = typename Prec<PREC>::scal;
     constexpr int D = L::D;
     constexpr bool DIAG = MODE != kModeStep;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z * blockDim.z + threadIdx.z;
-    const bool inbox = x < P.nx && y < P.ny && z < P.nz;
-    const long long idx = inbox ? ((long long)z * P.ny + y) * P.nx + x : 0;
-    const bool active = inbox && P.mask[idx] == LBFD_FLUID;
+    int x, y, z;
+    long long idx;
+    bool active, inbox;
+    if constexpr (FAST) {
+        x = blockIdx.x * blockDim.x + threadIdx.x;
+        y = blockIdx.y * blockDim.y + threadIdx.y;
+        z = blockIdx.z * blockDim.z + threadIdx.z;
+        inbox = x < P.nx && y < P.ny && z < P.nz;
+        idx = inbox ? ((long long)z * P.ny + y) * P.nx + x : 0;
+        active = inbox && P.code[idx] == kCodeInterior;
+    } else {
+        const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+        inbox = false;
+        active = t < P.n_boundary;
+        idx = active ? (long long)P.boundary[t] : 0;
+        x = (int)(idx % P.nx);
+        y = (int)((idx / P.nx) % P.ny);
+        z = (int)(idx / ((long long)P.nx * P.ny));
+    }
+    const long long sy = P.nx, sz = (long long)P.nx * P.ny;
     double acc[kNDiag];
     if constexpr (DIAG) diag_identity(acc);
+
+    // 2-D interior kernel: T, Y_k and rho of the block's 64 x 4 cells and a
+    // 2-cell halo staged once in LDS (field-major planes of 68 x 8 points);
+    // every finite-difference point is then an LDS read at a fixed offset.
+    // Halo points outside the box are left unset: only interior cells,
+    // whose stencils stay inside the box, read the tile.
+    constexpr int kTX = 64, kTY = 4, kHX = kTX + 4, kHY = kTY + 4, kNP = kHX * kHY;
+    constexpr bool TILE = FAST && D == 2;
+    __shared__ C tile[TILE ? (NSP + 2) * kNP : 1];
+    if constexpr (TILE) {
+        const int tid = threadIdx.x + kTX * threadIdx.y;
+        const int gx0 = blockIdx.x * kTX - 2, gy0 = blockIdx.y * kTY - 2;
+        for (int i = tid; i < kNP; i += kBlock) {
+            const int gx = gx0 + i % kHX, gy = gy0 + i / kHX;
+            if ((unsigned)gx < (unsigned)P.nx && (unsigned)gy < (unsigned)P.ny) {
+                Pt<NSP, C> pt;
+                load_point<NSP, PREC>(P, (long long)gy * P.nx + gx, pt);
+                tile[i] = pt.T;
+                tile[kNP + i] = pt.rho;
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) tile[(2 + k) * kNP + i] = pt.Y[k];
+            }
+        }
+        __syncthreads();
+    }
+    auto tile_point = [&](int dx, int dy, Pt<NSP, C> &o) {
+        const int i = (threadIdx.y + 2 + dy) * kHX + threadIdx.x + 2 + dx;
+        o.T = tile[i];
+        o.rho = tile[kNP + i];
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) o.Y[k] = tile[(2 + k) * kNP + i];
+    };
 
     if (active) {
         // streaming with boundary conditions (pull)
         C g[Q];
-        sfor<0, Q>([&](auto I) { g[decltype(I)::value] = gather<Q, PREC, decltype(I)::value>(P, x, y, z, idx); });
+        sfor<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (FAST)
+                g[i] = pop_load<Q, PREC, i>(P.pop_in, P.N, idx - (L::cx(i) + sy * L::cy(i) + sz * L::cz(i)));
+            else
+                g[i] = gather<Q, PREC, i>(P, x, y, z, idx);
+        });
         Pt<NSP, C> ctr;
-        load_point<NSP, PREC>(P, idx, ctr);
+        if constexpr (TILE)
+            tile_point(0, 0, ctr);
+        else
+            load_point<NSP, PREC>(P, idx, ctr);
         const C rho = ctr.rho;
 
         // moments: sum g and sum c g (Eq. 13)
@@ -547,36 +630,77 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
         const C u[3] = {m[0] * inv_rc, m[1] * inv_rc, m[2] * inv_rc};
         const C inv_rho = (C)1 / rho;
 
-        // finite differences per axis with ghost nodes (Sec. II.D, III.B)
+        // finite differences per axis with ghost nodes (Sec. II.D, III.B);
+        // one axis at a time, one scalar at a time, to bound register use
         C diffT = 0, CT = 0, grad[3] = {0, 0, 0};
         C diffY[NSP], CY[NSP];
 #pragma unroll
         for (int k = 0; k < NSP; ++k) diffY[k] = CY[k] = 0;
         double wallq = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            Pt<NSP, C> st[5];
-            bool near = false;
-            axis_stencil<NSP, PREC, DIAG>(P, x, y, z, d, ctr, st, near, wallq);
-            const C d1r = d1(st[0].rho, st[1].rho, st[2].rho, st[3].rho, st[4].rho);
-            grad[d] = d1r;
-            const C ud = u[d];
-            diffT += d2(st[0].T, st[1].T, st[2].T, st[3].T, st[4].T) +
-                     d1r * d1(st[0].T, st[1].T, st[2].T, st[3].T, st[4].T) * inv_rho;
-            const C cT = near ? (C)0.5 * (st[3].T - st[1].T) : weno3(st[0].T, st[1].T, st[2].T, st[3].T, st[4].T, ud);
-            CT += ud * cT;
+        auto axis_terms = [&](auto &&val, const C (&r5)[5], bool near, C ud) -> C {
+            // val(f, m): field f (0 = T, 2 + k = Y_k) at offset m = -2..2
+            const C d1r = d1(r5[0], r5[1], r5[2], r5[3], r5[4]);
+            {
+                const C a = val(0, -2), b = val(0, -1), c = ctr.T, e = val(0, 1), f = val(0, 2);
+                diffT += d2(a, b, c, e, f) + d1r * d1(a, b, c, e, f) * inv_rho;
+                CT += ud * (near ? (C)0.5 * (e - b) : weno3(a, b, c, e, f, ud));
+            }
             C cY[NSP], sumc = 0;
 #pragma unroll
             for (int k = 0; k < NSP; ++k) {
-                diffY[k] += d2(st[0].Y[k], st[1].Y[k], st[2].Y[k], st[3].Y[k], st[4].Y[k]) +
-                            d1r * d1(st[0].Y[k], st[1].Y[k], st[2].Y[k], st[3].Y[k], st[4].Y[k]) * inv_rho;
-                cY[k] = near ? (C)0.5 * (st[3].Y[k] - st[1].Y[k])
-                             : weno3(st[0].Y[k], st[1].Y[k], st[2].Y[k], st[3].Y[k], st[4].Y[k], ud);
+                const C a = val(2 + k, -2), b = val(2 + k, -1), c = ctr.Y[k], e = val(2 + k, 1), f = val(2 + k, 2);
+                diffY[k] += d2(a, b, c, e, f) + d1r * d1(a, b, c, e, f) * inv_rho;
+                cY[k] = near ? (C)0.5 * (e - b) : weno3(a, b, c, e, f, ud);
                 sumc += cY[k];
             }
             // mass-conserving correction of the convection (Eq. 26)
 #pragma unroll
             for (int k = 0; k < NSP; ++k) CY[k] += ud * (cY[k] - ctr.Y[k] * sumc);
+            return d1r;
+        };
+#pragma unroll 1
+        for (int d = 0; d < D; ++d) {
+            const C ud = d == 0 ? u[0] : d == 1 ? u[1] : u[2];
+            C d1r;
+            if constexpr (TILE) {
+                const int ic = (threadIdx.y + 2) * kHX + threadIdx.x + 2;
+                const int sd = d == 0 ? 1 : kHX;
+                C r5[5];
+#pragma unroll
+                for (int m = 0; m < 5; ++m) r5[m] = tile[kNP + ic + (m - 2) * sd];
+                d1r = axis_terms([&](int f, int m) -> C { return tile[f * kNP + ic + m * sd]; }, r5, false, ud);
+            } else if constexpr (FAST) {
+                const long long sd = d == 0 ? 1 : d == 1 ? sy : sz;
+                C r5[5];
+#pragma unroll
+                for (int m = 0; m < 5; ++m) {
+                    if (m == 2) {
+                        r5[m] = rho;
+                    } else {
+                        Pt<NSP, C> pt;
+                        load_point<NSP, PREC>(P, idx + (m - 2) * sd, pt);
+                        r5[m] = pt.rho;
+                    }
+                }
+                const char *sc = (const char *)P.sc_in;
+                const size_t fstride = (size_t)P.N * sizeof(S);
+                d1r = axis_terms(
+                    [&](int f, int m) -> C {
+                        const size_t fo = f == 0 ? 0 : (size_t)(f - 1) * fstride;
+                        return (C)ldo<S>(sc + fo, (uint32_t)(idx + m * sd) * (uint32_t)sizeof(S));
+                    },
+                    r5, false, ud);
+            } else {
+                Pt<NSP, C> st[5];
+                bool near = false;
+                axis_stencil<NSP, PREC, DIAG>(P, x, y, z, d, ctr, st, near, wallq);
+                C r5[5] = {st[0].rho, st[1].rho, st[2].rho, st[3].rho, st[4].rho};
+                d1r = axis_terms(
+                    [&](int f, int m) -> C { return f == 0 ? st[m + 2].T : st[m + 2].Y[f - 2]; }, r5, near, ud);
+            }
+            grad[0] = d == 0 ? d1r : grad[0];
+            grad[1] = d == 1 ? d1r : grad[1];
+            grad[2] = d == 2 ? d1r : grad[2];
         }
         const C alpha = (C)P.alpha;
         diffT *= alpha;
@@ -663,16 +787,18 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
 
         if constexpr (MODE != kModeFields) {
             sfor<0, Q>([&](auto I) { pop_store<Q, PREC, decltype(I)::value>(P.pop_out, P.N, idx, h[decltype(I)::value]); });
-            S *so = (S *)P.sc_out;
-            so[idx] = (S)Tn;
+            char *so = (char *)P.sc_out;
+            const size_t fstride = (size_t)P.N * sizeof(S);
+            const uint32_t off = (uint32_t)idx * (uint32_t)sizeof(S);
+            sto<S>(so, off, (S)Tn);
 #pragma unroll
-            for (int k = 0; k < NSP; ++k) so[(1 + k) * P.N + idx] = (S)Yn[k];
+            for (int k = 0; k < NSP; ++k) sto<S>(so + (size_t)(1 + k) * fstride, off, (S)Yn[k]);
             // outlet (Eq. 32): g_i(r) <- g_i(r-n)(cs - u.n) + g_i(r)(1 - cs + u.n)
             // for the populations entering through the face, with the
             // post-streaming values and velocity of this level
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
-                if (P.face[f] != LBFD_FACE_OUTFLOW || x != (f ? P.nx - 1 : 0)) continue;
+                if (FAST || P.face[f] != LBFD_FACE_OUTFLOW || x != (f ? P.nx - 1 : 0)) continue;
                 const int sign = f ? 1 : -1;
                 Nb in = classify(P, x - sign, y, z);
                 if (in.kind != kFluid) continue;
@@ -699,15 +825,15 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
             P.fields[3 * P.N + idx] = (double)u[2];
             P.fields[4 * P.N + idx] = (double)Ph;
         }
-    } else if constexpr (MODE == kModeFields) {
-        if (inbox)
+    } else if constexpr (MODE == kModeFields && FAST) {
+        if (inbox && P.code[idx] == kCodeSolid)
 #pragma unroll
             for (int c = 0; c < 5; ++c) P.fields[c * P.N + idx] = 0.0;
     }
 
     if constexpr (DIAG) {
         const long long blk = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
-        block_reduce_diag(acc, P.partials + blk * kNDiag);
+        block_reduce_diag(acc, P.partials + (FAST ? 0 : P.boundary_partial_offset) * kNDiag + blk * kNDiag);
     }
 }
 
@@ -770,15 +896,28 @@ __global__ void __launch_bounds__(kBlock) init_kernel(const KParams P, const dou
 // ------------------------------------------------------------ launchers
 // Instantiated once per configuration in inst/*.hip (explicit
 // instantiation), declared extern in the dispatcher.
+// One step = the interior kernel over the box grid, then the boundary
+// kernel over the boundary-cell list (both read level n, write level n+1,
+// disjoint cells).
+template <int Q, int NSP, int PREC, int MODE>
+hipError_t launch_pair(const KParams &kp, dim3 grid, dim3 block, hipStream_t s)
+{
+    step_kernel<Q, NSP, PREC, MODE, true><<<grid, block, 0, s>>>(kp);
+    if (kp.n_boundary > 0) {
+        const unsigned nb = (unsigned)((kp.n_boundary + kBlock - 1) / kBlock);
+        step_kernel<Q, NSP, PREC, MODE, false><<<dim3(nb), dim3(kBlock), 0, s>>>(kp);
+    }
+    return hipGetLastError();
+}
+
 template <int Q, int NSP, int PREC>
 hipError_t launch_step_t(int mode, const KParams &kp, dim3 grid, dim3 block, hipStream_t s)
 {
     switch (mode) {
-    case kModeStep: step_kernel<Q, NSP, PREC, kModeStep><<<grid, block, 0, s>>>(kp); break;
-    case kModeStepDiag: step_kernel<Q, NSP, PREC, kModeStepDiag><<<grid, block, 0, s>>>(kp); break;
-    default: step_kernel<Q, NSP, PREC, kModeFields><<<grid, block, 0, s>>>(kp); break;
+    case kModeStep: return launch_pair<Q, NSP, PREC, kModeStep>(kp, grid, block, s);
+    case kModeStepDiag: return launch_pair<Q, NSP, PREC, kModeStepDiag>(kp, grid, block, s);
+    default: return launch_pair<Q, NSP, PREC, kModeFields>(kp, grid, block, s);
     }
-    return hipGetLastError();
 }
 
 template <int Q, int NSP, int PREC>

@@ -54,7 +54,11 @@ def test_channel_flame_fp64_2000_steps():
         assert abs(dg[k] - do[k]) <= 1e-10 * max(abs(do[k]), 1e-30), (k, dg[k], do[k])
     assert np.allclose(dg["mom"], do["mom"], rtol=0, atol=1e-10 * max(1.0, np.abs(do["mom"]).max()))
     assert dg["max_sumY_err"] < 1e-13 and dg["nonfinite"] == 0
-    assert dg["hrr_idx"] == do["hrr_idx"]
+    # the channel is mirror-symmetric in y: the largest heat release is a
+    # tie between rows y and ny-1-y, so compare the value and accept either
+    assert abs(dg["hrr_max"] - do["hrr_max"]) <= 1e-10 * abs(do["hrr_max"])
+    ox, oy = do["hrr_idx"] % prob.nx, do["hrr_idx"] // prob.nx
+    assert dg["hrr_idx"] in (do["hrr_idx"], (prob.ny - 1 - oy) * prob.nx + ox)
 
 
 def test_channel_flame_adiabatic_ragged():
