@@ -97,6 +97,8 @@ def main():
                     help="first entry is the headline value, the others are reported beside it")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 512 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU sharding is a design note, "
@@ -115,6 +117,15 @@ def main():
         print("[bench] %s: %d warmup + %d timed steps" % (p, args.warmup, args.steps), file=sys.stderr, flush=True)
         results[p] = run_gpu(prob, p, args.steps, args.warmup)
         print("[bench] %s: %s" % (p, json.dumps(results[p])), file=sys.stderr, flush=True)
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] copy probe: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8),
+              file=sys.stderr, flush=True)
+        del src, dst
     head = results[precs[0]]
     cpu = None
     if not args.no_cpu_baseline:

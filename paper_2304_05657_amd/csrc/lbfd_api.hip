@@ -62,6 +62,7 @@ struct lbfd_ctx {
     int Q, D, nsp, prec;
     long long N;
     hipStream_t stream;
+    Streams streams = {nullptr, nullptr, nullptr, nullptr};
     void *pop[2] = {nullptr, nullptr};
     void *sc[2] = {nullptr, nullptr};
     int cur = 0;
@@ -69,6 +70,12 @@ struct lbfd_ctx {
     uint8_t *code = nullptr;
     int *boundary = nullptr;
     long long n_boundary = 0;
+    std::vector<int> boundary_host;
+    std::vector<uint8_t> mask_host;
+    std::vector<double> wall_T_host;
+    int *bsrc = nullptr, *bpt = nullptr;
+    uint8_t *bwk = nullptr;
+    double *btw = nullptr;
     int nblocks_interior = 0;
     double *wall_T = nullptr;
     double *outlet = nullptr;
@@ -87,10 +94,14 @@ struct lbfd_ctx {
 static void free_ctx(lbfd_ctx *c)
 {
     if (!c) return;
-    void *ptrs[] = {c->pop[0], c->pop[1], c->sc[0], c->sc[1], c->mask, c->code, c->boundary, c->wall_T, c->outlet,
+    void *ptrs[] = {c->pop[0], c->pop[1], c->sc[0], c->sc[1], c->mask, c->code, c->boundary, c->bsrc, c->bpt, c->bwk,
+                    c->btw, c->wall_T, c->outlet,
                     c->fields, c->partials, c->diag_dev, c->bad_dev, c->rx_dev};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    if (c->streams.side) (void)hipStreamDestroy(c->streams.side);
+    if (c->streams.fork) (void)hipEventDestroy(c->streams.fork);
+    if (c->streams.join) (void)hipEventDestroy(c->streams.join);
     delete c;
 }
 
@@ -195,6 +206,121 @@ static void classify_cells(const lbfd_params &p, const uint8_t *mask, std::vecto
             }
 }
 
+// Host copy of the kernels' neighbour rule: periodic faces wrap; outside
+// any other face the point is that face (walls before inflow before
+// outflow, lower axis and face first); inside, the mask decides.
+struct HostNb {
+    int kind, face;
+    long long idx;
+    double Tw;
+};
+
+static HostNb host_classify(const lbfd_params &p, const uint8_t *mask, const double *wall_T, int x, int y, int z)
+{
+    int q[3] = {x, y, z};
+    const int n[3] = {p.nx, p.ny, p.nz};
+    int best_face = -1, best_rank = 99;
+    for (int d = 0; d < 3; ++d) {
+        if (q[d] < 0 || q[d] >= n[d]) {
+            const int f = 2 * d + (q[d] >= n[d] ? 1 : 0);
+            if (p.face[f] == LBFD_FACE_PERIODIC) {
+                q[d] = ((q[d] % n[d]) + n[d]) % n[d];
+            } else {
+                const int rank = (p.face[f] == LBFD_FACE_WALL || p.face[f] == LBFD_FACE_WALL_ADIABATIC) ? 0
+                               : p.face[f] == LBFD_FACE_INFLOW ? 1 : 2;
+                if (rank < best_rank) {
+                    best_rank = rank;
+                    best_face = f;
+                }
+            }
+        }
+    }
+    HostNb r{kFluid, best_face, 0, 0.0};
+    if (best_face >= 0) {
+        const int kd = p.face[best_face];
+        r.kind = kd == LBFD_FACE_WALL ? kIso : kd == LBFD_FACE_WALL_ADIABATIC ? kAdia : kd == LBFD_FACE_INFLOW ? kInflow : kOutflow;
+        r.Tw = p.face_T[best_face];
+        return r;
+    }
+    r.idx = ((long long)q[2] * p.ny + q[1]) * p.nx + q[0];
+    const uint8_t m = mask[r.idx];
+    r.kind = m == LBFD_FLUID ? kFluid : m == LBFD_SOLID_ISOTHERMAL ? kIso : kAdia;
+    if (r.kind == kIso) r.Tw = wall_T[r.idx];
+    return r;
+}
+
+// Per boundary cell: pull source of every direction and, per axis and
+// offset m = -2, -1, 1, 2, the index of the value point (or of the ghost's
+// image: the cell itself for m = +-1 behind a first-neighbour wall, the
+// cell on the other side for m = +-2, clamped to the cell when not fluid,
+// or the first neighbour when the wall is the second), the kind of the wall
+// behind a ghost and its temperature.
+static int build_descriptors(lbfd_ctx *c)
+{
+    const lbfd_params &p = c->p;
+    const long long nb = c->n_boundary;
+    if (nb == 0) return LBFD_OK;
+    const int Q = c->Q, D = c->D;
+    const uint8_t *mask = c->mask_host.data();
+    const double *wT = c->wall_T_host.data();
+    std::vector<int> src((size_t)Q * nb, kSrcBounce), pt((size_t)12 * nb, 0);
+    std::vector<uint8_t> wk((size_t)12 * nb, kFluid);
+    std::vector<double> tw((size_t)12 * nb, 0.0);
+    const int zr = Q == 27 ? 1 : 0;
+    for (long long t = 0; t < nb; ++t) {
+        const long long idx = c->boundary_host[t];
+        const int x = (int)(idx % p.nx), y = (int)((idx / p.nx) % p.ny), z = (int)(idx / ((long long)p.nx * p.ny));
+        int i = 0;
+        for (int cz = -zr; cz <= zr; ++cz)
+            for (int cy = -1; cy <= 1; ++cy)
+                for (int cx = -1; cx <= 1; ++cx, ++i) {
+                    const HostNb s = host_classify(p, mask, wT, x - cx, y - cy, z - cz);
+                    int v = kSrcBounce;
+                    if (s.kind == kFluid) {
+                        v = (int)s.idx;
+                    } else if (s.kind == kInflow) {
+                        v = kSrcInflow;
+                    } else if (s.kind == kOutflow) {
+                        const int sign = (s.face & 1) ? 1 : -1;
+                        if (host_classify(p, mask, wT, x - sign, y, z).kind == kFluid) v = kSrcOutlet;
+                    }
+                    src[(size_t)i * nb + t] = v;
+                }
+        for (int d = 0; d < D; ++d) {
+            const int ox = d == 0, oy = d == 1, oz = d == 2;
+            for (int sg = -1; sg <= 1; sg += 2) {
+                const int j1 = sg < 0 ? 1 : 2, j2 = sg < 0 ? 0 : 3;
+                const size_t s1 = (size_t)(d * 4 + j1) * nb + t, s2 = (size_t)(d * 4 + j2) * nb + t;
+                const HostNb c1 = host_classify(p, mask, wT, x + sg * ox, y + sg * oy, z + sg * oz);
+                if (c1.kind != kFluid) {
+                    const HostNb cm = host_classify(p, mask, wT, x - sg * ox, y - sg * oy, z - sg * oz);
+                    pt[s1] = (int)idx;
+                    wk[s1] = (uint8_t)c1.kind;
+                    tw[s1] = c1.Tw;
+                    pt[s2] = cm.kind == kFluid ? (int)cm.idx : (int)idx;
+                    wk[s2] = (uint8_t)c1.kind;
+                    tw[s2] = c1.Tw;
+                } else {
+                    pt[s1] = (int)c1.idx;
+                    const HostNb c2 = host_classify(p, mask, wT, x + 2 * sg * ox, y + 2 * sg * oy, z + 2 * sg * oz);
+                    if (c2.kind != kFluid) {
+                        pt[s2] = (int)c1.idx;
+                        wk[s2] = (uint8_t)c2.kind;
+                        tw[s2] = c2.Tw;
+                    } else {
+                        pt[s2] = (int)c2.idx;
+                    }
+                }
+            }
+        }
+    }
+    HIP_TRY(hipMemcpy(c->bsrc, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->bpt, pt.data(), pt.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->bwk, wk.data(), wk.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->btw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice));
+    return LBFD_OK;
+}
+
 static KParams make_kparams(const lbfd_ctx *c)
 {
     const lbfd_params &p = c->p;
@@ -213,6 +339,10 @@ static KParams make_kparams(const lbfd_ctx *c)
     k.boundary = c->boundary;
     k.n_boundary = c->n_boundary;
     k.boundary_partial_offset = c->nblocks_interior;
+    k.bsrc = c->bsrc;
+    k.bpt = c->bpt;
+    k.bwk = c->bwk;
+    k.btw = c->btw;
     k.wall_T = c->wall_T;
     k.outlet = c->outlet;
     k.fields = c->fields;
@@ -313,6 +443,13 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     ALLOC(c->mask, N);
     ALLOC(c->code, N);
     ALLOC(c->boundary, sizeof(int) * (boundary.empty() ? 1 : boundary.size()));
+    {
+        const size_t nbd = boundary.empty() ? 1 : boundary.size();
+        ALLOC(c->bsrc, sizeof(int) * c->Q * nbd);
+        ALLOC(c->bpt, sizeof(int) * 12 * nbd);
+        ALLOC(c->bwk, 12 * nbd);
+        ALLOC(c->btw, sizeof(double) * 12 * nbd);
+    }
     ALLOC(c->wall_T, N * sizeof(double));
     ALLOC(c->outlet, c->outlet_n * sizeof(double));
     ALLOC(c->partials, (size_t)c->nblocks * kNDiag * sizeof(double));
@@ -344,15 +481,14 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     HIP_OR_FREE(hipMemcpy(c->code, code.data(), N, hipMemcpyHostToDevice));
     if (!boundary.empty())
         HIP_OR_FREE(hipMemcpy(c->boundary, boundary.data(), sizeof(int) * boundary.size(), hipMemcpyHostToDevice));
-    {
-        std::vector<double> wt;
-        const double *src = wall_T;
-        if (!src) {
-            wt.assign(N, 300.0);
-            src = wt.data();
-        }
-        HIP_OR_FREE(hipMemcpy(c->wall_T, src, N * sizeof(double), hipMemcpyHostToDevice));
-    }
+    c->mask_host.assign(mask, mask + N);
+    if (wall_T)
+        c->wall_T_host.assign(wall_T, wall_T + N);
+    else
+        c->wall_T_host.assign(N, 300.0);
+    HIP_OR_FREE(hipMemcpy(c->wall_T, c->wall_T_host.data(), N * sizeof(double), hipMemcpyHostToDevice));
+    c->boundary_host = boundary;
+    TRY_OR_FREE(build_descriptors(c));
     long long minus1 = -1;
     HIP_OR_FREE(hipMemcpy(c->bad_dev, &minus1, sizeof(minus1), hipMemcpyHostToDevice));
     if (p->n_reactions > 0)
@@ -360,6 +496,13 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     TRY_OR_FREE(upload_scalars(c, c->sc[0], T0, Y0));
     TRY_OR_FREE(upload_scalars(c, c->sc[1], T0, Y0));
 
+    c->streams.main = c->stream;
+    if (c->n_boundary > 0) {
+        // side stream for the boundary kernel (default priority)
+        HIP_OR_FREE(hipStreamCreateWithFlags(&c->streams.side, hipStreamNonBlocking));
+        HIP_OR_FREE(hipEventCreateWithFlags(&c->streams.fork, hipEventDisableTiming));
+        HIP_OR_FREE(hipEventCreateWithFlags(&c->streams.join, hipEventDisableTiming));
+    }
     c->base = make_kparams(c);
     double *u0_dev = nullptr, *Ph0_dev = nullptr;
     if (u0) {
@@ -400,7 +543,7 @@ int lbfd_step(lbfd_ctx *c, int64_t nsteps)
         k.sc_out = c->sc[1 - c->cur];
         const bool check = c->p.check_every > 0 && (c->level % c->p.check_every) == 0;
         HIP_TRY(launch_step(c->Q, c->nsp, c->prec, check ? kModeStepDiag : kModeStep, k, c->grid, c->block,
-                            c->stream));
+                            c->streams));
         if (check) HIP_TRY(launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream));
         c->cur ^= 1;
         c->level += 1;
@@ -433,7 +576,7 @@ static int evaluate(lbfd_ctx *c)
     KParams k = c->base;
     k.pop_in = c->pop[c->cur];
     k.sc_in = c->sc[c->cur];
-    HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeFields, k, c->grid, c->block, c->stream));
+    HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeFields, k, c->grid, c->block, c->streams));
     HIP_TRY(launch_finalize(c->partials, c->nblocks, c->diag_dev, nullptr, c->level, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return LBFD_OK;
@@ -494,8 +637,9 @@ int lbfd_set_wall_temperature(lbfd_ctx *c, const double *wall_T)
 {
     if (!c || !wall_T) return fail(LBFD_EINVAL, "null argument");
     HIP_TRY(hipStreamSynchronize(c->stream));
+    c->wall_T_host.assign(wall_T, wall_T + c->N);
     HIP_TRY(hipMemcpy(c->wall_T, wall_T, c->N * sizeof(double), hipMemcpyHostToDevice));
-    return LBFD_OK;
+    return build_descriptors(c);
 }
 
 static void state_sizes(const lbfd_ctx *c, size_t *pop, size_t *sc, size_t *outl)

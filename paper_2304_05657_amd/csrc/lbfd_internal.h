@@ -23,6 +23,9 @@ enum DiagSlot {
 // finite-difference point is an in-box fluid cell), boundary fluid.
 enum CellCode { kCodeSolid = 0, kCodeInterior = 1, kCodeBoundary = 2 };
 
+// Special pull sources of boundary cells.
+enum { kSrcBounce = -1, kSrcInflow = -2, kSrcOutlet = -3 };
+
 // Kind of what a neighbour coordinate lands on.
 enum NbKind { kFluid = 0, kIso = 1, kAdia = 2, kInflow = 3, kOutflow = 4 };
 
@@ -37,6 +40,11 @@ struct KParams {
     const uint8_t *code;        // CellCode per cell
     const int *boundary;        // boundary fluid cells, increasing index
     long long n_boundary;
+    // per boundary cell t (structure of arrays, stride n_boundary):
+    const int *bsrc;            // [Q][nb] pull source index, or kSrcBounce / kSrcInflow / kSrcOutlet
+    const int *bpt;             // [3*4][nb] finite-difference point (or ghost image) index, axis-major, m = -2,-1,1,2
+    const uint8_t *bwk;         // [3*4][nb] kind of the wall behind a ghost point, kFluid for a plain point
+    const double *btw;          // [3*4][nb] wall temperature of isothermal ghost walls
     long long boundary_partial_offset;  // first partial slot of the boundary kernel
     const double *wall_T;
     const void *pop_in;   // post-collision populations of the previous level
@@ -60,9 +68,17 @@ struct KParams {
 // Kernel modes.
 enum { kModeStep = 0, kModeStepDiag = 1, kModeFields = 2 };
 
-// Launchers (lbfd_step.hip).  Return hipSuccess or the launch error.
+// Streams of a step: the caller's stream, and an optional side stream
+// (default priority) with fork/join events for the boundary kernel.
+struct Streams {
+    hipStream_t main;
+    hipStream_t side;
+    hipEvent_t fork, join;
+};
+
+// Launchers (instantiated in inst/*.hip, dispatched in lbfd_dispatch.hip).
 hipError_t launch_step(int Q, int nsp, int prec, int mode, const KParams &kp,
-                       dim3 grid, dim3 block, hipStream_t s);
+                       dim3 grid, dim3 block, const Streams &s);
 hipError_t launch_init(int Q, int nsp, int prec, const KParams &kp, const double *u0,
                        const double *Ph0, dim3 grid, dim3 block, hipStream_t s);
 hipError_t launch_finalize(const double *partials, int nblocks, double *out,

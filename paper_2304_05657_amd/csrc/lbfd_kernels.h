@@ -255,47 +255,60 @@ __device__ __forceinline__ void ghost(const KParams &P, const Nb &w, const Pt<NS
     }
 }
 
-// Values at p + m e_d, m = -2..2 (slot m+2), ghosts included; `near` is
-// set when a non-fluid point lies within two cells on either side.
+// Boundary cells: pull and stencil from the per-cell descriptors built at
+// init (same rules as gather / axis_stencil, resolved once on the host).
+template <int Q, int PREC, int I>
+__device__ __forceinline__ typename Prec<PREC>::calc desc_pull(const KParams &P, long long t, long long nb,
+                                                               long long idx, int y, int z)
+{
+    using C = typename Prec<PREC>::calc;
+    using L = Lat<Q>;
+    constexpr int OPP = Q - 1 - I;
+    if constexpr (I == (Q - 1) / 2) {
+        return pop_load<Q, PREC, I>(P.pop_in, P.N, (uint32_t)idx);
+    } else {
+        const int src = P.bsrc[I * nb + t];
+        if (src >= 0) return pop_load<Q, PREC, I>(P.pop_in, P.N, (uint32_t)src);
+        if (src == kSrcInflow) {
+            const double cu = L::cx(I) * P.u_in[0] + L::cy(I) * P.u_in[1] + L::cz(I) * P.u_in[2];
+            return pop_load<Q, PREC, OPP>(P.pop_in, P.N, (uint32_t)idx) + (C)(2.0 * L::w(I) * P.rho_in * cu);
+        }
+        if (src == kSrcOutlet) return (C)P.outlet[outlet_index(P, L::cx(I) < 0 ? 1 : 0, I, Q, y, z)];
+        return pop_load<Q, PREC, OPP>(P.pop_in, P.N, (uint32_t)idx);
+    }
+}
+
 template <int NSP, int PREC, bool DIAG>
-__device__ __forceinline__ void axis_stencil(const KParams &P, int x, int y, int z, int d,
+__device__ __forceinline__ void desc_stencil(const KParams &P, long long t, long long nb, int d,
                                              const Pt<NSP, typename Prec<PREC>::calc> &ctr,
-                                             Pt<NSP, typename Prec<PREC>::calc> (&st)[5], bool &near,
-                                             double &wallq)
+                                             Pt<NSP, typename Prec<PREC>::calc> (&st)[5], bool &near, double &wallq)
 {
     using C = typename Prec<PREC>::calc;
     st[2] = ctr;
+    int pts[4], wks[4];
 #pragma unroll
-    for (int sg = -1; sg <= 1; sg += 2) {
-        int o1 = 2 + sg, o2 = 2 + 2 * sg;
-        const int ox = d == 0, oy = d == 1, oz = d == 2;
-        const int q1[3] = {x + sg * ox, y + sg * oy, z + sg * oz};
-        const int q2[3] = {x + 2 * sg * ox, y + 2 * sg * oy, z + 2 * sg * oz};
-        const int qm[3] = {x - sg * ox, y - sg * oy, z - sg * oz};
-        Nb c1 = classify(P, q1[0], q1[1], q1[2]);
-        if (c1.kind != kFluid) {
-            near = true;
-            if constexpr (DIAG) {
-                if (c1.kind == kIso)
-                    wallq += 2.0 * P.alpha * (double)density<NSP>(P, (C)c1.Tw, ctr.Y) *
-                             ((double)ctr.T - c1.Tw);
-            }
-            ghost<NSP>(P, c1, ctr, st[o1]);
-            Nb cm = classify(P, qm[0], qm[1], qm[2]);
-            Pt<NSP, C> img;
-            if (cm.kind == kFluid)
-                load_point<NSP, PREC>(P, cm.idx, img);
-            else
-                img = ctr;
-            ghost<NSP>(P, c1, img, st[o2]);
+    for (int j = 0; j < 4; ++j) {
+        pts[j] = P.bpt[(d * 4 + j) * nb + t];
+        wks[j] = P.bwk[(d * 4 + j) * nb + t];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int slot = j < 2 ? j : j + 1;
+        Pt<NSP, C> img;
+        load_point<NSP, PREC>(P, pts[j], img);
+        if (wks[j] == kFluid) {
+            st[slot] = img;
         } else {
-            load_point<NSP, PREC>(P, c1.idx, st[o1]);
-            Nb c2 = classify(P, q2[0], q2[1], q2[2]);
-            if (c2.kind != kFluid) {
-                near = true;
-                ghost<NSP>(P, c2, st[o1], st[o2]);
-            } else {
-                load_point<NSP, PREC>(P, c2.idx, st[o2]);
+            near = true;
+            Nb w;
+            w.kind = wks[j];
+            w.face = -1;
+            w.idx = 0;
+            w.Tw = w.kind == kIso ? P.btw[(d * 4 + j) * nb + t] : 0.0;
+            ghost<NSP>(P, w, img, st[slot]);
+            if constexpr (DIAG) {
+                if ((j == 1 || j == 2) && w.kind == kIso)
+                    wallq += 2.0 * P.alpha * (double)density<NSP>(P, (C)w.Tw, ctr.Y) * ((double)ctr.T - w.Tw);
             }
         }
     }
@@ -313,27 +326,31 @@ __device__ __forceinline__ C d2(C a, C b, C c, C d, C e)
     return ((C)16 * (b + d) - (a + e) - (C)30 * c) * (C)(1.0 / 12.0);
 }
 
-// WENO3 (Jiang-Shu, eps = 1e-6) value at the face between b and c from
-// the side of b; a is the far upwind point.  The normalised weight of the
-// one-sided candidate is e1^2 / (e1^2 + 2 e0^2), e_r = eps + beta_r.
-template <class C>
-__device__ __forceinline__ C weno_face(C a, C b, C c)
-{
-    const C eps = (C)1e-6;
-    C q0 = (C)1.5 * b - (C)0.5 * a;
-    C q1 = (C)0.5 * (b + c);
-    C e0 = eps + (b - a) * (b - a);
-    C e1 = eps + (c - b) * (c - b);
-    C e0s = e0 * e0, e1s = e1 * e1;
-    C w0 = e1s / (e1s + (C)2 * e0s);
-    return q1 + w0 * (q0 - q1);
-}
-
+// WENO3 convective derivative (Jiang-Shu weights, eps = 1e-6): for u >= 0
+// the face values at i+1/2 and i-1/2 are reconstructed from the left; for
+// u < 0 the stencil is mirrored and the result negated, which is the
+// right-biased reconstruction.  At a face between b and c reconstructed
+// from the side of b (a the far upwind point) the value is
+// q1 + w0 (q0 - q1), q0 = 3b/2 - a/2, q1 = (b+c)/2, with the normalised
+// weight w0 = e1^2 / (e1^2 + 2 e0^2), e0 = eps + (b-a)^2,
+// e1 = eps + (c-b)^2; both faces share one division.
 template <class C>
 __device__ __forceinline__ C weno3(C m2, C m1, C c0, C p1, C p2, C u)
 {
-    if (u >= (C)0) return weno_face(m1, c0, p1) - weno_face(m2, m1, c0);
-    return weno_face(p2, p1, c0) - weno_face(p1, c0, m1);
+    const bool neg = u < (C)0;
+    const C A = neg ? p2 : m2, B = neg ? p1 : m1, E = neg ? m1 : p1;
+    const C eps = (C)1e-6;
+    const C dA = B - A, dB = c0 - B, dE = E - c0;
+    const C eA = eps + dA * dA, eB = eps + dB * dB, eE = eps + dE * dE;
+    const C eA2 = eA * eA, eB2 = eB * eB, eE2 = eE * eE;
+    const C den_p = eE2 + (C)2 * eB2;  // face i+1/2: e0 = eB, e1 = eE
+    const C den_m = eB2 + (C)2 * eA2;  // face i-1/2: e0 = eA, e1 = eB
+    const C inv = (C)1 / (den_p * den_m);
+    const C w_p = eE2 * den_m * inv, w_m = eB2 * den_p * inv;
+    const C q0p = (C)1.5 * c0 - (C)0.5 * B, q1p = (C)0.5 * (c0 + E);
+    const C q0m = (C)1.5 * B - (C)0.5 * A, q1m = (C)0.5 * (B + c0);
+    const C conv = (q1p + w_p * (q0p - q1p)) - (q1m + w_m * (q0m - q1m));
+    return neg ? -conv : conv;
 }
 
 // ------------------------------------------------------------ chemistry
@@ -529,6 +546,121 @@ __device__ __forceinline__ void block_reduce_diag(double (&a)[kNDiag], double *o
 }
 
 // ------------------------------------------------------------ step kernel
+// Everything after the finite differences, for one fluid cell: Arrhenius
+// source, Lambda (Eq. 6), Euler update, P_h (Eq. 13a), source Xi_i (Eq. 9),
+// central-moment collision (Eqs. 14, 19, 21), diagnostics, stores.
+// diffT, diffY already carry the factor alpha.
+template <int Q, int NSP, int PREC, int MODE>
+__device__ __forceinline__ void finish_cell(const KParams &P, long long idx, const typename Prec<PREC>::calc (&g)[Q],
+                                            const Pt<NSP, typename Prec<PREC>::calc> &ctr,
+                                            const typename Prec<PREC>::calc (&u)[3],
+                                            const typename Prec<PREC>::calc (&m)[3], typename Prec<PREC>::calc sg,
+                                            typename Prec<PREC>::calc inv_rc, typename Prec<PREC>::calc diffT,
+                                            const typename Prec<PREC>::calc (&diffY)[NSP],
+                                            typename Prec<PREC>::calc CT, const typename Prec<PREC>::calc (&CY)[NSP],
+                                            const typename Prec<PREC>::calc (&grad)[3], double wallq,
+                                            double (&acc)[kNDiag])
+{
+    using L = Lat<Q>;
+    using C = typename Prec<PREC>::calc;
+    using S = typename Prec<PREC>::scal;
+    constexpr bool DIAG = MODE != kModeStep;
+    const C rho = ctr.rho;
+    // Arrhenius source (double)
+    double Yd[NSP], srcT, srcY[NSP];
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) Yd[k] = (double)ctr.Y[k];
+    chemistry<NSP>(P, (double)ctr.T, Yd, srcT, srcY);
+
+    // material derivatives, Lambda (Eq. 6), Euler update, P_h (Eq. 13a)
+    const C DtT = diffT + (C)srcT;
+    C DtY[NSP], invW = 0;
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) {
+        DtY[k] = diffY[k] + (C)srcY[k];
+        invW += ctr.Y[k] * (C)P.invW[k];
+    }
+    const C Wm = (C)1 / invW;
+    C Lam = DtT / ctr.T;
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) Lam += (Wm * (C)P.invW[k]) * DtY[k];
+    const C Tn = ctr.T - CT + DtT;
+    C Yn[NSP];
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) Yn[k] = ctr.Y[k] - CY[k] + DtY[k];
+    const C Ph = sg + (C)0.5 * rho * (C)kCs2 * Lam;
+
+    // source Xi_i (Eq. 9) and pre-conditioned populations (Eq. 19)
+    const C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    C xi[Q], h[Q], pi = 0, sxi = 0;
+    const C half_inv = (C)0.5 * inv_rc;
+    sfor<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr C wi = (C)L::w(i);
+        const C cu = (C)L::cx(i) * u[0] + (C)L::cy(i) * u[1] + (C)L::cz(i) * u[2];
+        const C feq_r = wi * ((C)1 + (C)3 * cu + (C)4.5 * cu * cu - (C)1.5 * uu);
+        const C proj = ((C)L::cx(i) - u[0]) * grad[0] + ((C)L::cy(i) - u[1]) * grad[1] +
+                       ((C)L::cz(i) - u[2]) * grad[2];
+        xi[i] = (C)kCs2 * (feq_r - wi) * proj + wi * rho * (C)kCs2 * Lam;
+        sxi += xi[i];
+        h[i] = g[i] * inv_rc + xi[i] * half_inv;
+        pi += h[i];
+    });
+    // unit-mass shift, central-moment relaxation, shift back (Eq. 14)
+    const C sh = (C)1 - pi;
+    sfor<0, Q>([&](auto I) { h[decltype(I)::value] += (C)L::w(decltype(I)::value) * sh; });
+    central_fwd<Q>(h, u);
+    relax<Q>(h, (C)P.omega2, (C)P.omega3, (C)P.omega4);
+    central_inv<Q>(h, u);
+    const C rc = rho * (C)kCs2;
+    sfor<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        h[i] = rc * (h[i] - (C)L::w(i) * sh) + (C)0.5 * xi[i];
+    });
+
+    if constexpr (DIAG) {
+        bool bad = !isfinite((double)ctr.T);
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) bad |= !isfinite((double)ctr.Y[k]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) bad |= !isfinite((double)g[i]);
+        if (bad) {
+            acc[kNonfinite] = 1.0;
+        } else {
+            double sy = 0.0;
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) sy += (double)ctr.Y[k];
+            acc[kSumG] = (double)sg;
+            acc[kSumXi] = (double)sxi;
+            acc[kMomX] = (double)m[0] * 3.0;
+            acc[kMomY] = (double)m[1] * 3.0;
+            acc[kMomZ] = (double)m[2] * 3.0;
+            acc[kMaxY] = fabs(sy - 1.0);
+            acc[kTheta] = ((double)ctr.T - P.T_u) / (P.T_b - P.T_u);
+            acc[kHrrMax] = srcT;
+            acc[kHrrIdx] = (double)idx;
+            acc[kWallQ] = wallq;
+            acc[kFuel] = -srcY[0];
+        }
+    }
+
+    if constexpr (MODE != kModeFields) {
+        sfor<0, Q>([&](auto I) { pop_store<Q, PREC, decltype(I)::value>(P.pop_out, P.N, idx, h[decltype(I)::value]); });
+        char *so = (char *)P.sc_out;
+        const size_t fstride = (size_t)P.N * sizeof(S);
+        const uint32_t off = (uint32_t)idx * (uint32_t)sizeof(S);
+        sto<S>(so, off, (S)Tn);
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) sto<S>(so + (size_t)(1 + k) * fstride, off, (S)Yn[k]);
+    } else {
+        P.fields[idx] = (double)rho;
+        P.fields[P.N + idx] = (double)u[0];
+        P.fields[2 * P.N + idx] = (double)u[1];
+        P.fields[3 * P.N + idx] = (double)u[2];
+        P.fields[4 * P.N + idx] = (double)Ph;
+    }
+}
+
 // FAST = true: the interior kernel -- a 2-D/3-D grid over the box whose
 // threads work only on interior fluid cells (every pull source and every
 // finite-difference point in the box and fluid), with plain offset loads.
@@ -543,7 +675,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
     constexpr int D = L::D;
     constexpr bool DIAG = MODE != kModeStep;
     int x, y, z;
-    long long idx;
+    long long idx, tb = 0;
     bool active, inbox;
     if constexpr (FAST) {
         x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -553,10 +685,10 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
         idx = inbox ? ((long long)z * P.ny + y) * P.nx + x : 0;
         active = inbox && P.code[idx] == kCodeInterior;
     } else {
-        const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+        tb = (long long)blockIdx.x * blockDim.x + threadIdx.x;
         inbox = false;
-        active = t < P.n_boundary;
-        idx = active ? (long long)P.boundary[t] : 0;
+        active = tb < P.n_boundary;
+        idx = active ? (long long)P.boundary[tb] : 0;
         x = (int)(idx % P.nx);
         y = (int)((idx / P.nx) % P.ny);
         z = (int)(idx / ((long long)P.nx * P.ny));
@@ -605,7 +737,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
             if constexpr (FAST)
                 g[i] = pop_load<Q, PREC, i>(P.pop_in, P.N, idx - (L::cx(i) + sy * L::cy(i) + sz * L::cz(i)));
             else
-                g[i] = gather<Q, PREC, i>(P, x, y, z, idx);
+                g[i] = desc_pull<Q, PREC, i>(P, tb, P.n_boundary, idx, y, z);
         });
         Pt<NSP, C> ctr;
         if constexpr (TILE)
@@ -693,7 +825,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
             } else {
                 Pt<NSP, C> st[5];
                 bool near = false;
-                axis_stencil<NSP, PREC, DIAG>(P, x, y, z, d, ctr, st, near, wallq);
+                desc_stencil<NSP, PREC, DIAG>(P, tb, P.n_boundary, d, ctr, st, near, wallq);
                 C r5[5] = {st[0].rho, st[1].rho, st[2].rho, st[3].rho, st[4].rho};
                 d1r = axis_terms(
                     [&](int f, int m) -> C { return f == 0 ? st[m + 2].T : st[m + 2].Y[f - 2]; }, r5, near, ud);
@@ -707,92 +839,8 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
 #pragma unroll
         for (int k = 0; k < NSP; ++k) diffY[k] *= alpha;
 
-        // Arrhenius source (double)
-        double Yd[NSP], srcT, srcY[NSP];
-#pragma unroll
-        for (int k = 0; k < NSP; ++k) Yd[k] = (double)ctr.Y[k];
-        chemistry<NSP>(P, (double)ctr.T, Yd, srcT, srcY);
-
-        // material derivatives, Lambda (Eq. 6), Euler update, P_h (Eq. 13a)
-        const C DtT = diffT + (C)srcT;
-        C DtY[NSP], invW = 0;
-#pragma unroll
-        for (int k = 0; k < NSP; ++k) {
-            DtY[k] = diffY[k] + (C)srcY[k];
-            invW += ctr.Y[k] * (C)P.invW[k];
-        }
-        const C Wm = (C)1 / invW;
-        C Lam = DtT / ctr.T;
-#pragma unroll
-        for (int k = 0; k < NSP; ++k) Lam += (Wm * (C)P.invW[k]) * DtY[k];
-        const C Tn = ctr.T - CT + DtT;
-        C Yn[NSP];
-#pragma unroll
-        for (int k = 0; k < NSP; ++k) Yn[k] = ctr.Y[k] - CY[k] + DtY[k];
-        const C Ph = sg + (C)0.5 * rho * (C)kCs2 * Lam;
-
-        // source Xi_i (Eq. 9) and pre-conditioned populations (Eq. 19)
-        const C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-        C xi[Q], h[Q], pi = 0, sxi = 0;
-        const C half_inv = (C)0.5 * inv_rc;
-        sfor<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            constexpr C wi = (C)L::w(i);
-            const C cu = (C)L::cx(i) * u[0] + (C)L::cy(i) * u[1] + (C)L::cz(i) * u[2];
-            const C feq_r = wi * ((C)1 + (C)3 * cu + (C)4.5 * cu * cu - (C)1.5 * uu);
-            const C proj = ((C)L::cx(i) - u[0]) * grad[0] + ((C)L::cy(i) - u[1]) * grad[1] +
-                           ((C)L::cz(i) - u[2]) * grad[2];
-            xi[i] = (C)kCs2 * (feq_r - wi) * proj + wi * rho * (C)kCs2 * Lam;
-            sxi += xi[i];
-            h[i] = g[i] * inv_rc + xi[i] * half_inv;
-            pi += h[i];
-        });
-        // unit-mass shift, central-moment relaxation, shift back (Eq. 14)
-        const C sh = (C)1 - pi;
-        sfor<0, Q>([&](auto I) { h[decltype(I)::value] += (C)L::w(decltype(I)::value) * sh; });
-        central_fwd<Q>(h, u);
-        relax<Q>(h, (C)P.omega2, (C)P.omega3, (C)P.omega4);
-        central_inv<Q>(h, u);
-        const C rc = rho * (C)kCs2;
-        sfor<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            h[i] = rc * (h[i] - (C)L::w(i) * sh) + (C)0.5 * xi[i];
-        });
-
-        if constexpr (DIAG) {
-            bool bad = !isfinite((double)ctr.T);
-#pragma unroll
-            for (int k = 0; k < NSP; ++k) bad |= !isfinite((double)ctr.Y[k]);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) bad |= !isfinite((double)g[i]);
-            if (bad) {
-                acc[kNonfinite] = 1.0;
-            } else {
-                double sy = 0.0;
-#pragma unroll
-                for (int k = 0; k < NSP; ++k) sy += (double)ctr.Y[k];
-                acc[kSumG] = (double)sg;
-                acc[kSumXi] = (double)sxi;
-                acc[kMomX] = (double)m[0] * 3.0;
-                acc[kMomY] = (double)m[1] * 3.0;
-                acc[kMomZ] = (double)m[2] * 3.0;
-                acc[kMaxY] = fabs(sy - 1.0);
-                acc[kTheta] = ((double)ctr.T - P.T_u) / (P.T_b - P.T_u);
-                acc[kHrrMax] = srcT;
-                acc[kHrrIdx] = (double)idx;
-                acc[kWallQ] = wallq;
-                acc[kFuel] = -srcY[0];
-            }
-        }
-
+        finish_cell<Q, NSP, PREC, MODE>(P, idx, g, ctr, u, m, sg, inv_rc, diffT, diffY, CT, CY, grad, wallq, acc);
         if constexpr (MODE != kModeFields) {
-            sfor<0, Q>([&](auto I) { pop_store<Q, PREC, decltype(I)::value>(P.pop_out, P.N, idx, h[decltype(I)::value]); });
-            char *so = (char *)P.sc_out;
-            const size_t fstride = (size_t)P.N * sizeof(S);
-            const uint32_t off = (uint32_t)idx * (uint32_t)sizeof(S);
-            sto<S>(so, off, (S)Tn);
-#pragma unroll
-            for (int k = 0; k < NSP; ++k) sto<S>(so + (size_t)(1 + k) * fstride, off, (S)Yn[k]);
             // outlet (Eq. 32): g_i(r) <- g_i(r-n)(cs - u.n) + g_i(r)(1 - cs + u.n)
             // for the populations entering through the face, with the
             // post-streaming values and velocity of this level
@@ -818,12 +866,6 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
                     }
                 });
             }
-        } else {
-            P.fields[idx] = (double)rho;
-            P.fields[P.N + idx] = (double)u[0];
-            P.fields[2 * P.N + idx] = (double)u[1];
-            P.fields[3 * P.N + idx] = (double)u[2];
-            P.fields[4 * P.N + idx] = (double)Ph;
         }
     } else if constexpr (MODE == kModeFields && FAST) {
         if (inbox && P.code[idx] == kCodeSolid)
@@ -899,24 +941,44 @@ __global__ void __launch_bounds__(kBlock) init_kernel(const KParams P, const dou
 // One step = the interior kernel over the box grid, then the boundary
 // kernel over the boundary-cell list (both read level n, write level n+1,
 // disjoint cells).
+// One step = the interior kernel over the box grid and the boundary kernel
+// over the boundary-cell list; both read level n and write disjoint cells
+// of level n+1.  With a side stream the boundary kernel runs concurrently
+// (fork: side waits on `fork` recorded on s; join: s waits on `join`).
 template <int Q, int NSP, int PREC, int MODE>
-hipError_t launch_pair(const KParams &kp, dim3 grid, dim3 block, hipStream_t s)
+hipError_t launch_pair(const KParams &kp, dim3 grid, dim3 block, const Streams &st)
 {
-    step_kernel<Q, NSP, PREC, MODE, true><<<grid, block, 0, s>>>(kp);
-    if (kp.n_boundary > 0) {
-        const unsigned nb = (unsigned)((kp.n_boundary + kBlock - 1) / kBlock);
-        step_kernel<Q, NSP, PREC, MODE, false><<<dim3(nb), dim3(kBlock), 0, s>>>(kp);
+    hipError_t e = hipSuccess;
+    {
+        const bool side = st.side != nullptr && kp.n_boundary > 0;
+        if (side) {
+            if ((e = hipEventRecord(st.fork, st.main)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(st.side, st.fork, 0)) != hipSuccess) return e;
+        }
+        // the boundary kernel (few, long-latency blocks) is queued first so
+        // that its blocks are resident while the interior blocks stream
+        if (kp.n_boundary > 0) {
+            const unsigned nb = (unsigned)((kp.n_boundary + kBlock - 1) / kBlock);
+            step_kernel<Q, NSP, PREC, MODE, false><<<dim3(nb), dim3(kBlock), 0, side ? st.side : st.main>>>(kp);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        step_kernel<Q, NSP, PREC, MODE, true><<<grid, block, 0, st.main>>>(kp);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (side) {
+            if ((e = hipEventRecord(st.join, st.side)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(st.main, st.join, 0)) != hipSuccess) return e;
+        }
+        return hipSuccess;
     }
-    return hipGetLastError();
 }
 
 template <int Q, int NSP, int PREC>
-hipError_t launch_step_t(int mode, const KParams &kp, dim3 grid, dim3 block, hipStream_t s)
+hipError_t launch_step_t(int mode, const KParams &kp, dim3 grid, dim3 block, const Streams &st)
 {
     switch (mode) {
-    case kModeStep: return launch_pair<Q, NSP, PREC, kModeStep>(kp, grid, block, s);
-    case kModeStepDiag: return launch_pair<Q, NSP, PREC, kModeStepDiag>(kp, grid, block, s);
-    default: return launch_pair<Q, NSP, PREC, kModeFields>(kp, grid, block, s);
+    case kModeStep: return launch_pair<Q, NSP, PREC, kModeStep>(kp, grid, block, st);
+    case kModeStepDiag: return launch_pair<Q, NSP, PREC, kModeStepDiag>(kp, grid, block, st);
+    default: return launch_pair<Q, NSP, PREC, kModeFields>(kp, grid, block, st);
     }
 }
 
@@ -935,7 +997,7 @@ hipError_t launch_init_t(const KParams &kp, const double *u0, const double *Ph0,
     X(9, 4, 2) X(27, 4, 2) X(27, 9, 2)
 
 #define LBFD_INSTANTIATE(q, n, p) \
-    template hipError_t launch_step_t<q, n, p>(int, const KParams &, dim3, dim3, hipStream_t); \
+    template hipError_t launch_step_t<q, n, p>(int, const KParams &, dim3, dim3, const Streams &); \
     template hipError_t launch_init_t<q, n, p>(const KParams &, const double *, const double *, dim3, dim3, \
                                                hipStream_t);
 
