@@ -28,6 +28,19 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS of coupled LBM+FD step and % HBM roofline, FP64 vs mixed precision"
 HBM_PEAK_GBS = 8000.0
+# Vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+# Both FP64 and FP32 issue at this rate: packed FP32 is not used.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2304_05657_amd", "csrc", "lbfd_kernels.h")
+# HBM bytes per launch of the interior kernel on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by
+# the same counters on a plain 512 MiB device copy (FETCH_SIZE reads 0.5x,
+# WRITE_SIZE 1.0x the copied bytes), valid for the kernel source whose
+# SHA-256 is given (profiles/traffic_step_kernels_burner_2048x512.md).
+TRAFFIC = {
+    "fp64": {"kernel_sha256": "2314322f5f9f6f7c1f0f738f09b1b2b15d7484709e8291c43c4f64f6a6d18748", "bytes_per_launch": 219.8e6},
+    "fp32": {"kernel_sha256": "2314322f5f9f6f7c1f0f738f09b1b2b15d7484709e8291c43c4f64f6a6d18748", "bytes_per_launch": 132.8e6},
+}
 POP_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 SCALAR_BYTES = {"fp64": 8, "fp32": 4, "fp16": 4}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16": "f32"}
@@ -38,6 +51,57 @@ def algorithmic_bytes(prob, precision: str) -> float:
     cell read and written once, one mask byte per cell."""
     per_fluid = 2 * prob.lattice * POP_BYTES[precision] + 2 * (1 + prob.n_species) * SCALAR_BYTES[precision]
     return float(prob.n_fluid * per_fluid + prob.N)
+
+
+def algorithmic_flops_per_cell(prob) -> int:
+    """Floating-point operations of one coupled step for one fluid cell
+    (FMA = 2, add/mul/div/exp = 1), counted from the minimal form of each
+    operation: moments, density, FD operators with WENO3 on 1 + N_sp scalars
+    per axis, Arrhenius source, Lambda, Euler update, P_h, source Xi and
+    pre-conditioning, per-axis central-moment transforms, relaxation."""
+    Q = prob.lattice
+    D = 2 if Q == 9 else 3
+    ns = prob.n_species
+    nrx = len(prob.reactions)
+    moments = (Q - 1) + D * (2 * Q // 3 - 1)
+    density = 2 * ns + 1
+    velocity = 2 + D + 1
+    fd = D * (6 + 56 * (1 + ns) + 5 * ns + 1) + (1 + ns)
+    chem = nrx * (10 + 2 * ns)
+    lam = 6 * ns + 2
+    euler = 2 + 2 * ns
+    ph = 3
+    xi = Q * (16 + 2 * D) + 4
+    shift = 1 + 2 * Q
+    transforms = 2 * 12 * D * Q // 3
+    relax = 3 * (Q - 1 - D)
+    out = 4 * Q + 1
+    return (moments + density + velocity + fd + chem + lam + euler + ph + xi + shift + transforms + relax
+            + out)
+
+
+def kernel_sha() -> str:
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+
+
+def flame_position(diag, prob) -> float:
+    """Front position in cells: the burnt length sum(theta) / (mean fluid
+    cells per x column), counted back from the outlet face."""
+    return prob.nx - diag["sum_theta"] / (prob.n_fluid / prob.nx)
+
+
+def accuracy(ref: dict, ref_diag: dict, fields: dict, diag: dict, prob) -> dict:
+    """Errors of a mixed-precision run against the FP64 run at the same level."""
+    import numpy as np
+    fl = prob.mask == 0
+    dims = 2 if prob.lattice == 9 else 3
+    umag_r = np.sqrt(sum(ref["u"][d][fl] ** 2 for d in range(dims)))
+    du = np.sqrt(sum((fields["u"][d][fl] - ref["u"][d][fl]) ** 2 for d in range(dims)))
+    dT = np.abs(fields["T"][fl] - ref["T"][fl]) / (prob.T_b - prob.T_u)
+    return {"u_max_rel": float(du.max() / umag_r.max()), "u_rms_rel": float(np.sqrt((du ** 2).mean()) / umag_r.max()),
+            "T_max_rel": float(dT.max()), "T_rms_rel": float(np.sqrt((dT ** 2).mean())),
+            "flame_dx_cells": float(flame_position(diag, prob) - flame_position(ref_diag, prob))}
 
 
 def run_gpu(prob, precision: str, steps: int, warmup: int) -> dict:
@@ -60,14 +124,29 @@ def run_gpu(prob, precision: str, steps: int, warmup: int) -> dict:
     per_step_s = ms * 1e-3 / steps
     nbytes = algorithmic_bytes(prob, precision)
     achieved = nbytes / per_step_s / 1e9
+    # the dominant kernel alone: interior cells, launches serialised and
+    # bracketed by HIP events on the solver's stream
+    n_fluid, n_boundary = s.cell_counts()
+    n_int = n_fluid - n_boundary
+    kms_i, kms_b = s.time_kernels(steps)
+    t_int = kms_i * 1e-3 / steps
+    per_fluid = algorithmic_bytes(prob, precision) - prob.N
+    per_fluid /= prob.n_fluid
+    int_bytes = n_int * per_fluid + prob.N
+    int_flops = n_int * algorithmic_flops_per_cell(prob)
     out = {
         "precision": precision, "ms_per_step": ms / steps, "wall_ms_per_step": wall * 1e3 / steps,
         "mlups": prob.N / per_step_s / 1e6, "mflups": prob.n_fluid / per_step_s / 1e6,
         "algorithmic_bytes_per_step": nbytes, "achieved_GBs": achieved,
         "hbm_frac": achieved / HBM_PEAK_GBS, "finite": ok,
+        "interior_kernel": {"cells": n_int, "ms_per_launch": kms_i / steps, "flops_per_cell":
+                            algorithmic_flops_per_cell(prob), "TFLOPs": int_flops / t_int / 1e12,
+                            "alu_frac": int_flops / t_int / 1e12 / VALU_PEAK_TFLOPS,
+                            "algorithmic_bytes": int_bytes, "GBs": int_bytes / t_int / 1e9,
+                            "hbm_frac": int_bytes / t_int / 1e9 / HBM_PEAK_GBS},
+        "boundary_kernel": {"cells": n_boundary, "ms_per_launch": kms_b / steps},
     }
-    s.close()
-    return out
+    return out, s
 
 
 def run_cpu_baseline(prob, budget_s: float) -> dict:
@@ -88,6 +167,20 @@ def run_cpu_baseline(prob, budget_s: float) -> dict:
                       "step), %.1f s" % (n, prob.nx, prob.ny, el)}
 
 
+def roofline(res: dict, precision: str) -> dict:
+    """Roofline of the dominant kernel (interior cells): it is bound by the
+    vector ALU (instruction issue), so achieved is algorithmic TFLOP/s
+    against the VALU peak; its HBM rate is given beside it."""
+    ik = res["interior_kernel"]
+    t = TRAFFIC.get(precision)
+    traffic = t["bytes_per_launch"] if t and t.get("kernel_sha256") == kernel_sha() else None
+    return {"kernel": "step_kernel (interior cells)", "bound": "alu", "achieved": ik["TFLOPs"],
+            "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ik["alu_frac"], "traffic": traffic,
+            "hbm_achieved_GBs": ik["GBs"], "hbm_peak_GBs": HBM_PEAK_GBS, "hbm_frac": ik["hbm_frac"],
+            "launch_ms": ik["ms_per_launch"], "algorithmic_flops_per_cell": ik["flops_per_cell"],
+            "algorithmic_bytes_per_launch": ik["algorithmic_bytes"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +190,8 @@ def main():
                     help="first entry is the headline value, the others are reported beside it")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--accuracy-steps", type=int, default=20000,
+                    help="level at which the mixed-precision runs are compared with the FP64 run (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 512 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -113,10 +208,27 @@ def main():
     prob = W.cylinder_burner()
     precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
     results = {}
+    ref = None
     for p in precs:
         print("[bench] %s: %d warmup + %d timed steps" % (p, args.warmup, args.steps), file=sys.stderr, flush=True)
-        results[p] = run_gpu(prob, p, args.steps, args.warmup)
+        results[p], solver = run_gpu(prob, p, args.steps, args.warmup)
         print("[bench] %s: %s" % (p, json.dumps(results[p])), file=sys.stderr, flush=True)
+        if args.accuracy_steps > 0:
+            # continue the same run (outside the timed region) to the
+            # comparison level and compare with the FP64 run
+            solver.step(max(0, args.accuracy_steps - solver.level))
+            solver.sync()
+            f, d = solver.fields(), solver.diagnostics()
+            results[p]["level"] = solver.level
+            results[p]["finite_at_level"] = d["nonfinite"] == 0
+            results[p]["flame_x_cells"] = flame_position(d, prob)
+            if p == "fp64":
+                ref = (f, d)
+            elif ref is not None:
+                results[p]["error_vs_fp64"] = accuracy(ref[0], ref[1], f, d, prob)
+                print("[bench] %s vs fp64 at level %d: %s" % (p, solver.level, json.dumps(results[p]["error_vs_fp64"])),
+                      file=sys.stderr, flush=True)
+        solver.close()
     if args.copy_probe:
         src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -146,8 +258,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": prob.name, "lattice": "D2Q9", "cells": prob.N, "fluid_cells": prob.n_fluid,
                    "species": prob.n_species, "reactions": len(prob.reactions), "storage": precs[0]},
-        "roofline": {"bound": "hbm", "achieved": head["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": head["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None},
+        "roofline": roofline(head, precs[0]),
         "cpu_baseline": cpu,
         "precisions": {p: {k: v for k, v in r.items() if k != "precision"} for p, r in results.items()},
     }

@@ -193,6 +193,18 @@ int lbfd_load_state(lbfd_ctx *c, const void *blob, size_t bytes);
  * milliseconds in *ms. */
 int lbfd_time_steps(lbfd_ctx *c, int64_t nsteps, double *ms);
 
+/* Per-kernel timing: queue nsteps steps with the interior-cell kernel and
+ * the boundary-cell kernel serialised on the context stream, each bracketed
+ * by HIP events; wait and return their summed durations in milliseconds.
+ * The state advances exactly as with lbfd_step. */
+int lbfd_time_kernels(lbfd_ctx *c, int64_t nsteps, double *ms_interior, double *ms_boundary);
+
+/* Cell counts of the context's geometry: fluid cells, and the fluid cells
+ * handled by the boundary kernel (every other fluid cell is interior: all
+ * of its pull sources and finite-difference points are fluid cells inside
+ * the box). */
+int lbfd_cell_counts(const lbfd_ctx *c, int64_t *n_fluid, int64_t *n_boundary);
+
 void lbfd_destroy(lbfd_ctx *c);
 
 const char *lbfd_strerror(int code);

@@ -62,7 +62,8 @@ struct lbfd_ctx {
     int Q, D, nsp, prec;
     long long N;
     hipStream_t stream;
-    Streams streams = {nullptr, nullptr, nullptr, nullptr};
+    Streams streams = {nullptr, nullptr, nullptr, nullptr, 0};
+    long long n_fluid = 0;
     void *pop[2] = {nullptr, nullptr};
     void *sc[2] = {nullptr, nullptr};
     int cur = 0;
@@ -426,6 +427,7 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     std::vector<int> boundary;
     classify_cells(*p, mask, code, boundary);
     c->n_boundary = (long long)boundary.size();
+    for (long long i = 0; i < c->N; ++i) c->n_fluid += mask[i] == LBFD_FLUID;
     c->nblocks_interior = c->grid.x * c->grid.y * c->grid.z;
     c->nblocks = c->nblocks_interior + (int)((c->n_boundary + kBlock - 1) / kBlock);
 
@@ -715,6 +717,54 @@ int lbfd_time_steps(lbfd_ctx *c, int64_t nsteps, double *ms)
     (void)hipEventDestroy(b);
     *ms = t;
     return rc;
+}
+
+int lbfd_time_kernels(lbfd_ctx *c, int64_t nsteps, double *ms_interior, double *ms_boundary)
+{
+    if (!c || !ms_interior || !ms_boundary || nsteps < 0) return fail(LBFD_EINVAL, "bad arguments");
+    hipEvent_t e0, e1, e2;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventCreate(&e2));
+    double ti = 0.0, tb = 0.0;
+    int rc = LBFD_OK;
+    for (int64_t s = 0; s < nsteps && rc == LBFD_OK; ++s) {
+        KParams k = c->base;
+        k.pop_in = c->pop[c->cur];
+        k.pop_out = c->pop[1 - c->cur];
+        k.sc_in = c->sc[c->cur];
+        k.sc_out = c->sc[1 - c->cur];
+        Streams st = c->streams;
+        HIP_TRY(hipEventRecord(e0, c->stream));
+        st.part = 1;
+        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStep, k, c->grid, c->block, st));
+        HIP_TRY(hipEventRecord(e1, c->stream));
+        st.part = 2;
+        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStep, k, c->grid, c->block, st));
+        HIP_TRY(hipEventRecord(e2, c->stream));
+        HIP_TRY(hipEventSynchronize(e2));
+        float a = 0.0f, b = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&a, e0, e1));
+        HIP_TRY(hipEventElapsedTime(&b, e1, e2));
+        ti += a;
+        tb += b;
+        c->cur ^= 1;
+        c->level += 1;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    *ms_interior = ti;
+    *ms_boundary = tb;
+    return rc;
+}
+
+int lbfd_cell_counts(const lbfd_ctx *c, int64_t *n_fluid, int64_t *n_boundary)
+{
+    if (!c || !n_fluid || !n_boundary) return fail(LBFD_EINVAL, "null argument");
+    *n_fluid = c->n_fluid;
+    *n_boundary = c->n_boundary;
+    return LBFD_OK;
 }
 
 void lbfd_destroy(lbfd_ctx *c)

@@ -74,6 +74,7 @@ struct Streams {
     hipStream_t main;
     hipStream_t side;
     hipEvent_t fork, join;
+    int part;  // 0: both kernels, 1: interior kernel only, 2: boundary kernel only (on main)
 };
 
 // Launchers (instantiated in inst/*.hip, dispatched in lbfd_dispatch.hip).

@@ -950,20 +950,22 @@ hipError_t launch_pair(const KParams &kp, dim3 grid, dim3 block, const Streams &
 {
     hipError_t e = hipSuccess;
     {
-        const bool side = st.side != nullptr && kp.n_boundary > 0;
+        const bool side = st.part == 0 && st.side != nullptr && kp.n_boundary > 0;
         if (side) {
             if ((e = hipEventRecord(st.fork, st.main)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(st.side, st.fork, 0)) != hipSuccess) return e;
         }
         // the boundary kernel (few, long-latency blocks) is queued first so
         // that its blocks are resident while the interior blocks stream
-        if (kp.n_boundary > 0) {
+        if (kp.n_boundary > 0 && st.part != 1) {
             const unsigned nb = (unsigned)((kp.n_boundary + kBlock - 1) / kBlock);
             step_kernel<Q, NSP, PREC, MODE, false><<<dim3(nb), dim3(kBlock), 0, side ? st.side : st.main>>>(kp);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
-        step_kernel<Q, NSP, PREC, MODE, true><<<grid, block, 0, st.main>>>(kp);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (st.part != 2) {
+            step_kernel<Q, NSP, PREC, MODE, true><<<grid, block, 0, st.main>>>(kp);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
         if (side) {
             if ((e = hipEventRecord(st.join, st.side)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(st.main, st.join, 0)) != hipSuccess) return e;

@@ -25,7 +25,8 @@ ERRORS = {0: "LBFD_OK", -1: "LBFD_EINVAL", -2: "LBFD_ENOMEM", -3: "LBFD_EDEVICE"
 
 EXPORTS = ("lbfd_init", "lbfd_step", "lbfd_sync", "lbfd_level", "lbfd_read_fields",
            "lbfd_diagnostics", "lbfd_set_wall_temperature", "lbfd_state_size",
-           "lbfd_save_state", "lbfd_load_state", "lbfd_time_steps", "lbfd_destroy",
+           "lbfd_save_state", "lbfd_load_state", "lbfd_time_steps", "lbfd_time_kernels",
+           "lbfd_cell_counts", "lbfd_destroy",
            "lbfd_strerror", "lbfd_last_error")
 
 
@@ -87,6 +88,8 @@ def load_library():
     lib.lbfd_save_state.argtypes = [vp, vp, C.c_size_t]
     lib.lbfd_load_state.argtypes = [vp, vp, C.c_size_t]
     lib.lbfd_time_steps.argtypes = [vp, C.c_int64, dp]
+    lib.lbfd_time_kernels.argtypes = [vp, C.c_int64, dp, dp]
+    lib.lbfd_cell_counts.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.lbfd_destroy.argtypes = [vp]
     lib.lbfd_destroy.restype = None
     lib.lbfd_strerror.argtypes = [C.c_int]
@@ -199,6 +202,18 @@ class Solver:
         ms = C.c_double()
         _check(self._lib, self._lib.lbfd_time_steps(self._h, int(n), C.byref(ms)))
         return ms.value
+
+    def time_kernels(self, n: int) -> tuple:
+        """(ms interior kernel, ms boundary kernel) summed over n serialised steps."""
+        a, b = C.c_double(), C.c_double()
+        _check(self._lib, self._lib.lbfd_time_kernels(self._h, int(n), C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def cell_counts(self) -> tuple:
+        """(fluid cells, boundary-kernel cells)."""
+        a, b = C.c_int64(), C.c_int64()
+        _check(self._lib, self._lib.lbfd_cell_counts(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def fields(self) -> dict:
         pr = self.prob
