@@ -193,6 +193,32 @@ int lbfd_load_state(lbfd_ctx *c, const void *blob, size_t bytes);
  * milliseconds in *ms. */
 int lbfd_time_steps(lbfd_ctx *c, int64_t nsteps, double *ms);
 
+/* Replace the Arrhenius parameters of reaction j (A [1/s], b, Ta [K]). */
+int lbfd_set_reaction(lbfd_ctx *c, int j, double A, double b, double Ta);
+
+/* Forward only: run nsteps steps from the current level L and return
+ * J = sum_{n = L}^{L + nsteps - 1} wall_q(level n) (the objective of
+ * lbfd_adjoint). */
+int lbfd_objective(lbfd_ctx *c, int64_t nsteps, double *J);
+
+/* Discrete adjoint of the FP64 step (the paper's differentiation use of the
+ * solver; objective: the time-integrated wall heat flux).  Starting from the
+ * current level L, runs nsteps steps and computes
+ *   J = sum_{n = L}^{L + nsteps - 1} wall_q(level n)
+ * (wall_q as in lbfd_diag) and its exact derivatives with respect to the
+ * wall temperature of every isothermal solid cell (dJ_dwallT [N], host, may
+ * be NULL; zero at other cells) and the Arrhenius A and Ta of every reaction
+ * (dJ_dA, dJ_dTa [n_reactions], host, may be NULL).  Checkpoints are taken
+ * every K steps and each segment is recomputed once during the backward
+ * sweep (device memory: about (nsteps/K + K + 4) states).  On return the
+ * context is at level L + nsteps, as after lbfd_step(nsteps).  Requires FP64
+ * precision, no OUTFLOW face, and a lattice/species combination with an
+ * adjoint kernel (D2Q9 or D3Q27 with 4 species); LBFD_EINVAL otherwise.
+ * Contributions are accumulated with atomic adds, so results may differ in
+ * the last bits between runs. */
+int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwallT, double *dJ_dA,
+                 double *dJ_dTa);
+
 /* Per-kernel timing: queue nsteps steps with the interior-cell kernel and
  * the boundary-cell kernel serialised on the context stream, each bracketed
  * by HIP events; wait and return their summed durations in milliseconds.

@@ -231,6 +231,15 @@ class Oracle:
                 "hrr_idx": int(out[8]), "hrr_max": out[9], "wall_q": out[10],
                 "fuel_rate": out[11]}
 
+    def objective(self, nsteps: int) -> float:
+        """Time-integrated wall heat flux: the sum over the next nsteps levels
+        of the wall heat flux diagnostic (evaluated before each step)."""
+        J = 0.0
+        for _ in range(int(nsteps)):
+            J += self.diagnostics()["wall_q"]
+            self.step(1)
+        return J
+
     def pops(self) -> np.ndarray:
         pr = self.prob
         g = np.empty(pr.lattice * self.N)

@@ -28,7 +28,8 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
 
 
 def sources() -> list[str]:
-    return ([os.path.join(CSRC, "lbfd_api.hip"), os.path.join(CSRC, "lbfd_dispatch.hip")]
+    return ([os.path.join(CSRC, "lbfd_api.hip"), os.path.join(CSRC, "lbfd_dispatch.hip"),
+             os.path.join(CSRC, "lbfd_adjoint.hip")]
             + sorted(glob.glob(os.path.join(CSRC, "inst", "*.hip"))))
 
 

@@ -759,6 +759,152 @@ int lbfd_time_kernels(lbfd_ctx *c, int64_t nsteps, double *ms_interior, double *
     return rc;
 }
 
+int lbfd_set_reaction(lbfd_ctx *c, int j, double A, double b, double Ta)
+{
+    if (!c || j < 0 || j >= c->p.n_reactions) return fail(LBFD_EINVAL, "bad reaction index");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->rx[j].A = A;
+    c->rx[j].b = b;
+    c->rx[j].Ta = Ta;
+    HIP_TRY(hipMemcpy(c->rx_dev + j, &c->rx[j], sizeof(lbfd_reaction), hipMemcpyHostToDevice));
+    return LBFD_OK;
+}
+
+namespace {
+// device buffers owned by one lbfd_adjoint call
+struct AdjBuffers {
+    std::vector<void *> ptrs;
+    ~AdjBuffers()
+    {
+        for (void *q : ptrs) (void)hipFree(q);
+    }
+    void *get(size_t bytes)
+    {
+        void *q = nullptr;
+        if (hipMalloc(&q, bytes ? bytes : 1) != hipSuccess) return nullptr;
+        ptrs.push_back(q);
+        return q;
+    }
+};
+}  // namespace
+
+int lbfd_objective(lbfd_ctx *c, int64_t nsteps, double *J)
+{
+    if (!c || !J || nsteps < 0) return fail(LBFD_EINVAL, "bad arguments");
+    double *Jd = nullptr;
+    if (hipMalloc((void **)&Jd, sizeof(double)) != hipSuccess) return fail(LBFD_ENOMEM, "hipMalloc failed");
+    hipError_t e = hipMemsetAsync(Jd, 0, sizeof(double), c->stream);
+    for (int64_t n = 0; n < nsteps && e == hipSuccess; ++n) {
+        KParams k = c->base;
+        k.pop_in = c->pop[c->cur];
+        k.pop_out = c->pop[1 - c->cur];
+        k.sc_in = c->sc[c->cur];
+        k.sc_out = c->sc[1 - c->cur];
+        e = launch_step(c->Q, c->nsp, c->prec, kModeStepDiag, k, c->grid, c->block, c->streams);
+        if (e == hipSuccess) e = launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream);
+        if (e == hipSuccess) e = launch_accumulate(Jd, c->diag_dev + kWallQ, c->stream);
+        c->cur ^= 1;
+        c->level += 1;
+    }
+    if (e == hipSuccess) e = hipMemcpy(J, Jd, sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(Jd);
+    if (e != hipSuccess) return fail(LBFD_EDEVICE, "objective: %s", hipGetErrorString(e));
+    return LBFD_OK;
+}
+
+int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwallT, double *dJ_dA,
+                 double *dJ_dTa)
+{
+    if (!c || nsteps < 1 || K < 1) return fail(LBFD_EINVAL, "bad arguments");
+    if (c->prec != LBFD_FP64) return fail(LBFD_EINVAL, "the adjoint needs FP64 precision");
+    if (!adjoint_supported(c->Q, c->nsp))
+        return fail(LBFD_EINVAL, "no adjoint kernel for lattice %d with %d species", c->Q, c->nsp);
+    for (int f = 0; f < 6; ++f)
+        if (c->p.face[f] == LBFD_FACE_OUTFLOW) return fail(LBFD_EINVAL, "the adjoint does not support OUTFLOW faces");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const long long N = c->N;
+    const int Q = c->Q, ns = c->nsp, nrx = c->p.n_reactions;
+    const size_t pop_b = (size_t)Q * N * sizeof(double), sc_b = (size_t)(1 + ns) * N * sizeof(double);
+    const int64_t nseg = (nsteps + K - 1) / K;
+    const int kseg = (int)(nsteps < K ? nsteps : K);
+    AdjBuffers mem;
+    char *ckpt = (char *)mem.get((size_t)nseg * (pop_b + sc_b));
+    char *segs = (char *)mem.get((size_t)kseg * (pop_b + sc_b));
+    double *lam[2], *lsc[2];
+    for (int b = 0; b < 2; ++b) {
+        lam[b] = (double *)mem.get(pop_b);
+        lsc[b] = (double *)mem.get(sc_b);
+    }
+    double *dW = (double *)mem.get(N * sizeof(double));
+    double *dP = (double *)mem.get(2 * LBFD_MAX_REACTIONS * sizeof(double));
+    double *Jd = (double *)mem.get(sizeof(double));
+    if (!ckpt || !segs || !lam[0] || !lam[1] || !lsc[0] || !lsc[1] || !dW || !dP || !Jd)
+        return fail(LBFD_ENOMEM, "adjoint: device allocation failed");
+    auto ck_pop = [&](int64_t s) { return ckpt + (size_t)s * (pop_b + sc_b); };
+    auto ck_sc = [&](int64_t s) { return ckpt + (size_t)s * (pop_b + sc_b) + pop_b; };
+    auto sg_pop = [&](int64_t s) { return segs + (size_t)s * (pop_b + sc_b); };
+    auto sg_sc = [&](int64_t s) { return segs + (size_t)s * (pop_b + sc_b) + pop_b; };
+
+    // forward pass: checkpoints and the objective
+    HIP_TRY(hipMemsetAsync(Jd, 0, sizeof(double), c->stream));
+    for (int64_t n = 0; n < nsteps; ++n) {
+        if (n % K == 0) {
+            HIP_TRY(hipMemcpyAsync(ck_pop(n / K), c->pop[c->cur], pop_b, hipMemcpyDeviceToDevice, c->stream));
+            HIP_TRY(hipMemcpyAsync(ck_sc(n / K), c->sc[c->cur], sc_b, hipMemcpyDeviceToDevice, c->stream));
+        }
+        KParams k = c->base;
+        k.pop_in = c->pop[c->cur];
+        k.pop_out = c->pop[1 - c->cur];
+        k.sc_in = c->sc[c->cur];
+        k.sc_out = c->sc[1 - c->cur];
+        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStepDiag, k, c->grid, c->block, c->streams));
+        HIP_TRY(launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream));
+        HIP_TRY(launch_accumulate(Jd, c->diag_dev + kWallQ, c->stream));
+        c->cur ^= 1;
+        c->level += 1;
+    }
+
+    // backward sweep over segments, each recomputed from its checkpoint
+    HIP_TRY(hipMemsetAsync(lam[0], 0, pop_b, c->stream));
+    HIP_TRY(hipMemsetAsync(lsc[0], 0, sc_b, c->stream));
+    HIP_TRY(hipMemsetAsync(dW, 0, N * sizeof(double), c->stream));
+    HIP_TRY(hipMemsetAsync(dP, 0, 2 * LBFD_MAX_REACTIONS * sizeof(double), c->stream));
+    int nxt = 0;  // lam[nxt], lsc[nxt]: adjoint of level n+1
+    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+        const int64_t n0 = seg * K, n1 = (n0 + K < nsteps) ? n0 + K : nsteps;
+        HIP_TRY(hipMemcpyAsync(sg_pop(0), ck_pop(seg), pop_b, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(sg_sc(0), ck_sc(seg), sc_b, hipMemcpyDeviceToDevice, c->stream));
+        for (int64_t n = n0; n < n1 - 1; ++n) {
+            KParams k = c->base;
+            k.pop_in = sg_pop(n - n0);
+            k.pop_out = sg_pop(n - n0 + 1);
+            k.sc_in = sg_sc(n - n0);
+            k.sc_out = sg_sc(n - n0 + 1);
+            HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStep, k, c->grid, c->block, c->streams));
+        }
+        for (int64_t n = n1 - 1; n >= n0; --n) {
+            const int cu = 1 - nxt;
+            HIP_TRY(hipMemsetAsync(lam[cu], 0, pop_b, c->stream));
+            HIP_TRY(hipMemsetAsync(lsc[cu], 0, sc_b, c->stream));
+            KParams k = c->base;
+            k.pop_in = sg_pop(n - n0);
+            k.sc_in = sg_sc(n - n0);
+            HIP_TRY(launch_adjoint(c->Q, c->nsp, k, lam[nxt], lsc[nxt], lam[cu], lsc[cu], dW, dP, c->stream));
+            nxt = cu;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double hP[2 * LBFD_MAX_REACTIONS];
+    HIP_TRY(hipMemcpy(hP, dP, sizeof(hP), hipMemcpyDeviceToHost));
+    if (J) HIP_TRY(hipMemcpy(J, Jd, sizeof(double), hipMemcpyDeviceToHost));
+    if (dJ_dwallT) HIP_TRY(hipMemcpy(dJ_dwallT, dW, N * sizeof(double), hipMemcpyDeviceToHost));
+    for (int j = 0; j < nrx; ++j) {
+        if (dJ_dA) dJ_dA[j] = hP[2 * j];
+        if (dJ_dTa) dJ_dTa[j] = hP[2 * j + 1];
+    }
+    return LBFD_OK;
+}
+
 int lbfd_cell_counts(const lbfd_ctx *c, int64_t *n_fluid, int64_t *n_boundary)
 {
     if (!c || !n_fluid || !n_boundary) return fail(LBFD_EINVAL, "null argument");

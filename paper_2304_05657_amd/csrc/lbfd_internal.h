@@ -86,4 +86,10 @@ hipError_t launch_finalize(const double *partials, int nblocks, double *out,
                            long long *first_bad, long long level, hipStream_t s);
 bool supported(int Q, int nsp, int prec);
 
+// Adjoint (lbfd_adjoint.hip): one backward step of the FP64 coupled step.
+bool adjoint_supported(int Q, int nsp);
+hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_pop_next, const double *lam_sc_next,
+                          double *lam_pop, double *lam_sc, double *dwallT, double *dparam, hipStream_t s);
+hipError_t launch_accumulate(double *acc, const double *v, hipStream_t s);
+
 }  // namespace lbfd

@@ -26,7 +26,7 @@ ERRORS = {0: "LBFD_OK", -1: "LBFD_EINVAL", -2: "LBFD_ENOMEM", -3: "LBFD_EDEVICE"
 EXPORTS = ("lbfd_init", "lbfd_step", "lbfd_sync", "lbfd_level", "lbfd_read_fields",
            "lbfd_diagnostics", "lbfd_set_wall_temperature", "lbfd_state_size",
            "lbfd_save_state", "lbfd_load_state", "lbfd_time_steps", "lbfd_time_kernels",
-           "lbfd_cell_counts", "lbfd_destroy",
+           "lbfd_cell_counts", "lbfd_set_reaction", "lbfd_objective", "lbfd_adjoint", "lbfd_destroy",
            "lbfd_strerror", "lbfd_last_error")
 
 
@@ -90,6 +90,9 @@ def load_library():
     lib.lbfd_time_steps.argtypes = [vp, C.c_int64, dp]
     lib.lbfd_time_kernels.argtypes = [vp, C.c_int64, dp, dp]
     lib.lbfd_cell_counts.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.lbfd_set_reaction.argtypes = [vp, C.c_int, C.c_double, C.c_double, C.c_double]
+    lib.lbfd_objective.argtypes = [vp, C.c_int64, dp]
+    lib.lbfd_adjoint.argtypes = [vp, C.c_int64, C.c_int, dp, dp, dp, dp]
     lib.lbfd_destroy.argtypes = [vp]
     lib.lbfd_destroy.restype = None
     lib.lbfd_strerror.argtypes = [C.c_int]
@@ -215,6 +218,27 @@ class Solver:
         _check(self._lib, self._lib.lbfd_cell_counts(self._h, C.byref(a), C.byref(b)))
         return a.value, b.value
 
+    def set_reaction(self, j: int, A: float, b: float, Ta: float):
+        _check(self._lib, self._lib.lbfd_set_reaction(self._h, int(j), float(A), float(b), float(Ta)))
+
+    def objective(self, nsteps: int) -> float:
+        """Time-integrated wall heat flux over the next nsteps levels (forward only)."""
+        J = C.c_double()
+        _check(self._lib, self._lib.lbfd_objective(self._h, int(nsteps), C.byref(J)))
+        return J.value
+
+    def adjoint(self, nsteps: int, K: int):
+        """(J, dJ/dwall_T [nz, ny, nx], dJ/dA [n_rx], dJ/dTa [n_rx]) over the next
+        nsteps levels, checkpointing every K steps."""
+        pr = self.prob
+        J = C.c_double()
+        gW = np.zeros(self.N)
+        nrx = max(1, len(pr.reactions))
+        gA, gTa = np.zeros(nrx), np.zeros(nrx)
+        _check(self._lib, self._lib.lbfd_adjoint(self._h, int(nsteps), int(K), C.byref(J), _dp(gW), _dp(gA),
+                                                 _dp(gTa)))
+        return J.value, gW.reshape((pr.nz, pr.ny, pr.nx)), gA[: len(pr.reactions)], gTa[: len(pr.reactions)]
+
     def fields(self) -> dict:
         pr = self.prob
         shp = (pr.nz, pr.ny, pr.nx)
@@ -260,3 +284,29 @@ def _torch_stream():
     if not torch.cuda.is_available():
         return 0
     return int(torch.cuda.current_stream().cuda_stream)
+
+
+def wall_heat_flux_objective(solver: Solver, state: bytes, nsteps: int, K: int, wall_T, A, Ta):
+    """Differentiable time-integrated wall heat flux J(wall_T, A, Ta) of
+    reaction 0 over nsteps steps from the checkpoint `state`, as a torch
+    scalar; its backward uses the library's discrete adjoint."""
+    import torch
+
+    class _WallHeatFlux(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, wall_T, A, Ta):
+            solver.load_state(state)
+            solver.set_wall_temperature(wall_T.detach().to(torch.float64).cpu().numpy())
+            r = solver.prob.reactions[0]
+            solver.set_reaction(0, float(A), r.b, float(Ta))
+            J, gW, gA, gTa = solver.adjoint(nsteps, K)
+            ctx.save_for_backward(torch.from_numpy(gW).to(wall_T.dtype), torch.tensor(gA[0], dtype=A.dtype),
+                                  torch.tensor(gTa[0], dtype=Ta.dtype))
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            gW, gA, gTa = ctx.saved_tensors
+            return gJ.to(gW.dtype) * gW, gJ.to(gA.dtype) * gA, gJ.to(gTa.dtype) * gTa
+
+    return _WallHeatFlux.apply(wall_T, A, Ta)

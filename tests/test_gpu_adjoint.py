@@ -1,0 +1,172 @@
+"""Discrete adjoint of the FP64 step: gradients of the time-integrated wall
+heat flux J with respect to the wall temperature field and the Arrhenius
+A, Ta, checked against central finite differences of the GPU forward
+(eps = 1e-6 relative, FP64), against central finite differences of the
+oracle (CPU reference gradient), and through torch.autograd.
+
+Tolerance: 1e-5 relative (central differences carry O(eps^2) truncation and
+~1e-16 J / eps round-off, i.e. < 1e-8 here; the adjoint differs from the
+forward kernels only by rounding)."""
+import numpy as np
+import pytest
+
+from paper_2304_05657_amd import workloads as W
+
+from .gpu_util import need_gpu, oracle_threads, say
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-5
+
+
+def _fd_params(s, state, prob, nsteps, eps=1e-6):
+    r = prob.reactions[0]
+    out = []
+    for which in ("A", "Ta"):
+        vals = []
+        for sg in (1, -1):
+            s.load_state(state)
+            A = r.A * (1 + sg * eps) if which == "A" else r.A
+            Ta = r.Ta * (1 + sg * eps) if which == "Ta" else r.Ta
+            s.set_reaction(0, A, r.b, Ta)
+            vals.append(s.objective(nsteps))
+        h = (r.A if which == "A" else r.Ta) * eps
+        out.append((vals[0] - vals[1]) / (2 * h))
+    s.set_reaction(0, r.A, r.b, r.Ta)
+    return out
+
+
+def _fd_wall(s, state, prob, nsteps, direction, eps_T=3e-4):
+    vals = []
+    for sg in (1, -1):
+        s.load_state(state)
+        s.set_wall_temperature(prob.wall_T + sg * eps_T * direction)
+        vals.append(s.objective(nsteps))
+    s.set_wall_temperature(prob.wall_T)
+    return (vals[0] - vals[1]) / (2 * eps_T)
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def _check_case(prob, nsteps, K, n_cells, n_dirs, seed):
+    from paper_2304_05657_amd.lbfd import Solver
+    need_gpu()
+    s = Solver(prob)
+    state = s.save_state()
+    import time
+    t0 = time.perf_counter()
+    J, gW, gA, gTa = s.adjoint(nsteps, K)
+    t_adj = time.perf_counter() - t0
+    s.load_state(state)
+    J2 = s.objective(nsteps)
+    say("  J=%.12e (forward %.12e), adjoint %.2f s" % (J, J2, t_adj))
+    assert _rel(J, J2) < 1e-12
+    # eps = 1e-6: the FD numerator J(+) - J(-) can be as small as 1e-11 |J|,
+    # where the round-off of J (~1e-15 |J| per evaluation) is a 1e-4-level
+    # noise; the bound adds that floor.  eps = 1e-4 lowers the floor 100x
+    # (truncation O(eps^2) ~ 1e-8) and is held to RTOL alone.
+    r = prob.reactions[0]
+    for eps in (1e-6, 1e-4):
+        fA, fTa = _fd_params(s, state, prob, nsteps, eps)
+        say("  eps %.0e: dJ/dA adjoint %.10e fd %.10e rel %.2e" % (eps, gA[0], fA, _rel(gA[0], fA)))
+        say("  eps %.0e: dJ/dTa adjoint %.10e fd %.10e rel %.2e" % (eps, gTa[0], fTa, _rel(gTa[0], fTa)))
+        floor_A = 4e-15 * abs(J) / (2 * r.A * eps) if eps < 1e-5 else 0.0
+        floor_Ta = 4e-15 * abs(J) / (2 * r.Ta * eps) if eps < 1e-5 else 0.0
+        assert abs(gA[0] - fA) <= RTOL * abs(fA) + floor_A
+        assert abs(gTa[0] - fTa) <= RTOL * abs(fTa) + floor_Ta
+    rng = np.random.default_rng(seed)
+    walls = np.argwhere(prob.mask == 1)
+    nz = [tuple(w) for w in walls if abs(gW[tuple(w)]) > 1e-3 * np.abs(gW).max()]
+    pick = [nz[i] for i in rng.choice(len(nz), size=min(n_cells, len(nz)), replace=False)]
+    for w in pick:
+        d = np.zeros_like(prob.wall_T)
+        d[w] = 1.0
+        fd = _fd_wall(s, state, prob, nsteps, d)
+        say("  dJ/dTw%s adjoint %.10e fd %.10e rel %.2e" % (w, gW[w], fd, _rel(gW[w], fd)))
+        assert _rel(gW[w], fd) < RTOL
+    for _ in range(n_dirs):
+        d = np.where(prob.mask == 1, rng.normal(size=prob.wall_T.shape), 0.0)
+        fd = _fd_wall(s, state, prob, nsteps, d)
+        ad = float((gW * d).sum())
+        # a random direction sums hundreds of terms of both signs: compare
+        # relative to the magnitude of the summed terms
+        scale = float(np.abs(gW * d).sum())
+        say("  direction: adjoint %.10e fd %.10e diff/sum|terms| %.2e" % (ad, fd, abs(ad - fd) / scale))
+        assert abs(ad - fd) < RTOL * scale
+    # only isothermal wall cells carry a gradient
+    assert np.all(gW[prob.mask != 1] == 0.0)
+    return J, gW, gA, gTa
+
+
+def test_adjoint_small_channel_vs_gpu_fd():
+    prob = W.channel_flame(nx=96, ny=24, front_x=30.0, name="adj_channel_96x24")
+    say("case adjoint channel 96x24, 40 steps, K=8")
+    _check_case(prob, 40, 8, 4, 2, seed=1)
+
+
+def test_adjoint_3d_vs_gpu_fd():
+    prob = W.porous_3d(nx=24, ny=12, nz=12, porosity=0.9, radius=3.0, margin=4, front_x=12.0, name="adj_porous")
+    prob = prob.replace(faces=("periodic",) * 6)
+    say("case adjoint D3Q27 closed porous 24x12x12, 12 steps, K=5")
+    _check_case(prob, 12, 5, 3, 1, seed=2)
+
+
+def test_adjoint_vs_oracle_reference_gradient():
+    """CPU reference gradient: central differences of the oracle's J."""
+    import oracle
+    from paper_2304_05657_amd.lbfd import Solver
+    need_gpu()
+    prob = W.channel_flame(nx=64, ny=16, front_x=20.0, name="adj_channel_64x16")
+    nsteps, K, eps = 30, 7, 1e-6
+    say("case adjoint vs oracle, channel 64x16, %d steps, K=%d" % (nsteps, K))
+    s = Solver(prob)
+    J, gW, gA, gTa = s.adjoint(nsteps, K)
+    Jo = oracle.Oracle(prob, threads=oracle_threads()).objective(nsteps)
+    assert _rel(J, Jo) < 1e-10, (J, Jo)
+    r = prob.reactions[0]
+
+    def oJ(A=r.A, Ta=r.Ta, wall_T=None):
+        p = prob.replace(reactions=[W.Reaction(r.reactants, A, r.b, Ta, r.nu, r.q)],
+                         wall_T=prob.wall_T if wall_T is None else wall_T)
+        return oracle.Oracle(p, threads=oracle_threads()).objective(nsteps)
+
+    fA = (oJ(A=r.A * (1 + eps)) - oJ(A=r.A * (1 - eps))) / (2 * r.A * eps)
+    fTa = (oJ(Ta=r.Ta * (1 + eps)) - oJ(Ta=r.Ta * (1 - eps))) / (2 * r.Ta * eps)
+    w = (0, 0, 40)
+    wt_p, wt_m = prob.wall_T.copy(), prob.wall_T.copy()
+    wt_p[w] += 3e-4
+    wt_m[w] -= 3e-4
+    fW = (oJ(wall_T=wt_p) - oJ(wall_T=wt_m)) / 6e-4
+    say("  A: gpu adjoint %.10e oracle fd %.10e; Ta: %.10e / %.10e; Tw%s: %.10e / %.10e" % (
+        gA[0], fA, gTa[0], fTa, w, gW[w], fW))
+    assert _rel(gA[0], fA) < RTOL and _rel(gTa[0], fTa) < RTOL and _rel(gW[w], fW) < RTOL
+
+
+def test_autograd_function():
+    import torch
+    from paper_2304_05657_amd.lbfd import Solver, wall_heat_flux_objective
+    need_gpu()
+    prob = W.channel_flame(nx=64, ny=16, front_x=20.0, name="adj_autograd")
+    say("case adjoint through torch.autograd")
+    s = Solver(prob)
+    state = s.save_state()
+    wT = torch.tensor(prob.wall_T, dtype=torch.float32, requires_grad=True)
+    A = torch.tensor(prob.reactions[0].A, dtype=torch.float64, requires_grad=True)
+    Ta = torch.tensor(prob.reactions[0].Ta, dtype=torch.float64, requires_grad=True)
+    J = wall_heat_flux_objective(s, state, 20, 6, wT, A, Ta)
+    J.backward()
+    s.load_state(state)
+    J2, gW, gA, gTa = s.adjoint(20, 6)
+    assert abs(J.item() - J2) <= 1e-12 * abs(J2)
+    assert abs(A.grad.item() - gA[0]) <= 1e-12 * abs(gA[0])
+    assert abs(Ta.grad.item() - gTa[0]) <= 1e-12 * abs(gTa[0])
+    assert np.allclose(wT.grad.numpy(), gW.astype(np.float32), rtol=1e-6, atol=0)
+
+
+def test_adjoint_channel_1024x256_500_steps():
+    """The differentiation workload: channel 1024x256, 500 steps, K = 25;
+    FD checks on A, Ta, 8 random wall cells and 4 random directions."""
+    prob = W.named("channel_adjoint")
+    say("case adjoint channel 1024x256, 500 steps, K=25")
+    _check_case(prob, 500, 25, 8, 4, seed=3)
