@@ -1,17 +1,21 @@
 """Benchmark of the coupled LB/FD step on one MI355X.
 
-Workload: the pseudo 2-D porous burner, D2Q9, 2048 x 512 cells, staggered
-cylinders (radius 20, pitch 64) at 400 K, lean inflow at u = 0.02, outflow,
-4 species / 1 reaction -- synthetic, seeded inputs built by
-``paper_2304_05657_amd.workloads.cylinder_burner``.
+Default workload: the pseudo 2-D porous burner, D2Q9, 2048 x 512 cells,
+staggered cylinders (radius 20, pitch 64) at 400 K, lean inflow at
+u = 0.02, outflow, 4 species / 1 reaction -- synthetic, seeded inputs built
+by ``paper_2304_05657_amd.workloads.cylinder_burner``.  ``--workload``
+selects another of ``workloads.named`` (``porous``: D3Q27 256^3 sphere
+packing; ``porous_mech``: D3Q27 512 x 256^2, 9 species / 20 reactions).
 
 Prints one JSON line.  ``value`` is the FP64 step's throughput in MLUPS
 (all cells of the box per second), with every input resident in HBM before
 the timed region; the mixed-precision forms are reported beside it.
-``roofline`` is for the step kernel: algorithmic bytes per launch (per fluid
-cell 2 Q b_pop + 2 (1 + N_sp) b_scalar, plus 1 byte of mask per cell) over
-the launch duration measured with HIP events on the stream the kernel runs
-on.  ``cpu_baseline`` times the FP64 oracle (test infrastructure) on the
+``roofline`` is for the dominant kernel (the single step launch in 2-D, the
+interior-cell launch in 3-D): algorithmic flops per launch against the
+vector-ALU peak, with the algorithmic bytes per launch (per fluid cell
+2 Q b_pop + 2 (1 + N_sp) b_scalar, plus 1 byte of mask per cell) beside
+them, over the launch duration measured with HIP events on the stream the
+kernel runs on.  ``cpu_baseline`` times the FP64 oracle (test infrastructure) on the
 host cores for a bounded number of steps of the same workload.
 """
 from __future__ import annotations
@@ -32,11 +36,12 @@ HBM_PEAK_GBS = 8000.0
 # Both FP64 and FP32 issue at this rate: packed FP32 is not used.
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2304_05657_amd", "csrc", "lbfd_kernels.h")
-# HBM bytes per launch of the interior kernel on this workload, from two
+# HBM bytes per launch of the dominant kernel on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by
 # the same counters on a plain 512 MiB device copy (FETCH_SIZE reads 0.5x,
 # WRITE_SIZE 1.0x the copied bytes), valid for the kernel source whose
 # SHA-256 is given (profiles/traffic_step_kernels_burner_2048x512.md).
+TRAFFIC_WORKLOAD = "cylinder_burner_2048x512"
 TRAFFIC = {
     "fp64": {"kernel_sha256": "2314322f5f9f6f7c1f0f738f09b1b2b15d7484709e8291c43c4f64f6a6d18748", "bytes_per_launch": 219.8e6},
     "fp32": {"kernel_sha256": "2314322f5f9f6f7c1f0f738f09b1b2b15d7484709e8291c43c4f64f6a6d18748", "bytes_per_launch": 132.8e6},
@@ -134,8 +139,25 @@ def run_gpu(prob, precision: str, steps: int, warmup: int) -> dict:
     per_fluid /= prob.n_fluid
     int_bytes = n_int * per_fluid + prob.N
     int_flops = n_int * algorithmic_flops_per_cell(prob)
+    launches = s.step_launches()
+    fpc = algorithmic_flops_per_cell(prob)
+    if launches == 1:
+        # one launch per step: the step kernel is the whole step, and its
+        # average launch duration is the event-timed step above
+        dominant = {"kernel": "step_kernel (one launch per step: boundary and interior cells)",
+                    "cells": n_fluid, "ms_per_launch": ms / steps, "flops": n_fluid * fpc,
+                    "algorithmic_bytes": nbytes}
+    else:
+        dominant = {"kernel": "step_kernel (interior cells)", "cells": n_int, "ms_per_launch": kms_i / steps,
+                    "flops": int_flops, "algorithmic_bytes": int_bytes}
+    t_dom = dominant["ms_per_launch"] * 1e-3
+    dominant.update({"flops_per_cell": fpc, "TFLOPs": dominant["flops"] / t_dom / 1e12,
+                     "alu_frac": dominant["flops"] / t_dom / 1e12 / VALU_PEAK_TFLOPS,
+                     "GBs": dominant["algorithmic_bytes"] / t_dom / 1e9,
+                     "hbm_frac": dominant["algorithmic_bytes"] / t_dom / 1e9 / HBM_PEAK_GBS})
     out = {
         "precision": precision, "ms_per_step": ms / steps, "wall_ms_per_step": wall * 1e3 / steps,
+        "launches_per_step": launches, "dominant_kernel": dominant,
         "mlups": prob.N / per_step_s / 1e6, "mflups": prob.n_fluid / per_step_s / 1e6,
         "algorithmic_bytes_per_step": nbytes, "achieved_GBs": achieved,
         "hbm_frac": achieved / HBM_PEAK_GBS, "finite": ok,
@@ -163,22 +185,24 @@ def run_cpu_baseline(prob, budget_s: float) -> dict:
         if el >= budget_s or n >= 200:
             break
     return {"value": prob.N * n / el / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": "%d FP64 steps of the same %dx%d burner from its initial state (after one untimed "
-                      "step), %.1f s" % (n, prob.nx, prob.ny, el)}
+            "sample": "%d FP64 steps of the same workload (%s) from its initial state (after one untimed "
+                      "step), %.1f s" % (n, prob.name, el)}
 
 
-def roofline(res: dict, precision: str) -> dict:
-    """Roofline of the dominant kernel (interior cells): it is bound by the
-    vector ALU (instruction issue), so achieved is algorithmic TFLOP/s
-    against the VALU peak; its HBM rate is given beside it."""
-    ik = res["interior_kernel"]
-    t = TRAFFIC.get(precision)
+def roofline(res: dict, precision: str, workload: str) -> dict:
+    """Roofline of the dominant kernel (the one step launch in 2-D, the
+    interior-cell launch in 3-D): it is bound by the vector ALU (instruction
+    issue), so achieved is algorithmic TFLOP/s against the VALU peak; its
+    HBM rate is given beside it."""
+    dk = res["dominant_kernel"]
+    t = TRAFFIC.get(precision) if workload == TRAFFIC_WORKLOAD else None
     traffic = t["bytes_per_launch"] if t and t.get("kernel_sha256") == kernel_sha() else None
-    return {"kernel": "step_kernel (interior cells)", "bound": "alu", "achieved": ik["TFLOPs"],
-            "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ik["alu_frac"], "traffic": traffic,
-            "hbm_achieved_GBs": ik["GBs"], "hbm_peak_GBs": HBM_PEAK_GBS, "hbm_frac": ik["hbm_frac"],
-            "launch_ms": ik["ms_per_launch"], "algorithmic_flops_per_cell": ik["flops_per_cell"],
-            "algorithmic_bytes_per_launch": ik["algorithmic_bytes"]}
+    return {"kernel": dk["kernel"], "bound": "alu", "achieved": dk["TFLOPs"],
+            "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": dk["alu_frac"], "traffic": traffic,
+            "hbm_achieved_GBs": dk["GBs"], "hbm_peak_GBs": HBM_PEAK_GBS, "hbm_frac": dk["hbm_frac"],
+            "launch_ms": dk["ms_per_launch"], "cells_per_launch": dk["cells"],
+            "algorithmic_flops_per_cell": dk["flops_per_cell"],
+            "algorithmic_bytes_per_launch": dk["algorithmic_bytes"]}
 
 
 def main():
@@ -190,8 +214,11 @@ def main():
                     help="first entry is the headline value, the others are reported beside it")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--accuracy-steps", type=int, default=20000,
-                    help="level at which the mixed-precision runs are compared with the FP64 run (0: skip)")
+    ap.add_argument("--workload", default="burner",
+                    help="burner (default), channel, porous or porous_mech")
+    ap.add_argument("--accuracy-steps", type=int, default=None,
+                    help="level at which the mixed-precision runs are compared with the FP64 run "
+                         "(0: skip; default 20000 for the burner, 2000 otherwise)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 512 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -205,7 +232,9 @@ def main():
         sys.exit(3)
     from paper_2304_05657_amd import workloads as W
 
-    prob = W.cylinder_burner()
+    prob = W.named(args.workload)
+    if args.accuracy_steps is None:
+        args.accuracy_steps = 20000 if args.workload == "burner" else 2000
     precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
     results = {}
     ref = None
@@ -256,9 +285,9 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[precs[0]],
         "data": "synthetic",
-        "config": {"workload": prob.name, "lattice": "D2Q9", "cells": prob.N, "fluid_cells": prob.n_fluid,
+        "config": {"workload": prob.name, "lattice": "D2Q9" if prob.lattice == 9 else "D3Q27", "cells": prob.N, "fluid_cells": prob.n_fluid,
                    "species": prob.n_species, "reactions": len(prob.reactions), "storage": precs[0]},
-        "roofline": roofline(head, precs[0]),
+        "roofline": roofline(head, precs[0], prob.name),
         "cpu_baseline": cpu,
         "precisions": {p: {k: v for k, v in r.items() if k != "precision"} for p, r in results.items()},
     }

@@ -219,17 +219,23 @@ int lbfd_objective(lbfd_ctx *c, int64_t nsteps, double *J);
 int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwallT, double *dJ_dA,
                  double *dJ_dTa);
 
-/* Per-kernel timing: queue nsteps steps with the interior-cell kernel and
- * the boundary-cell kernel serialised on the context stream, each bracketed
- * by HIP events; wait and return their summed durations in milliseconds.
- * The state advances exactly as with lbfd_step. */
+/* Per-part timing: queue nsteps steps with the interior-cell part and the
+ * boundary-cell part launched separately on the context stream, each
+ * bracketed by HIP events; wait and return their summed durations in
+ * milliseconds.  The state advances exactly as with lbfd_step. */
 int lbfd_time_kernels(lbfd_ctx *c, int64_t nsteps, double *ms_interior, double *ms_boundary);
 
 /* Cell counts of the context's geometry: fluid cells, and the fluid cells
- * handled by the boundary kernel (every other fluid cell is interior: all
+ * handled by the boundary-cell path (every other fluid cell is interior: all
  * of its pull sources and finite-difference points are fluid cells inside
  * the box). */
 int lbfd_cell_counts(const lbfd_ctx *c, int64_t *n_fluid, int64_t *n_boundary);
+
+/* Kernel launches queued by one lbfd_step level without diagnostics: 1 for
+ * D2Q9 (one launch covers boundary and interior cells); for D3Q27 the
+ * boundary cells, the interior cells and, with an outflow face, the outlet
+ * update (Eq. 32) are separate launches.  Negative on a null context. */
+int lbfd_step_launches(const lbfd_ctx *c);
 
 void lbfd_destroy(lbfd_ctx *c);
 

@@ -59,7 +59,14 @@ struct lbo_state {
     double *rho;    /* density of every cell at the current level */
     double *ux;     /* velocity of every fluid cell at the current level */
     long level;
+    const uint8_t *active;  /* NULL, or the cells a step / fields call covers */
 };
+
+/* Whether a fluid cell is covered by the current active set. */
+static int covered(const lbo_state *s, long idx)
+{
+    return s->active == NULL || s->active[idx] != 0;
+}
 
 typedef struct {
     int kind;
@@ -702,7 +709,7 @@ static void stream(lbo_state *s)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
                 long idx = ((long)z * p->ny + y) * p->nx + x;
-                if (s->mask[idx] != LBO_FLUID)
+                if (s->mask[idx] != LBO_FLUID || !covered(s, idx))
                     continue;
                 for (int i = 0; i < Q; ++i) {
                     int opp = Q - 1 - i;
@@ -747,7 +754,7 @@ int lbo_step(lbo_state *s, long nsteps)
             for (int y = 0; y < p->ny; ++y)
                 for (int x = 0; x < p->nx; ++x) {
                     long idx = ((long)z * p->ny + y) * p->nx + x;
-                    if (s->mask[idx] != LBO_FLUID)
+                    if (s->mask[idx] != LBO_FLUID || !covered(s, idx))
                         continue;
                     cell_eval_t o;
                     eval_cell(s, x, y, z, &o);
@@ -765,7 +772,7 @@ int lbo_step(lbo_state *s, long nsteps)
         /* solid cells keep their (never used) values in both buffers */
 #pragma omp parallel for schedule(static)
         for (long idx = 0; idx < N; ++idx) {
-            if (s->mask[idx] != LBO_FLUID)
+            if (s->mask[idx] != LBO_FLUID || !covered(s, idx))
                 continue;
             s->T[idx] = s->Tn[idx];
             for (int k = 0; k < ns; ++k)
@@ -777,6 +784,18 @@ int lbo_step(lbo_state *s, long nsteps)
 }
 
 long lbo_level(const lbo_state *s) { return s->level; }
+
+/*
+ * Restrict the following lbo_step / lbo_fields calls to the cells with
+ * active[idx] != 0 (NULL: every cell).  Cells outside the set are neither
+ * updated nor reported (lbo_fields gives NaN there), so after a restricted
+ * step only the cells whose whole dependency region was covered hold the
+ * values of the full step: a cell's new state reads the previous level
+ * within three cells (its pull sources, and their finite-difference
+ * stencils of half-width two).  The array is not copied; it must outlive
+ * its use.  lbo_diagnostics needs the full set.
+ */
+void lbo_set_active(lbo_state *s, const uint8_t *active) { s->active = active; }
 
 void lbo_set_threads(int n)
 {
@@ -806,6 +825,18 @@ void lbo_fields(lbo_state *s, double *rho, double *u, double *T, double *Y, doub
                 if (Y)
                     for (int k = 0; k < ns; ++k)
                         Y[k * N + idx] = s->Y[k * N + idx];
+                if (s->mask[idx] == LBO_FLUID && !covered(s, idx)) {
+                    if (T) T[idx] = NAN;
+                    if (Y)
+                        for (int k = 0; k < ns; ++k)
+                            Y[k * N + idx] = NAN;
+                    if (rho) rho[idx] = NAN;
+                    if (Ph) Ph[idx] = NAN;
+                    if (u)
+                        for (int d = 0; d < 3; ++d)
+                            u[d * N + idx] = NAN;
+                    continue;
+                }
                 if (s->mask[idx] != LBO_FLUID) {
                     if (rho) rho[idx] = 0.0;
                     if (Ph) Ph[idx] = 0.0;
@@ -837,6 +868,11 @@ void lbo_fields(lbo_state *s, double *rho, double *u, double *T, double *Y, doub
  */
 void lbo_diagnostics(lbo_state *s, double *out)
 {
+    if (s->active) {
+        for (int k = 0; k < 12; ++k)
+            out[k] = NAN;
+        return;
+    }
     const lbo_params *p = &s->p;
     long N = s->N;
     int Q = s->Q, ns = p->n_species, D = s->D;

@@ -76,6 +76,7 @@ lbo_state *lbo_create(const lbo_params *p, const uint8_t *mask,
 void lbo_destroy(lbo_state *s);
 int lbo_step(lbo_state *s, long nsteps);
 long lbo_level(const lbo_state *s);
+void lbo_set_active(lbo_state *s, const uint8_t *active);
 void lbo_fields(lbo_state *s, double *rho, double *u, double *T, double *Y,
                 double *Ph);
 void lbo_diagnostics(lbo_state *s, double *out);

@@ -101,6 +101,7 @@ def _load():
         lib.lbo_step.restype = C.c_int
         lib.lbo_level.argtypes = [C.c_void_p]
         lib.lbo_level.restype = C.c_long
+        lib.lbo_set_active.argtypes = [C.c_void_p, C.c_void_p]
         lib.lbo_fields.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
         lib.lbo_diagnostics.argtypes = [C.c_void_p, dp]
         lib.lbo_get_pops.argtypes = [C.c_void_p, dp]
@@ -209,6 +210,40 @@ class Oracle:
 
     def step(self, n: int = 1):
         self._lib.lbo_step(self._h, int(n))
+
+    # A cell's state at level n+1 reads level n within this many cells
+    # (pull sources one cell away, their stencils two further).
+    CONE_STEP = 3
+
+    def set_active(self, active):
+        """Restrict later steps and fields() to the cells where ``active``
+        (box-shaped, any dtype) is nonzero; None restores the whole box."""
+        if active is None:
+            self._active = None
+            self._lib.lbo_set_active(self._h, None)
+            return
+        a = np.ascontiguousarray(np.asarray(active).reshape(-1) != 0, dtype=np.uint8)
+        if a.size != self.N:
+            raise ValueError("active set must cover the box")
+        self._active = a  # kept alive while the C side holds the pointer
+        self._lib.lbo_set_active(self._h, a.ctypes.data)
+
+    def step_sampled(self, sample, n: int):
+        """Advance n levels computing only the dependency cone of the cells
+        where ``sample`` is true: the step to level k covers the cells within
+        CONE_STEP (n - k) + 3 of the sample (cube, wrapped across the box),
+        which leaves the sample's state -- and the stencil region P_h and u
+        need -- equal to that of n full steps.  fields() then reports the
+        sample cells (NaN elsewhere)."""
+        from scipy.ndimage import maximum_filter
+        sample = np.asarray(sample, dtype=bool).reshape(self.prob.nz, self.prob.ny, self.prob.nx)
+        flat = self.prob.nz == 1
+        for k in range(1, int(n) + 1):
+            r = self.CONE_STEP * (int(n) - k) + 3
+            size = (1 if flat else 2 * r + 1, 2 * r + 1, 2 * r + 1)
+            self.set_active(maximum_filter(sample.astype(np.uint8), size=size, mode="wrap"))
+            self.step(1)
+        self.set_active(sample)
 
     def fields(self) -> dict:
         pr = self.prob

@@ -62,7 +62,7 @@ struct lbfd_ctx {
     int Q, D, nsp, prec;
     long long N;
     hipStream_t stream;
-    Streams streams = {nullptr, nullptr, nullptr, nullptr, 0};
+    Streams streams = {nullptr, 0};
     long long n_fluid = 0;
     void *pop[2] = {nullptr, nullptr};
     void *sc[2] = {nullptr, nullptr};
@@ -80,6 +80,7 @@ struct lbfd_ctx {
     int nblocks_interior = 0;
     double *wall_T = nullptr;
     double *outlet = nullptr;
+    double *outlet_un = nullptr;
     size_t outlet_n = 0;
     double *fields = nullptr;
     double *partials = nullptr;
@@ -96,13 +97,10 @@ static void free_ctx(lbfd_ctx *c)
 {
     if (!c) return;
     void *ptrs[] = {c->pop[0], c->pop[1], c->sc[0], c->sc[1], c->mask, c->code, c->boundary, c->bsrc, c->bpt, c->bwk,
-                    c->btw, c->wall_T, c->outlet,
+                    c->btw, c->wall_T, c->outlet, c->outlet_un,
                     c->fields, c->partials, c->diag_dev, c->bad_dev, c->rx_dev};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
-    if (c->streams.side) (void)hipStreamDestroy(c->streams.side);
-    if (c->streams.fork) (void)hipEventDestroy(c->streams.fork);
-    if (c->streams.join) (void)hipEventDestroy(c->streams.join);
     delete c;
 }
 
@@ -339,13 +337,18 @@ static KParams make_kparams(const lbfd_ctx *c)
     k.code = c->code;
     k.boundary = c->boundary;
     k.n_boundary = c->n_boundary;
-    k.boundary_partial_offset = c->nblocks_interior;
+    k.boundary_blocks = c->nblocks - c->nblocks_interior;
+    k.interior_blocks = c->nblocks_interior;
+    k.block_begin = 0;
+    k.tiles_x = (int)c->grid.x;
+    k.tiles_y = (int)c->grid.y;
     k.bsrc = c->bsrc;
     k.bpt = c->bpt;
     k.bwk = c->bwk;
     k.btw = c->btw;
     k.wall_T = c->wall_T;
     k.outlet = c->outlet;
+    k.outlet_un = c->outlet_un;
     k.fields = c->fields;
     k.partials = c->partials;
     k.rx = c->rx_dev;
@@ -429,7 +432,9 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     c->n_boundary = (long long)boundary.size();
     for (long long i = 0; i < c->N; ++i) c->n_fluid += mask[i] == LBFD_FLUID;
     c->nblocks_interior = c->grid.x * c->grid.y * c->grid.z;
-    c->nblocks = c->nblocks_interior + (int)((c->n_boundary + kBlock - 1) / kBlock);
+    // boundary blocks padded to a multiple of 8 (one per XCD in turn), so
+    // that the interior tiles after them start on XCD 0
+    c->nblocks = c->nblocks_interior + (int)(((c->n_boundary + kBlock - 1) / kBlock + 7) / 8 * 8);
 
 #define ALLOC(ptr, bytes)                                                          \
     do {                                                                           \
@@ -454,6 +459,7 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     }
     ALLOC(c->wall_T, N * sizeof(double));
     ALLOC(c->outlet, c->outlet_n * sizeof(double));
+    ALLOC(c->outlet_un, (size_t)2 * p->ny * p->nz * sizeof(double));
     ALLOC(c->partials, (size_t)c->nblocks * kNDiag * sizeof(double));
     ALLOC(c->diag_dev, kNDiag * sizeof(double));
     ALLOC(c->bad_dev, sizeof(long long));
@@ -499,12 +505,6 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     TRY_OR_FREE(upload_scalars(c, c->sc[1], T0, Y0));
 
     c->streams.main = c->stream;
-    if (c->n_boundary > 0) {
-        // side stream for the boundary kernel (default priority)
-        HIP_OR_FREE(hipStreamCreateWithFlags(&c->streams.side, hipStreamNonBlocking));
-        HIP_OR_FREE(hipEventCreateWithFlags(&c->streams.fork, hipEventDisableTiming));
-        HIP_OR_FREE(hipEventCreateWithFlags(&c->streams.join, hipEventDisableTiming));
-    }
     c->base = make_kparams(c);
     double *u0_dev = nullptr, *Ph0_dev = nullptr;
     if (u0) {
@@ -544,7 +544,7 @@ int lbfd_step(lbfd_ctx *c, int64_t nsteps)
         k.sc_in = c->sc[c->cur];
         k.sc_out = c->sc[1 - c->cur];
         const bool check = c->p.check_every > 0 && (c->level % c->p.check_every) == 0;
-        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, check ? kModeStepDiag : kModeStep, k, c->grid, c->block,
+        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, check ? kModeStepDiag : kModeStep, k,
                             c->streams));
         if (check) HIP_TRY(launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream));
         c->cur ^= 1;
@@ -578,7 +578,7 @@ static int evaluate(lbfd_ctx *c)
     KParams k = c->base;
     k.pop_in = c->pop[c->cur];
     k.sc_in = c->sc[c->cur];
-    HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeFields, k, c->grid, c->block, c->streams));
+    HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeFields, k, c->streams));
     HIP_TRY(launch_finalize(c->partials, c->nblocks, c->diag_dev, nullptr, c->level, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return LBFD_OK;
@@ -737,10 +737,10 @@ int lbfd_time_kernels(lbfd_ctx *c, int64_t nsteps, double *ms_interior, double *
         Streams st = c->streams;
         HIP_TRY(hipEventRecord(e0, c->stream));
         st.part = 1;
-        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStep, k, c->grid, c->block, st));
+        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStep, k, st));
         HIP_TRY(hipEventRecord(e1, c->stream));
         st.part = 2;
-        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStep, k, c->grid, c->block, st));
+        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStep, k, st));
         HIP_TRY(hipEventRecord(e2, c->stream));
         HIP_TRY(hipEventSynchronize(e2));
         float a = 0.0f, b = 0.0f;
@@ -800,7 +800,7 @@ int lbfd_objective(lbfd_ctx *c, int64_t nsteps, double *J)
         k.pop_out = c->pop[1 - c->cur];
         k.sc_in = c->sc[c->cur];
         k.sc_out = c->sc[1 - c->cur];
-        e = launch_step(c->Q, c->nsp, c->prec, kModeStepDiag, k, c->grid, c->block, c->streams);
+        e = launch_step(c->Q, c->nsp, c->prec, kModeStepDiag, k, c->streams);
         if (e == hipSuccess) e = launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream);
         if (e == hipSuccess) e = launch_accumulate(Jd, c->diag_dev + kWallQ, c->stream);
         c->cur ^= 1;
@@ -857,7 +857,7 @@ int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwall
         k.pop_out = c->pop[1 - c->cur];
         k.sc_in = c->sc[c->cur];
         k.sc_out = c->sc[1 - c->cur];
-        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStepDiag, k, c->grid, c->block, c->streams));
+        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStepDiag, k, c->streams));
         HIP_TRY(launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream));
         HIP_TRY(launch_accumulate(Jd, c->diag_dev + kWallQ, c->stream));
         c->cur ^= 1;
@@ -880,7 +880,7 @@ int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwall
             k.pop_out = sg_pop(n - n0 + 1);
             k.sc_in = sg_sc(n - n0);
             k.sc_out = sg_sc(n - n0 + 1);
-            HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStep, k, c->grid, c->block, c->streams));
+            HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStep, k, c->streams));
         }
         for (int64_t n = n1 - 1; n >= n0; --n) {
             const int cu = 1 - nxt;
@@ -911,6 +911,12 @@ int lbfd_cell_counts(const lbfd_ctx *c, int64_t *n_fluid, int64_t *n_boundary)
     *n_fluid = c->n_fluid;
     *n_boundary = c->n_boundary;
     return LBFD_OK;
+}
+
+int lbfd_step_launches(const lbfd_ctx *c)
+{
+    if (!c) return fail(LBFD_EINVAL, "null context");
+    return step_launches(c->Q, c->base);
 }
 
 void lbfd_destroy(lbfd_ctx *c)

@@ -5,7 +5,7 @@
 namespace lbfd {
 
 #define X(q, n, p) \
-    extern template hipError_t launch_step_t<q, n, p>(int, const KParams &, dim3, dim3, const Streams &); \
+    extern template hipError_t launch_step_t<q, n, p>(int, const KParams &, const Streams &); \
     extern template hipError_t launch_init_t<q, n, p>(const KParams &, const double *, const double *, dim3, \
                                                       dim3, hipStream_t);
 LBFD_FOR_CONFIGS(X)
@@ -48,10 +48,9 @@ bool supported(int Q, int nsp, int prec)
     return false;
 }
 
-hipError_t launch_step(int Q, int nsp, int prec, int mode, const KParams &kp, dim3 grid, dim3 block,
-                       const Streams &s)
+hipError_t launch_step(int Q, int nsp, int prec, int mode, const KParams &kp, const Streams &s)
 {
-#define X(q, n, p) if (Q == q && nsp == n && prec == p) return launch_step_t<q, n, p>(mode, kp, grid, block, s);
+#define X(q, n, p) if (Q == q && nsp == n && prec == p) return launch_step_t<q, n, p>(mode, kp, s);
     LBFD_FOR_CONFIGS(X)
 #undef X
     return hipErrorInvalidValue;

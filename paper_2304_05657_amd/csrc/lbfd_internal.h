@@ -45,15 +45,20 @@ struct KParams {
     const int *bpt;             // [3*4][nb] finite-difference point (or ghost image) index, axis-major, m = -2,-1,1,2
     const uint8_t *bwk;         // [3*4][nb] kind of the wall behind a ghost point, kFluid for a plain point
     const double *btw;          // [3*4][nb] wall temperature of isothermal ghost walls
-    long long boundary_partial_offset;  // first partial slot of the boundary kernel
+    // block list of a step launch: boundary_blocks (a multiple of 8) blocks
+    // of 256 boundary cells, then interior_blocks tiles of tiles_x x tiles_y
+    // x (nz / tile depth); a launch covers blocks [block_begin, + gridDim.x)
+    long long boundary_blocks, interior_blocks, block_begin;
+    int tiles_x, tiles_y;
     const double *wall_T;
     const void *pop_in;   // post-collision populations of the previous level
     void *pop_out;        // post-collision populations of this level
     const void *sc_in;    // [1 + n_species][N]: T then Y_k
     void *sc_out;
     double *outlet;       // [2 x faces][Q][ny*nz] post-streaming outlet populations
+    double *outlet_un;    // [2 x faces][ny*nz] outward normal velocity of the face cells (this level)
     double *fields;       // [5][N]: rho, u_x, u_y, u_z, P_h  (fields mode)
-    double *partials;     // [blocks][kNDiag]  (diagnostics modes)
+    double *partials;     // [interior_blocks + boundary_blocks][kNDiag]  (diagnostics modes)
     const lbfd_reaction *rx;
     int n_rx;
     int chem_substeps_max;
@@ -68,18 +73,27 @@ struct KParams {
 // Kernel modes.
 enum { kModeStep = 0, kModeStepDiag = 1, kModeFields = 2 };
 
-// Streams of a step: the caller's stream, and an optional side stream
-// (default priority) with fork/join events for the boundary kernel.
+// D2Q9 steps are one launch over boundary blocks and interior tiles;
+// D3Q27 steps launch them separately (one kernel holding both paths slows
+// the 3-D interior tiles), plus the outlet update with an outflow face.
+constexpr bool fused_step(int Q) { return Q == 9; }
+
+inline int step_launches(int Q, const KParams &kp)
+{
+    if (fused_step(Q)) return kp.boundary_blocks + kp.interior_blocks > 0 ? 1 : 0;
+    const bool outlet = kp.n_boundary > 0 && (kp.face[0] == LBFD_FACE_OUTFLOW || kp.face[1] == LBFD_FACE_OUTFLOW);
+    return (kp.boundary_blocks > 0) + (kp.interior_blocks > 0) + (outlet ? 1 : 0);
+}
+
+// Where a step is launched: the context stream, and which blocks (0: all,
+// 1: interior tiles only, 2: boundary blocks only -- for per-part timing).
 struct Streams {
     hipStream_t main;
-    hipStream_t side;
-    hipEvent_t fork, join;
-    int part;  // 0: both kernels, 1: interior kernel only, 2: boundary kernel only (on main)
+    int part;
 };
 
 // Launchers (instantiated in inst/*.hip, dispatched in lbfd_dispatch.hip).
-hipError_t launch_step(int Q, int nsp, int prec, int mode, const KParams &kp,
-                       dim3 grid, dim3 block, const Streams &s);
+hipError_t launch_step(int Q, int nsp, int prec, int mode, const KParams &kp, const Streams &s);
 hipError_t launch_init(int Q, int nsp, int prec, const KParams &kp, const double *u0,
                        const double *Ph0, dim3 grid, dim3 block, hipStream_t s);
 hipError_t launch_finalize(const double *partials, int nblocks, double *out,

@@ -661,31 +661,42 @@ __device__ __forceinline__ void finish_cell(const KParams &P, long long idx, con
     }
 }
 
-// FAST = true: the interior kernel -- a 2-D/3-D grid over the box whose
-// threads work only on interior fluid cells (every pull source and every
-// finite-difference point in the box and fluid), with plain offset loads.
-// FAST = false: the boundary kernel -- a 1-D grid over the list of the
-// other fluid cells, with the general geometry logic.
+// Interior tile of one 256-thread block: 64 x 4 cells in 2-D, 64 x 2 x 2
+// in 3-D.
+template <int D> struct TileShape {
+    static constexpr int X = 64, Y = D == 2 ? 4 : 2, Z = D == 2 ? 1 : 2;
+};
+
+// One block of the step.
+// FAST = true: an interior tile (bx, by, bz) of the box whose threads work
+// only on interior fluid cells (every pull source and every finite-difference
+// point in the box and fluid), with plain offset loads.
+// FAST = false: block bx of the list of the other fluid cells (boundary
+// cells), with the general geometry logic.
+// (tx, ty, tz): the thread's place in the tile (FAST) or tx in 0..255.
+// slot: the block's row of the diagnostics partials.
 template <int Q, int NSP, int PREC, int MODE, bool FAST>
-__global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
+__device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int bz, int tx, int ty, int tz,
+                                           long long slot)
 {
     using L = Lat<Q>;
     using C = typename Prec<PREC>::calc;
     using S = typename Prec<PREC>::scal;
     constexpr int D = L::D;
     constexpr bool DIAG = MODE != kModeStep;
+    using TS = TileShape<D>;
     int x, y, z;
     long long idx, tb = 0;
     bool active, inbox;
     if constexpr (FAST) {
-        x = blockIdx.x * blockDim.x + threadIdx.x;
-        y = blockIdx.y * blockDim.y + threadIdx.y;
-        z = blockIdx.z * blockDim.z + threadIdx.z;
+        x = bx * TS::X + tx;
+        y = by * TS::Y + ty;
+        z = bz * TS::Z + tz;
         inbox = x < P.nx && y < P.ny && z < P.nz;
         idx = inbox ? ((long long)z * P.ny + y) * P.nx + x : 0;
         active = inbox && P.code[idx] == kCodeInterior;
     } else {
-        tb = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+        tb = (long long)bx * kBlock + tx;
         inbox = false;
         active = tb < P.n_boundary;
         idx = active ? (long long)P.boundary[tb] : 0;
@@ -706,8 +717,8 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
     constexpr bool TILE = FAST && D == 2;
     __shared__ C tile[TILE ? (NSP + 2) * kNP : 1];
     if constexpr (TILE) {
-        const int tid = threadIdx.x + kTX * threadIdx.y;
-        const int gx0 = blockIdx.x * kTX - 2, gy0 = blockIdx.y * kTY - 2;
+        const int tid = tx + kTX * ty;
+        const int gx0 = bx * kTX - 2, gy0 = by * kTY - 2;
         for (int i = tid; i < kNP; i += kBlock) {
             const int gx = gx0 + i % kHX, gy = gy0 + i / kHX;
             if ((unsigned)gx < (unsigned)P.nx && (unsigned)gy < (unsigned)P.ny) {
@@ -722,7 +733,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
         __syncthreads();
     }
     auto tile_point = [&](int dx, int dy, Pt<NSP, C> &o) {
-        const int i = (threadIdx.y + 2 + dy) * kHX + threadIdx.x + 2 + dx;
+        const int i = (ty + 2 + dy) * kHX + tx + 2 + dx;
         o.T = tile[i];
         o.rho = tile[kNP + i];
 #pragma unroll
@@ -795,7 +806,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
             const C ud = d == 0 ? u[0] : d == 1 ? u[1] : u[2];
             C d1r;
             if constexpr (TILE) {
-                const int ic = (threadIdx.y + 2) * kHX + threadIdx.x + 2;
+                const int ic = (ty + 2) * kHX + tx + 2;
                 const int sd = d == 0 ? 1 : kHX;
                 C r5[5];
 #pragma unroll
@@ -822,13 +833,63 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
                         return (C)ldo<S>(sc + fo, (uint32_t)(idx + m * sd) * (uint32_t)sizeof(S));
                     },
                     r5, false, ud);
-            } else {
+            } else if constexpr (D == 2) {
+                // boundary cell (2-D): whole stencil points from the descriptors
                 Pt<NSP, C> st[5];
                 bool near = false;
                 desc_stencil<NSP, PREC, DIAG>(P, tb, P.n_boundary, d, ctr, st, near, wallq);
                 C r5[5] = {st[0].rho, st[1].rho, st[2].rho, st[3].rho, st[4].rho};
                 d1r = axis_terms(
                     [&](int f, int m) -> C { return f == 0 ? st[m + 2].T : st[m + 2].Y[f - 2]; }, r5, near, ud);
+            } else {
+                // boundary cell (3-D): per offset m = -2, -1, 1, 2 the descriptor
+                // gives the point holding the value (or the ghost's image)
+                // and the kind of the wall behind a ghost (Sec. III.B)
+                const long long nbd = P.n_boundary;
+                int pts[4], wks[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    pts[j] = P.bpt[(d * 4 + j) * nbd + tb];
+                    wks[j] = P.bwk[(d * 4 + j) * nbd + tb];
+                }
+                const bool near = (wks[0] | wks[1] | wks[2] | wks[3]) != kFluid;
+                C r5[5];
+                r5[2] = rho;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int slot = j < 2 ? j : j + 1;
+                    Pt<NSP, C> pt;
+                    load_point<NSP, PREC>(P, pts[j], pt);
+                    r5[slot] = pt.rho;
+                    if (wks[j] == kIso) {
+                        const C Tw = (C)P.btw[(d * 4 + j) * nbd + tb];
+                        r5[slot] = (C)2 * density<NSP>(P, Tw, pt.Y) - pt.rho;
+                        if constexpr (DIAG) {
+                            if (j == 1 || j == 2)
+                                wallq += 2.0 * P.alpha * (double)density<NSP>(P, Tw, ctr.Y) *
+                                         ((double)ctr.T - (double)Tw);
+                        }
+                    } else if (wks[j] == kInflow) {
+                        r5[slot] = (C)2 * (C)P.rho_in - pt.rho;
+                    }
+                }
+                const char *sc = (const char *)P.sc_in;
+                const size_t fstride = (size_t)P.N * sizeof(S);
+                d1r = axis_terms(
+                    [&](int f, int m) -> C {
+                        const int j = m < 0 ? m + 2 : m + 1;
+                        const size_t fo = f == 0 ? 0 : (size_t)(f - 1) * fstride;
+                        const C v = (C)ldo<S>(sc + fo, (uint32_t)pts[j] * (uint32_t)sizeof(S));
+                        if (wks[j] == kFluid) return v;
+                        if (f == 0) {
+                            if (wks[j] == kIso) return (C)2 * (C)P.btw[(d * 4 + j) * nbd + tb] - v;
+                            if (wks[j] == kInflow) return (C)2 * (C)P.T_in - v;
+                            return v;
+                        }
+                        if (wks[j] == kInflow) return (C)2 * (C)P.Y_in[f - 2] - v;
+                        return v;
+                    },
+                    r5, near, ud);
             }
             grad[0] = d == 0 ? d1r : grad[0];
             grad[1] = d == 1 ? d1r : grad[1];
@@ -841,30 +902,41 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
 
         finish_cell<Q, NSP, PREC, MODE>(P, idx, g, ctr, u, m, sg, inv_rc, diffT, diffY, CT, CY, grad, wallq, acc);
         if constexpr (MODE != kModeFields) {
-            // outlet (Eq. 32): g_i(r) <- g_i(r-n)(cs - u.n) + g_i(r)(1 - cs + u.n)
-            // for the populations entering through the face, with the
-            // post-streaming values and velocity of this level
+            if constexpr (!FAST && D == 2) {
+                // outlet (Eq. 32): g_i(r) <- g_i(r-n)(cs - u.n) + g_i(r)(1 - cs + u.n)
+                // for the populations entering through the face, with the
+                // post-streaming values and velocity of this level
 #pragma unroll
-            for (int f = 0; f < 2; ++f) {
-                if (FAST || P.face[f] != LBFD_FACE_OUTFLOW || x != (f ? P.nx - 1 : 0)) continue;
-                const int sign = f ? 1 : -1;
-                Nb in = classify(P, x - sign, y, z);
-                if (in.kind != kFluid) continue;
-                const C cs = (C)0.57735026918962576451;
-                const C un = (C)sign * u[0];
-                sfor<0, Q>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    if constexpr (L::cx(i) != 0) {
-                        if (L::cx(i) == -sign) {
-                            Nb s = classify(P, x - L::cx(i), y - L::cy(i), z - L::cz(i));
-                            if (s.kind == kOutflow && s.face == f) {
-                                C G = gather<Q, PREC, i>(P, x - sign, y, z, in.idx);
-                                P.outlet[outlet_index(P, f, i, Q, y, z)] =
-                                    (double)(G * (cs - un) + g[i] * ((C)1 - cs + un));
+                for (int f = 0; f < 2; ++f) {
+                    if (P.face[f] != LBFD_FACE_OUTFLOW || x != (f ? P.nx - 1 : 0)) continue;
+                    const int sign = f ? 1 : -1;
+                    Nb in = classify(P, x - sign, y, z);
+                    if (in.kind != kFluid) continue;
+                    const C cs = (C)0.57735026918962576451;
+                    const C un = (C)sign * u[0];
+                    sfor<0, Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        if constexpr (L::cx(i) != 0) {
+                            if (L::cx(i) == -sign) {
+                                Nb s = classify(P, x - L::cx(i), y - L::cy(i), z - L::cz(i));
+                                if (s.kind == kOutflow && s.face == f) {
+                                    C G = gather<Q, PREC, i>(P, x - sign, y, z, in.idx);
+                                    P.outlet[outlet_index(P, f, i, Q, y, z)] =
+                                        (double)(G * (cs - un) + g[i] * ((C)1 - cs + un));
+                                }
                             }
                         }
-                    }
-                });
+                    });
+                }
+            } else if constexpr (!FAST) {
+                // 3-D: outlet cells hand their outward normal velocity to
+                // outlet_kernel, which applies the same update (keeps the
+                // nine extra gathers out of this kernel's registers)
+#pragma unroll
+                for (int f = 0; f < 2; ++f)
+                    if (P.face[f] == LBFD_FACE_OUTFLOW && x == (f ? P.nx - 1 : 0))
+                        P.outlet_un[(long long)f * P.ny * P.nz + (long long)z * P.ny + y] =
+                            (double)(f ? u[0] : -u[0]);
             }
         }
     } else if constexpr (MODE == kModeFields && FAST) {
@@ -873,10 +945,94 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const KParams P)
             for (int c = 0; c < 5; ++c) P.fields[c * P.N + idx] = 0.0;
     }
 
-    if constexpr (DIAG) {
-        const long long blk = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
-        block_reduce_diag(acc, P.partials + (FAST ? 0 : P.boundary_partial_offset) * kNDiag + blk * kNDiag);
+    if constexpr (DIAG) block_reduce_diag(acc, P.partials + slot * kNDiag);
+}
+
+// Minimum waves per SIMD asked of the register allocator for the step
+// kernel: the 2-D tiles fit three (168 VGPRs); the boundary path, which
+// needs more, spills instead of lowering the tiles' occupancy.
+template <int Q, int NSP, int PREC> struct StepWaves {
+    static constexpr int value = (Q == 9 && NSP <= 4) ? 3 : 1;
+};
+
+// The step over the block range [block_begin, block_begin + gridDim.x) of
+// the list (boundary blocks, then interior tiles).  PART 0: one launch
+// covers both kinds -- boundary blocks first, so that their long dependent
+// chains of descriptor and neighbour loads start with the launch and the
+// interior tiles fill the remaining wave slots (D2Q9).  PART 2 / PART 1:
+// boundary blocks / interior tiles only, two launches in stream order
+// (D3Q27, where one kernel holding both paths slows the interior tiles).
+// Consecutive blocks go to the 8 XCDs in turn, so the interior tiles are
+// renumbered to give each XCD one contiguous band of the box;
+// boundary_blocks is a multiple of 8, which keeps the XCD of a tile block
+// equal to its index modulo 8.
+template <int Q, int NSP, int PREC, int MODE, int PART>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepWaves<Q, NSP, PREC>::value)))
+step_kernel(const KParams P)
+{
+    using TS = TileShape<Lat<Q>::D>;
+    const long long b = (long long)blockIdx.x + P.block_begin;
+    if constexpr (PART != 1) {
+        if (b < P.boundary_blocks) {
+            step_block<Q, NSP, PREC, MODE, false>(P, (int)b, 0, 0, (int)threadIdx.x, 0, 0,
+                                                  P.interior_blocks + b);
+            return;
+        }
     }
+    if constexpr (PART != 2) {
+        const long long t = b - P.boundary_blocks;
+        const long long n = P.interior_blocks, q = n >> 3;
+        const int xcd = (int)(t & 7), r = (int)(n & 7);
+        const long long tile = xcd * q + (xcd < r ? xcd : r) + (t >> 3);
+        const int bx = (int)(tile % P.tiles_x);
+        const int by = (int)((tile / P.tiles_x) % P.tiles_y);
+        const int bz = (int)(tile / ((long long)P.tiles_x * P.tiles_y));
+        const int tx = (int)threadIdx.x % TS::X;
+        const int ty = ((int)threadIdx.x / TS::X) % TS::Y;
+        const int tz = (int)threadIdx.x / (TS::X * TS::Y);
+        step_block<Q, NSP, PREC, MODE, true>(P, bx, by, bz, tx, ty, tz, tile);
+    }
+}
+
+// ------------------------------------------------------------ outlet
+// Outlet (Eq. 32): for every fluid cell of an outflow face whose inner
+// neighbour is fluid, the populations entering through the face become
+// g_i(r) <- g_i(r-n)(cs - u.n) + g_i(r)(1 - cs + u.n), with the
+// post-streaming values g_i(r) (the outlet buffer, read by this step) and
+// g_i(r-n) (pulled again from the buffer this step read), and u.n of this
+// level (written by the boundary blocks).  Runs after them; used for D3Q27
+// (D2Q9 applies the update in the boundary blocks).
+template <int Q, int PREC>
+__global__ void __launch_bounds__(kBlock) outlet_kernel(const KParams P)
+{
+    using L = Lat<Q>;
+    using C = typename Prec<PREC>::calc;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nf = (long long)P.ny * P.nz;
+    if (t >= 2 * nf) return;
+    const int f = (int)(t / nf);
+    const int y = (int)((t % nf) % P.ny), z = (int)((t % nf) / P.ny);
+    if (P.face[f] != LBFD_FACE_OUTFLOW) return;
+    const int x = f ? P.nx - 1 : 0, sign = f ? 1 : -1;
+    const long long idx = ((long long)z * P.ny + y) * P.nx + x;
+    if (P.mask[idx] != LBFD_FLUID) return;
+    const Nb in = classify(P, x - sign, y, z);
+    if (in.kind != kFluid) return;
+    const C cs = (C)0.57735026918962576451;
+    const C un = (C)P.outlet_un[t];
+    sfor<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (L::cx(i) != 0) {
+            if (L::cx(i) == -sign) {
+                const Nb s = classify(P, x - L::cx(i), y - L::cy(i), z - L::cz(i));
+                if (s.kind == kOutflow && s.face == f) {
+                    const C G = gather<Q, PREC, i>(P, x - sign, y, z, in.idx);
+                    double &S = P.outlet[outlet_index(P, f, i, Q, y, z)];
+                    S = (double)(G * (cs - un) + (C)S * ((C)1 - cs + un));
+                }
+            }
+        }
+    });
 }
 
 // ------------------------------------------------------------ init kernel
@@ -938,49 +1094,51 @@ __global__ void __launch_bounds__(kBlock) init_kernel(const KParams P, const dou
 // ------------------------------------------------------------ launchers
 // Instantiated once per configuration in inst/*.hip (explicit
 // instantiation), declared extern in the dispatcher.
-// One step = the interior kernel over the box grid, then the boundary
-// kernel over the boundary-cell list (both read level n, write level n+1,
-// disjoint cells).
-// One step = the interior kernel over the box grid and the boundary kernel
-// over the boundary-cell list; both read level n and write disjoint cells
-// of level n+1.  With a side stream the boundary kernel runs concurrently
-// (fork: side waits on `fork` recorded on s; join: s waits on `join`).
-template <int Q, int NSP, int PREC, int MODE>
-hipError_t launch_pair(const KParams &kp, dim3 grid, dim3 block, const Streams &st)
+// One step: the boundary blocks and the interior tiles (both read level n
+// and write disjoint cells of level n+1), on the context stream, then for
+// D3Q27 the outlet update.
+template <int Q, int NSP, int PREC, int MODE, int PART>
+hipError_t launch_range(const KParams &kp0, long long begin, long long count, hipStream_t s)
 {
+    if (count <= 0) return hipSuccess;
+    KParams kp = kp0;
+    kp.block_begin = begin;
+    step_kernel<Q, NSP, PREC, MODE, PART><<<dim3((unsigned)count), dim3(kBlock), 0, s>>>(kp);
+    return hipGetLastError();
+}
+
+template <int Q, int NSP, int PREC, int MODE>
+hipError_t launch_pair(const KParams &kp, const Streams &st)
+{
+    // st.part 0: every block; 1: interior tiles only; 2: boundary blocks only
+    const long long nbb = kp.boundary_blocks, nti = kp.interior_blocks;
     hipError_t e = hipSuccess;
-    {
-        const bool side = st.part == 0 && st.side != nullptr && kp.n_boundary > 0;
-        if (side) {
-            if ((e = hipEventRecord(st.fork, st.main)) != hipSuccess) return e;
-            if ((e = hipStreamWaitEvent(st.side, st.fork, 0)) != hipSuccess) return e;
-        }
-        // the boundary kernel (few, long-latency blocks) is queued first so
-        // that its blocks are resident while the interior blocks stream
-        if (kp.n_boundary > 0 && st.part != 1) {
-            const unsigned nb = (unsigned)((kp.n_boundary + kBlock - 1) / kBlock);
-            step_kernel<Q, NSP, PREC, MODE, false><<<dim3(nb), dim3(kBlock), 0, side ? st.side : st.main>>>(kp);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-        if (st.part != 2) {
-            step_kernel<Q, NSP, PREC, MODE, true><<<grid, block, 0, st.main>>>(kp);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-        if (side) {
-            if ((e = hipEventRecord(st.join, st.side)) != hipSuccess) return e;
-            if ((e = hipStreamWaitEvent(st.main, st.join, 0)) != hipSuccess) return e;
-        }
-        return hipSuccess;
+    if constexpr (fused_step(Q)) {
+        const long long begin = st.part == 1 ? nbb : 0;
+        const long long count = st.part == 1 ? nti : st.part == 2 ? nbb : nbb + nti;
+        if ((e = launch_range<Q, NSP, PREC, MODE, 0>(kp, begin, count, st.main)) != hipSuccess) return e;
+    } else {
+        if (st.part != 1 && (e = launch_range<Q, NSP, PREC, MODE, 2>(kp, 0, nbb, st.main)) != hipSuccess)
+            return e;
+        if (st.part != 2 && (e = launch_range<Q, NSP, PREC, MODE, 1>(kp, nbb, nti, st.main)) != hipSuccess)
+            return e;
     }
+    if (Lat<Q>::D == 3 && MODE != kModeFields && st.part != 1 && kp.n_boundary > 0 &&
+        (kp.face[0] == LBFD_FACE_OUTFLOW || kp.face[1] == LBFD_FACE_OUTFLOW)) {
+        const unsigned no = (unsigned)((2LL * kp.ny * kp.nz + kBlock - 1) / kBlock);
+        outlet_kernel<Q, PREC><<<dim3(no), dim3(kBlock), 0, st.main>>>(kp);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int Q, int NSP, int PREC>
-hipError_t launch_step_t(int mode, const KParams &kp, dim3 grid, dim3 block, const Streams &st)
+hipError_t launch_step_t(int mode, const KParams &kp, const Streams &st)
 {
     switch (mode) {
-    case kModeStep: return launch_pair<Q, NSP, PREC, kModeStep>(kp, grid, block, st);
-    case kModeStepDiag: return launch_pair<Q, NSP, PREC, kModeStepDiag>(kp, grid, block, st);
-    default: return launch_pair<Q, NSP, PREC, kModeFields>(kp, grid, block, st);
+    case kModeStep: return launch_pair<Q, NSP, PREC, kModeStep>(kp, st);
+    case kModeStepDiag: return launch_pair<Q, NSP, PREC, kModeStepDiag>(kp, st);
+    default: return launch_pair<Q, NSP, PREC, kModeFields>(kp, st);
     }
 }
 
@@ -999,7 +1157,7 @@ hipError_t launch_init_t(const KParams &kp, const double *u0, const double *Ph0,
     X(9, 4, 2) X(27, 4, 2) X(27, 9, 2)
 
 #define LBFD_INSTANTIATE(q, n, p) \
-    template hipError_t launch_step_t<q, n, p>(int, const KParams &, dim3, dim3, const Streams &); \
+    template hipError_t launch_step_t<q, n, p>(int, const KParams &, const Streams &); \
     template hipError_t launch_init_t<q, n, p>(const KParams &, const double *, const double *, dim3, dim3, \
                                                hipStream_t);
 

@@ -26,7 +26,7 @@ ERRORS = {0: "LBFD_OK", -1: "LBFD_EINVAL", -2: "LBFD_ENOMEM", -3: "LBFD_EDEVICE"
 EXPORTS = ("lbfd_init", "lbfd_step", "lbfd_sync", "lbfd_level", "lbfd_read_fields",
            "lbfd_diagnostics", "lbfd_set_wall_temperature", "lbfd_state_size",
            "lbfd_save_state", "lbfd_load_state", "lbfd_time_steps", "lbfd_time_kernels",
-           "lbfd_cell_counts", "lbfd_set_reaction", "lbfd_objective", "lbfd_adjoint", "lbfd_destroy",
+           "lbfd_cell_counts", "lbfd_step_launches", "lbfd_set_reaction", "lbfd_objective", "lbfd_adjoint", "lbfd_destroy",
            "lbfd_strerror", "lbfd_last_error")
 
 
@@ -90,6 +90,8 @@ def load_library():
     lib.lbfd_time_steps.argtypes = [vp, C.c_int64, dp]
     lib.lbfd_time_kernels.argtypes = [vp, C.c_int64, dp, dp]
     lib.lbfd_cell_counts.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.lbfd_step_launches.argtypes = [vp]
+    lib.lbfd_step_launches.restype = C.c_int
     lib.lbfd_set_reaction.argtypes = [vp, C.c_int, C.c_double, C.c_double, C.c_double]
     lib.lbfd_objective.argtypes = [vp, C.c_int64, dp]
     lib.lbfd_adjoint.argtypes = [vp, C.c_int64, C.c_int, dp, dp, dp, dp]
@@ -213,11 +215,16 @@ class Solver:
         return a.value, b.value
 
     def cell_counts(self) -> tuple:
-        """(fluid cells, boundary-kernel cells)."""
+        """(fluid cells, cells on the boundary-cell path)."""
         a, b = C.c_int64(), C.c_int64()
         _check(self._lib, self._lib.lbfd_cell_counts(self._h, C.byref(a), C.byref(b)))
         return a.value, b.value
 
+    def step_launches(self) -> int:
+        """Kernel launches per step (1: one launch covers every cell)."""
+        n = self._lib.lbfd_step_launches(self._h)
+        _check(self._lib, min(n, 0))
+        return n
     def set_reaction(self, j: int, A: float, b: float, Ta: float):
         _check(self._lib, self._lib.lbfd_set_reaction(self._h, int(j), float(A), float(b), float(Ta)))
 

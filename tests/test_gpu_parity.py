@@ -92,11 +92,19 @@ def test_burner_inflow_outflow_fp64():
     _assert_tol(errs, TOL64)
 
 
-def test_burner_full_size_first_steps():
+def test_burner_full_size_500_steps():
     """The 2048x512 burner at full size, in the launch configuration the
-    benchmark times: all fields after 2 steps (plus the level-0 moments)."""
+    benchmark times: all fields over the first 500 steps (and the level-0
+    moments)."""
     prob = W.cylinder_burner()
-    _, _, errs = _run_pair(prob, 2, checkpoints=[0, 1])
+    _, _, errs = _run_pair(prob, 500, checkpoints=[0, 1, 100])
+    _assert_tol(errs, TOL64)
+
+
+def test_channel_1024x256_500_steps():
+    """The 1024x256 channel flame of the gradient runs, forward step only."""
+    prob = W.named("channel_adjoint")
+    _, _, errs = _run_pair(prob, 500, checkpoints=[1, 50])
     _assert_tol(errs, TOL64)
 
 
