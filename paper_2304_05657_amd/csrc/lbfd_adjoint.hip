@@ -42,6 +42,11 @@ __device__ inline Dual operator/(Dual a, Dual b)
     const double q = a.v / b.v;
     return Dual(q, (a.d - q * b.d) / b.v);
 }
+__device__ inline Dual rcp(Dual a)
+{
+    const double r = rcp(a.v);
+    return Dual(r, -a.d * r * r);
+}
 __device__ inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
 __device__ inline bool operator>(Dual a, Dual b) { return a.v > b.v; }
 __device__ inline bool operator>=(Dual a, Dual b) { return a.v >= b.v; }

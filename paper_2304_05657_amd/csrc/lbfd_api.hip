@@ -4,6 +4,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -163,6 +164,10 @@ static int validate(const lbfd_params *p, const uint8_t *mask, const double *T0,
 // neighbours) and every finite-difference point (+-1, +-2 along each axis)
 // lies inside the box without wrapping and is fluid; boundary fluid
 // otherwise.  Returns the boundary cells in increasing index order.
+// Brick shape of the boundary-cell list order (x, y[, z]); 0: cell index order.
+constexpr int kBrick2D[2] = {16, 16};
+constexpr int kBrick3D[3] = {0, 0, 0};
+
 static void classify_cells(const lbfd_params &p, const uint8_t *mask, std::vector<uint8_t> &code,
                            std::vector<int> &boundary)
 {
@@ -203,6 +208,19 @@ static void classify_cells(const lbfd_params &p, const uint8_t *mask, std::vecto
                 code[i] = interior ? kCodeInterior : kCodeBoundary;
                 if (!interior) boundary.push_back((int)i);
             }
+    // Order of the boundary-cell list (the cell each thread takes): by
+    // bricks of the box, cell index within a brick, so that the neighbour
+    // gathers of one wave stay in a compact region.  (0: cell index order.)
+    const int bx = D == 2 ? kBrick2D[0] : kBrick3D[0], by = D == 2 ? kBrick2D[1] : kBrick3D[1],
+              bz = D == 2 ? 1 : kBrick3D[2];
+    if (bx > 0) {
+        const long long nbx = (p.nx + bx - 1) / bx, nby = (p.ny + by - 1) / by;
+        auto brick = [&](int i) {
+            const long long x = i % p.nx, y = (i / p.nx) % p.ny, z = i / sz;
+            return ((z / bz) * nby + y / by) * nbx + x / bx;
+        };
+        std::stable_sort(boundary.begin(), boundary.end(), [&](int a, int b) { return brick(a) < brick(b); });
+    }
 }
 
 // Host copy of the kernels' neighbour rule: periodic faces wrap; outside

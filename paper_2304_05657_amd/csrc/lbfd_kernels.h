@@ -203,6 +203,22 @@ __device__ __forceinline__ typename Prec<PREC>::calc gather(const KParams &P, in
     }
 }
 
+// ------------------------------------------------------------ reciprocal
+// 1/x for a positive normal x (densities, temperatures, WENO denominators):
+// the hardware estimate, refined in double precision by two Newton-Raphson
+// steps r <- r + r (1 - x r), each of which doubles the correct bits (the
+// step sequence of the compiler's own division, without the scaling and
+// fix-up it needs near the ends of the exponent range); the single-precision
+// estimate is already within 1 ulp.
+__device__ __forceinline__ double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // ------------------------------------------------------------ scalars
 template <int NSP, class C>
 struct Pt {
@@ -216,7 +232,7 @@ __device__ __forceinline__ C density(const KParams &P, C T, const C *Y)
     C s = 0;
 #pragma unroll
     for (int k = 0; k < NSP; ++k) s += Y[k] * (C)P.invW[k];
-    return (C)P.T_ref_over_W_ref / (T * s);
+    return (C)P.T_ref_over_W_ref * rcp(T * s);
 }
 
 template <int NSP, int PREC>
@@ -345,7 +361,7 @@ __device__ __forceinline__ C weno3(C m2, C m1, C c0, C p1, C p2, C u)
     const C eA2 = eA * eA, eB2 = eB * eB, eE2 = eE * eE;
     const C den_p = eE2 + (C)2 * eB2;  // face i+1/2: e0 = eB, e1 = eE
     const C den_m = eB2 + (C)2 * eA2;  // face i-1/2: e0 = eA, e1 = eB
-    const C inv = (C)1 / (den_p * den_m);
+    const C inv = rcp(den_p * den_m);
     const C w_p = eE2 * den_m * inv, w_m = eB2 * den_p * inv;
     const C q0p = (C)1.5 * c0 - (C)0.5 * B, q1p = (C)0.5 * (c0 + E);
     const C q0m = (C)1.5 * B - (C)0.5 * A, q1m = (C)0.5 * (B + c0);
@@ -362,7 +378,7 @@ __device__ __forceinline__ C weno3(C m2, C m1, C c0, C p1, C p2, C u)
 __device__ __forceinline__ double rate_coeff(const lbfd_reaction &r, double dt, double T)
 {
     const double tb = r.b == 0.0 ? 1.0 : pow(T, r.b);
-    return r.A * dt * tb * exp(-r.Ta / T);
+    return r.A * dt * tb * exp(-r.Ta * rcp(T));
 }
 
 template <int NSP>
@@ -376,6 +392,7 @@ __device__ __forceinline__ void chemistry(const KParams &P, double T, const doub
         double want = ceil(kmax / 0.1);
         nsub = want < 1.0 ? 1 : want > (double)P.chem_substeps_max ? P.chem_substeps_max : (int)want;
     }
+    const double inv_nsub = nsub == 1 ? 1.0 : rcp((double)nsub);
     double dT = 0.0, dY[NSP];
 #pragma unroll
     for (int k = 0; k < NSP; ++k) dY[k] = 0.0;
@@ -389,7 +406,7 @@ __device__ __forceinline__ void chemistry(const KParams &P, double T, const doub
         for (int k = 0; k < NSP; ++k) incY[k] = 0.0;
         for (int j = 0; j < P.n_rx; ++j) {
             const lbfd_reaction &r = P.rx[j];
-            double rr = rate_coeff(r, P.dt_phys, Tc) / nsub;
+            double rr = rate_coeff(r, P.dt_phys, Tc) * inv_nsub;
             for (int m = 0; m < r.n_react; ++m) {
                 int kr = r.react[m];
                 double yv = 0.0;
@@ -580,8 +597,8 @@ __device__ __forceinline__ void finish_cell(const KParams &P, long long idx, con
         DtY[k] = diffY[k] + (C)srcY[k];
         invW += ctr.Y[k] * (C)P.invW[k];
     }
-    const C Wm = (C)1 / invW;
-    C Lam = DtT / ctr.T;
+    const C Wm = rcp(invW);
+    C Lam = DtT * rcp(ctr.T);
 #pragma unroll
     for (int k = 0; k < NSP; ++k) Lam += (Wm * (C)P.invW[k]) * DtY[k];
     const C Tn = ctr.T - CT + DtT;
@@ -769,9 +786,9 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
             if constexpr (L::cz(i) == 1) m[2] += g[i];
             if constexpr (L::cz(i) == -1) m[2] -= g[i];
         });
-        const C inv_rc = (C)1 / (rho * (C)kCs2);
+        const C inv_rho = rcp(rho);
+        const C inv_rc = (C)3 * inv_rho;  // 1 / (rho cs^2)
         const C u[3] = {m[0] * inv_rc, m[1] * inv_rc, m[2] * inv_rc};
-        const C inv_rho = (C)1 / rho;
 
         // finite differences per axis with ghost nodes (Sec. II.D, III.B);
         // one axis at a time, one scalar at a time, to bound register use
@@ -948,11 +965,16 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
     if constexpr (DIAG) block_reduce_diag(acc, P.partials + slot * kNDiag);
 }
 
-// Minimum waves per SIMD asked of the register allocator for the step
-// kernel: the 2-D tiles fit three (168 VGPRs); the boundary path, which
-// needs more, spills instead of lowering the tiles' occupancy.
-template <int Q, int NSP, int PREC> struct StepWaves {
-    static constexpr int value = (Q == 9 && NSP <= 4) ? 3 : 1;
+// Minimum waves per SIMD asked of the register allocator for a step
+// kernel (measured on MI355X).  2-D with up to 4 species: three waves
+// (168 VGPRs) in FP64 and four (128) in the mixed forms -- the boundary
+// path, which needs more, spills instead of lowering the tiles' occupancy.
+// 3-D FP64 boundary cells with up to 4 species: two waves (256 VGPRs).
+// Otherwise the allocator is left free (1).
+template <int Q, int NSP, int PREC, int PART> struct StepWaves {
+    static constexpr int value = (Q == 9 && NSP <= 4)                                     ? (PREC == LBFD_FP64 ? 3 : 4)
+                                 : (Q == 27 && NSP <= 4 && PART == 2 && PREC == LBFD_FP64) ? 2
+                                                                                           : 1;
 };
 
 // The step over the block range [block_begin, block_begin + gridDim.x) of
@@ -967,7 +989,7 @@ template <int Q, int NSP, int PREC> struct StepWaves {
 // boundary_blocks is a multiple of 8, which keeps the XCD of a tile block
 // equal to its index modulo 8.
 template <int Q, int NSP, int PREC, int MODE, int PART>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepWaves<Q, NSP, PREC>::value)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepWaves<Q, NSP, PREC, PART>::value)))
 step_kernel(const KParams P)
 {
     using TS = TileShape<Lat<Q>::D>;
