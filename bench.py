@@ -35,16 +35,20 @@ HBM_PEAK_GBS = 8000.0
 # Vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 # Both FP64 and FP32 issue at this rate: packed FP32 is not used.
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2304_05657_amd", "csrc", "lbfd_kernels.h")
+# sources that fix what the step kernel reads and writes (device code, the
+# host-side launch plan and the boundary-cell list)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_05657_amd", "csrc", f)
+                  for f in ("lbfd_kernels.h", "lbfd_internal.h", "lbfd_api.hip")]
 # HBM bytes per launch of the dominant kernel on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by
 # the same counters on a plain 512 MiB device copy (FETCH_SIZE reads 0.5x,
-# WRITE_SIZE 1.0x the copied bytes), valid for the kernel source whose
-# SHA-256 is given (profiles/traffic_step_kernels_burner_2048x512.md).
+# WRITE_SIZE 1.0x the copied bytes), valid for the kernel sources whose
+# SHA-256 (kernel_sha) is given (profiles/traffic_step_kernels_burner_2048x512.md).
 TRAFFIC_WORKLOAD = "cylinder_burner_2048x512"
 TRAFFIC = {
-    "fp64": {"kernel_sha256": "2314322f5f9f6f7c1f0f738f09b1b2b15d7484709e8291c43c4f64f6a6d18748", "bytes_per_launch": 219.8e6},
-    "fp32": {"kernel_sha256": "2314322f5f9f6f7c1f0f738f09b1b2b15d7484709e8291c43c4f64f6a6d18748", "bytes_per_launch": 132.8e6},
+    "fp64": {"kernel_sha256": "e5d122407b7fbc3e3be36e16903c6cc944b0921d7a1b1fde2b870f70c84487b3", "bytes_per_launch": 295.8e6},
+    "fp32": {"kernel_sha256": "e5d122407b7fbc3e3be36e16903c6cc944b0921d7a1b1fde2b870f70c84487b3", "bytes_per_launch": 179.0e6},
+    "fp16": {"kernel_sha256": "e5d122407b7fbc3e3be36e16903c6cc944b0921d7a1b1fde2b870f70c84487b3", "bytes_per_launch": 133.0e6},
 }
 POP_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 SCALAR_BYTES = {"fp64": 8, "fp32": 4, "fp16": 4}
@@ -86,8 +90,12 @@ def algorithmic_flops_per_cell(prob) -> int:
 
 
 def kernel_sha() -> str:
+    """SHA-256 over the concatenated KERNEL_SOURCES."""
     import hashlib
-    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def flame_position(diag, prob) -> float:
