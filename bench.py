@@ -192,9 +192,20 @@ def run_cpu_baseline(prob, budget_s: float) -> dict:
         el = time.perf_counter() - t0
         if el >= budget_s or n >= 200:
             break
+    # the same oracle on one core, continuing the run, for a quarter of the budget
+    o.set_threads(1)
+    n1, t1 = 0, time.perf_counter()
+    while True:
+        o.step(1)
+        n1 += 1
+        el1 = time.perf_counter() - t1
+        if el1 >= budget_s / 4 or n1 >= 50:
+            break
     return {"value": prob.N * n / el / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": "%d FP64 steps of the same workload (%s) from its initial state (after one untimed "
-                      "step), %.1f s" % (n, prob.name, el)}
+                      "step), %.1f s" % (n, prob.name, el),
+            "single_core": {"value": prob.N * n1 / el1 / 1e6, "unit": "MLUPS", "cores": 1,
+                            "sample": "the next %d steps of that run on one thread, %.1f s" % (n1, el1)}}
 
 
 def roofline(res: dict, precision: str, workload: str) -> dict:

@@ -196,16 +196,31 @@ int lbfd_time_steps(lbfd_ctx *c, int64_t nsteps, double *ms);
 /* Replace the Arrhenius parameters of reaction j (A [1/s], b, Ta [K]). */
 int lbfd_set_reaction(lbfd_ctx *c, int j, double A, double b, double Ta);
 
-/* Forward only: run nsteps steps from the current level L and return
- * J = sum_{n = L}^{L + nsteps - 1} wall_q(level n) (the objective of
+/* Objectives of lbfd_objective / lbfd_adjoint, per level n:
+ *   LBFD_OBJ_WALL_HEAT_FLUX  q(n) = wall_q of lbfd_diag (Sec. III.B ghost
+ *                            walls: per fluid cell and first-neighbour
+ *                            isothermal wall, 2 alpha rho(T_w, Y)(T - T_w));
+ *   LBFD_OBJ_FLAME_POSITION  q(n) = x_f = nx - sum_theta / (n_fluid / nx),
+ *                            theta = (T - T_u)/(T_b - T_u): the burnt length
+ *                            counted back from the +x face, in cells. */
+enum { LBFD_OBJ_WALL_HEAT_FLUX = 0, LBFD_OBJ_FLAME_POSITION = 1 };
+
+/* Select the objective of later lbfd_objective / lbfd_adjoint calls: with
+ * L the level at which such a call starts, J = sum of q(n) over the levels
+ * n = L + t, t_begin <= t < t_end (and t < nsteps).  The default is the wall
+ * heat flux over every level (t_begin = 0, t_end = INT64_MAX).  LBFD_EINVAL
+ * for an unknown kind, t_begin < 0 or t_end < t_begin. */
+int lbfd_set_objective(lbfd_ctx *c, int kind, int64_t t_begin, int64_t t_end);
+
+/* Forward only: run nsteps steps from the current level L and return the
+ * objective J selected by lbfd_set_objective over them (the J of
  * lbfd_adjoint). */
 int lbfd_objective(lbfd_ctx *c, int64_t nsteps, double *J);
 
 /* Discrete adjoint of the FP64 step (the paper's differentiation use of the
- * solver; objective: the time-integrated wall heat flux).  Starting from the
- * current level L, runs nsteps steps and computes
- *   J = sum_{n = L}^{L + nsteps - 1} wall_q(level n)
- * (wall_q as in lbfd_diag) and its exact derivatives with respect to the
+ * solver).  Starting from the current level L, runs nsteps steps and
+ * computes the objective J selected by lbfd_set_objective and its exact
+ * derivatives with respect to the
  * wall temperature of every isothermal solid cell (dJ_dwallT [N], host, may
  * be NULL; zero at other cells) and the Arrhenius A and Ta of every reaction
  * (dJ_dA, dJ_dTa [n_reactions], host, may be NULL).  Checkpoints are taken

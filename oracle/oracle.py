@@ -204,6 +204,10 @@ class Oracle:
             self._lib.lbo_destroy(h)
             self._h = None
 
+    def set_threads(self, n: int):
+        """OpenMP threads of the following steps (process-wide)."""
+        self._lib.lbo_set_threads(int(n))
+
     @property
     def level(self) -> int:
         return int(self._lib.lbo_level(self._h))
@@ -266,12 +270,22 @@ class Oracle:
                 "hrr_idx": int(out[8]), "hrr_max": out[9], "wall_q": out[10],
                 "fuel_rate": out[11]}
 
-    def objective(self, nsteps: int) -> float:
-        """Time-integrated wall heat flux: the sum over the next nsteps levels
-        of the wall heat flux diagnostic (evaluated before each step)."""
+    def objective(self, nsteps: int, kind: str = "wall_q", t_begin: int = 0, t_end: int | None = None) -> float:
+        """Sum over the next nsteps levels, offsets t_begin <= t < t_end, of
+        q(level) evaluated before each step: "wall_q" the wall heat flux
+        diagnostic, "flame_x" the flame position nx - sum_theta / (fluid cells
+        per x column), in cells."""
+        pr = self.prob
         J = 0.0
-        for _ in range(int(nsteps)):
-            J += self.diagnostics()["wall_q"]
+        for t in range(int(nsteps)):
+            if t >= t_begin and (t_end is None or t < t_end):
+                d = self.diagnostics()
+                if kind == "wall_q":
+                    J += d["wall_q"]
+                elif kind == "flame_x":
+                    J += pr.nx - d["sum_theta"] / (pr.n_fluid / pr.nx)
+                else:
+                    raise ValueError(kind)
             self.step(1)
         return J
 

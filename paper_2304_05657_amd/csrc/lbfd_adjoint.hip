@@ -1,9 +1,10 @@
 // lbfd_adjoint.hip -- discrete adjoint of the coupled step (FP64).
 //
-// The objective is the time-integrated wall heat flux
-//   J = sum_{n = 0}^{N-1} q(s^n),  q = sum over fluid cells and axis sides
-//   whose first neighbour is an isothermal wall of 2 alpha rho(T_w, Y)(T - T_w),
-// and the state s^n = (post-collision populations read by step n, T^n, Y^n).
+// The objective is J = sum_{n = 0}^{N-1} w_n q(s^n), w_n = 1 inside the
+// chosen window of levels, with q either the wall heat flux (the sum over
+// fluid cells and axis sides whose first neighbour is an isothermal wall of
+// 2 alpha rho(T_w, Y)(T - T_w)) or the flame position
+// nx - sum_cells (T - T_u)/(T_b - T_u) nx / n_fluid, and the state s^n = (post-collision populations read by step n, T^n, Y^n).
 // With s^{n+1} = F(s^n; theta), theta = (wall temperatures, A_j, Ta_j), the
 // adjoint recursion is lambda^N = 0,
 //   lambda^n = (dF/ds^n)^T lambda^{n+1} + (dq/ds^n)^T,
@@ -362,6 +363,8 @@ struct AdjParams {
     double *lam_sc;         // [1+NSP][N]
     double *dwallT;         // [N] dJ/d wall_T (accumulated)
     double *dparam;         // [2 n_rx]: dJ/dA_j, dJ/dTa_j (accumulated)
+    int obj_kind;           // LBFD_OBJ_*
+    double obj_w;           // weight of this level's q (flame position: times dq/dT of a cell)
 };
 
 template <int Q, int NSP>
@@ -393,7 +396,11 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(const AdjParams AP)
             }
             Dual out[Q + 1 + NSP], qc;
             cell_eval<Q, NSP, Dual>(P, in, seed, out, qc);
-            double contrib = qc.d;
+            // the objective's share: the wall heat flux through this cell's
+            // walls, or the flame position's linear term in the cell's own T
+            double contrib = AP.obj_kind == LBFD_OBJ_WALL_HEAT_FLUX ? AP.obj_w * qc.d
+                             : seed == S::scal                      ? AP.obj_w
+                                                                    : 0.0;
             for (int o = 0; o < Q + 1 + NSP; ++o) contrib += lam_out[o] * out[o].d;
             if (seed < S::scal) {
                 atomicAdd(&AP.lam_pop[(long long)in.tdir[seed] * P.N + in.tcell[seed]], contrib);
@@ -412,15 +419,16 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(const AdjParams AP)
         if (red[j] != 0.0) atomicAdd(&AP.dparam[j], red[j]);
 }
 
-__global__ void accumulate_kernel(double *acc, const double *v)
+__global__ void accumulate_kernel(double *acc, const double *diag, int slot, double a, double b)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *acc += *v;
+    if (threadIdx.x == 0 && blockIdx.x == 0) *acc += a * diag[slot] + b;
 }
 
 bool adjoint_supported(int Q, int nsp) { return (Q == 9 && nsp == 4) || (Q == 27 && nsp == 4); }
 
 hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_pop_next, const double *lam_sc_next,
-                          double *lam_pop, double *lam_sc, double *dwallT, double *dparam, hipStream_t s)
+                          double *lam_pop, double *lam_sc, double *dwallT, double *dparam, int obj_kind,
+                          double obj_w, hipStream_t s)
 {
     AdjParams ap;
     ap.k = kp;
@@ -430,6 +438,8 @@ hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_p
     ap.lam_sc = lam_sc;
     ap.dwallT = dwallT;
     ap.dparam = dparam;
+    ap.obj_kind = obj_kind;
+    ap.obj_w = obj_w;
     const unsigned nb = (unsigned)((kp.N + kBlock - 1) / kBlock);
     if (Q == 9 && nsp == 4)
         adjoint_kernel<9, 4><<<nb, kBlock, 0, s>>>(ap);
@@ -440,9 +450,9 @@ hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_p
     return hipGetLastError();
 }
 
-hipError_t launch_accumulate(double *acc, const double *v, hipStream_t s)
+hipError_t launch_accumulate(double *acc, const double *diag, int slot, double a, double b, hipStream_t s)
 {
-    accumulate_kernel<<<1, 1, 0, s>>>(acc, v);
+    accumulate_kernel<<<1, 1, 0, s>>>(acc, diag, slot, a, b);
     return hipGetLastError();
 }
 

@@ -64,6 +64,8 @@ struct lbfd_ctx {
     long long N;
     hipStream_t stream;
     Streams streams = {nullptr, 0};
+    int obj_kind = LBFD_OBJ_WALL_HEAT_FLUX;  // objective of lbfd_objective / lbfd_adjoint
+    int64_t obj_t0 = 0, obj_t1 = INT64_MAX;  // its window of level offsets
     long long n_fluid = 0;
     void *pop[2] = {nullptr, nullptr};
     void *sc[2] = {nullptr, nullptr};
@@ -806,6 +808,43 @@ struct AdjBuffers {
 };
 }  // namespace
 
+// The selected objective's share of level offset t: accumulate coefficients
+// (*acc += a diag[slot] + b) and the adjoint weight.
+struct ObjTerm {
+    bool on;
+    int slot;
+    double a, b, w;
+};
+
+static ObjTerm objective_term(const lbfd_ctx *c, int64_t t)
+{
+    ObjTerm o{t >= c->obj_t0 && t < c->obj_t1, kWallQ, 1.0, 0.0, 1.0};
+    if (c->obj_kind == LBFD_OBJ_FLAME_POSITION) {
+        const double nx = c->p.nx, per_col = (double)c->n_fluid / nx;
+        o.slot = kTheta;
+        o.a = -1.0 / per_col;
+        o.b = nx;
+        o.w = -1.0 / (per_col * (c->p.T_b - c->p.T_u));
+    }
+    if (!o.on) o.w = 0.0;
+    return o;
+}
+
+int lbfd_set_objective(lbfd_ctx *c, int kind, int64_t t_begin, int64_t t_end)
+{
+    if (!c) return fail(LBFD_EINVAL, "null context");
+    if (kind != LBFD_OBJ_WALL_HEAT_FLUX && kind != LBFD_OBJ_FLAME_POSITION)
+        return fail(LBFD_EINVAL, "unknown objective kind %d", kind);
+    if (t_begin < 0 || t_end < t_begin) return fail(LBFD_EINVAL, "bad objective window [%lld, %lld)",
+                                                    (long long)t_begin, (long long)t_end);
+    if (kind == LBFD_OBJ_FLAME_POSITION && !(c->p.T_b > c->p.T_u))
+        return fail(LBFD_EINVAL, "the flame position needs T_b > T_u");
+    c->obj_kind = kind;
+    c->obj_t0 = t_begin;
+    c->obj_t1 = t_end;
+    return LBFD_OK;
+}
+
 int lbfd_objective(lbfd_ctx *c, int64_t nsteps, double *J)
 {
     if (!c || !J || nsteps < 0) return fail(LBFD_EINVAL, "bad arguments");
@@ -818,9 +857,11 @@ int lbfd_objective(lbfd_ctx *c, int64_t nsteps, double *J)
         k.pop_out = c->pop[1 - c->cur];
         k.sc_in = c->sc[c->cur];
         k.sc_out = c->sc[1 - c->cur];
-        e = launch_step(c->Q, c->nsp, c->prec, kModeStepDiag, k, c->streams);
-        if (e == hipSuccess) e = launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream);
-        if (e == hipSuccess) e = launch_accumulate(Jd, c->diag_dev + kWallQ, c->stream);
+        const ObjTerm o = objective_term(c, n);
+        e = launch_step(c->Q, c->nsp, c->prec, o.on ? kModeStepDiag : kModeStep, k, c->streams);
+        if (e == hipSuccess && o.on)
+            e = launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream);
+        if (e == hipSuccess && o.on) e = launch_accumulate(Jd, c->diag_dev, o.slot, o.a, o.b, c->stream);
         c->cur ^= 1;
         c->level += 1;
     }
@@ -875,9 +916,12 @@ int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwall
         k.pop_out = c->pop[1 - c->cur];
         k.sc_in = c->sc[c->cur];
         k.sc_out = c->sc[1 - c->cur];
-        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStepDiag, k, c->streams));
-        HIP_TRY(launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream));
-        HIP_TRY(launch_accumulate(Jd, c->diag_dev + kWallQ, c->stream));
+        const ObjTerm o = objective_term(c, n);
+        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, o.on ? kModeStepDiag : kModeStep, k, c->streams));
+        if (o.on) {
+            HIP_TRY(launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream));
+            HIP_TRY(launch_accumulate(Jd, c->diag_dev, o.slot, o.a, o.b, c->stream));
+        }
         c->cur ^= 1;
         c->level += 1;
     }
@@ -907,7 +951,9 @@ int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwall
             KParams k = c->base;
             k.pop_in = sg_pop(n - n0);
             k.sc_in = sg_sc(n - n0);
-            HIP_TRY(launch_adjoint(c->Q, c->nsp, k, lam[nxt], lsc[nxt], lam[cu], lsc[cu], dW, dP, c->stream));
+            const ObjTerm o = objective_term(c, n);
+            HIP_TRY(launch_adjoint(c->Q, c->nsp, k, lam[nxt], lsc[nxt], lam[cu], lsc[cu], dW, dP, c->obj_kind,
+                                   o.w, c->stream));
             nxt = cu;
         }
     }

@@ -102,8 +102,13 @@ bool supported(int Q, int nsp, int prec);
 
 // Adjoint (lbfd_adjoint.hip): one backward step of the FP64 coupled step.
 bool adjoint_supported(int Q, int nsp);
+// The objective's share of one level: kind LBFD_OBJ_*, weight w (0 outside
+// the objective's window; for the flame position w carries d x_f / d T of
+// one cell, -nx / (n_fluid (T_b - T_u))).
 hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_pop_next, const double *lam_sc_next,
-                          double *lam_pop, double *lam_sc, double *dwallT, double *dparam, hipStream_t s);
-hipError_t launch_accumulate(double *acc, const double *v, hipStream_t s);
+                          double *lam_pop, double *lam_sc, double *dwallT, double *dparam, int obj_kind,
+                          double obj_w, hipStream_t s);
+// *acc += a * diag[slot] + b (one thread).
+hipError_t launch_accumulate(double *acc, const double *diag, int slot, double a, double b, hipStream_t s);
 
 }  // namespace lbfd

@@ -26,8 +26,10 @@ ERRORS = {0: "LBFD_OK", -1: "LBFD_EINVAL", -2: "LBFD_ENOMEM", -3: "LBFD_EDEVICE"
 EXPORTS = ("lbfd_init", "lbfd_step", "lbfd_sync", "lbfd_level", "lbfd_read_fields",
            "lbfd_diagnostics", "lbfd_set_wall_temperature", "lbfd_state_size",
            "lbfd_save_state", "lbfd_load_state", "lbfd_time_steps", "lbfd_time_kernels",
-           "lbfd_cell_counts", "lbfd_step_launches", "lbfd_set_reaction", "lbfd_objective", "lbfd_adjoint", "lbfd_destroy",
-           "lbfd_strerror", "lbfd_last_error")
+           "lbfd_cell_counts", "lbfd_step_launches", "lbfd_set_reaction", "lbfd_set_objective",
+           "lbfd_objective", "lbfd_adjoint", "lbfd_destroy", "lbfd_strerror", "lbfd_last_error")
+# objective kinds (lbfd_set_objective)
+OBJECTIVES = {"wall_q": 0, "flame_x": 1}
 
 
 class LbfdError(RuntimeError):
@@ -93,6 +95,7 @@ def load_library():
     lib.lbfd_step_launches.argtypes = [vp]
     lib.lbfd_step_launches.restype = C.c_int
     lib.lbfd_set_reaction.argtypes = [vp, C.c_int, C.c_double, C.c_double, C.c_double]
+    lib.lbfd_set_objective.argtypes = [vp, C.c_int, C.c_int64, C.c_int64]
     lib.lbfd_objective.argtypes = [vp, C.c_int64, dp]
     lib.lbfd_adjoint.argtypes = [vp, C.c_int64, C.c_int, dp, dp, dp, dp]
     lib.lbfd_destroy.argtypes = [vp]
@@ -225,11 +228,19 @@ class Solver:
         n = self._lib.lbfd_step_launches(self._h)
         _check(self._lib, min(n, 0))
         return n
+
     def set_reaction(self, j: int, A: float, b: float, Ta: float):
         _check(self._lib, self._lib.lbfd_set_reaction(self._h, int(j), float(A), float(b), float(Ta)))
 
+    def set_objective(self, kind: str = "wall_q", t_begin: int = 0, t_end: int | None = None):
+        """Objective of objective() / adjoint(): the sum of q(level) over the
+        level offsets t_begin <= t < t_end of those calls, q = "wall_q" (wall
+        heat flux) or "flame_x" (flame position, cells)."""
+        t_end = (1 << 63) - 1 if t_end is None else int(t_end)
+        _check(self._lib, self._lib.lbfd_set_objective(self._h, OBJECTIVES[kind], int(t_begin), t_end))
+
     def objective(self, nsteps: int) -> float:
-        """Time-integrated wall heat flux over the next nsteps levels (forward only)."""
+        """The selected objective over the next nsteps levels (forward only)."""
         J = C.c_double()
         _check(self._lib, self._lib.lbfd_objective(self._h, int(nsteps), C.byref(J)))
         return J.value
