@@ -131,7 +131,12 @@ typedef struct {
  *  wall_q    per fluid cell and axis side whose first neighbour is an
  *            isothermal solid or wall face: 2 alpha rho(T_w, Y) (T - T_w)
  *  fuel_rate sum of the per-step consumption of species 0
- *  step      level the diagnostics refer to */
+ *  step      level the diagnostics refer to
+ *  fuel_mass_rate     sum of rho times the per-step consumption of species 0
+ *  consumption_speed  fuel_mass_rate / (rho_in Y_in[0] A), A = n_fluid / nx
+ *            (mean fluid cross-section): the speed, in cells per step, of a
+ *            flat flame consuming fuel at that rate; the ratio of two runs'
+ *            values is the normalised consumption speed of Sec. IV.C */
 typedef struct {
     double sum_g, sum_xi, mom[3], max_abs_sumY_minus_1;
     int64_t nonfinite;
@@ -139,6 +144,7 @@ typedef struct {
     int64_t hrr_idx;
     double hrr_max, wall_q, fuel_rate;
     int64_t step;
+    double fuel_mass_rate, consumption_speed;
 } lbfd_diag;
 
 typedef struct lbfd_ctx lbfd_ctx;
@@ -176,6 +182,28 @@ int lbfd_read_fields(lbfd_ctx *c, double *rho, double *u, double *T,
 
 /* Diagnostics of the current level (synchronous). */
 int lbfd_diagnostics(lbfd_ctx *c, lbfd_diag *d);
+
+/* Inlet velocity profile of the x face `face` (0: -x, 1: +x), which must
+ * be an INFLOW face: u [3][nz][ny] (host, lattice units) is the velocity
+ * imposed (Eq. 31) on every population entering the box through that face
+ * at the fluid cell (face cell, y, z); NULL restores the uniform u_in of the
+ * parameters.  The current state is unchanged: the profile applies to the
+ * populations entering from the next step on. */
+int lbfd_set_inflow(lbfd_ctx *c, int face, const double *u);
+
+/* Flame holding (Sec. IV.A: the flow rate follows the flame speed so that
+ * the front stays in the box): run nsteps steps in cycles of `every`; after
+ * each cycle set the inlet velocity of the INFLOW x face (the -x face if
+ * both are) to U times the profile's shape (the profile at the call,
+ * normalised to a unit mean normal velocity over the face's fluid cells;
+ * uniform if that mean is zero), with
+ *   U = max(0, consumption_speed - gain (x_f - x_target)),
+ * x_f = nx - sum_theta / (n_fluid / nx) (cells from the -x face, as the
+ * flame-position objective).  u_mean and x_flame (may be NULL) receive U
+ * and x_f of each cycle (nsteps / every entries).  LBFD_ENONFINITE if a
+ * cycle ends in a non-finite state. */
+int lbfd_hold_flame(lbfd_ctx *c, int64_t nsteps, int every, double x_target, double gain, double *u_mean,
+                    double *x_flame);
 
 /* Replace the wall temperature of isothermal solid cells (host [N]). */
 int lbfd_set_wall_temperature(lbfd_ctx *c, const double *wall_T);

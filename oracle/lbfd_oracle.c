@@ -60,6 +60,7 @@ struct lbo_state {
     double *ux;     /* velocity of every fluid cell at the current level */
     long level;
     const uint8_t *active;  /* NULL, or the cells a step / fields call covers */
+    double *u_face;         /* NULL, or [2 x faces][3][nz][ny] inlet velocity per face cell */
 };
 
 /* Whether a fluid cell is covered by the current active set. */
@@ -718,9 +719,15 @@ static void stream(lbo_state *s)
                     if (src.kind == K_FLUID) {
                         v = s->gstar[i * N + src.idx];
                     } else if (src.kind == K_INFLOW) {
+                        /* an x face may carry a profile: the velocity of the
+                           receiving cell's (y, z) on that face */
                         double cu = 0.0;
-                        for (int d = 0; d < 3; ++d)
-                            cu += s->c[i][d] * p->u_in[d];
+                        for (int d = 0; d < 3; ++d) {
+                            double ud = p->u_in[d];
+                            if (s->u_face && (src.face == 0 || src.face == 1))
+                                ud = s->u_face[((long)(3 * src.face + d) * p->nz + z) * p->ny + y];
+                            cu += s->c[i][d] * ud;
+                        }
                         v = s->gstar[opp * N + idx] + 2.0 * s->w[i] * rho_in * cu;
                     } else if (src.kind == K_OUTFLOW) {
                         int d = src.face / 2;
@@ -797,6 +804,31 @@ long lbo_level(const lbo_state *s) { return s->level; }
  */
 void lbo_set_active(lbo_state *s, const uint8_t *active) { s->active = active; }
 
+/*
+ * Inlet velocity profile of x face `face` (0: -x, 1: +x): u [3][nz][ny] is
+ * imposed (Eq. 31) on the populations entering through that face at the
+ * fluid cell (face cell, y, z); NULL restores the uniform u_in.  Returns 0,
+ * or -1 for a face that is not 0 or 1.
+ */
+int lbo_set_inflow(lbo_state *s, int face, const double *u)
+{
+    const lbo_params *p = &s->p;
+    long nf = (long)p->ny * p->nz;
+    if (face != 0 && face != 1)
+        return -1;
+    if (!s->u_face) {
+        s->u_face = (double *)malloc(sizeof(double) * 6 * nf);
+        for (int f = 0; f < 2; ++f)
+            for (int d = 0; d < 3; ++d)
+                for (long i = 0; i < nf; ++i)
+                    s->u_face[(3 * f + d) * nf + i] = p->u_in[d];
+    }
+    for (int d = 0; d < 3; ++d)
+        for (long i = 0; i < nf; ++i)
+            s->u_face[(3 * face + d) * nf + i] = u ? u[d * nf + i] : p->u_in[d];
+    return 0;
+}
+
 void lbo_set_threads(int n)
 {
 #ifdef _OPENMP
@@ -865,11 +897,14 @@ void lbo_fields(lbo_state *s, double *rho, double *u, double *T, double *Y, doub
  *      side whose first neighbour is an isothermal solid or wall face,
  *      2 alpha rho_B (T - T_w), rho_B = rho(T_w, Y) (ghost-consistent)
  *  [11] fuel consumption: sum of -src(Y_0)
+ *  [12] fuel mass consumption: sum of -rho src(Y_0)
+ *  [13] consumption speed: [12] / (rho(T_in, Y_in) Y_in[0] n_fluid / nx),
+ *       cells per step (cells with a non-finite state are not counted)
  */
 void lbo_diagnostics(lbo_state *s, double *out)
 {
     if (s->active) {
-        for (int k = 0; k < 12; ++k)
+        for (int k = 0; k < LBO_NDIAG; ++k)
             out[k] = NAN;
         return;
     }
@@ -882,6 +917,7 @@ void lbo_diagnostics(lbo_state *s, double *out)
         out[k] = 0.0;
     out[8] = -1.0;
     out[9] = -INFINITY;
+    long nfluid = 0;
     for (int z = 0; z < p->nz; ++z)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
@@ -914,6 +950,8 @@ void lbo_diagnostics(lbo_state *s, double *out)
                     out[8] = (double)idx;
                 }
                 out[11] += -o.src_Y[0];
+                out[12] += -o.src_Y[0] * o.rho;
+                nfluid += 1;
                 double Yc[LBO_MAXSP];
                 for (int k = 0; k < ns; ++k)
                     Yc[k] = s->Y[k * N + idx];
@@ -927,6 +965,10 @@ void lbo_diagnostics(lbo_state *s, double *out)
                             out[10] += 2.0 * alpha * density(p, nb.Tw, Yc) * (s->T[idx] - nb.Tw);
                     }
             }
+    /* consumption speed: the fuel mass consumed per step over the fuel mass
+       flux of fresh inflow gas through the mean fluid cross-section */
+    double fresh = density(p, p->T_in, p->Y_in) * p->Y_in[0] * ((double)nfluid / p->nx);
+    out[13] = fresh > 0.0 ? out[12] / fresh : 0.0;
 }
 
 void lbo_get_pops(const lbo_state *s, double *g)
@@ -1033,5 +1075,6 @@ void lbo_destroy(lbo_state *s)
         return;
     free(s->mask); free(s->wall_T); free(s->g); free(s->gn); free(s->gstar);
     free(s->T); free(s->Tn); free(s->Y); free(s->Yn); free(s->rho); free(s->ux);
+    free(s->u_face);
     free(s);
 }

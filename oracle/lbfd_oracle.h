@@ -67,7 +67,7 @@ typedef struct {
 typedef struct lbo_state lbo_state;
 
 /* Diagnostics of the state at the current level, see lbo_diagnostics. */
-#define LBO_NDIAG 12
+#define LBO_NDIAG 14
 
 lbo_state *lbo_create(const lbo_params *p, const uint8_t *mask,
                       const double *wall_T, const double *T0,
@@ -77,6 +77,7 @@ void lbo_destroy(lbo_state *s);
 int lbo_step(lbo_state *s, long nsteps);
 long lbo_level(const lbo_state *s);
 void lbo_set_active(lbo_state *s, const uint8_t *active);
+int lbo_set_inflow(lbo_state *s, int face, const double *u);
 void lbo_fields(lbo_state *s, double *rho, double *u, double *T, double *Y,
                 double *Ph);
 void lbo_diagnostics(lbo_state *s, double *out);

@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liblbfd_oracle.so")
 
 MAXSP = 16
 MAXRX = 32
-NDIAG = 12
+NDIAG = 14
 FACE_CODES = {"periodic": 0, "wall": 1, "inflow": 2, "outflow": 3, "wall_adiabatic": 4}
 
 
@@ -102,6 +102,8 @@ def _load():
         lib.lbo_level.argtypes = [C.c_void_p]
         lib.lbo_level.restype = C.c_long
         lib.lbo_set_active.argtypes = [C.c_void_p, C.c_void_p]
+        lib.lbo_set_inflow.argtypes = [C.c_void_p, C.c_int, dp]
+        lib.lbo_set_inflow.restype = C.c_int
         lib.lbo_fields.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
         lib.lbo_diagnostics.argtypes = [C.c_void_p, dp]
         lib.lbo_get_pops.argtypes = [C.c_void_p, dp]
@@ -204,6 +206,14 @@ class Oracle:
             self._lib.lbo_destroy(h)
             self._h = None
 
+    def set_inflow(self, face: int, u=None):
+        """Inlet velocity profile u [3, nz, ny] of x face 0 (-x) or 1 (+x);
+        None restores the uniform inflow velocity."""
+        pr = self.prob
+        a = None if u is None else np.ascontiguousarray(u, dtype=np.float64).reshape(3 * pr.nz * pr.ny)
+        if self._lib.lbo_set_inflow(self._h, int(face), _dp(a)) != 0:
+            raise ValueError("inlet profiles are set on x faces 0 and 1")
+
     def set_threads(self, n: int):
         """OpenMP threads of the following steps (process-wide)."""
         self._lib.lbo_set_threads(int(n))
@@ -268,7 +278,7 @@ class Oracle:
         return {"sum_g": out[0], "sum_xi": out[1], "mom": out[2:5].copy(),
                 "max_sumY_err": out[5], "nonfinite": int(out[6]), "sum_theta": out[7],
                 "hrr_idx": int(out[8]), "hrr_max": out[9], "wall_q": out[10],
-                "fuel_rate": out[11]}
+                "fuel_rate": out[11], "fuel_mass_rate": out[12], "consumption_speed": out[13]}
 
     def objective(self, nsteps: int, kind: str = "wall_q", t_begin: int = 0, t_end: int | None = None) -> float:
         """Sum over the next nsteps levels, offsets t_begin <= t < t_end, of

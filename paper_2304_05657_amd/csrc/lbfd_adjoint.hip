@@ -107,10 +107,7 @@ __device__ void gather_inputs(const KParams &P, int x, int y, int z, long long i
             } else {
                 in.tdir[i] = opp;
                 in.tcell[i] = (int)idx;
-                if (s.kind == kInflow) {
-                    const double cu = cx * P.u_in[0] + cy * P.u_in[1] + cz * P.u_in[2];
-                    in.corr[i] = 2.0 * L::w(i) * P.rho_in * cu;
-                }
+                if (s.kind == kInflow) in.corr[i] = 2.0 * L::w(i) * P.rho_in * inflow_cu_c(P, cx, cy, cz, x, y, z);
             }
         }
         in.g[i] = pop[(long long)in.tdir[i] * P.N + in.tcell[i]];

@@ -84,6 +84,9 @@ struct lbfd_ctx {
     double *wall_T = nullptr;
     double *outlet = nullptr;
     double *outlet_un = nullptr;
+    double *inflow_u = nullptr;         // [2 x faces][3][nz][ny] inlet velocity profiles
+    double *inflow_du = nullptr;        // [3][nz][ny] staging of a profile change
+    std::vector<double> inflow_host;   // host copy
     size_t outlet_n = 0;
     double *fields = nullptr;
     double *partials = nullptr;
@@ -100,7 +103,7 @@ static void free_ctx(lbfd_ctx *c)
 {
     if (!c) return;
     void *ptrs[] = {c->pop[0], c->pop[1], c->sc[0], c->sc[1], c->mask, c->code, c->boundary, c->bsrc, c->bpt, c->bwk,
-                    c->btw, c->wall_T, c->outlet, c->outlet_un,
+                    c->btw, c->wall_T, c->outlet, c->outlet_un, c->inflow_u, c->inflow_du,
                     c->fields, c->partials, c->diag_dev, c->bad_dev, c->rx_dev};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -371,6 +374,7 @@ static KParams make_kparams(const lbfd_ctx *c)
     k.wall_T = c->wall_T;
     k.outlet = c->outlet;
     k.outlet_un = c->outlet_un;
+    k.inflow_u = c->inflow_u;
     k.fields = c->fields;
     k.partials = c->partials;
     k.rx = c->rx_dev;
@@ -458,12 +462,14 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     // that the interior tiles after them start on XCD 0
     c->nblocks = c->nblocks_interior + (int)(((c->n_boundary + kBlock - 1) / kBlock + 7) / 8 * 8);
 
-#define ALLOC(ptr, bytes)                                                          \
-    do {                                                                           \
-        if (hipMalloc((void **)&(ptr), (bytes)) != hipSuccess) {                   \
-            free_ctx(c);                                                           \
-            return fail(LBFD_ENOMEM, "hipMalloc of %zu bytes failed", (size_t)(bytes)); \
-        }                                                                          \
+#define ALLOC(ptr, bytes)                                                                   \
+    do {                                                                                    \
+        const hipError_t ea_ = hipMalloc((void **)&(ptr), (bytes));                         \
+        if (ea_ != hipSuccess) {                                                            \
+            free_ctx(c);                                                                    \
+            return fail(LBFD_ENOMEM, "hipMalloc of %zu bytes failed: %s", (size_t)(bytes), \
+                        hipGetErrorString(ea_));                                            \
+        }                                                                                   \
     } while (0)
     ALLOC(c->pop[0], pop_bytes);
     ALLOC(c->pop[1], pop_bytes);
@@ -482,6 +488,8 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     ALLOC(c->wall_T, N * sizeof(double));
     ALLOC(c->outlet, c->outlet_n * sizeof(double));
     ALLOC(c->outlet_un, (size_t)2 * p->ny * p->nz * sizeof(double));
+    ALLOC(c->inflow_u, (size_t)6 * p->ny * p->nz * sizeof(double));
+    ALLOC(c->inflow_du, (size_t)3 * p->ny * p->nz * sizeof(double));
     ALLOC(c->partials, (size_t)c->nblocks * kNDiag * sizeof(double));
     ALLOC(c->diag_dev, kNDiag * sizeof(double));
     ALLOC(c->bad_dev, sizeof(long long));
@@ -507,6 +515,15 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     HIP_OR_FREE(hipMemset(c->pop[0], 0, pop_bytes));
     HIP_OR_FREE(hipMemset(c->pop[1], 0, pop_bytes));
     HIP_OR_FREE(hipMemset(c->outlet, 0, c->outlet_n * sizeof(double)));
+    {
+        // both x faces start with the uniform inflow velocity of the parameters
+        const size_t nf = (size_t)p->ny * p->nz;
+        c->inflow_host.assign(6 * nf, 0.0);
+        for (int f = 0; f < 2; ++f)
+            for (int d = 0; d < 3; ++d)
+                for (size_t i = 0; i < nf; ++i) c->inflow_host[(3 * f + d) * nf + i] = p->u_in[d];
+        HIP_OR_FREE(hipMemcpy(c->inflow_u, c->inflow_host.data(), 6 * nf * sizeof(double), hipMemcpyHostToDevice));
+    }
     HIP_OR_FREE(hipMemcpy(c->mask, mask, N, hipMemcpyHostToDevice));
     HIP_OR_FREE(hipMemcpy(c->code, code.data(), N, hipMemcpyHostToDevice));
     if (!boundary.empty())
@@ -654,6 +671,90 @@ int lbfd_diagnostics(lbfd_ctx *c, lbfd_diag *d)
     d->wall_q = a[kWallQ];
     d->fuel_rate = a[kFuel];
     d->step = c->level;
+    d->fuel_mass_rate = a[kFuelMass];
+    const double fresh = c->base.rho_in * c->p.Y_in[0] * ((double)c->n_fluid / c->p.nx);
+    d->consumption_speed = fresh > 0.0 ? a[kFuelMass] / fresh : 0.0;
+    return LBFD_OK;
+}
+
+int lbfd_set_inflow(lbfd_ctx *c, int face, const double *u)
+{
+    if (!c) return fail(LBFD_EINVAL, "null context");
+    if (face != 0 && face != 1) return fail(LBFD_EINVAL, "inlet profiles are set on x faces (0 or 1)");
+    if (c->p.face[face] != LBFD_FACE_INFLOW) return fail(LBFD_EINVAL, "face %d is not an INFLOW face", face);
+    const size_t nf = (size_t)c->p.ny * c->p.nz;
+    for (size_t i = 0; u && i < 3 * nf; ++i)
+        if (!std::isfinite(u[i])) return fail(LBFD_EINVAL, "non-finite inlet velocity");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double *dst = c->inflow_host.data() + 3 * nf * face;
+    std::vector<double> du(3 * nf);
+    for (int d = 0; d < 3; ++d)
+        for (size_t i = 0; i < nf; ++i) {
+            const double v = u ? u[d * nf + i] : c->p.u_in[d];
+            du[d * nf + i] = dst[d * nf + i] - v;
+            dst[d * nf + i] = v;
+        }
+    // the current level keeps its entering populations; the new profile
+    // applies from the next streaming on
+    HIP_TRY(hipMemcpy(c->inflow_du, du.data(), 3 * nf * sizeof(double), hipMemcpyHostToDevice));
+    KParams k = c->base;
+    k.pop_in = c->pop[c->cur];
+    k.pop_out = c->pop[c->cur];
+    HIP_TRY(launch_inflow_shift(c->Q, c->prec, k, face, c->inflow_du, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->inflow_u + 3 * nf * face, dst, 3 * nf * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LBFD_OK;
+}
+
+int lbfd_hold_flame(lbfd_ctx *c, int64_t nsteps, int every, double x_target, double gain, double *u_mean,
+                    double *x_flame)
+{
+    if (!c || nsteps < 0 || every < 1 || !(gain >= 0.0)) return fail(LBFD_EINVAL, "bad arguments");
+    const int face = c->p.face[0] == LBFD_FACE_INFLOW ? 0 : c->p.face[1] == LBFD_FACE_INFLOW ? 1 : -1;
+    if (face < 0) return fail(LBFD_EINVAL, "flame holding needs an INFLOW x face");
+    const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
+    const size_t nf = (size_t)ny * nz;
+    // shape of the current profile, scaled to a unit mean of the inward
+    // normal velocity over the fluid cells next to the face (a uniform
+    // inward unit velocity when that mean is zero)
+    const int xc = face == 0 ? 0 : nx - 1;
+    const double sign = face == 0 ? 1.0 : -1.0;  // inward normal along x
+    std::vector<double> shape(c->inflow_host.begin() + 3 * nf * face, c->inflow_host.begin() + 3 * nf * (face + 1));
+    double mean = 0.0;
+    long long nface = 0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            if (c->mask_host[((size_t)z * ny + y) * nx + xc] == LBFD_FLUID) {
+                mean += sign * shape[(size_t)z * ny + y];
+                ++nface;
+            }
+    if (nface == 0) return fail(LBFD_EINVAL, "no fluid cell next to the inflow face");
+    mean /= (double)nface;
+    if (std::fabs(mean) > 0.0) {
+        for (double &v : shape) v /= mean;
+    } else {
+        std::fill(shape.begin(), shape.end(), 0.0);
+        for (size_t i = 0; i < nf; ++i) shape[i] = sign;
+    }
+    std::vector<double> prof(3 * nf);
+    const int64_t ncycle = nsteps / every;
+    for (int64_t k = 0; k < ncycle; ++k) {
+        int rc = lbfd_step(c, every);
+        if (rc) return rc;
+        lbfd_diag d;
+        rc = lbfd_diagnostics(c, &d);
+        if (rc) return rc;
+        if (d.nonfinite > 0) return fail(LBFD_ENONFINITE, "non-finite state at level %lld", (long long)c->level);
+        const double xf = nx - d.sum_theta / ((double)c->n_fluid / nx);
+        double U = d.consumption_speed - gain * (xf - x_target);
+        if (U < 0.0) U = 0.0;
+        for (size_t i = 0; i < 3 * nf; ++i) prof[i] = U * shape[i];
+        rc = lbfd_set_inflow(c, face, prof.data());
+        if (rc) return rc;
+        if (u_mean) u_mean[k] = U;
+        if (x_flame) x_flame[k] = xf;
+    }
     return LBFD_OK;
 }
 

@@ -65,6 +65,54 @@ hipError_t launch_init(int Q, int nsp, int prec, const KParams &kp, const double
     return hipErrorInvalidValue;
 }
 
+// When the inlet profile of x face `face` changes by -du (du = old - new,
+// [3][nz][ny]), the stored outgoing population g*_opp of each fluid cell
+// next to that face is shifted by 2 w_i rho_in c_i.du for every direction i
+// entering through the face: those values are read only by the inlet rule
+// of the same cell (they stream out of the box), so the populations
+// entering at the current level keep the values the old profile gave them,
+// and the new profile applies from the next streaming on.
+template <int Q, int PREC>
+__global__ void __launch_bounds__(kBlock) inflow_shift_kernel(const KParams P, int face, const double *du)
+{
+    using L = Lat<Q>;
+    using C = typename Prec<PREC>::calc;
+    const long long nf = (long long)P.ny * P.nz;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nf) return;
+    const int y = (int)(t % P.ny), z = (int)(t / P.ny);
+    const int x = face ? P.nx - 1 : 0, cin = face ? -1 : 1;
+    const long long idx = ((long long)z * P.ny + y) * P.nx + x;
+    if (P.mask[idx] != LBFD_FLUID) return;
+    sfor<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int opp = Q - 1 - i;
+        if constexpr (L::cx(i) != 0) {
+            if (L::cx(i) == cin) {
+                const Nb s = classify(P, x - L::cx(i), y - L::cy(i), z - L::cz(i));
+                if (s.kind == kInflow && s.face == face) {
+                    const double cdu = L::cx(i) * du[t] + L::cy(i) * du[nf + t] + L::cz(i) * du[2 * nf + t];
+                    const C v = pop_load<Q, PREC, opp>(P.pop_in, P.N, idx) + (C)(2.0 * L::w(i) * P.rho_in * cdu);
+                    pop_store<Q, PREC, opp>(P.pop_out, P.N, idx, v);
+                }
+            }
+        }
+    });
+}
+
+hipError_t launch_inflow_shift(int Q, int prec, const KParams &kp, int face, const double *du, hipStream_t s)
+{
+    const unsigned nb = (unsigned)(((long long)kp.ny * kp.nz + kBlock - 1) / kBlock);
+#define SHIFT(q, p)                                                                        \
+    if (Q == q && prec == p) {                                                             \
+        inflow_shift_kernel<q, p><<<dim3(nb), dim3(kBlock), 0, s>>>(kp, face, du);         \
+        return hipGetLastError();                                                          \
+    }
+    SHIFT(9, 0) SHIFT(9, 1) SHIFT(9, 2) SHIFT(27, 0) SHIFT(27, 1) SHIFT(27, 2)
+#undef SHIFT
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_finalize(const double *partials, int nblocks, double *out, long long *first_bad,
                            long long level, hipStream_t s)
 {

@@ -10,13 +10,13 @@
 namespace lbfd {
 
 constexpr int kMaxSp = LBFD_MAX_SPECIES;
-constexpr int kNDiag = 12;  // per-block partial diagnostics, see DiagSlot
+constexpr int kNDiag = 13;  // per-block partial diagnostics, see DiagSlot
 constexpr int kBlock = 256;
 
 // Slots of the per-block and final diagnostics arrays (double).
 enum DiagSlot {
     kSumG = 0, kSumXi = 1, kMomX = 2, kMomY = 3, kMomZ = 4, kMaxY = 5,
-    kNonfinite = 6, kTheta = 7, kHrrMax = 8, kHrrIdx = 9, kWallQ = 10, kFuel = 11
+    kNonfinite = 6, kTheta = 7, kHrrMax = 8, kHrrIdx = 9, kWallQ = 10, kFuel = 11, kFuelMass = 12
 };
 
 // Per-cell geometry code: solid, interior fluid (every pull source and
@@ -67,6 +67,7 @@ struct KParams {
     double T_ref, W_ref, T_ref_over_W_ref;
     double invW[kMaxSp];
     double u_in[3], T_in, Y_in[kMaxSp], rho_in;
+    const double *inflow_u;  // [2 x faces][3][nz][ny] inlet velocity of the cells next to an x face
     double T_u, T_b;
 };
 
@@ -96,6 +97,9 @@ struct Streams {
 hipError_t launch_step(int Q, int nsp, int prec, int mode, const KParams &kp, const Streams &s);
 hipError_t launch_init(int Q, int nsp, int prec, const KParams &kp, const double *u0,
                        const double *Ph0, dim3 grid, dim3 block, hipStream_t s);
+// Keep the populations entering through inflow face `face` at the current
+// level when its profile changes by -du (lbfd_dispatch.hip).
+hipError_t launch_inflow_shift(int Q, int prec, const KParams &kp, int face, const double *du, hipStream_t s);
 hipError_t launch_finalize(const double *partials, int nblocks, double *out,
                            long long *first_bad, long long level, hipStream_t s);
 bool supported(int Q, int nsp, int prec);

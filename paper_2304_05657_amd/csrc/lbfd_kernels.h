@@ -175,6 +175,31 @@ __device__ __forceinline__ long long outlet_index(const KParams &P, int face, in
     return ((long long)((face & 1) * Q + i) * P.nz + z) * P.ny + y;
 }
 
+// c_I . u_in for population I of fluid cell (x, y, z) entering through an
+// inflow face (Eq. 31): an x face carries a per-cell inlet profile, indexed
+// by the entering cell's (y, z); other faces the uniform inflow velocity.
+// (A source beyond an x inflow face and another non-periodic face is the
+// wall's, or the x face's: walls rank first, then the lower axis.)
+__device__ __forceinline__ double inflow_cu_c(const KParams &P, int cx, int cy, int cz, int x, int y, int z)
+{
+    const int f = (cx == 1 && x == 0 && P.face[0] == LBFD_FACE_INFLOW)               ? 0
+                  : (cx == -1 && x == P.nx - 1 && P.face[1] == LBFD_FACE_INFLOW) ? 1
+                                                                                 : -1;
+    if (f >= 0) {
+        const long long s = (long long)P.ny * P.nz;
+        const double *u = P.inflow_u + 3 * s * f + (long long)z * P.ny + y;
+        return cx * u[0] + cy * u[s] + cz * u[2 * s];
+    }
+    return cx * P.u_in[0] + cy * P.u_in[1] + cz * P.u_in[2];
+}
+
+template <int Q, int I>
+__device__ __forceinline__ double inflow_cu(const KParams &P, int x, int y, int z)
+{
+    using L = Lat<Q>;
+    return inflow_cu_c(P, L::cx(I), L::cy(I), L::cz(I), x, y, z);
+}
+
 // Post-streaming population i of fluid cell (x, y, z) at the current level
 // from the post-collision buffer: pull from r - c_i; half-way bounce-back
 // from a solid or wall; velocity inlet (Eq. 31 in g units:
@@ -191,7 +216,7 @@ __device__ __forceinline__ typename Prec<PREC>::calc gather(const KParams &P, in
         Nb s = classify(P, x - L::cx(I), y - L::cy(I), z - L::cz(I));
         if (s.kind == kFluid) return pop_load<Q, PREC, I>(P.pop_in, P.N, s.idx);
         if (s.kind == kInflow) {
-            double cu = L::cx(I) * P.u_in[0] + L::cy(I) * P.u_in[1] + L::cz(I) * P.u_in[2];
+            const double cu = inflow_cu<Q, I>(P, x, y, z);
             return pop_load<Q, PREC, OPP>(P.pop_in, P.N, idx) + (C)(2.0 * L::w(I) * P.rho_in * cu);
         }
         if (s.kind == kOutflow) {
@@ -275,7 +300,7 @@ __device__ __forceinline__ void ghost(const KParams &P, const Nb &w, const Pt<NS
 // init (same rules as gather / axis_stencil, resolved once on the host).
 template <int Q, int PREC, int I>
 __device__ __forceinline__ typename Prec<PREC>::calc desc_pull(const KParams &P, long long t, long long nb,
-                                                               long long idx, int y, int z)
+                                                               long long idx, int x, int y, int z)
 {
     using C = typename Prec<PREC>::calc;
     using L = Lat<Q>;
@@ -286,7 +311,7 @@ __device__ __forceinline__ typename Prec<PREC>::calc desc_pull(const KParams &P,
         const int src = P.bsrc[I * nb + t];
         if (src >= 0) return pop_load<Q, PREC, I>(P.pop_in, P.N, (uint32_t)src);
         if (src == kSrcInflow) {
-            const double cu = L::cx(I) * P.u_in[0] + L::cy(I) * P.u_in[1] + L::cz(I) * P.u_in[2];
+            const double cu = inflow_cu<Q, I>(P, x, y, z);
             return pop_load<Q, PREC, OPP>(P.pop_in, P.N, (uint32_t)idx) + (C)(2.0 * L::w(I) * P.rho_in * cu);
         }
         if (src == kSrcOutlet) return (C)P.outlet[outlet_index(P, L::cx(I) < 0 ? 1 : 0, I, Q, y, z)];
@@ -526,6 +551,7 @@ __device__ __forceinline__ void diag_combine(double (&a)[kNDiag], const double *
     }
     a[kWallQ] += b[kWallQ];
     a[kFuel] += b[kFuel];
+    a[kFuelMass] += b[kFuelMass];
 }
 
 __device__ __forceinline__ void diag_identity(double (&a)[kNDiag])
@@ -658,6 +684,7 @@ __device__ __forceinline__ void finish_cell(const KParams &P, long long idx, con
             acc[kHrrIdx] = (double)idx;
             acc[kWallQ] = wallq;
             acc[kFuel] = -srcY[0];
+            acc[kFuelMass] = -srcY[0] * (double)ctr.rho;
         }
     }
 
@@ -765,7 +792,7 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
             if constexpr (FAST)
                 g[i] = pop_load<Q, PREC, i>(P.pop_in, P.N, idx - (L::cx(i) + sy * L::cy(i) + sz * L::cz(i)));
             else
-                g[i] = desc_pull<Q, PREC, i>(P, tb, P.n_boundary, idx, y, z);
+                g[i] = desc_pull<Q, PREC, i>(P, tb, P.n_boundary, idx, x, y, z);
         });
         Pt<NSP, C> ctr;
         if constexpr (TILE)
@@ -1097,7 +1124,7 @@ __global__ void __launch_bounds__(kBlock) init_kernel(const KParams P, const dou
             if (s.kind == kFluid) {
                 pop_store<Q, PREC, i>(P.pop_out, P.N, s.idx, (C)g0);
             } else if (s.kind == kInflow) {
-                const double ci = L::cx(i) * P.u_in[0] + L::cy(i) * P.u_in[1] + L::cz(i) * P.u_in[2];
+                const double ci = inflow_cu<Q, i>(P, x, y, z);
                 pop_store<Q, PREC, opp>(P.pop_out, P.N, idx, (C)(g0 - 2.0 * L::w(i) * P.rho_in * ci));
             } else if (s.kind == kOutflow) {
                 const int sign = (s.face & 1) ? 1 : -1;

@@ -27,7 +27,8 @@ EXPORTS = ("lbfd_init", "lbfd_step", "lbfd_sync", "lbfd_level", "lbfd_read_field
            "lbfd_diagnostics", "lbfd_set_wall_temperature", "lbfd_state_size",
            "lbfd_save_state", "lbfd_load_state", "lbfd_time_steps", "lbfd_time_kernels",
            "lbfd_cell_counts", "lbfd_step_launches", "lbfd_set_reaction", "lbfd_set_objective",
-           "lbfd_objective", "lbfd_adjoint", "lbfd_destroy", "lbfd_strerror", "lbfd_last_error")
+           "lbfd_objective", "lbfd_adjoint", "lbfd_set_inflow", "lbfd_hold_flame", "lbfd_destroy",
+           "lbfd_strerror", "lbfd_last_error")
 # objective kinds (lbfd_set_objective)
 OBJECTIVES = {"wall_q": 0, "flame_x": 1}
 
@@ -62,17 +63,25 @@ class Diag(C.Structure):
     _fields_ = [("sum_g", C.c_double), ("sum_xi", C.c_double), ("mom", C.c_double * 3),
                 ("max_abs_sumY_minus_1", C.c_double), ("nonfinite", C.c_int64),
                 ("sum_theta", C.c_double), ("hrr_idx", C.c_int64), ("hrr_max", C.c_double),
-                ("wall_q", C.c_double), ("fuel_rate", C.c_double), ("step", C.c_int64)]
+                ("wall_q", C.c_double), ("fuel_rate", C.c_double), ("step", C.c_int64),
+                ("fuel_mass_rate", C.c_double), ("consumption_speed", C.c_double)]
 
 
 _lib = None
 
 
 def load_library():
-    """Load liblbfd.so; raises if it has not been built."""
+    """Load liblbfd.so; raises if it has not been built.  When torch is
+    importable it is imported first, so that the library binds to the HIP
+    runtime torch has loaded (one runtime per process: torch's streams and
+    the library's allocations then belong to the same one)."""
     global _lib
     if _lib is not None:
         return _lib
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError("liblbfd.so is not built (run python -m paper_2304_05657_amd.build); "
                           "the GPU library has no CPU fallback")
@@ -96,6 +105,8 @@ def load_library():
     lib.lbfd_step_launches.restype = C.c_int
     lib.lbfd_set_reaction.argtypes = [vp, C.c_int, C.c_double, C.c_double, C.c_double]
     lib.lbfd_set_objective.argtypes = [vp, C.c_int, C.c_int64, C.c_int64]
+    lib.lbfd_set_inflow.argtypes = [vp, C.c_int, dp]
+    lib.lbfd_hold_flame.argtypes = [vp, C.c_int64, C.c_int, C.c_double, C.c_double, dp, dp]
     lib.lbfd_objective.argtypes = [vp, C.c_int64, dp]
     lib.lbfd_adjoint.argtypes = [vp, C.c_int64, C.c_int, dp, dp, dp, dp]
     lib.lbfd_destroy.argtypes = [vp]
@@ -276,7 +287,25 @@ class Solver:
         return {"sum_g": d.sum_g, "sum_xi": d.sum_xi, "mom": np.array(list(d.mom)),
                 "max_sumY_err": d.max_abs_sumY_minus_1, "nonfinite": int(d.nonfinite),
                 "sum_theta": d.sum_theta, "hrr_idx": int(d.hrr_idx), "hrr_max": d.hrr_max,
-                "wall_q": d.wall_q, "fuel_rate": d.fuel_rate, "step": int(d.step)}
+                "wall_q": d.wall_q, "fuel_rate": d.fuel_rate, "step": int(d.step),
+                "fuel_mass_rate": d.fuel_mass_rate, "consumption_speed": d.consumption_speed}
+
+    def set_inflow(self, face: int, u=None):
+        """Inlet velocity profile u [3, nz, ny] of x face 0 (-x) or 1 (+x),
+        which must be an inflow face; None restores the uniform inflow."""
+        pr = self.prob
+        a = None if u is None else np.ascontiguousarray(u, dtype=np.float64).reshape(3 * pr.nz * pr.ny)
+        _check(self._lib, self._lib.lbfd_set_inflow(self._h, int(face), _dp(a)))
+
+    def hold_flame(self, nsteps: int, every: int, x_target: float, gain: float):
+        """Run nsteps steps holding the flame at x_target (cells) by scaling
+        the inlet profile after every `every` steps; returns the per-cycle
+        (mean inlet velocity, flame position) arrays."""
+        n = int(nsteps) // int(every)
+        U, X = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        _check(self._lib, self._lib.lbfd_hold_flame(self._h, int(nsteps), int(every), float(x_target), float(gain),
+                                                    _dp(U), _dp(X)))
+        return U[:n], X[:n]
 
     def set_wall_temperature(self, wall_T):
         a = np.ascontiguousarray(wall_T, dtype=np.float64).reshape(-1)

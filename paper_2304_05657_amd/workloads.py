@@ -142,6 +142,42 @@ def channel_flame(nx: int = 256, ny: int = 64, steps: int = 2000, front_x: float
     )
 
 
+def poiseuille_profile(prob, u_mean: float):
+    """Inlet profile [3, nz, ny] of a D2Q9 channel whose first and last rows
+    are solid: the half-way-wall parabola u_x = 6 u_mean s (1 - s),
+    s = (y - 1/2) / H, H = ny - 2, on the fluid rows (Sec. IV.A: a 2-D
+    Poiseuille inlet with a target flow rate); zero on the solid rows."""
+    H = prob.ny - 2
+    y = np.arange(prob.ny, dtype=np.float64)
+    s = (y - 0.5) / H
+    ux = np.where((y >= 1) & (y <= prob.ny - 2), 6.0 * u_mean * s * (1.0 - s), 0.0)
+    u = np.zeros((3, prob.nz, prob.ny))
+    u[0] = ux[None, :]
+    return u
+
+
+def flame_channel(nx: int = 512, ny: int = 34, u_mean: float = 0.002, front_x: float = 256.0,
+                  adiabatic: bool = True, A: float = 1e10, name: str | None = None) -> Problem:
+    """Flame-holding channel, D2Q9: rows 0 and ny-1 solid walls (adiabatic,
+    or isothermal at 300 K), fresh stoichiometric inflow at 300 K at -x,
+    outflow at +x; tanh front at front_x with the burnt state downstream; the
+    fresh side starts with the Poiseuille inlet profile of mean u_mean
+    (poiseuille_profile), the burnt side at rest.  A = 1e10 1/s (a faster
+    flame than the channel flame's 1e9, so that it forms within ~1e4 steps)."""
+    base = channel_flame(nx=nx, ny=ny, front_x=front_x, adiabatic=adiabatic, name="tmp")
+    r = base.reactions[0]
+    prob = base.replace(name=name or "flame_channel_%dx%d" % (nx, ny),
+                        faces=("inflow", "outflow", "periodic", "periodic", "periodic", "periodic"),
+                        u_in=(u_mean, 0.0, 0.0),
+                        reactions=[Reaction(r.reactants, A, r.b, r.Ta, r.nu, r.q)])
+    prof = poiseuille_profile(prob, u_mean)
+    x = np.arange(nx, dtype=np.float64)
+    fresh = (x < front_x)[None, None, :]
+    u0 = np.zeros((3, 1, ny, nx))
+    u0[0] = np.where(fresh, prof[0][:, :, None], 0.0)
+    return prob.replace(u0=u0)
+
+
 def wall_layer(T, Y, mask, wall_T, periodic_axes, delta=4.0):
     """Initial thermal layer next to solids: within `delta` cells of a solid
     cell the gas temperature is blended linearly from the nearest wall

@@ -606,3 +606,58 @@ def test_sampled_cone_equals_full_steps(oracle_mod, case):
         # outside the sample the restricted oracle reports nothing
     outside = fluid & ~sample
     assert np.isnan(got["T"][outside]).all()
+
+
+def test_consumption_speed_zero_d(oracle_mod):
+    """Consumption speed of a homogeneous reacting box, against its closed
+    form: fuel mass consumed per step rho r per cell (r the one-step rate of
+    the scalar recurrence), over the fresh fuel mass flux
+    rho(T_in, Y_in) Y_in[0] through the box's cross-section n_fluid / nx."""
+    prob = W.channel_flame(nx=8, ny=4)
+    prob.mask[:] = 0
+    Yu = np.array(W.Y_UNBURNT_STOICH)
+    prob = prob.replace(T0=np.full((1, 4, 8), 1600.0),
+                        Y0=np.stack([np.full((1, 4, 8), v) for v in Yu]))
+    o = oracle_mod.Oracle(prob)
+    T, Y = 1600.0, Yu.copy()
+    Wk = np.array(W.W4)
+    rho_in = (300.0 / 300.0) * (1.0 / (Yu / Wk).sum()) / 28.0
+    nf = prob.mask.size
+    for n in range(20):
+        d = o.diagnostics()
+        rho = (300.0 / T) * (1.0 / (Y / Wk).sum()) / 28.0
+        r = 1e9 * 7.5e-8 * math.exp(-15000.0 / T) * Y[0] * Y[1]
+        assert d["fuel_mass_rate"] == pytest.approx(nf * rho * r, rel=1e-12)
+        assert d["consumption_speed"] == pytest.approx(nf * rho * r / (rho_in * Yu[0] * nf / prob.nx), rel=1e-12)
+        T += 3e4 * r
+        Y = Y + np.array([-1.0, -4.0, 5.0, 0.0]) * r
+        o.step(1)
+
+
+def test_inlet_profile_first_step(oracle_mod):
+    """Velocity inlet with a per-cell profile (Eq. 31): from rest with
+    uniform T, Y and no reaction every post-collision population is zero,
+    so one step later the populations entering through the -x face are
+    exactly 2 w_i rho_in c_i.u(y), u(y) the profile value of the receiving
+    cell, and every other population is zero."""
+    prob = W.flame_channel(nx=12, ny=10, u_mean=0.01, front_x=1e4, A=0.0, name="inlet_pin")
+    prob = prob.replace(u0=None)
+    o = oracle_mod.Oracle(prob)
+    rng = np.random.default_rng(9)
+    u = W.poiseuille_profile(prob, 0.01)
+    u[1] = rng.uniform(-2e-3, 2e-3, size=u[1].shape)  # a transverse component too
+    o.set_inflow(0, u)
+    o.step(1)
+    g = o.pops()
+    c, w = oracle_mod.single.lattice(9)
+    Yu = np.array(W.Y_UNBURNT_STOICH)
+    rho_in = (1.0 / (Yu / np.array(W.W4)).sum()) / 28.0
+    want = np.zeros_like(g)
+    fluid = prob.mask[0] == 0
+    for i in range(9):
+        if c[i][0] == 1:
+            want[i, 0, :, 0] = np.where(fluid[:, 0], 2.0 * w[i] * rho_in * (c[i][0] * u[0, 0] + c[i][1] * u[1, 0]), 0.0)
+    got = np.where(fluid[None, None], g, 0.0)
+    # the rest state carries round-off of ~1e-17 in every population
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-15)
+    assert np.count_nonzero(want) > 0
