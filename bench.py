@@ -233,6 +233,8 @@ def main():
                     help="first entry is the headline value, the others are reported beside it")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--collision", default="central_moments", choices=("central_moments", "cumulants"),
+                    help="relaxation of the orders >= 4: central moments (default) or cumulants")
     ap.add_argument("--workload", default="burner",
                     help="burner (default), channel, porous or porous_mech")
     ap.add_argument("--accuracy-steps", type=int, default=None,
@@ -251,7 +253,7 @@ def main():
         sys.exit(3)
     from paper_2304_05657_amd import workloads as W
 
-    prob = W.named(args.workload)
+    prob = W.named(args.workload).replace(collision=args.collision)
     if args.accuracy_steps is None:
         args.accuracy_steps = 20000 if args.workload == "burner" else 2000
     precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
@@ -305,7 +307,8 @@ def main():
         "dtype": DTYPE[precs[0]],
         "data": "synthetic",
         "config": {"workload": prob.name, "lattice": "D2Q9" if prob.lattice == 9 else "D3Q27", "cells": prob.N, "fluid_cells": prob.n_fluid,
-                   "species": prob.n_species, "reactions": len(prob.reactions), "storage": precs[0]},
+                   "species": prob.n_species, "reactions": len(prob.reactions), "storage": precs[0],
+                   "collision": prob.collision},
         "roofline": roofline(head, precs[0], prob.name),
         "cpu_baseline": cpu,
         "precisions": {p: {k: v for k, v in r.items() if k != "precision"} for p, r in results.items()},

@@ -64,6 +64,13 @@ enum { LBFD_D2Q9 = 9, LBFD_D3Q27 = 27 };
  *    (round to nearest even). */
 enum { LBFD_FP64 = 0, LBFD_MIXED_FP32 = 1, LBFD_MIXED_FP16 = 2 };
 
+/* Collision (Sec. II.C): every order relaxed as central moments, or the
+ * orders >= 4 relaxed as cumulants (for the unit-mass, zero-mean shifted
+ * distribution, cumulants and central moments coincide at orders 2 and 3).
+ * Orders >= 4 relax at omega4 toward the Maxwellian values (central moments
+ * c_s^2 per squared axis; cumulants 0). */
+enum { LBFD_CENTRAL_MOMENTS = 0, LBFD_CUMULANTS = 1 };
+
 /* Face kinds.  WALL: isothermal no-slip wall at face_T (bounce-back, and a
  * Dirichlet ghost for T).  WALL_ADIABATIC: no-slip, Neumann ghost for T.
  * INFLOW: velocity inlet at u_in with Dirichlet T_in, Y_in (Eq. 31).
@@ -118,6 +125,7 @@ typedef struct {
     int chem_substeps_max;   /* <= 1: one Euler source step; else sub-cycled */
     int check_every;         /* steps between NaN/Inf checks; 0 = never */
     double T_u, T_b;         /* progress variable theta = (T-T_u)/(T_b-T_u) */
+    int collision;           /* LBFD_CENTRAL_MOMENTS or LBFD_CUMULANTS */
 } lbfd_params;
 
 /* Diagnostics of the state at one level (plain sums over fluid cells in

@@ -235,6 +235,73 @@ static void gauss_solve(int n, double *A, double *b)
  * moments are taken of h = f' + w (1 - sum f'), which has unit mass and
  * mean velocity u; the shift is undone after relaxation.
  */
+/* ------------------------------------------------------------------ */
+/* Cumulants (Sec. II.C).  The printed cumulant formulas are garbled    */
+/* (reading: the multivariate moment-cumulant relation, derived here,   */
+/* not transcribed).  A moment index j carries exponents (p, q, r) =     */
+/* (c_x + 1, c_y + 1, c_z + 1) of direction j, i.e. j = p + 3q + 9r.    */
+/* The multi-index a of (p, q, r) is the multiset of its p x's, q y's    */
+/* and r z's; over the set partitions pi of a's positions               */
+/*   C_a   = sum_pi (-1)^(|pi|-1) (|pi|-1)! prod_{B in pi} kap_B,         */
+/*   kap_a = sum_pi prod_{B in pi} C_B,                                   */
+/* with kap_B (C_B) the moment (cumulant) of B's exponents.  Only        */
+/* orders >= 2 are transformed; orders 0 and 1 are copied.               */
+/* ------------------------------------------------------------------ */
+static int order_of(int j) { return j % 3 + (j / 3) % 3 + j / 9; }
+
+/* sum over the set partitions of the first n positions of axis[] (blocks
+   numbered by first appearance), each term the product of vals at the
+   blocks' exponents, times (-1)^(k-1) (k-1)! for k blocks when signed */
+static double partition_sum(int n, const int *axis, int pos, int *blk, int nblk,
+                            const double *vals, int signed_terms)
+{
+    if (pos == n) {
+        double prod = 1.0;
+        for (int b = 0; b < nblk; ++b) {
+            int e[3] = {0, 0, 0};
+            for (int i = 0; i < n; ++i)
+                if (blk[i] == b)
+                    e[axis[i]] += 1;
+            prod *= vals[e[0] + 3 * e[1] + 9 * e[2]];
+        }
+        if (signed_terms) {
+            double cf = (nblk % 2 == 1) ? 1.0 : -1.0;
+            for (int k = 2; k < nblk; ++k)
+                cf *= k;
+            prod *= cf;
+        }
+        return prod;
+    }
+    double s = 0.0;
+    for (int b = 0; b <= nblk; ++b) {
+        blk[pos] = b;
+        s += partition_sum(n, axis, pos + 1, blk, b == nblk ? nblk + 1 : nblk, vals, signed_terms);
+    }
+    return s;
+}
+
+static double transform_one(int j, const double *vals, int signed_terms)
+{
+    int axis[6], blk[6], n = 0;
+    int e[3] = {j % 3, (j / 3) % 3, j / 9};
+    for (int d = 0; d < 3; ++d)
+        for (int k = 0; k < e[d]; ++k)
+            axis[n++] = d;
+    return partition_sum(n, axis, 0, blk, 0, vals, signed_terms);
+}
+
+void lbo_cumulants(int Q, const double *kap, double *cum)
+{
+    for (int j = 0; j < Q; ++j)
+        cum[j] = order_of(j) < 2 ? kap[j] : transform_one(j, kap, 1);
+}
+
+void lbo_cumulants_inverse(int Q, const double *cum, double *kap)
+{
+    for (int j = 0; j < Q; ++j)
+        kap[j] = order_of(j) < 2 ? cum[j] : transform_one(j, cum, 0);
+}
+
 void lbo_collide(const lbo_params *p, const double *g, const double *xi,
                  double rho, const double *u, double *gstar)
 {
@@ -264,12 +331,27 @@ void lbo_collide(const lbo_params *p, const double *g, const double *xi,
             keq[j] = v;
         }
     }
-    for (int j = 0; j < Q; ++j) {
-        int order = 0;
-        for (int d = 0; d < 3; ++d)
-            order += (Q == 9 && d == 2) ? 0 : c[3 * j + d] + 1;
-        double om = order <= 1 ? 0.0 : order == 2 ? 1.0 / p->tau : order == 3 ? p->omega3 : p->omega4;
-        kap[j] = kap[j] - om * (kap[j] - keq[j]);
+    if (p->collision == LBO_CUMULANTS) {
+        /* relax cumulants toward those of the targets: orders 2, 3 at 1/tau
+           and omega3 (equal to the central moments there), orders >= 4 at
+           omega4; then back to central moments */
+        double cum[MAXQ], ceq[MAXQ];
+        lbo_cumulants(Q, kap, cum);
+        lbo_cumulants(Q, keq, ceq);
+        for (int j = 0; j < Q; ++j) {
+            int order = order_of(j);
+            double om = order <= 1 ? 0.0 : order == 2 ? 1.0 / p->tau : order == 3 ? p->omega3 : p->omega4;
+            cum[j] = cum[j] - om * (cum[j] - ceq[j]);
+        }
+        lbo_cumulants_inverse(Q, cum, kap);
+    } else {
+        for (int j = 0; j < Q; ++j) {
+            int order = 0;
+            for (int d = 0; d < 3; ++d)
+                order += (Q == 9 && d == 2) ? 0 : c[3 * j + d] + 1;
+            double om = order <= 1 ? 0.0 : order == 2 ? 1.0 / p->tau : order == 3 ? p->omega3 : p->omega4;
+            kap[j] = kap[j] - om * (kap[j] - keq[j]);
+        }
     }
     moment_matrix(Q, u, M);
     gauss_solve(Q, M, kap);  /* kap now holds h* */

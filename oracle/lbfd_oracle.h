@@ -62,7 +62,14 @@ typedef struct {
     int chem_substeps_max;  /* 1 = plain explicit Euler source */
     double body_force[3];   /* oracle-only test fixture (0 in every workload) */
     double T_u, T_b;        /* progress-variable temperatures (diagnostics) */
+    int collision;          /* LBO_CENTRAL_MOMENTS or LBO_CUMULANTS */
 } lbo_params;
+
+/* Collision operators (Sec. II.C): relaxation of central moments (every
+   order), or of cumulants for the orders >= 4 (orders 2, 3: the two coincide
+   for the unit-mass, zero-mean distributions relaxed here). */
+#define LBO_CENTRAL_MOMENTS 0
+#define LBO_CUMULANTS 1
 
 typedef struct lbo_state lbo_state;
 
@@ -89,6 +96,8 @@ void lbo_lattice(int Q, int *c, double *w);
 void lbo_feq(int Q, double rho, const double *u, double *feq);
 void lbo_geq(int Q, double Ph, double rho, const double *u, double *geq);
 void lbo_central_moments(int Q, const double *h, const double *u, double *kap);
+void lbo_cumulants(int Q, const double *kap, double *cum);
+void lbo_cumulants_inverse(int Q, const double *cum, double *kap);
 void lbo_collide(const lbo_params *p, const double *g, const double *xi,
                  double rho, const double *u, double *gstar);
 void lbo_source_xi(int Q, double rho, const double *u, const double *grad_rho,

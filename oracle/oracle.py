@@ -64,6 +64,7 @@ class _Params(C.Structure):
         ("body_force", C.c_double * 3),
         ("T_u", C.c_double),
         ("T_b", C.c_double),
+        ("collision", C.c_int),
     ]
 
 
@@ -112,6 +113,8 @@ def _load():
         lib.lbo_feq.argtypes = [C.c_int, C.c_double, dp, dp]
         lib.lbo_geq.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp]
         lib.lbo_central_moments.argtypes = [C.c_int, dp, dp, dp]
+        lib.lbo_cumulants.argtypes = [C.c_int, dp, dp]
+        lib.lbo_cumulants_inverse.argtypes = [C.c_int, dp, dp]
         lib.lbo_collide.argtypes = [C.POINTER(_Params), dp, dp, C.c_double, dp, dp]
         lib.lbo_source_xi.argtypes = [C.c_int, C.c_double, dp, dp, C.c_double, dp]
         lib.lbo_weno3.argtypes = [dp, C.c_double]
@@ -166,6 +169,7 @@ def make_params(prob, **over) -> _Params:
     p.eq_discrete = int(prob.eq_discrete)
     p.chem_substeps_max = prob.chem_substeps_max
     p.T_u, p.T_b = prob.T_u, prob.T_b
+    p.collision = {"central_moments": 0, "cumulants": 1}[getattr(prob, "collision", "central_moments")]
     bf = over.pop("body_force", (0.0, 0.0, 0.0))
     for d in range(3):
         p.body_force[d] = bf[d]
@@ -334,6 +338,18 @@ class single:
         out = np.empty(Q)
         _load().lbo_central_moments(Q, _dp(np.ascontiguousarray(h, dtype=np.float64)),
                                      _dp(np.asarray(u, dtype=np.float64)), _dp(out))
+        return out
+
+    @staticmethod
+    def cumulants(Q, kap):
+        out = np.empty(Q)
+        _load().lbo_cumulants(Q, _dp(np.ascontiguousarray(kap, dtype=np.float64)), _dp(out))
+        return out
+
+    @staticmethod
+    def cumulants_inverse(Q, cum):
+        out = np.empty(Q)
+        _load().lbo_cumulants_inverse(Q, _dp(np.ascontiguousarray(cum, dtype=np.float64)), _dp(out))
         return out
 
     @staticmethod

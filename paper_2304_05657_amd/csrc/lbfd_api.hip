@@ -150,6 +150,8 @@ static int validate(const lbfd_params *p, const uint8_t *mask, const double *T0,
         if (!(p->W[k] > 0.0)) return fail(LBFD_EINVAL, "molar masses must be positive");
     if (!(p->T_ref > 0.0) || !(p->W_ref > 0.0)) return fail(LBFD_EINVAL, "T_ref, W_ref must be positive");
     if (p->check_every < 0) return fail(LBFD_EINVAL, "check_every must be >= 0");
+    if (p->collision != LBFD_CENTRAL_MOMENTS && p->collision != LBFD_CUMULANTS)
+        return fail(LBFD_EINVAL, "bad collision kind %d", p->collision);
     const long long N = (long long)p->nx * p->ny * p->nz;
     long long nfluid = 0;
     for (long long i = 0; i < N; ++i) {
@@ -397,6 +399,7 @@ static KParams make_kparams(const lbfd_ctx *c)
     k.rho_in = mixture_density(p, p.T_in, p.Y_in);
     k.T_u = p.T_u;
     k.T_b = p.T_b;
+    k.collision = p.collision;
     return k;
 }
 
@@ -979,6 +982,8 @@ int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwall
 {
     if (!c || nsteps < 1 || K < 1) return fail(LBFD_EINVAL, "bad arguments");
     if (c->prec != LBFD_FP64) return fail(LBFD_EINVAL, "the adjoint needs FP64 precision");
+    if (c->p.collision != LBFD_CENTRAL_MOMENTS)
+        return fail(LBFD_EINVAL, "the adjoint differentiates the central-moment collision only");
     if (!adjoint_supported(c->Q, c->nsp))
         return fail(LBFD_EINVAL, "no adjoint kernel for lattice %d with %d species", c->Q, c->nsp);
     for (int f = 0; f < 6; ++f)

@@ -69,6 +69,7 @@ struct KParams {
     double u_in[3], T_in, Y_in[kMaxSp], rho_in;
     const double *inflow_u;  // [2 x faces][3][nz][ny] inlet velocity of the cells next to an x face
     double T_u, T_b;
+    int collision;  // LBFD_CENTRAL_MOMENTS or LBFD_CUMULANTS
 };
 
 // Kernel modes.

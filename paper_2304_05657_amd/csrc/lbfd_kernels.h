@@ -534,6 +534,75 @@ __device__ __forceinline__ void relax(C (&k)[Q], C om2, C om3, C om4)
     });
 }
 
+// Relaxation with the orders >= 4 taken as cumulants (the cumulant form of
+// the collision, Sec. II.C).  For the unit-mass, zero-mean shifted
+// distribution the cumulants of orders 2 and 3 are the central moments;
+// those of orders 4-6 on the 3 x 3 (x 3) cube follow from the
+// moment-cumulant relation, kappa_a = sum over the set partitions of a's
+// index positions into blocks of two or more of the product of the blocks'
+// cumulants (first-order blocks vanish), expanded here by hand:
+//   order 4: C_xxyy = k_xxyy - k_xx k_yy - 2 k_xy^2,
+//            C_xxyz = k_xxyz - k_xx k_yz - 2 k_xy k_xz;
+//   order 5: C_xxyyz = k_xxyyz - k_xx k_yyz - k_yy k_xxz - 2 k_xz k_xyy
+//                      - 2 k_yz k_xxy - 4 k_xy k_xyz;
+//   order 6: C_xxyyzz = k_xxyyzz - (pair x 4-block: 15 terms)
+//                       - (two triples: 10) - (three pairs: 15),
+// and the inverse with the relaxed cumulants and the post-collision
+// orders 2, 3.  Cumulants of order >= 4 relax at om4 toward 0 (those of the
+// Maxwellian); orders 2, 3 as in relax().
+template <int Q, class C>
+__device__ __forceinline__ void relax_cumulants(C (&k)[Q], C om2, C om3, C om4)
+{
+    auto K = [&](int p, int q, int r) -> C & { return k[p + 3 * q + 9 * r]; };
+    const C keep = (C)1 - om4;
+    if constexpr (Q == 9) {
+        const C c22 = K(2, 2, 0) - K(2, 0, 0) * K(0, 2, 0) - (C)2 * K(1, 1, 0) * K(1, 1, 0);
+        relax<Q>(k, om2, om3, (C)0);
+        K(2, 2, 0) = keep * c22 + K(2, 0, 0) * K(0, 2, 0) + (C)2 * K(1, 1, 0) * K(1, 1, 0);
+    } else {
+        // pre-collision second and third orders
+        const C a = K(2, 0, 0), b = K(0, 2, 0), c = K(0, 0, 2);          // xx, yy, zz
+        const C xy = K(1, 1, 0), xz = K(1, 0, 1), yz = K(0, 1, 1);
+        const C xxy = K(2, 1, 0), xxz = K(2, 0, 1), xyy = K(1, 2, 0), yyz = K(0, 2, 1);
+        const C xzz = K(1, 0, 2), yzz = K(0, 1, 2), xyz = K(1, 1, 1);
+        // pre-collision cumulants of orders 4, 5, 6
+        const C c220 = K(2, 2, 0) - a * b - (C)2 * xy * xy;
+        const C c202 = K(2, 0, 2) - a * c - (C)2 * xz * xz;
+        const C c022 = K(0, 2, 2) - b * c - (C)2 * yz * yz;
+        const C c211 = K(2, 1, 1) - a * yz - (C)2 * xy * xz;
+        const C c121 = K(1, 2, 1) - b * xz - (C)2 * xy * yz;
+        const C c112 = K(1, 1, 2) - c * xy - (C)2 * xz * yz;
+        const C c221 = K(2, 2, 1) - a * yyz - b * xxz - (C)2 * xz * xyy - (C)2 * yz * xxy - (C)4 * xy * xyz;
+        const C c212 = K(2, 1, 2) - a * yzz - c * xxy - (C)2 * xy * xzz - (C)2 * yz * xxz - (C)4 * xz * xyz;
+        const C c122 = K(1, 2, 2) - b * xzz - c * xyy - (C)2 * xy * yzz - (C)2 * xz * yyz - (C)4 * yz * xyz;
+        const C s42 = a * c022 + b * c202 + c * c220 + (C)4 * (xy * c112 + xz * c121 + yz * c211);
+        const C s33 = (C)2 * (xxy * yzz + xxz * yyz + xyy * xzz) + (C)4 * xyz * xyz;
+        const C s222 = a * b * c + (C)2 * (a * yz * yz + b * xz * xz + c * xy * xy) + (C)8 * xy * xz * yz;
+        const C c222 = K(2, 2, 2) - s42 - s33 - s222;
+        relax<Q>(k, om2, om3, (C)0);
+        // post-collision second and third orders, relaxed cumulants
+        const C A = K(2, 0, 0), B = K(0, 2, 0), Cc = K(0, 0, 2);
+        const C XY = K(1, 1, 0), XZ = K(1, 0, 1), YZ = K(0, 1, 1);
+        const C XXY = K(2, 1, 0), XXZ = K(2, 0, 1), XYY = K(1, 2, 0), YYZ = K(0, 2, 1);
+        const C XZZ = K(1, 0, 2), YZZ = K(0, 1, 2), XYZ = K(1, 1, 1);
+        const C d220 = keep * c220, d202 = keep * c202, d022 = keep * c022;
+        const C d211 = keep * c211, d121 = keep * c121, d112 = keep * c112;
+        K(2, 2, 0) = d220 + A * B + (C)2 * XY * XY;
+        K(2, 0, 2) = d202 + A * Cc + (C)2 * XZ * XZ;
+        K(0, 2, 2) = d022 + B * Cc + (C)2 * YZ * YZ;
+        K(2, 1, 1) = d211 + A * YZ + (C)2 * XY * XZ;
+        K(1, 2, 1) = d121 + B * XZ + (C)2 * XY * YZ;
+        K(1, 1, 2) = d112 + Cc * XY + (C)2 * XZ * YZ;
+        K(2, 2, 1) = keep * c221 + A * YYZ + B * XXZ + (C)2 * XZ * XYY + (C)2 * YZ * XXY + (C)4 * XY * XYZ;
+        K(2, 1, 2) = keep * c212 + A * YZZ + Cc * XXY + (C)2 * XY * XZZ + (C)2 * YZ * XXZ + (C)4 * XZ * XYZ;
+        K(1, 2, 2) = keep * c122 + B * XZZ + Cc * XYY + (C)2 * XY * YZZ + (C)2 * XZ * YYZ + (C)4 * YZ * XYZ;
+        const C S42 = A * d022 + B * d202 + Cc * d220 + (C)4 * (XY * d112 + XZ * d121 + YZ * d211);
+        const C S33 = (C)2 * (XXY * YZZ + XXZ * YYZ + XYY * XZZ) + (C)4 * XYZ * XYZ;
+        const C S222 = A * B * Cc + (C)2 * (A * YZ * YZ + B * XZ * XZ + Cc * XY * XY) + (C)8 * XY * XZ * YZ;
+        K(2, 2, 2) = keep * c222 + S42 + S33 + S222;
+    }
+}
+
 // ------------------------------------------------------------ reductions
 __device__ __forceinline__ void diag_combine(double (&a)[kNDiag], const double *b)
 {
@@ -653,7 +722,10 @@ __device__ __forceinline__ void finish_cell(const KParams &P, long long idx, con
     const C sh = (C)1 - pi;
     sfor<0, Q>([&](auto I) { h[decltype(I)::value] += (C)L::w(decltype(I)::value) * sh; });
     central_fwd<Q>(h, u);
-    relax<Q>(h, (C)P.omega2, (C)P.omega3, (C)P.omega4);
+    if (P.collision == LBFD_CUMULANTS)
+        relax_cumulants<Q>(h, (C)P.omega2, (C)P.omega3, (C)P.omega4);
+    else
+        relax<Q>(h, (C)P.omega2, (C)P.omega3, (C)P.omega4);
     central_inv<Q>(h, u);
     const C rc = rho * (C)kCs2;
     sfor<0, Q>([&](auto I) {

@@ -29,6 +29,8 @@ EXPORTS = ("lbfd_init", "lbfd_step", "lbfd_sync", "lbfd_level", "lbfd_read_field
            "lbfd_cell_counts", "lbfd_step_launches", "lbfd_set_reaction", "lbfd_set_objective",
            "lbfd_objective", "lbfd_adjoint", "lbfd_set_inflow", "lbfd_hold_flame", "lbfd_destroy",
            "lbfd_strerror", "lbfd_last_error")
+# collision operators (lbfd_params.collision)
+COLLISIONS = {"central_moments": 0, "cumulants": 1}
 # objective kinds (lbfd_set_objective)
 OBJECTIVES = {"wall_q": 0, "flame_x": 1}
 
@@ -55,7 +57,7 @@ class Params(C.Structure):
         ("rxn", C.POINTER(Reaction)), ("u_in", C.c_double * 3), ("T_in", C.c_double),
         ("Y_in", C.c_double * MAX_SPECIES), ("omega3", C.c_double), ("omega4", C.c_double),
         ("chem_substeps_max", C.c_int), ("check_every", C.c_int),
-        ("T_u", C.c_double), ("T_b", C.c_double),
+        ("T_u", C.c_double), ("T_b", C.c_double), ("collision", C.c_int),
     ]
 
 
@@ -162,6 +164,7 @@ def make_params(prob, precision="fp64", check_every: int = 0):
     p.chem_substeps_max = prob.chem_substeps_max
     p.check_every = check_every
     p.T_u, p.T_b = prob.T_u, prob.T_b
+    p.collision = COLLISIONS[getattr(prob, "collision", "central_moments")]
     if prob.eq_discrete:
         raise ValueError("the GPU library relaxes toward Maxwellian central moments only")
     return p, rx

@@ -74,6 +74,7 @@ class Problem:
     omega4: float = 1.0
     eq_discrete: bool = False
     chem_substeps_max: int = 1
+    collision: str = "central_moments"  # or "cumulants" (orders >= 4 relaxed as cumulants)
     T_u: float = 300.0
     T_b: float = 1800.0
     steps: int = 0

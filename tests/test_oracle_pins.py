@@ -661,3 +661,127 @@ def test_inlet_profile_first_step(oracle_mod):
     # the rest state carries round-off of ~1e-17 in every population
     assert np.allclose(got, want, rtol=1e-13, atol=1e-15)
     assert np.count_nonzero(want) > 0
+
+
+def _product_distribution(Q, rng):
+    """h = a (x) b (x) c of random 3-point distributions (unit mass each) on
+    the velocities -1, 0, 1, and its mean velocity."""
+    D = 2 if Q == 9 else 3
+    parts = [rng.dirichlet(np.ones(3)) for _ in range(D)]
+    h = parts[0][None, :] * parts[1][:, None] if D == 2 else \
+        parts[0][None, None, :] * parts[1][None, :, None] * parts[2][:, None, None]
+    u = np.zeros(3)
+    for d in range(D):
+        u[d] = parts[d][2] - parts[d][0]
+    return h.reshape(-1), u
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_cumulants_of_product_distributions(oracle_mod, Q):
+    """Independent axes have vanishing mixed cumulants: for h = a (x) b (x) c
+    every cumulant whose exponents involve two or more axes is zero (on the
+    3 x 3 (x 3) cube that is every cumulant of order >= 4), and second-order
+    cumulants equal the central moments."""
+    c, _ = oracle_mod.single.lattice(Q)
+    rng = np.random.default_rng(11)
+    for _ in range(10):
+        h, u = _product_distribution(Q, rng)
+        kap = oracle_mod.single.central_moments(Q, h, u)
+        cum = oracle_mod.single.cumulants(Q, kap)
+        for j in range(Q):
+            e = c[j] + 1
+            if Q == 9:
+                e = e.copy()
+                e[2] = 0
+            if np.count_nonzero(e) >= 2:
+                assert abs(cum[j]) < 1e-15, (j, e, cum[j])
+            if e.sum() == 2:
+                assert abs(cum[j] - kap[j]) < 1e-15
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_cumulant_transform_inverts(oracle_mod, Q):
+    """The cumulants determine the moments: inverse(forward(kappa)) = kappa
+    for arbitrary zero-mean, unit-mass central moments."""
+    rng = np.random.default_rng(12)
+    c, _ = oracle_mod.single.lattice(Q)
+    for _ in range(5):
+        kap = rng.normal(0.0, 0.1, Q)
+        for j in range(Q):
+            e = c[j] + 1
+            order = int(e[:2].sum() if Q == 9 else e.sum())
+            if order == 0:
+                kap[j] = 1.0
+            elif order == 1:
+                kap[j] = 0.0
+        back = oracle_mod.single.cumulants_inverse(Q, oracle_mod.single.cumulants(Q, kap))
+        assert np.allclose(back, kap, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_cumulant_collision_equals_central_moments_at_tau_one(oracle_mod, Q):
+    """With every rate 1 the post-collision second- and third-order moments
+    are the Maxwellian ones, whose higher cumulants vanish, so relaxing the
+    higher orders as cumulants or as central moments gives the same g*;
+    at tau != 1 the two differ."""
+    D = 2 if Q == 9 else 3
+    c, w = oracle_mod.single.lattice(Q)
+    rng = np.random.default_rng(13)
+    for tau, same in ((1.0, True), (0.6, False)):
+        pm = _params(oracle_mod, Q, tau=tau, omega3=1.0, omega4=1.0)
+        pc = _params(oracle_mod, Q, tau=tau, omega3=1.0, omega4=1.0, collision=1)
+        rho, u, g = _random_cell(Q, rng, D)
+        u = np.zeros(3)
+        u[:D] = (g @ c)[:D] / (rho * CS2)
+        # a source with no first moment (as Xi of Eq. 9: sum c Xi = 0), so
+        # that u is the mean velocity of the pre-conditioned populations
+        xi = rng.normal(0.0, 1e-3, Q)
+        xi -= w * (c @ (xi @ c)) / CS2
+        a = oracle_mod.single.collide(pm, g, xi, rho, u)
+        b = oracle_mod.single.collide(pc, g, xi, rho, u)
+        if same:
+            assert np.allclose(a, b, rtol=0, atol=1e-15 * np.abs(a).max() + 1e-18)
+        else:
+            assert np.abs(a - b).max() > 1e-8
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_cumulant_collision_conserves_mass_and_momentum(oracle_mod, Q):
+    """Orders 0-1 are untouched by the cumulant collision too: sum g* and
+    sum c g* equal those of g + Xi (Sec. II.C)."""
+    D = 2 if Q == 9 else 3
+    c, _ = oracle_mod.single.lattice(Q)
+    rng = np.random.default_rng(14)
+    p = _params(oracle_mod, Q, tau=0.6, omega3=1.0, omega4=1.0, collision=1)
+    for _ in range(5):
+        rho, u, g = _random_cell(Q, rng, D)
+        xi = rng.normal(0.0, 1e-3, Q)
+        gs = oracle_mod.single.collide(p, g, xi, rho, u)
+        # the collision relaxes about the u it is given; conserved are the
+        # moments of g + Xi / 2 shifted back, i.e. sum g* = sum (g + Xi)
+        assert abs(gs.sum() - (g + xi).sum()) < 1e-15
+        assert np.allclose(gs @ c, (g + xi) @ c, rtol=0, atol=1e-15)
+
+
+def test_taylor_green_decay_cumulants(oracle_mod):
+    """The cumulant collision keeps the shear viscosity nu = cs^2 (tau - 1/2):
+    the Taylor-Green decay rate is that of the central-moment collision."""
+    n = 32
+    U0 = 0.01
+    k = 2 * math.pi / n
+    prob = _uniform_problem(n, n).replace(collision="cumulants")
+    x = np.arange(n) + 0.0
+    X, Yy = np.meshgrid(x, x, indexing="xy")
+    u0 = np.zeros((3, 1, n, n))
+    u0[0, 0] = U0 * np.sin(k * X) * np.cos(k * Yy)
+    u0[1, 0] = -U0 * np.cos(k * X) * np.sin(k * Yy)
+    Ph0 = (-0.25 * U0 ** 2 * (np.cos(2 * k * X) + np.cos(2 * k * Yy)))[None]
+    prob = prob.replace(u0=u0, Ph0=Ph0)
+    o = oracle_mod.Oracle(prob)
+    nu = CS2 * (0.6 - 0.5)
+    basis = np.sin(k * X) * np.cos(k * Yy)
+    a0 = (o.fields()["u"][0, 0] * basis).sum() / (basis * basis).sum()
+    o.step(300)
+    a1 = (o.fields()["u"][0, 0] * basis).sum() / (basis * basis).sum()
+    rate = -math.log(a1 / a0) / 300
+    assert abs(rate / (2 * nu * k * k) - 1.0) < 1e-2, rate / (2 * nu * k * k)
