@@ -46,9 +46,9 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_05657_amd", "csrc", f)
 # SHA-256 (kernel_sha) is given (profiles/traffic_step_kernels_burner_2048x512.md).
 TRAFFIC_WORKLOAD = "cylinder_burner_2048x512"
 TRAFFIC = {
-    "fp64": {"kernel_sha256": "e5d122407b7fbc3e3be36e16903c6cc944b0921d7a1b1fde2b870f70c84487b3", "bytes_per_launch": 295.8e6},
-    "fp32": {"kernel_sha256": "e5d122407b7fbc3e3be36e16903c6cc944b0921d7a1b1fde2b870f70c84487b3", "bytes_per_launch": 179.0e6},
-    "fp16": {"kernel_sha256": "e5d122407b7fbc3e3be36e16903c6cc944b0921d7a1b1fde2b870f70c84487b3", "bytes_per_launch": 133.0e6},
+    "fp64": {"kernel_sha256": "43e162b7db20a12e1443b88bbf44f9fc5c425269dc3be49f8df2559be2ebf6e1", "bytes_per_launch": 295.2e6},
+    "fp32": {"kernel_sha256": "43e162b7db20a12e1443b88bbf44f9fc5c425269dc3be49f8df2559be2ebf6e1", "bytes_per_launch": 177.4e6},
+    "fp16": {"kernel_sha256": "43e162b7db20a12e1443b88bbf44f9fc5c425269dc3be49f8df2559be2ebf6e1", "bytes_per_launch": 133.2e6},
 }
 POP_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 SCALAR_BYTES = {"fp64": 8, "fp32": 4, "fp16": 4}
