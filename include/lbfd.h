@@ -191,6 +191,21 @@ int lbfd_read_fields(lbfd_ctx *c, double *rho, double *u, double *T,
 /* Diagnostics of the current level (synchronous). */
 int lbfd_diagnostics(lbfd_ctx *c, lbfd_diag *d);
 
+/* Curved walls (interpolated bounce-back, the post-collision form of the
+ * linear interpolation cited in Sec. III.A): link k runs from fluid cell
+ * cell[k] along lattice direction dir[k] (lattice order: c_z, c_y, c_x
+ * lexicographic, x fastest) to a solid cell or wall face, which it meets at
+ * the fraction q[k] in (0, 1] of its length.  The population entering
+ * cell[k] in the opposite direction then takes, with i = dir[k] and g* the
+ * post-collision populations,
+ *   q <  1/2:  2 q g*_i(r) + (1 - 2q) g*_i(r - c_i)   (half-way bounce-back
+ *              when r - c_i is not a fluid cell),
+ *   q >= 1/2:  g*_i(r) / (2q) + (2q - 1)/(2q) g*_opp(r);
+ * every other wall link bounces back half-way (q = 1/2).  Replaces the
+ * previous set; n = 0 clears it.  q is stored in single precision.
+ * LBFD_EINVAL for a link that does not run from a fluid cell to a wall. */
+int lbfd_set_wall_links(lbfd_ctx *c, int64_t n, const int64_t *cell, const int32_t *dir, const double *q);
+
 /* Inlet velocity profile of the x face `face` (0: -x, 1: +x), which must
  * be an INFLOW face: u [3][nz][ny] (host, lattice units) is the velocity
  * imposed (Eq. 31) on every population entering the box through that face

@@ -61,6 +61,7 @@ struct lbo_state {
     long level;
     const uint8_t *active;  /* NULL, or the cells a step / fields call covers */
     double *u_face;         /* NULL, or [2 x faces][3][nz][ny] inlet velocity per face cell */
+    double *q_link;         /* NULL, or [Q][N] wall distance of link (cell, i), NAN = half-way */
 };
 
 /* Whether a fluid cell is covered by the current active set. */
@@ -824,7 +825,24 @@ static void stream(lbo_state *s)
                             v = s->gstar[opp * N + idx];
                         }
                     } else {
+                        /* bounce-back; with a wall distance q of the link
+                           from this cell toward the wall (direction opp),
+                           the post-collision form of the linearly
+                           interpolated bounce-back (the curved-wall
+                           treatment of Sec. III.A) */
                         v = s->gstar[opp * N + idx];
+                        double q = s->q_link ? s->q_link[(long)opp * N + idx] : NAN;
+                        if (!isnan(q)) {
+                            if (q < 0.5) {
+                                cellref far = classify(s, x + s->c[i][0], y + s->c[i][1], z + s->c[i][2]);
+                                if (far.kind == K_FLUID)
+                                    v = 2.0 * q * s->gstar[opp * N + idx] +
+                                        (1.0 - 2.0 * q) * s->gstar[opp * N + far.idx];
+                            } else {
+                                v = s->gstar[opp * N + idx] / (2.0 * q) +
+                                    (2.0 * q - 1.0) / (2.0 * q) * s->gstar[i * N + idx];
+                            }
+                        }
                     }
                     s->gn[i * N + idx] = v;
                 }
@@ -892,6 +910,36 @@ void lbo_set_active(lbo_state *s, const uint8_t *active) { s->active = active; }
  * fluid cell (face cell, y, z); NULL restores the uniform u_in.  Returns 0,
  * or -1 for a face that is not 0 or 1.
  */
+/*
+ * Wall distances of links (interpolated bounce-back): link k runs from
+ * fluid cell cell[k] along lattice direction dir[k] toward a solid cell or
+ * wall and meets the wall at the fraction q[k] in (0, 1] of the link.  The
+ * population entering cell[k] in the opposite direction then takes, for
+ * q < 1/2, 2 q g*_i(r) + (1 - 2q) g*_i(r - c_i) (half-way bounce-back when
+ * r - c_i is not fluid), and for q >= 1/2,
+ * g*_i(r) / (2q) + (2q - 1)/(2q) g*_opp(r), with i = dir[k] and g* the
+ * post-collision populations; other links bounce back half-way.  n = 0
+ * clears.  Returns 0, or -1 for an entry out of range.
+ */
+int lbo_set_wall_links(lbo_state *s, long n, const long *cell, const int *dir, const double *q)
+{
+    long N = s->N;
+    int Q = s->Q;
+    free(s->q_link);
+    s->q_link = NULL;
+    if (n <= 0)
+        return 0;
+    s->q_link = (double *)malloc(sizeof(double) * (size_t)Q * (size_t)N);
+    for (long k = 0; k < (long)Q * N; ++k)
+        s->q_link[k] = NAN;
+    for (long k = 0; k < n; ++k) {
+        if (cell[k] < 0 || cell[k] >= N || dir[k] < 0 || dir[k] >= Q || !(q[k] > 0.0 && q[k] <= 1.0))
+            return -1;
+        s->q_link[(long)dir[k] * N + cell[k]] = q[k];
+    }
+    return 0;
+}
+
 int lbo_set_inflow(lbo_state *s, int face, const double *u)
 {
     const lbo_params *p = &s->p;
@@ -1158,5 +1206,6 @@ void lbo_destroy(lbo_state *s)
     free(s->mask); free(s->wall_T); free(s->g); free(s->gn); free(s->gstar);
     free(s->T); free(s->Tn); free(s->Y); free(s->Yn); free(s->rho); free(s->ux);
     free(s->u_face);
+    free(s->q_link);
     free(s);
 }

@@ -104,6 +104,8 @@ def _load():
         lib.lbo_level.restype = C.c_long
         lib.lbo_set_active.argtypes = [C.c_void_p, C.c_void_p]
         lib.lbo_set_inflow.argtypes = [C.c_void_p, C.c_int, dp]
+        lib.lbo_set_wall_links.argtypes = [C.c_void_p, C.c_long, C.c_void_p, C.c_void_p, dp]
+        lib.lbo_set_wall_links.restype = C.c_int
         lib.lbo_set_inflow.restype = C.c_int
         lib.lbo_fields.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
         lib.lbo_diagnostics.argtypes = [C.c_void_p, dp]
@@ -217,6 +219,18 @@ class Oracle:
         a = None if u is None else np.ascontiguousarray(u, dtype=np.float64).reshape(3 * pr.nz * pr.ny)
         if self._lib.lbo_set_inflow(self._h, int(face), _dp(a)) != 0:
             raise ValueError("inlet profiles are set on x faces 0 and 1")
+
+    def set_wall_links(self, cell=None, direction=None, q=None):
+        """Interpolated bounce-back on the listed links (fluid cell,
+        direction toward the wall, wall fraction q); None clears."""
+        if cell is None or len(cell) == 0:
+            self._lib.lbo_set_wall_links(self._h, 0, None, None, None)
+            return
+        c = np.ascontiguousarray(cell, dtype=np.int64)
+        d = np.ascontiguousarray(direction, dtype=np.int32)
+        qq = np.ascontiguousarray(q, dtype=np.float64)
+        if self._lib.lbo_set_wall_links(self._h, len(c), c.ctypes.data, d.ctypes.data, _dp(qq)) != 0:
+            raise ValueError("wall link out of range")
 
     def set_threads(self, n: int):
         """OpenMP threads of the following steps (process-wide)."""

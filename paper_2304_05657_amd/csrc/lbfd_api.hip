@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <vector>
 
 #include "lbfd_internal.h"
@@ -86,6 +87,7 @@ struct lbfd_ctx {
     double *outlet_un = nullptr;
     double *inflow_u = nullptr;         // [2 x faces][3][nz][ny] inlet velocity profiles
     double *inflow_du = nullptr;        // [3][nz][ny] staging of a profile change
+    float *bq = nullptr;                // [Q][nb] interpolated bounce-back wall distances (optional)
     std::vector<double> inflow_host;   // host copy
     size_t outlet_n = 0;
     double *fields = nullptr;
@@ -103,7 +105,7 @@ static void free_ctx(lbfd_ctx *c)
 {
     if (!c) return;
     void *ptrs[] = {c->pop[0], c->pop[1], c->sc[0], c->sc[1], c->mask, c->code, c->boundary, c->bsrc, c->bpt, c->bwk,
-                    c->btw, c->wall_T, c->outlet, c->outlet_un, c->inflow_u, c->inflow_du,
+                    c->btw, c->wall_T, c->outlet, c->outlet_un, c->inflow_u, c->inflow_du, c->bq,
                     c->fields, c->partials, c->diag_dev, c->bad_dev, c->rx_dev};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -377,6 +379,7 @@ static KParams make_kparams(const lbfd_ctx *c)
     k.outlet = c->outlet;
     k.outlet_un = c->outlet_un;
     k.inflow_u = c->inflow_u;
+    k.bq = c->bq;
     k.fields = c->fields;
     k.partials = c->partials;
     k.rx = c->rx_dev;
@@ -677,6 +680,45 @@ int lbfd_diagnostics(lbfd_ctx *c, lbfd_diag *d)
     d->fuel_mass_rate = a[kFuelMass];
     const double fresh = c->base.rho_in * c->p.Y_in[0] * ((double)c->n_fluid / c->p.nx);
     d->consumption_speed = fresh > 0.0 ? a[kFuelMass] / fresh : 0.0;
+    return LBFD_OK;
+}
+
+int lbfd_set_wall_links(lbfd_ctx *c, int64_t n, const int64_t *cell, const int32_t *dir, const double *q)
+{
+    if (!c || n < 0 || (n > 0 && (!cell || !dir || !q))) return fail(LBFD_EINVAL, "bad arguments");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (n == 0) {
+        if (c->bq) (void)hipFree(c->bq);
+        c->bq = nullptr;
+        c->base.bq = nullptr;
+        return LBFD_OK;
+    }
+    const long long nb = c->n_boundary, N = c->N;
+    const int Q = c->Q;
+    std::vector<int> slot(N, -1);  // cell -> position in the boundary list
+    for (long long t = 0; t < nb; ++t) slot[c->boundary_host[t]] = (int)t;
+    std::vector<float> h((size_t)Q * nb, std::numeric_limits<float>::quiet_NaN());
+    const lbfd_params &p = c->p;
+    for (int64_t k = 0; k < n; ++k) {
+        const long long i = cell[k];
+        const int d = dir[k];
+        if (i < 0 || i >= N || d < 0 || d >= Q || !(q[k] > 0.0 && q[k] <= 1.0))
+            return fail(LBFD_EINVAL, "wall link %lld out of range", (long long)k);
+        if (c->mask_host[i] != LBFD_FLUID || slot[i] < 0)
+            return fail(LBFD_EINVAL, "wall link %lld does not start at a boundary fluid cell", (long long)k);
+        const int x = (int)(i % p.nx), y = (int)((i / p.nx) % p.ny), z = (int)(i / ((long long)p.nx * p.ny));
+        const int cx = d % 3 - 1, cy = (d / 3) % 3 - 1, cz = Q == 9 ? 0 : d / 9 - 1;
+        const HostNb nbr = host_classify(p, c->mask_host.data(), c->wall_T_host.data(), x + cx, y + cy, z + cz);
+        if (nbr.kind != kIso && nbr.kind != kAdia)
+            return fail(LBFD_EINVAL, "wall link %lld does not end at a wall", (long long)k);
+        h[(size_t)(Q - 1 - d) * nb + slot[i]] = (float)q[k];  // stored by the entering direction
+    }
+    if (!c->bq && hipMalloc((void **)&c->bq, h.size() * sizeof(float)) != hipSuccess) {
+        c->bq = nullptr;
+        return fail(LBFD_ENOMEM, "hipMalloc of the wall-distance table failed");
+    }
+    HIP_TRY(hipMemcpy(c->bq, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+    c->base.bq = c->bq;
     return LBFD_OK;
 }
 

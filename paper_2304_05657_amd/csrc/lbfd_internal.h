@@ -45,6 +45,8 @@ struct KParams {
     const int *bpt;             // [3*4][nb] finite-difference point (or ghost image) index, axis-major, m = -2,-1,1,2
     const uint8_t *bwk;         // [3*4][nb] kind of the wall behind a ghost point, kFluid for a plain point
     const double *btw;          // [3*4][nb] wall temperature of isothermal ghost walls
+    const float *bq;            // [Q][nb] wall distance of the bounced link of population I, NaN: half-way
+                                // (nullptr: every link half-way)
     // block list of a step launch: boundary_blocks (a multiple of 8) blocks
     // of 256 boundary cells, then interior_blocks tiles of tiles_x x tiles_y
     // x (nz / tile depth); a launch covers blocks [block_begin, + gridDim.x)

@@ -298,7 +298,7 @@ __device__ __forceinline__ void ghost(const KParams &P, const Nb &w, const Pt<NS
 
 // Boundary cells: pull and stencil from the per-cell descriptors built at
 // init (same rules as gather / axis_stencil, resolved once on the host).
-template <int Q, int PREC, int I>
+template <int Q, int PREC, int I, bool BZ>
 __device__ __forceinline__ typename Prec<PREC>::calc desc_pull(const KParams &P, long long t, long long nb,
                                                                long long idx, int x, int y, int z)
 {
@@ -315,7 +315,24 @@ __device__ __forceinline__ typename Prec<PREC>::calc desc_pull(const KParams &P,
             return pop_load<Q, PREC, OPP>(P.pop_in, P.N, (uint32_t)idx) + (C)(2.0 * L::w(I) * P.rho_in * cu);
         }
         if (src == kSrcOutlet) return (C)P.outlet[outlet_index(P, L::cx(I) < 0 ? 1 : 0, I, Q, y, z)];
-        return pop_load<Q, PREC, OPP>(P.pop_in, P.N, (uint32_t)idx);
+        const C gb = pop_load<Q, PREC, OPP>(P.pop_in, P.N, (uint32_t)idx);
+        if constexpr (BZ) {
+            // linearly interpolated bounce-back (post-collision form) for a
+            // wall met at the fraction q of the link toward it (direction OPP)
+            const float qs = P.bq[I * nb + t];
+            if (qs == qs) {
+                const C q2 = (C)2 * (C)qs;  // weights in the arithmetic precision
+                if (qs < 0.5f) {
+                    const Nb far = classify(P, x + L::cx(I), y + L::cy(I), z + L::cz(I));
+                    if (far.kind == kFluid)
+                        return q2 * gb + ((C)1 - q2) * pop_load<Q, PREC, OPP>(P.pop_in, P.N, (uint32_t)far.idx);
+                } else {
+                    const C iq = (C)1 / q2;
+                    return gb * iq + (q2 - (C)1) * iq * pop_load<Q, PREC, I>(P.pop_in, P.N, (uint32_t)idx);
+                }
+            }
+        }
+        return gb;
     }
 }
 
@@ -791,7 +808,10 @@ template <int D> struct TileShape {
 // cells), with the general geometry logic.
 // (tx, ty, tz): the thread's place in the tile (FAST) or tx in 0..255.
 // slot: the block's row of the diagnostics partials.
-template <int Q, int NSP, int PREC, int MODE, bool FAST>
+// BZ: boundary cells apply the interpolated bounce-back of P.bq (a separate
+// instantiation, so that contexts without curved-wall links keep the
+// registers of plain bounce-back).
+template <int Q, int NSP, int PREC, int MODE, bool FAST, bool BZ = false>
 __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int bz, int tx, int ty, int tz,
                                            long long slot)
 {
@@ -864,7 +884,7 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
             if constexpr (FAST)
                 g[i] = pop_load<Q, PREC, i>(P.pop_in, P.N, idx - (L::cx(i) + sy * L::cy(i) + sz * L::cz(i)));
             else
-                g[i] = desc_pull<Q, PREC, i>(P, tb, P.n_boundary, idx, x, y, z);
+                g[i] = desc_pull<Q, PREC, i, BZ>(P, tb, P.n_boundary, idx, x, y, z);
         });
         Pt<NSP, C> ctr;
         if constexpr (TILE)
@@ -1087,7 +1107,7 @@ template <int Q, int NSP, int PREC, int PART> struct StepWaves {
 // renumbered to give each XCD one contiguous band of the box;
 // boundary_blocks is a multiple of 8, which keeps the XCD of a tile block
 // equal to its index modulo 8.
-template <int Q, int NSP, int PREC, int MODE, int PART>
+template <int Q, int NSP, int PREC, int MODE, int PART, bool BZ = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepWaves<Q, NSP, PREC, PART>::value)))
 step_kernel(const KParams P)
 {
@@ -1095,7 +1115,7 @@ step_kernel(const KParams P)
     const long long b = (long long)blockIdx.x + P.block_begin;
     if constexpr (PART != 1) {
         if (b < P.boundary_blocks) {
-            step_block<Q, NSP, PREC, MODE, false>(P, (int)b, 0, 0, (int)threadIdx.x, 0, 0,
+            step_block<Q, NSP, PREC, MODE, false, BZ>(P, (int)b, 0, 0, (int)threadIdx.x, 0, 0,
                                                   P.interior_blocks + b);
             return;
         }
@@ -1224,7 +1244,14 @@ hipError_t launch_range(const KParams &kp0, long long begin, long long count, hi
     if (count <= 0) return hipSuccess;
     KParams kp = kp0;
     kp.block_begin = begin;
-    step_kernel<Q, NSP, PREC, MODE, PART><<<dim3((unsigned)count), dim3(kBlock), 0, s>>>(kp);
+    if constexpr (PART != 1) {
+        // boundary cells with interpolated bounce-back links
+        if (kp.bq != nullptr) {
+            step_kernel<Q, NSP, PREC, MODE, PART, true><<<dim3((unsigned)count), dim3(kBlock), 0, s>>>(kp);
+            return hipGetLastError();
+        }
+    }
+    step_kernel<Q, NSP, PREC, MODE, PART, false><<<dim3((unsigned)count), dim3(kBlock), 0, s>>>(kp);
     return hipGetLastError();
 }
 

@@ -27,7 +27,8 @@ EXPORTS = ("lbfd_init", "lbfd_step", "lbfd_sync", "lbfd_level", "lbfd_read_field
            "lbfd_diagnostics", "lbfd_set_wall_temperature", "lbfd_state_size",
            "lbfd_save_state", "lbfd_load_state", "lbfd_time_steps", "lbfd_time_kernels",
            "lbfd_cell_counts", "lbfd_step_launches", "lbfd_set_reaction", "lbfd_set_objective",
-           "lbfd_objective", "lbfd_adjoint", "lbfd_set_inflow", "lbfd_hold_flame", "lbfd_destroy",
+           "lbfd_objective", "lbfd_adjoint", "lbfd_set_inflow", "lbfd_hold_flame", "lbfd_set_wall_links",
+           "lbfd_destroy",
            "lbfd_strerror", "lbfd_last_error")
 # collision operators (lbfd_params.collision)
 COLLISIONS = {"central_moments": 0, "cumulants": 1}
@@ -108,6 +109,7 @@ def load_library():
     lib.lbfd_set_reaction.argtypes = [vp, C.c_int, C.c_double, C.c_double, C.c_double]
     lib.lbfd_set_objective.argtypes = [vp, C.c_int, C.c_int64, C.c_int64]
     lib.lbfd_set_inflow.argtypes = [vp, C.c_int, dp]
+    lib.lbfd_set_wall_links.argtypes = [vp, C.c_int64, vp, vp, dp]
     lib.lbfd_hold_flame.argtypes = [vp, C.c_int64, C.c_int, C.c_double, C.c_double, dp, dp]
     lib.lbfd_objective.argtypes = [vp, C.c_int64, dp]
     lib.lbfd_adjoint.argtypes = [vp, C.c_int64, C.c_int, dp, dp, dp, dp]
@@ -292,6 +294,18 @@ class Solver:
                 "sum_theta": d.sum_theta, "hrr_idx": int(d.hrr_idx), "hrr_max": d.hrr_max,
                 "wall_q": d.wall_q, "fuel_rate": d.fuel_rate, "step": int(d.step),
                 "fuel_mass_rate": d.fuel_mass_rate, "consumption_speed": d.consumption_speed}
+
+    def set_wall_links(self, cell=None, direction=None, q=None):
+        """Interpolated bounce-back on the listed links (fluid cell, direction
+        toward the wall, wall fraction q), e.g. workloads.wall_links(prob);
+        None clears."""
+        if cell is None or len(cell) == 0:
+            _check(self._lib, self._lib.lbfd_set_wall_links(self._h, 0, None, None, None))
+            return
+        c = np.ascontiguousarray(cell, dtype=np.int64)
+        d = np.ascontiguousarray(direction, dtype=np.int32)
+        qq = np.ascontiguousarray(q, dtype=np.float64)
+        _check(self._lib, self._lib.lbfd_set_wall_links(self._h, len(c), c.ctypes.data, d.ctypes.data, _dp(qq)))
 
     def set_inflow(self, face: int, u=None):
         """Inlet velocity profile u [3, nz, ny] of x face 0 (-x) or 1 (+x),

@@ -179,6 +179,61 @@ def flame_channel(nx: int = 512, ny: int = 34, u_mean: float = 0.002, front_x: f
     return prob.replace(u0=u0)
 
 
+def wall_links(prob):
+    """Wall distances of the links that cross the curved walls of the
+    problem's shapes (prob.notes["shapes"]: cylinders (cx, cy, 0, r) of a
+    D2Q9 box, spheres (cx, cy, cz, r) of a D3Q27 box; solid where the cell
+    centre is within r, y and z periodic, x restricted to prob.notes["slab"]),
+    as input for an interpolated bounce-back.  For every fluid cell p and
+    lattice direction i whose neighbour p + c_i is a solid cell of a shape,
+    q is the fraction of the segment from p to p + c_i at which it enters
+    the shape (the smallest over the shapes covering p + c_i that do not
+    cover p).  Returns (cell [n] int64, dir [n] int32, q [n] float64),
+    sorted by cell then direction, directions in the lattice order (c_z,
+    c_y, c_x lexicographic, x fastest).  Links into solids of no shape are
+    not listed."""
+    shapes = prob.notes.get("shapes", [])
+    x0, x1 = prob.notes.get("slab", (0, prob.nx))
+    D = 2 if prob.lattice == 9 else 3
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    dirs = [(cx, cy, cz) for cz in ((-1, 0, 1) if D == 3 else (0,)) for cy in (-1, 0, 1) for cx in (-1, 0, 1)]
+    fluid = prob.mask.reshape(-1) == FLUID
+    best = {}
+    for (sx, sy, sz, r) in shapes:
+        ri = int(np.ceil(r)) + 2
+        xs = np.arange(max(0, int(np.floor(sx)) - ri), min(nx, int(np.ceil(sx)) + ri + 1))
+        ys = np.arange(int(np.floor(sy)) - ri, int(np.ceil(sy)) + ri + 1)
+        zs = np.arange(int(np.floor(sz)) - ri, int(np.ceil(sz)) + ri + 1) if D == 3 else np.zeros(1, int)
+        Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+        # positions relative to the centre (the unwrapped image nearest to it)
+        px, py, pz = X - sx, Y - sy, (Z - sz if D == 3 else np.zeros_like(X, dtype=float))
+        cell = ((Z % nz) * ny + (Y % ny)) * nx + X
+        out_p = (px * px + py * py + pz * pz > r * r) | (X < x0) | (X >= x1)
+        for i, (cx, cy, cz) in enumerate(dirs):
+            if cx == 0 and cy == 0 and cz == 0:
+                continue
+            qx, qy, qz = px + cx, py + cy, pz + cz
+            Xn = X + cx
+            in_n = (qx * qx + qy * qy + qz * qz <= r * r) & (Xn >= x0) & (Xn < x1)
+            sel = out_p & in_n & fluid[cell]
+            if not sel.any():
+                continue
+            a = float(cx * cx + cy * cy + cz * cz)
+            bq = 2.0 * (px * cx + py * cy + pz * cz)
+            cq = px * px + py * py + pz * pz - r * r
+            disc = np.sqrt(np.maximum(bq * bq - 4.0 * a * cq, 0.0))
+            t = (-bq - disc) / (2.0 * a)
+            for c, tv in zip(cell[sel].tolist(), t[sel].tolist()):
+                key = (c, i)
+                if tv > 0.0 and (key not in best or tv < best[key]):
+                    best[key] = min(tv, 1.0)
+    keys = sorted(best)
+    cells = np.array([k[0] for k in keys], dtype=np.int64)
+    dirs_out = np.array([k[1] for k in keys], dtype=np.int32)
+    q = np.array([best[k] for k in keys], dtype=np.float64)
+    return cells, dirs_out, q
+
+
 def wall_layer(T, Y, mask, wall_T, periodic_axes, delta=4.0):
     """Initial thermal layer next to solids: within `delta` cells of a solid
     cell the gas temperature is blended linearly from the nearest wall
@@ -221,12 +276,14 @@ def cylinder_burner(nx: int = 2048, ny: int = 512, radius: float = 20.0, pitch: 
     shape = (1, ny, nx)
     mask = np.zeros(shape, dtype=np.uint8)
     yy, xx = np.mgrid[0:ny, 0:nx]
+    cylinders = []
     for col, cx in enumerate(range(x_begin, x_end, pitch)):
         for j in range(ny // pitch):
             cy = pitch // 2 + pitch * j + (pitch // 2) * (col % 2)
             cy %= ny
             inside = (xx - cx) ** 2 + _periodic_delta(yy, cy, ny) ** 2 <= radius * radius
             mask[0][inside] = SOLID_ISOTHERMAL
+            cylinders.append((float(cx), float(cy), 0.0, float(radius)))
     x = np.arange(nx, dtype=np.float64)[None, None, :]
     T0, Y0 = _front_fields(shape, x, front_x, 4.0, 300.0, 1500.0, Y_UNBURNT_LEAN, Y_BURNT_LEAN)
     wT = np.full(shape, wall_T)
@@ -240,6 +297,7 @@ def cylinder_burner(nx: int = 2048, ny: int = 512, radius: float = 20.0, pitch: 
         u_in=(u_in, 0.0, 0.0), T_in=300.0, Y_in=Y_UNBURNT_LEAN,
         mask=mask, wall_T=wT, T0=T0, Y0=Y0, steps=steps,
         T_u=300.0, T_b=1500.0,
+        notes={"shapes": cylinders, "slab": (0, nx)},
     )
 
 
@@ -302,7 +360,7 @@ def porous_3d(nx: int = 256, ny: int = 256, nz: int = 256, porosity: float = 0.8
     inflow at -x (u_in, 300 K), outflow at +x, periodic in y and z; tanh
     front at front_x (default nx/2) with burnt gas downstream."""
     shape = (nz, ny, nx)
-    solid, _ = sphere_packing_mask(nx, ny, nz, porosity, radius, radius, seed, margin)
+    solid, spheres = sphere_packing_mask(nx, ny, nz, porosity, radius, radius, seed, margin)
     mask = np.where(solid, SOLID_ISOTHERMAL, FLUID).astype(np.uint8)
     T0, Y0 = _three_d_front(shape, nx, nx / 2 if front_x is None else front_x, 300.0, 1800.0,
                             Y_UNBURNT_STOICH, Y_BURNT_STOICH)
@@ -315,7 +373,7 @@ def porous_3d(nx: int = 256, ny: int = 256, nz: int = 256, porosity: float = 0.8
         W_ref=W_REF, W=W4, reactions=[one_step_reaction()],
         u_in=(u_in, 0.0, 0.0), T_in=300.0, Y_in=Y_UNBURNT_STOICH,
         mask=mask, wall_T=np.full(shape, wall_T), T0=T0, Y0=Y0, steps=steps,
-        notes={"seed": seed, "porosity_target": porosity},
+        notes={"seed": seed, "porosity_target": porosity, "shapes": spheres, "slab": (margin, nx - margin)},
     )
 
 
@@ -360,7 +418,7 @@ def porous_3d_mech(nx: int = 512, ny: int = 256, nz: int = 256, porosity: float 
     (all molar masses 28, so the mixture molar mass is constant)."""
     ns = 9
     shape = (nz, ny, nx)
-    solid, _ = sphere_packing_mask(nx, ny, nz, porosity, radius[0], radius[1], seed, margin)
+    solid, spheres = sphere_packing_mask(nx, ny, nz, porosity, radius[0], radius[1], seed, margin)
     mask = np.where(solid, SOLID_ISOTHERMAL, FLUID).astype(np.uint8)
     Y_lo = (0.05, 0.2) + (0.0,) * 6 + (0.75,)
     Y_hi = (0.0, 0.0) + (0.05, 0.05, 0.05, 0.05, 0.0, 0.05) + (0.75,)
@@ -374,7 +432,8 @@ def porous_3d_mech(nx: int = 512, ny: int = 256, nz: int = 256, porosity: float 
         W_ref=28.0, W=(28.0,) * ns, reactions=synthetic_mechanism(ns, 20, mech_seed),
         u_in=(u_in, 0.0, 0.0), T_in=300.0, Y_in=Y_lo,
         mask=mask, wall_T=np.full(shape, wall_T), T0=T0, Y0=Y0, steps=steps,
-        chem_substeps_max=substeps_max, notes={"seed": seed, "mech_seed": mech_seed},
+        chem_substeps_max=substeps_max,
+        notes={"seed": seed, "mech_seed": mech_seed, "shapes": spheres, "slab": (margin, nx - margin)},
     )
 
 

@@ -785,3 +785,60 @@ def test_taylor_green_decay_cumulants(oracle_mod):
     a1 = (o.fields()["u"][0, 0] * basis).sum() / (basis * basis).sum()
     rate = -math.log(a1 / a0) / 300
     assert abs(rate / (2 * nu * k * k) - 1.0) < 1e-2, rate / (2 * nu * k * k)
+
+
+def _poiseuille_offgrid_error(oracle_mod, H, q, links=True):
+    """Body-force channel whose walls cut the boundary links at the fraction
+    q (walls at y = 1 - q and y = H + q), against its parabola."""
+    prob = _uniform_problem(2, H + 2)
+    prob.mask[0, 0, :] = 2
+    prob.mask[0, H + 1, :] = 2
+    nu = CS2 * 0.1
+    yb, yt = 1.0 - q, H + q
+    L = yt - yb
+    F = 0.005 * 2 * nu * 4 / L ** 2
+    o = oracle_mod.Oracle(prob, body_force=(F, 0.0, 0.0))
+    if links:
+        cells, dirs = [], []
+        for x in range(2):
+            for i in range(9):
+                cy = i // 3 - 1
+                if cy == -1:
+                    cells.append(1 * 2 + x)
+                    dirs.append(i)
+                elif cy == 1:
+                    cells.append(H * 2 + x)
+                    dirs.append(i)
+        o.set_wall_links(cells, dirs, [q] * len(cells))
+    o.step(int(4 * L * L / nu))
+    u = o.fields()["u"][0, 0, 1:H + 1, 0]
+    y = np.arange(1, H + 1)
+    exact = F / (2 * nu) * (y - yb) * (yt - y)
+    return np.abs(u - exact).max() / exact.max()
+
+
+@pytest.mark.parametrize("q", [0.25, 0.75])
+def test_interpolated_bounce_back_poiseuille(oracle_mod, q):
+    """Curved-wall (interpolated) bounce-back: walls met at the fraction q of
+    the links; the channel flow converges to the parabola between the true
+    walls at second order, where half-way bounce-back (wall misplaced by
+    |q - 1/2|) stalls at first order."""
+    e8 = _poiseuille_offgrid_error(oracle_mod, 8, q)
+    e16 = _poiseuille_offgrid_error(oracle_mod, 16, q)
+    assert e16 < 1e-2 and e8 / e16 > 3.4, (e8, e16)
+    b8 = _poiseuille_offgrid_error(oracle_mod, 8, q, links=False)
+    b16 = _poiseuille_offgrid_error(oracle_mod, 16, q, links=False)
+    assert b16 > 5 * e16 and b8 / b16 < 2.5, (b8, b16)
+
+
+def test_half_way_links_are_plain_bounce_back(oracle_mod):
+    """Links listed with q = 1/2 give half-way bounce-back bit for bit."""
+    prob = W.cylinder_burner(nx=160, ny=64, x_begin=40, x_end=120, front_x=80.0, name="links_half")
+    cells, dirs, _ = W.wall_links(prob)
+    a = oracle_mod.Oracle(prob)
+    b = oracle_mod.Oracle(prob)
+    b.set_wall_links(cells, dirs, np.full(len(cells), 0.5))
+    a.step(20)
+    b.step(20)
+    assert np.array_equal(a.pops(), b.pops())
+    assert len(cells) > 100
