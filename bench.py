@@ -46,9 +46,9 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_05657_amd", "csrc", f)
 # SHA-256 (kernel_sha) is given (profiles/traffic_step_kernels_burner_2048x512.md).
 TRAFFIC_WORKLOAD = "cylinder_burner_2048x512"
 TRAFFIC = {
-    "fp64": {"kernel_sha256": "43e162b7db20a12e1443b88bbf44f9fc5c425269dc3be49f8df2559be2ebf6e1", "bytes_per_launch": 295.2e6},
-    "fp32": {"kernel_sha256": "43e162b7db20a12e1443b88bbf44f9fc5c425269dc3be49f8df2559be2ebf6e1", "bytes_per_launch": 177.4e6},
-    "fp16": {"kernel_sha256": "43e162b7db20a12e1443b88bbf44f9fc5c425269dc3be49f8df2559be2ebf6e1", "bytes_per_launch": 133.2e6},
+    "fp64": {"kernel_sha256": "080044cdc6f3851e0b95fd38e04b4899f6a74789800f36015c4f48ecc958c4d7", "bytes_per_launch": 295.2e6},
+    "fp32": {"kernel_sha256": "080044cdc6f3851e0b95fd38e04b4899f6a74789800f36015c4f48ecc958c4d7", "bytes_per_launch": 177.3e6},
+    "fp16": {"kernel_sha256": "080044cdc6f3851e0b95fd38e04b4899f6a74789800f36015c4f48ecc958c4d7", "bytes_per_launch": 132.9e6},
 }
 POP_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 SCALAR_BYTES = {"fp64": 8, "fp32": 4, "fp16": 4}
