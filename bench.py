@@ -117,13 +117,15 @@ def accuracy(ref: dict, ref_diag: dict, fields: dict, diag: dict, prob) -> dict:
             "flame_dx_cells": float(flame_position(diag, prob) - flame_position(ref_diag, prob))}
 
 
-def run_gpu(prob, precision: str, steps: int, warmup: int, links=None) -> dict:
+def run_gpu(prob, precision: str, steps: int, warmup: int, links=None, images=None) -> dict:
     import torch
     from paper_2304_05657_amd.lbfd import Solver
 
     s = Solver(prob, precision=precision, stream=int(torch.cuda.current_stream().cuda_stream))
     if links is not None:
         s.set_wall_links(*links)
+    if images is not None:
+        s.set_image_points(*images)
     s.step(warmup)
     s.sync()
     torch.cuda.synchronize()
@@ -239,6 +241,9 @@ def main():
                     help="relaxation of the orders >= 4: central moments (default) or cumulants")
     ap.add_argument("--wall-links", action="store_true",
                     help="interpolated bounce-back on the links crossing the workload's cylinders / spheres")
+    ap.add_argument("--image-points", action="store_true",
+                    help="Shepard-reconstructed image points for the ghost nodes inside the workload's "
+                         "cylinders / spheres")
     ap.add_argument("--workload", default="burner",
                     help="burner (default), channel, porous or porous_mech")
     ap.add_argument("--accuracy-steps", type=int, default=None,
@@ -259,6 +264,7 @@ def main():
 
     prob = W.named(args.workload).replace(collision=args.collision)
     links = W.wall_links(prob) if args.wall_links else None
+    images = W.image_points(prob) if args.image_points else None
     if args.accuracy_steps is None:
         args.accuracy_steps = 20000 if args.workload == "burner" else 2000
     precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
@@ -266,7 +272,7 @@ def main():
     ref = None
     for p in precs:
         print("[bench] %s: %d warmup + %d timed steps" % (p, args.warmup, args.steps), file=sys.stderr, flush=True)
-        results[p], solver = run_gpu(prob, p, args.steps, args.warmup, links)
+        results[p], solver = run_gpu(prob, p, args.steps, args.warmup, links, images)
         print("[bench] %s: %s" % (p, json.dumps(results[p])), file=sys.stderr, flush=True)
         if args.accuracy_steps > 0:
             # continue the same run (outside the timed region) to the
@@ -313,7 +319,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": prob.name, "lattice": "D2Q9" if prob.lattice == 9 else "D3Q27", "cells": prob.N, "fluid_cells": prob.n_fluid,
                    "species": prob.n_species, "reactions": len(prob.reactions), "storage": precs[0],
-                   "collision": prob.collision, "wall_links": links is not None},
+                   "collision": prob.collision, "wall_links": links is not None,
+                   "image_points": images is not None},
         "roofline": roofline(head, precs[0], prob.name),
         "cpu_baseline": cpu,
         "precisions": {p: {k: v for k, v in r.items() if k != "precision"} for p, r in results.items()},

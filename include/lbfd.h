@@ -206,6 +206,25 @@ int lbfd_diagnostics(lbfd_ctx *c, lbfd_diag *d);
  * LBFD_EINVAL for a link that does not run from a fluid cell to a wall. */
 int lbfd_set_wall_links(lbfd_ctx *c, int64_t n, const int64_t *cell, const int32_t *dir, const double *q);
 
+/* Curved walls for the finite differences (image/ghost nodes, Sec. III.B,
+ * with Shepard's inverse-distance reconstruction): entry k names the ghost
+ * node at offset m = (-2, -1, +1, +2)[j] along axis a of boundary fluid
+ * cell cell[k] (slot[k] = 4 a + j, a = 0 x, 1 y, 2 z) -- a point of the
+ * cell's finite-difference stencil that lies behind a wall (solid cell) --
+ * and image[3k..3k+2] the lattice coordinates (x, y, z; z = 0 for D2Q9;
+ * unwrapped across periodic faces) of its image point I = 2B - G, B the
+ * wall point nearest to the ghost G.  The ghost's wall value then comes
+ * from the value at I reconstructed by inverse-distance weighting over
+ * every fluid node r_j with |I - r_j| <= 4 cells, weights |I - r_j|^-2
+ * normalised to sum to one (a node at I takes the whole weight), instead
+ * of the axis-mirror image; unlisted ghosts keep the axis mirror.  The
+ * weights are computed here, once, in double precision and held on the
+ * device (4 + 8 bytes per node).  Replaces the previous set; n = 0 clears.
+ * LBFD_EINVAL for a slot that is not a ghost behind a wall, a repeated
+ * ghost, or an image point with no fluid node within four cells;
+ * LBFD_ENOMEM when the tables do not fit. */
+int lbfd_set_image_points(lbfd_ctx *c, int64_t n, const int64_t *cell, const int32_t *slot, const double *image);
+
 /* Inlet velocity profile of the x face `face` (0: -x, 1: +x), which must
  * be an INFLOW face: u [3][nz][ny] (host, lattice units) is the velocity
  * imposed (Eq. 31) on every population entering the box through that face

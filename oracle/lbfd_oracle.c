@@ -62,6 +62,9 @@ struct lbo_state {
     const uint8_t *active;  /* NULL, or the cells a step / fields call covers */
     double *u_face;         /* NULL, or [2 x faces][3][nz][ny] inlet velocity per face cell */
     double *q_link;         /* NULL, or [Q][N] wall distance of link (cell, i), NAN = half-way */
+    long n_img;             /* image points of ghost nodes on curved walls, sorted by key */
+    long *img_key;          /* cell * 12 + axis * 4 + j (offset m = -2, -1, 1, 2 for j = 0..3) */
+    double *img_x;          /* [n_img][3] lattice coordinates of the image point */
 };
 
 /* Whether a fluid cell is covered by the current active set. */
@@ -580,6 +583,79 @@ static void ghost_value(const lbo_state *s, const cellref *wall, const scal *img
     }
 }
 
+/* Shepard's inverse-distance reconstruction (Sec. III.B): the value at  */
+/* the point x is the average of every fluid node r_j with |x - r_j| <= */
+/* 4 cells, weighted by |x - r_j|^-2 (p = 2), the weights normalised to */
+/* sum to one; a node at distance zero takes the whole weight.  Nodes   */
+/* are found through classify (periodic faces wrap; reading: candidate  */
+/* points are the integer points of the cube around x, in a D2Q9 box    */
+/* those of the plane z = 0).  Returns the number of nodes used.        */
+static int shepard(const lbo_state *s, const double *x, scal *o)
+{
+    int ns = s->p.n_species;
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        if (d < s->D) {
+            lo[d] = (int)ceil(x[d] - 4.0);
+            hi[d] = (int)floor(x[d] + 4.0);
+        } else {
+            lo[d] = hi[d] = 0;
+        }
+    }
+    double wsum = 0.0, T = 0.0, rho = 0.0, Y[LBO_MAXSP];
+    for (int k = 0; k < ns; ++k)
+        Y[k] = 0.0;
+    int n = 0;
+    for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y)
+            for (int xx = lo[0]; xx <= hi[0]; ++xx) {
+                double dx = xx - x[0], dy = y - x[1], dz = s->D == 3 ? z - x[2] : 0.0;
+                double d2 = dx * dx + dy * dy + dz * dz;
+                if (d2 > 16.0)
+                    continue;
+                cellref c = classify(s, xx, y, z);
+                if (c.kind != K_FLUID)
+                    continue;
+                if (d2 == 0.0) {            /* x is this node */
+                    load_scal(s, c.idx, o);
+                    return 1;
+                }
+                double w = 1.0 / d2;
+                wsum += w;
+                T += w * s->T[c.idx];
+                rho += w * s->rho[c.idx];
+                for (int k = 0; k < ns; ++k)
+                    Y[k] += w * s->Y[k * s->N + c.idx];
+                ++n;
+            }
+    if (n == 0)
+        return 0;
+    o->T = T / wsum;
+    o->rho = rho / wsum;
+    for (int k = 0; k < ns; ++k)
+        o->Y[k] = Y[k] / wsum;
+    return n;
+}
+
+/* The image of the ghost node at slot (axis d, offset index j) of cell */
+/* idx when one is listed: the Shepard value at that image point.       */
+static int listed_image(const lbo_state *s, long idx, int d, int j, scal *o)
+{
+    if (s->n_img == 0)
+        return 0;
+    long key = idx * 12 + d * 4 + j, lo = 0, hi = s->n_img - 1;
+    while (lo <= hi) {
+        long mid = (lo + hi) / 2;
+        if (s->img_key[mid] == key)
+            return shepard(s, &s->img_x[3 * mid], o) > 0;
+        if (s->img_key[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid - 1;
+    }
+    return 0;
+}
+
 /* Values at p + m e_d, m = -2..2, with ghosts; *near is set when a      */
 /* non-fluid point lies within two cells on either side.                 */
 static void axis_stencil(const lbo_state *s, const int *pc, long pidx, int d,
@@ -594,21 +670,29 @@ static void axis_stencil(const lbo_state *s, const int *pc, long pidx, int d,
         cellref c1 = classify(s, q1[0], q1[1], q1[2]);
         cellref c2 = classify(s, q2[0], q2[1], q2[2]);
         scal *s1 = &st[2 + sg], *s2 = &st[2 + 2 * sg];
+        /* offset index j of m = -2, -1, 1, 2 for the listed image points */
+        int j1 = sg < 0 ? 1 : 2, j2 = sg < 0 ? 0 : 3;
+        scal img;
         if (c1.kind != K_FLUID) {
             *near = 1;
-            scal img;
-            ghost_value(s, &c1, &st[2], s1);           /* image of p+s is p */
-            cellref cm = classify(s, qm[0], qm[1], qm[2]);
-            if (cm.kind == K_FLUID)
-                load_scal(s, cm.idx, &img);              /* image of p+2s is p-s */
-            else
-                img = st[2];                             /* clamped to p */
+            if (!listed_image(s, pidx, d, j1, &img))
+                img = st[2];                             /* image of p+s is p */
+            ghost_value(s, &c1, &img, s1);
+            if (!listed_image(s, pidx, d, j2, &img)) {
+                cellref cm = classify(s, qm[0], qm[1], qm[2]);
+                if (cm.kind == K_FLUID)
+                    load_scal(s, cm.idx, &img);          /* image of p+2s is p-s */
+                else
+                    img = st[2];                         /* clamped to p */
+            }
             ghost_value(s, &c1, &img, s2);
         } else {
             load_scal(s, c1.idx, s1);
             if (c2.kind != K_FLUID) {
                 *near = 1;
-                ghost_value(s, &c2, s1, s2);             /* image of p+2s is p+s */
+                if (!listed_image(s, pidx, d, j2, &img))
+                    img = *s1;                           /* image of p+2s is p+s */
+                ghost_value(s, &c2, &img, s2);
             } else {
                 load_scal(s, c2.idx, s2);
             }
@@ -940,6 +1024,72 @@ int lbo_set_wall_links(lbo_state *s, long n, const long *cell, const int *dir, c
     return 0;
 }
 
+/*
+ * Image points of ghost nodes on curved walls (Sec. III.B): for the ghost
+ * at offset m = (-2, -1, 1, 2)[j] along axis d of fluid cell cell[k]
+ * (slot[k] = 4 d + j), the image point I = 2B - G of the ghost G across
+ * the wall point B nearest to it, image[3k..3k+2] in lattice coordinates.
+ * The ghost then takes its wall value from the Shepard reconstruction at
+ * I instead of the axis mirror.  n = 0 clears.  Returns 0, or -1 for an
+ * entry out of range or a repeated (cell, slot).
+ */
+static int cmp_long(const void *a, const void *b)
+{
+    long x = *(const long *)a, y = *(const long *)b;
+    return x < y ? -1 : x > y;
+}
+
+int lbo_set_image_points(lbo_state *s, long n, const long *cell, const int *slot, const double *image)
+{
+    free(s->img_key);
+    free(s->img_x);
+    s->img_key = NULL;
+    s->img_x = NULL;
+    s->n_img = 0;
+    if (n <= 0)
+        return 0;
+    /* sort (key, position) pairs, then gather the coordinates */
+    long *pairs = (long *)malloc(sizeof(long) * 2 * (size_t)n);
+    for (long k = 0; k < n; ++k) {
+        if (cell[k] < 0 || cell[k] >= s->N || slot[k] < 0 || slot[k] >= 4 * s->D) {
+            free(pairs);
+            return -1;
+        }
+        pairs[2 * k] = cell[k] * 12 + slot[k];
+        pairs[2 * k + 1] = k;
+    }
+    qsort(pairs, (size_t)n, 2 * sizeof(long), cmp_long);
+    s->img_key = (long *)malloc(sizeof(long) * (size_t)n);
+    s->img_x = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    for (long k = 0; k < n; ++k) {
+        if (k > 0 && pairs[2 * k] == pairs[2 * k - 2]) {
+            free(pairs);
+            lbo_set_image_points(s, 0, NULL, NULL, NULL);
+            return -1;
+        }
+        s->img_key[k] = pairs[2 * k];
+        for (int d = 0; d < 3; ++d)
+            s->img_x[3 * k + d] = image[3 * pairs[2 * k + 1] + d];
+    }
+    s->n_img = n;
+    free(pairs);
+    return 0;
+}
+
+/* Shepard reconstruction of T and Y_k at the point x from the current   */
+/* level (pins of the reconstruction); returns the number of nodes.     */
+int lbo_image_value(lbo_state *s, const double *x, double *T, double *Y)
+{
+    scal o;
+    int n = shepard(s, x, &o);
+    if (n > 0) {
+        *T = o.T;
+        for (int k = 0; k < s->p.n_species; ++k)
+            Y[k] = o.Y[k];
+    }
+    return n;
+}
+
 int lbo_set_inflow(lbo_state *s, int face, const double *u)
 {
     const lbo_params *p = &s->p;
@@ -1207,5 +1357,7 @@ void lbo_destroy(lbo_state *s)
     free(s->T); free(s->Tn); free(s->Y); free(s->Yn); free(s->rho); free(s->ux);
     free(s->u_face);
     free(s->q_link);
+    free(s->img_key);
+    free(s->img_x);
     free(s);
 }

@@ -86,6 +86,8 @@ long lbo_level(const lbo_state *s);
 void lbo_set_active(lbo_state *s, const uint8_t *active);
 int lbo_set_inflow(lbo_state *s, int face, const double *u);
 int lbo_set_wall_links(lbo_state *s, long n, const long *cell, const int *dir, const double *q);
+int lbo_set_image_points(lbo_state *s, long n, const long *cell, const int *slot, const double *image);
+int lbo_image_value(lbo_state *s, const double *x, double *T, double *Y);
 void lbo_fields(lbo_state *s, double *rho, double *u, double *T, double *Y,
                 double *Ph);
 void lbo_diagnostics(lbo_state *s, double *out);

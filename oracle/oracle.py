@@ -106,6 +106,10 @@ def _load():
         lib.lbo_set_inflow.argtypes = [C.c_void_p, C.c_int, dp]
         lib.lbo_set_wall_links.argtypes = [C.c_void_p, C.c_long, C.c_void_p, C.c_void_p, dp]
         lib.lbo_set_wall_links.restype = C.c_int
+        lib.lbo_set_image_points.argtypes = [C.c_void_p, C.c_long, C.c_void_p, C.c_void_p, dp]
+        lib.lbo_set_image_points.restype = C.c_int
+        lib.lbo_image_value.argtypes = [C.c_void_p, dp, dp, dp]
+        lib.lbo_image_value.restype = C.c_int
         lib.lbo_set_inflow.restype = C.c_int
         lib.lbo_fields.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
         lib.lbo_diagnostics.argtypes = [C.c_void_p, dp]
@@ -231,6 +235,30 @@ class Oracle:
         qq = np.ascontiguousarray(q, dtype=np.float64)
         if self._lib.lbo_set_wall_links(self._h, len(c), c.ctypes.data, d.ctypes.data, _dp(qq)) != 0:
             raise ValueError("wall link out of range")
+
+    def set_image_points(self, cell=None, slot=None, image=None):
+        """Shepard-reconstructed image points of the listed ghost nodes
+        (fluid cell, slot = 4 axis + j for the offset (-2, -1, 1, 2)[j],
+        image point [n, 3] in lattice coordinates); None clears."""
+        if cell is None or len(cell) == 0:
+            self._lib.lbo_set_image_points(self._h, 0, None, None, None)
+            return
+        c = np.ascontiguousarray(cell, dtype=np.int64)
+        sl = np.ascontiguousarray(slot, dtype=np.int32)
+        im = np.ascontiguousarray(image, dtype=np.float64).reshape(-1, 3)
+        if len(im) != len(c) or len(sl) != len(c):
+            raise ValueError("cell, slot and image lengths differ")
+        if self._lib.lbo_set_image_points(self._h, len(c), c.ctypes.data, sl.ctypes.data, _dp(im)) != 0:
+            raise ValueError("image point out of range or repeated")
+
+    def image_value(self, x):
+        """Shepard reconstruction (T, Y[n_species], nodes used) at the
+        point x of the current level."""
+        xx = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(3))
+        T = np.zeros(1)
+        Y = np.zeros(max(1, self.nsp))
+        n = self._lib.lbo_image_value(self._h, _dp(xx), _dp(T), _dp(Y))
+        return float(T[0]), Y[: self.nsp].copy(), int(n)
 
     def set_threads(self, n: int):
         """OpenMP threads of the following steps (process-wide)."""

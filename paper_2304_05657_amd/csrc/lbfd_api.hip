@@ -88,6 +88,14 @@ struct lbfd_ctx {
     double *inflow_u = nullptr;         // [2 x faces][3][nz][ny] inlet velocity profiles
     double *inflow_du = nullptr;        // [3][nz][ny] staging of a profile change
     float *bq = nullptr;                // [Q][nb] interpolated bounce-back wall distances (optional)
+    int *bimg = nullptr;                // [12][nb] image point of a ghost node, -1 none (optional)
+    long long n_img = 0;                // image points:
+    int img_lpp = 64;                   //   lanes per Shepard row
+    int2 *img_rng = nullptr;            //   Shepard list ranges
+    int *img_idx = nullptr;             //   their fluid nodes
+    double *img_w = nullptr;            //   and weights
+    double *img_val = nullptr;          //   reconstructed values of the current level
+    std::vector<uint8_t> bwk_host;      // host copy of the ghost kinds of the descriptors
     std::vector<double> inflow_host;   // host copy
     size_t outlet_n = 0;
     double *fields = nullptr;
@@ -106,6 +114,7 @@ static void free_ctx(lbfd_ctx *c)
     if (!c) return;
     void *ptrs[] = {c->pop[0], c->pop[1], c->sc[0], c->sc[1], c->mask, c->code, c->boundary, c->bsrc, c->bpt, c->bwk,
                     c->btw, c->wall_T, c->outlet, c->outlet_un, c->inflow_u, c->inflow_du, c->bq,
+                    c->bimg, c->img_rng, c->img_idx, c->img_w, c->img_val,
                     c->fields, c->partials, c->diag_dev, c->bad_dev, c->rx_dev};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -345,6 +354,7 @@ static int build_descriptors(lbfd_ctx *c)
     HIP_TRY(hipMemcpy(c->bsrc, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->bpt, pt.data(), pt.size() * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->bwk, wk.data(), wk.size(), hipMemcpyHostToDevice));
+    c->bwk_host = wk;
     HIP_TRY(hipMemcpy(c->btw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice));
     return LBFD_OK;
 }
@@ -380,6 +390,13 @@ static KParams make_kparams(const lbfd_ctx *c)
     k.outlet_un = c->outlet_un;
     k.inflow_u = c->inflow_u;
     k.bq = c->bq;
+    k.bimg = c->bimg;
+    k.n_img = c->n_img;
+    k.img_lpp = c->img_lpp;
+    k.img_rng = c->img_rng;
+    k.img_idx = c->img_idx;
+    k.img_w = c->img_w;
+    k.img_val = c->img_val;
     k.fields = c->fields;
     k.partials = c->partials;
     k.rx = c->rx_dev;
@@ -722,6 +739,121 @@ int lbfd_set_wall_links(lbfd_ctx *c, int64_t n, const int64_t *cell, const int32
     return LBFD_OK;
 }
 
+static void clear_image_points(lbfd_ctx *c)
+{
+    void *ptrs[] = {c->bimg, c->img_rng, c->img_idx, c->img_w, c->img_val};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    c->bimg = nullptr;
+    c->img_rng = nullptr;
+    c->img_idx = nullptr;
+    c->img_w = nullptr;
+    c->img_val = nullptr;
+    c->n_img = 0;
+    c->base.bimg = nullptr;
+    c->base.n_img = 0;
+    c->base.img_rng = nullptr;
+    c->base.img_idx = nullptr;
+    c->base.img_w = nullptr;
+    c->base.img_val = nullptr;
+}
+
+int lbfd_set_image_points(lbfd_ctx *c, int64_t n, const int64_t *cell, const int32_t *slot, const double *image)
+{
+    if (!c || n < 0 || (n > 0 && (!cell || !slot || !image))) return fail(LBFD_EINVAL, "bad arguments");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    clear_image_points(c);
+    if (n == 0) return LBFD_OK;
+    const lbfd_params &p = c->p;
+    const long long nb = c->n_boundary, N = c->N;
+    const int D = c->D;
+    const uint8_t *mask = c->mask_host.data();
+    const double *wT = c->wall_T_host.data();
+    std::vector<int> pos(N, -1);  // cell -> position in the boundary list
+    for (long long t = 0; t < nb; ++t) pos[c->boundary_host[t]] = (int)t;
+    if (n > (int64_t)INT32_MAX) return fail(LBFD_EINVAL, "too many image points");
+    std::vector<int> which((size_t)12 * nb, -1);
+    std::vector<int2> range((size_t)n);
+    std::vector<int> nodes;
+    std::vector<double> wts;
+    for (int64_t k = 0; k < n; ++k) {
+        const long long i = cell[k];
+        const int s = slot[k];
+        const double *xi = image + 3 * k;
+        if (i < 0 || i >= N || s < 0 || s >= 4 * D || !std::isfinite(xi[0]) || !std::isfinite(xi[1]) ||
+            !std::isfinite(xi[2]))
+            return fail(LBFD_EINVAL, "image point %lld out of range", (long long)k);
+        if (mask[i] != LBFD_FLUID || pos[i] < 0)
+            return fail(LBFD_EINVAL, "image point %lld does not belong to a boundary fluid cell", (long long)k);
+        const size_t r = (size_t)s * nb + pos[i];
+        if (c->bwk_host[r] != kIso && c->bwk_host[r] != kAdia)
+            return fail(LBFD_EINVAL, "image point %lld: its stencil point is not a ghost node behind a wall",
+                        (long long)k);
+        if (which[r] >= 0) return fail(LBFD_EINVAL, "image point %lld repeats a ghost node", (long long)k);
+        // Shepard weights: every fluid node within four cells of the image
+        // point, weight d^-2 normalised; a node at distance zero takes all
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int d = 0; d < D; ++d) {
+            lo[d] = (int)std::ceil(xi[d] - 4.0);
+            hi[d] = (int)std::floor(xi[d] + 4.0);
+        }
+        const size_t begin = nodes.size();
+        double wsum = 0.0;
+        bool exact = false;
+        for (int z = lo[2]; z <= hi[2] && !exact; ++z)
+            for (int y = lo[1]; y <= hi[1] && !exact; ++y)
+                for (int x = lo[0]; x <= hi[0]; ++x) {
+                    const double dx = x - xi[0], dy = y - xi[1], dz = D == 3 ? z - xi[2] : 0.0;
+                    const double d2 = dx * dx + dy * dy + dz * dz;
+                    if (d2 > 16.0) continue;
+                    const HostNb h = host_classify(p, mask, wT, x, y, z);
+                    if (h.kind != kFluid) continue;
+                    if (d2 == 0.0) {
+                        nodes.resize(begin);
+                        wts.resize(begin);
+                        nodes.push_back((int)h.idx);
+                        wts.push_back(1.0);
+                        exact = true;
+                        break;
+                    }
+                    nodes.push_back((int)h.idx);
+                    wts.push_back(1.0 / d2);
+                    wsum += 1.0 / d2;
+                }
+        if (nodes.size() == begin)
+            return fail(LBFD_EINVAL, "image point %lld has no fluid node within four cells", (long long)k);
+        if (!exact)
+            for (size_t e = begin; e < nodes.size(); ++e) wts[e] /= wsum;
+        if (nodes.size() > (size_t)INT32_MAX) return fail(LBFD_EINVAL, "too many Shepard nodes");
+        range[k] = make_int2((int)begin, (int)(nodes.size() - begin));
+        which[r] = (int)k;
+    }
+    if (hipMalloc((void **)&c->bimg, which.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&c->img_rng, range.size() * sizeof(int2)) != hipSuccess ||
+        hipMalloc((void **)&c->img_idx, nodes.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&c->img_w, wts.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->img_val, (size_t)(2 + c->nsp) * n * sizeof(double)) != hipSuccess) {
+        clear_image_points(c);
+        return fail(LBFD_ENOMEM, "hipMalloc of the image-point tables failed");
+    }
+    HIP_TRY(hipMemcpy(c->bimg, which.data(), which.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->img_rng, range.data(), range.size() * sizeof(int2), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->img_idx, nodes.data(), nodes.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->img_w, wts.data(), wts.size() * sizeof(double), hipMemcpyHostToDevice));
+    // lanes per row: about two nodes per lane on average
+    const double mean = (double)nodes.size() / (double)n;
+    c->img_lpp = mean <= 32.0 ? 16 : mean <= 64.0 ? 32 : 64;
+    c->n_img = n;
+    c->base.bimg = c->bimg;
+    c->base.n_img = n;
+    c->base.img_lpp = c->img_lpp;
+    c->base.img_rng = c->img_rng;
+    c->base.img_idx = c->img_idx;
+    c->base.img_w = c->img_w;
+    c->base.img_val = c->img_val;
+    return LBFD_OK;
+}
+
 int lbfd_set_inflow(lbfd_ctx *c, int face, const double *u)
 {
     if (!c) return fail(LBFD_EINVAL, "null context");
@@ -1026,6 +1158,8 @@ int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwall
     if (c->prec != LBFD_FP64) return fail(LBFD_EINVAL, "the adjoint needs FP64 precision");
     if (c->p.collision != LBFD_CENTRAL_MOMENTS)
         return fail(LBFD_EINVAL, "the adjoint differentiates the central-moment collision only");
+    if (c->bq || c->bimg)
+        return fail(LBFD_EINVAL, "the adjoint differentiates half-way bounce-back and axis-mirror ghosts only");
     if (!adjoint_supported(c->Q, c->nsp))
         return fail(LBFD_EINVAL, "no adjoint kernel for lattice %d with %d species", c->Q, c->nsp);
     for (int f = 0; f < 6; ++f)

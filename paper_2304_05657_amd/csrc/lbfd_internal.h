@@ -47,6 +47,14 @@ struct KParams {
     const double *btw;          // [3*4][nb] wall temperature of isothermal ghost walls
     const float *bq;            // [Q][nb] wall distance of the bounced link of population I, NaN: half-way
                                 // (nullptr: every link half-way)
+    const int *bimg;            // [3*4][nb] a ghost's image point in img_val, -1: axis mirror
+                                // (nullptr: every ghost)
+    long long n_img;            // image points:
+    int img_lpp;                //   lanes per Shepard row (16, 32 or 64)
+    const int2 *img_rng;        //   [n_img] {begin, count} of the Shepard list
+    const int *img_idx;         //   fluid nodes of the lists
+    const double *img_w;        //   and their normalised weights
+    double *img_val;            //   [2 + n_species][n_img] T, rho, Y_k at the image points (this level)
     // block list of a step launch: boundary_blocks (a multiple of 8) blocks
     // of 256 boundary cells, then interior_blocks tiles of tiles_x x tiles_y
     // x (nz / tile depth); a launch covers blocks [block_begin, + gridDim.x)
@@ -84,9 +92,10 @@ constexpr bool fused_step(int Q) { return Q == 9; }
 
 inline int step_launches(int Q, const KParams &kp)
 {
-    if (fused_step(Q)) return kp.boundary_blocks + kp.interior_blocks > 0 ? 1 : 0;
+    const int images = kp.bimg != nullptr && kp.n_img > 0 ? 1 : 0;
+    if (fused_step(Q)) return (kp.boundary_blocks + kp.interior_blocks > 0 ? 1 : 0) + images;
     const bool outlet = kp.n_boundary > 0 && (kp.face[0] == LBFD_FACE_OUTFLOW || kp.face[1] == LBFD_FACE_OUTFLOW);
-    return (kp.boundary_blocks > 0) + (kp.interior_blocks > 0) + (outlet ? 1 : 0);
+    return (kp.boundary_blocks > 0) + (kp.interior_blocks > 0) + (outlet ? 1 : 0) + images;
 }
 
 // Where a step is launched: the context stream, and which blocks (0: all,

@@ -280,25 +280,20 @@ __device__ __forceinline__ void load_point(const KParams &P, long long idx, Pt<N
 template <int NSP, class C>
 __device__ __forceinline__ void ghost(const KParams &P, const Nb &w, const Pt<NSP, C> &img, Pt<NSP, C> &o)
 {
-    if (w.kind == kIso) {
-        C Tw = (C)w.Tw;
-        o.T = (C)2 * Tw - img.T;
+    // selects rather than branches: every field of o is written once
+    const bool iso = w.kind == kIso, inf = w.kind == kInflow;
+    const C Tw = (C)w.Tw;
+    C rho_b = (C)P.rho_in;
+    if (iso) rho_b = density<NSP>(P, Tw, img.Y);
+    o.T = iso ? (C)2 * Tw - img.T : inf ? (C)2 * (C)P.T_in - img.T : img.T;
 #pragma unroll
-        for (int k = 0; k < NSP; ++k) o.Y[k] = img.Y[k];
-        o.rho = (C)2 * density<NSP>(P, Tw, img.Y) - img.rho;
-    } else if (w.kind == kInflow) {
-        o.T = (C)2 * (C)P.T_in - img.T;
-#pragma unroll
-        for (int k = 0; k < NSP; ++k) o.Y[k] = (C)2 * (C)P.Y_in[k] - img.Y[k];
-        o.rho = (C)2 * (C)P.rho_in - img.rho;
-    } else {
-        o = img;
-    }
+    for (int k = 0; k < NSP; ++k) o.Y[k] = inf ? (C)2 * (C)P.Y_in[k] - img.Y[k] : img.Y[k];
+    o.rho = iso || inf ? (C)2 * rho_b - img.rho : img.rho;
 }
 
 // Boundary cells: pull and stencil from the per-cell descriptors built at
 // init (same rules as gather / axis_stencil, resolved once on the host).
-template <int Q, int PREC, int I, bool BZ>
+template <int Q, int PREC, int I, bool CW>
 __device__ __forceinline__ typename Prec<PREC>::calc desc_pull(const KParams &P, long long t, long long nb,
                                                                long long idx, int x, int y, int z)
 {
@@ -316,16 +311,17 @@ __device__ __forceinline__ typename Prec<PREC>::calc desc_pull(const KParams &P,
         }
         if (src == kSrcOutlet) return (C)P.outlet[outlet_index(P, L::cx(I) < 0 ? 1 : 0, I, Q, y, z)];
         const C gb = pop_load<Q, PREC, OPP>(P.pop_in, P.N, (uint32_t)idx);
-        if constexpr (BZ) {
+        if constexpr (CW) {
             // linearly interpolated bounce-back (post-collision form) for a
             // wall met at the fraction q of the link toward it (direction OPP)
-            const float qs = P.bq[I * nb + t];
+            const float qs = P.bq ? P.bq[I * nb + t] : __builtin_nanf("");
             if (qs == qs) {
                 const C q2 = (C)2 * (C)qs;  // weights in the arithmetic precision
                 if (qs < 0.5f) {
-                    const Nb far = classify(P, x + L::cx(I), y + L::cy(I), z + L::cz(I));
-                    if (far.kind == kFluid)
-                        return q2 * gb + ((C)1 - q2) * pop_load<Q, PREC, OPP>(P.pop_in, P.N, (uint32_t)far.idx);
+                    // the far node r + c_I is the pull source of direction OPP
+                    const int far = P.bsrc[OPP * nb + t];
+                    if (far >= 0)
+                        return q2 * gb + ((C)1 - q2) * pop_load<Q, PREC, OPP>(P.pop_in, P.N, (uint32_t)far);
                 } else {
                     const C iq = (C)1 / q2;
                     return gb * iq + (q2 - (C)1) * iq * pop_load<Q, PREC, I>(P.pop_in, P.N, (uint32_t)idx);
@@ -336,7 +332,18 @@ __device__ __forceinline__ typename Prec<PREC>::calc desc_pull(const KParams &P,
     }
 }
 
-template <int NSP, int PREC, bool DIAG>
+// Values (T, rho, Y_k) at a listed image point, reconstructed for this
+// level by image_kernel.
+template <int NSP, class C>
+__device__ __forceinline__ void image_value(const KParams &P, int li, Pt<NSP, C> &o)
+{
+    o.T = (C)P.img_val[li];
+    o.rho = (C)P.img_val[P.n_img + li];
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) o.Y[k] = (C)P.img_val[(2 + k) * P.n_img + li];
+}
+
+template <int NSP, int PREC, bool DIAG, bool CW = false>
 __device__ __forceinline__ void desc_stencil(const KParams &P, long long t, long long nb, int d,
                                              const Pt<NSP, typename Prec<PREC>::calc> &ctr,
                                              Pt<NSP, typename Prec<PREC>::calc> (&st)[5], bool &near, double &wallq)
@@ -353,21 +360,22 @@ __device__ __forceinline__ void desc_stencil(const KParams &P, long long t, long
     for (int j = 0; j < 4; ++j) {
         const int slot = j < 2 ? j : j + 1;
         Pt<NSP, C> img;
-        load_point<NSP, PREC>(P, pts[j], img);
-        if (wks[j] == kFluid) {
-            st[slot] = img;
-        } else {
-            near = true;
-            Nb w;
-            w.kind = wks[j];
-            w.face = -1;
-            w.idx = 0;
-            w.Tw = w.kind == kIso ? P.btw[(d * 4 + j) * nb + t] : 0.0;
-            ghost<NSP>(P, w, img, st[slot]);
-            if constexpr (DIAG) {
-                if ((j == 1 || j == 2) && w.kind == kIso)
-                    wallq += 2.0 * P.alpha * (double)density<NSP>(P, (C)w.Tw, ctr.Y) * ((double)ctr.T - w.Tw);
-            }
+        const int li = CW && P.bimg != nullptr ? P.bimg[(d * 4 + j) * nb + t] : -1;
+        if (li >= 0)
+            image_value<NSP>(P, li, img);
+        else
+            load_point<NSP, PREC>(P, pts[j], img);
+        // a fluid point passes through ghost() unchanged
+        Nb w;
+        w.kind = wks[j];
+        w.face = -1;
+        w.idx = 0;
+        w.Tw = P.btw[(d * 4 + j) * nb + t];
+        near |= w.kind != kFluid;
+        ghost<NSP>(P, w, img, st[slot]);
+        if constexpr (DIAG) {
+            if ((j == 1 || j == 2) && w.kind == kIso)
+                wallq += 2.0 * P.alpha * (double)density<NSP>(P, (C)w.Tw, ctr.Y) * ((double)ctr.T - w.Tw);
         }
     }
 }
@@ -808,10 +816,11 @@ template <int D> struct TileShape {
 // cells), with the general geometry logic.
 // (tx, ty, tz): the thread's place in the tile (FAST) or tx in 0..255.
 // slot: the block's row of the diagnostics partials.
-// BZ: boundary cells apply the interpolated bounce-back of P.bq (a separate
-// instantiation, so that contexts without curved-wall links keep the
-// registers of plain bounce-back).
-template <int Q, int NSP, int PREC, int MODE, bool FAST, bool BZ = false>
+// CW: boundary cells apply the curved-wall treatments when listed: the
+// interpolated bounce-back of P.bq and the Shepard image points of P.bimg (a
+// separate instantiation, so that contexts without them keep the registers
+// of plain bounce-back and axis-mirror ghosts).
+template <int Q, int NSP, int PREC, int MODE, bool FAST, bool CW = false>
 __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int bz, int tx, int ty, int tz,
                                            long long slot)
 {
@@ -884,7 +893,7 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
             if constexpr (FAST)
                 g[i] = pop_load<Q, PREC, i>(P.pop_in, P.N, idx - (L::cx(i) + sy * L::cy(i) + sz * L::cz(i)));
             else
-                g[i] = desc_pull<Q, PREC, i, BZ>(P, tb, P.n_boundary, idx, x, y, z);
+                g[i] = desc_pull<Q, PREC, i, CW>(P, tb, P.n_boundary, idx, x, y, z);
         });
         Pt<NSP, C> ctr;
         if constexpr (TILE)
@@ -973,7 +982,7 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
                 // boundary cell (2-D): whole stencil points from the descriptors
                 Pt<NSP, C> st[5];
                 bool near = false;
-                desc_stencil<NSP, PREC, DIAG>(P, tb, P.n_boundary, d, ctr, st, near, wallq);
+                desc_stencil<NSP, PREC, DIAG, CW>(P, tb, P.n_boundary, d, ctr, st, near, wallq);
                 C r5[5] = {st[0].rho, st[1].rho, st[2].rho, st[3].rho, st[4].rho};
                 d1r = axis_terms(
                     [&](int f, int m) -> C { return f == 0 ? st[m + 2].T : st[m + 2].Y[f - 2]; }, r5, near, ud);
@@ -981,12 +990,14 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
                 // boundary cell (3-D): per offset m = -2, -1, 1, 2 the descriptor
                 // gives the point holding the value (or the ghost's image)
                 // and the kind of the wall behind a ghost (Sec. III.B)
+                // (or the listed image point of a curved wall)
                 const long long nbd = P.n_boundary;
-                int pts[4], wks[4];
+                int pts[4], wks[4], lis[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     pts[j] = P.bpt[(d * 4 + j) * nbd + tb];
                     wks[j] = P.bwk[(d * 4 + j) * nbd + tb];
+                    lis[j] = CW && P.bimg != nullptr ? P.bimg[(d * 4 + j) * nbd + tb] : -1;
                 }
                 const bool near = (wks[0] | wks[1] | wks[2] | wks[3]) != kFluid;
                 C r5[5];
@@ -995,7 +1006,10 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
                 for (int j = 0; j < 4; ++j) {
                     const int slot = j < 2 ? j : j + 1;
                     Pt<NSP, C> pt;
-                    load_point<NSP, PREC>(P, pts[j], pt);
+                    if (CW && lis[j] >= 0)
+                        image_value<NSP>(P, lis[j], pt);
+                    else
+                        load_point<NSP, PREC>(P, pts[j], pt);
                     r5[slot] = pt.rho;
                     if (wks[j] == kIso) {
                         const C Tw = (C)P.btw[(d * 4 + j) * nbd + tb];
@@ -1015,7 +1029,8 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
                     [&](int f, int m) -> C {
                         const int j = m < 0 ? m + 2 : m + 1;
                         const size_t fo = f == 0 ? 0 : (size_t)(f - 1) * fstride;
-                        const C v = (C)ldo<S>(sc + fo, (uint32_t)pts[j] * (uint32_t)sizeof(S));
+                        const C v = CW && lis[j] >= 0 ? (C)P.img_val[(size_t)f * P.n_img + lis[j]]
+                                                      : (C)ldo<S>(sc + fo, (uint32_t)pts[j] * (uint32_t)sizeof(S));
                         if (wks[j] == kFluid) return v;
                         if (f == 0) {
                             if (wks[j] == kIso) return (C)2 * (C)P.btw[(d * 4 + j) * nbd + tb] - v;
@@ -1107,7 +1122,7 @@ template <int Q, int NSP, int PREC, int PART> struct StepWaves {
 // renumbered to give each XCD one contiguous band of the box;
 // boundary_blocks is a multiple of 8, which keeps the XCD of a tile block
 // equal to its index modulo 8.
-template <int Q, int NSP, int PREC, int MODE, int PART, bool BZ = false>
+template <int Q, int NSP, int PREC, int MODE, int PART, bool CW = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepWaves<Q, NSP, PREC, PART>::value)))
 step_kernel(const KParams P)
 {
@@ -1115,7 +1130,7 @@ step_kernel(const KParams P)
     const long long b = (long long)blockIdx.x + P.block_begin;
     if constexpr (PART != 1) {
         if (b < P.boundary_blocks) {
-            step_block<Q, NSP, PREC, MODE, false, BZ>(P, (int)b, 0, 0, (int)threadIdx.x, 0, 0,
+            step_block<Q, NSP, PREC, MODE, false, CW>(P, (int)b, 0, 0, (int)threadIdx.x, 0, 0,
                                                   P.interior_blocks + b);
             return;
         }
@@ -1133,6 +1148,58 @@ step_kernel(const KParams P)
         const int tz = (int)threadIdx.x / (TS::X * TS::Y);
         step_block<Q, NSP, PREC, MODE, true>(P, bx, by, bz, tx, ty, tz, tile);
     }
+}
+
+// ------------------------------------------------------------ image points
+// Shepard reconstruction at the image points of curved-wall ghost nodes
+// (Sec. III.B) for the current level: T, rho, Y_k averaged over the listed
+// fluid nodes within four cells with the normalised inverse-square-distance
+// weights -- a sparse matrix-vector product, one row per image point.  LPP
+// lanes share a row (chosen at set-up from the mean row length), stride over
+// its nodes and combine their sums with a butterfly inside the group; the
+// result is written before the step launches that read it.
+template <int NSP, int PREC, int LPP>
+__global__ void __launch_bounds__(kBlock) image_kernel(const KParams P)
+{
+    using C = typename Prec<PREC>::calc;
+    const long long k = ((long long)blockIdx.x * kBlock + threadIdx.x) / LPP;
+    const int lane = (int)threadIdx.x % LPP;
+    const bool live = k < P.n_img;  // every lane stays for the butterfly
+    const int2 r = live ? P.img_rng[k] : make_int2(0, 0);
+    C acc[2 + NSP];
+#pragma unroll
+    for (int f = 0; f < 2 + NSP; ++f) acc[f] = 0;
+#pragma unroll 2
+    for (int e = r.x + lane; e < r.x + r.y; e += LPP) {
+        Pt<NSP, C> pt;
+        load_point<NSP, PREC>(P, P.img_idx[e], pt);
+        const C w = (C)P.img_w[e];
+        acc[0] += w * pt.T;
+        acc[1] += w * pt.rho;
+#pragma unroll
+        for (int q = 0; q < NSP; ++q) acc[2 + q] += w * pt.Y[q];
+    }
+#pragma unroll
+    for (int f = 0; f < 2 + NSP; ++f) {
+        C v = acc[f];
+#pragma unroll
+        for (int o = LPP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (live && lane == 0) P.img_val[(size_t)f * P.n_img + k] = (double)v;
+    }
+}
+
+template <int NSP, int PREC>
+hipError_t launch_images(const KParams &kp, hipStream_t s)
+{
+    const int lpp = kp.img_lpp;
+    const unsigned nb = (unsigned)((kp.n_img * lpp + kBlock - 1) / kBlock);
+    if (lpp == 16)
+        image_kernel<NSP, PREC, 16><<<dim3(nb), dim3(kBlock), 0, s>>>(kp);
+    else if (lpp == 32)
+        image_kernel<NSP, PREC, 32><<<dim3(nb), dim3(kBlock), 0, s>>>(kp);
+    else
+        image_kernel<NSP, PREC, 64><<<dim3(nb), dim3(kBlock), 0, s>>>(kp);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------ outlet
@@ -1245,8 +1312,8 @@ hipError_t launch_range(const KParams &kp0, long long begin, long long count, hi
     KParams kp = kp0;
     kp.block_begin = begin;
     if constexpr (PART != 1) {
-        // boundary cells with interpolated bounce-back links
-        if (kp.bq != nullptr) {
+        // boundary cells with curved-wall links or image points
+        if (kp.bq != nullptr || kp.bimg != nullptr) {
             step_kernel<Q, NSP, PREC, MODE, PART, true><<<dim3((unsigned)count), dim3(kBlock), 0, s>>>(kp);
             return hipGetLastError();
         }
@@ -1261,6 +1328,8 @@ hipError_t launch_pair(const KParams &kp, const Streams &st)
     // st.part 0: every block; 1: interior tiles only; 2: boundary blocks only
     const long long nbb = kp.boundary_blocks, nti = kp.interior_blocks;
     hipError_t e = hipSuccess;
+    if (kp.bimg != nullptr && kp.n_img > 0 && st.part != 1)
+        if ((e = launch_images<NSP, PREC>(kp, st.main)) != hipSuccess) return e;
     if constexpr (fused_step(Q)) {
         const long long begin = st.part == 1 ? nbb : 0;
         const long long count = st.part == 1 ? nti : st.part == 2 ? nbb : nbb + nti;

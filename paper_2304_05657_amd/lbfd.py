@@ -28,7 +28,7 @@ EXPORTS = ("lbfd_init", "lbfd_step", "lbfd_sync", "lbfd_level", "lbfd_read_field
            "lbfd_save_state", "lbfd_load_state", "lbfd_time_steps", "lbfd_time_kernels",
            "lbfd_cell_counts", "lbfd_step_launches", "lbfd_set_reaction", "lbfd_set_objective",
            "lbfd_objective", "lbfd_adjoint", "lbfd_set_inflow", "lbfd_hold_flame", "lbfd_set_wall_links",
-           "lbfd_destroy",
+           "lbfd_set_image_points", "lbfd_destroy",
            "lbfd_strerror", "lbfd_last_error")
 # collision operators (lbfd_params.collision)
 COLLISIONS = {"central_moments": 0, "cumulants": 1}
@@ -110,6 +110,7 @@ def load_library():
     lib.lbfd_set_objective.argtypes = [vp, C.c_int, C.c_int64, C.c_int64]
     lib.lbfd_set_inflow.argtypes = [vp, C.c_int, dp]
     lib.lbfd_set_wall_links.argtypes = [vp, C.c_int64, vp, vp, dp]
+    lib.lbfd_set_image_points.argtypes = [vp, C.c_int64, vp, vp, dp]
     lib.lbfd_hold_flame.argtypes = [vp, C.c_int64, C.c_int, C.c_double, C.c_double, dp, dp]
     lib.lbfd_objective.argtypes = [vp, C.c_int64, dp]
     lib.lbfd_adjoint.argtypes = [vp, C.c_int64, C.c_int, dp, dp, dp, dp]
@@ -306,6 +307,21 @@ class Solver:
         d = np.ascontiguousarray(direction, dtype=np.int32)
         qq = np.ascontiguousarray(q, dtype=np.float64)
         _check(self._lib, self._lib.lbfd_set_wall_links(self._h, len(c), c.ctypes.data, d.ctypes.data, _dp(qq)))
+
+    def set_image_points(self, cell=None, slot=None, image=None):
+        """Shepard-reconstructed image points of ghost nodes on curved walls
+        (boundary fluid cell, slot = 4 axis + j for the stencil offset
+        (-2, -1, 1, 2)[j], image point [n, 3] in lattice coordinates), e.g.
+        workloads.image_points(prob); None clears."""
+        if cell is None or len(cell) == 0:
+            _check(self._lib, self._lib.lbfd_set_image_points(self._h, 0, None, None, None))
+            return
+        c = np.ascontiguousarray(cell, dtype=np.int64)
+        sl = np.ascontiguousarray(slot, dtype=np.int32)
+        im = np.ascontiguousarray(image, dtype=np.float64).reshape(-1, 3)
+        if len(sl) != len(c) or len(im) != len(c):
+            raise ValueError("cell, slot and image lengths differ")
+        _check(self._lib, self._lib.lbfd_set_image_points(self._h, len(c), c.ctypes.data, sl.ctypes.data, _dp(im)))
 
     def set_inflow(self, face: int, u=None):
         """Inlet velocity profile u [3, nz, ny] of x face 0 (-x) or 1 (+x),

@@ -234,6 +234,98 @@ def wall_links(prob):
     return cells, dirs_out, q
 
 
+def image_points(prob):
+    """Image points of the finite-difference ghost nodes that lie inside the
+    problem's shapes (the cylinders / spheres of prob.notes["shapes"], as
+    for wall_links), as input for a ghost-node treatment of curved walls.
+    The ghost nodes of a fluid cell p along axis a are its stencil points
+    p + m e_a (m = -2, -1, 1, 2) behind a wall: both points of a side whose
+    first neighbour is not fluid, else the second neighbour when that is
+    not fluid.  For a ghost G inside a shape (the one of least depth when
+    several cover it) with centre c and radius r, B is the nearest point of
+    that shape's surface and the image I = 2B - G = G + 2 (r - |v|) v / |v|,
+    v = G - c (nearest periodic image).  Returns (cell [n] int64, slot [n]
+    int32 = 4 a + j for m = (-2, -1, 1, 2)[j], image [n, 3] float64 in
+    lattice coordinates unwrapped from p), sorted by cell then slot.
+    Ghosts in solids of no shape are not listed."""
+    shapes = prob.notes.get("shapes", [])
+    x0, x1 = prob.notes.get("slab", (0, prob.nx))
+    D = 2 if prob.lattice == 9 else 3
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    n = (nx, ny, nz)
+    periodic = [prob.faces[2 * a] == "periodic" for a in range(3)]
+    mask = np.asarray(prob.mask).reshape(nz, ny, nx)
+    # the shape of least depth covering each cell centre
+    label = np.full(mask.shape, -1, np.int64)
+    depth = np.full(mask.shape, np.inf)
+    for k, (sx, sy, sz, r) in enumerate(shapes):
+        ri = int(np.ceil(r)) + 1
+        xs = np.arange(max(x0, int(np.floor(sx)) - ri), min(x1, int(np.ceil(sx)) + ri + 1))
+        ys = np.arange(int(np.floor(sy)) - ri, int(np.ceil(sy)) + ri + 1)
+        zs = np.arange(int(np.floor(sz)) - ri, int(np.ceil(sz)) + ri + 1) if D == 3 else np.zeros(1, int)
+        Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+        px, py, pz = X - sx, Y - sy, (Z - sz if D == 3 else np.zeros_like(X, dtype=float))
+        dep = r - np.sqrt(px * px + py * py + pz * pz)
+        Zw, Yw = Z % nz, Y % ny
+        sel = (dep >= 0.0) & (dep < depth[Zw, Yw, X])
+        depth[Zw[sel], Yw[sel], X[sel]] = dep[sel]
+        label[Zw[sel], Yw[sel], X[sel]] = k
+    fz, fy, fx = np.nonzero(mask == FLUID)
+    pc = [fx, fy, fz]
+    cell = (fz.astype(np.int64) * ny + fy) * nx + fx
+
+    def probe(a, m):
+        """(fluid?, shape label, wrapped coords) of p + m e_a per fluid cell."""
+        q = [c.copy() for c in pc]
+        q[a] = q[a] + m
+        inbox = np.ones(len(fx), bool)
+        if periodic[a]:
+            q[a] %= n[a]
+        else:
+            inbox = (q[a] >= 0) & (q[a] < n[a])
+            q[a] = np.clip(q[a], 0, n[a] - 1)
+        fl = inbox & (mask[q[2], q[1], q[0]] == FLUID)
+        lab = np.where(inbox, label[q[2], q[1], q[0]], -1)
+        return fl, lab
+
+    out_c, out_s, out_i = [], [], []
+    cen = np.array([[s[0], s[1], s[2]] for s in shapes], dtype=np.float64).reshape(-1, 3)
+    rad = np.array([s[3] for s in shapes], dtype=np.float64)
+    for a in range(D):
+        for sg in (-1, 1):
+            j1, j2 = (1, 0) if sg < 0 else (2, 3)
+            f1, l1 = probe(a, sg)
+            f2, l2 = probe(a, 2 * sg)
+            for m, j, ghost, lab in ((sg, j1, ~f1, l1), (2 * sg, j2, ~f1 | ~f2, l2)):
+                sel = ghost & (lab >= 0)
+                if not sel.any():
+                    continue
+                G = np.stack([c[sel].astype(np.float64) for c in pc], axis=1)
+                G[:, a] += m
+                if D == 2:
+                    G[:, 2] = 0.0
+                c = cen[lab[sel]]
+                v = G - c
+                for ax in range(D):
+                    if periodic[ax]:
+                        v[:, ax] -= n[ax] * np.round(v[:, ax] / n[ax])
+                if D == 2:
+                    v[:, 2] = 0.0
+                dv = np.sqrt((v * v).sum(axis=1))
+                ok = dv > 0.0
+                img = G + 2.0 * ((rad[lab[sel]] - dv) / np.where(ok, dv, 1.0))[:, None] * v
+                out_c.append(cell[sel][ok])
+                out_s.append(np.full(int(ok.sum()), 4 * a + j, np.int32))
+                out_i.append(img[ok])
+    if not out_c:
+        return np.zeros(0, np.int64), np.zeros(0, np.int32), np.zeros((0, 3))
+    c = np.concatenate(out_c)
+    sl = np.concatenate(out_s)
+    im = np.concatenate(out_i)
+    order = np.lexsort((sl, c))
+    return c[order], sl[order], im[order]
+
+
 def wall_layer(T, Y, mask, wall_T, periodic_axes, delta=4.0):
     """Initial thermal layer next to solids: within `delta` cells of a solid
     cell the gas temperature is blended linearly from the nearest wall

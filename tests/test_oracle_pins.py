@@ -842,3 +842,94 @@ def test_half_way_links_are_plain_bounce_back(oracle_mod):
     b.step(20)
     assert np.array_equal(a.pops(), b.pops())
     assert len(cells) > 100
+
+
+# ------------------------------------------------ curved-wall ghost nodes
+def _ghost_channel(H=10, nx=6):
+    """Channel between isothermal walls (rows 0 and H + 1) at 300 / 600 K
+    with a linear start, x periodic."""
+    prob = _uniform_problem(nx, H + 2)
+    prob.mask[0, 0, :] = 1
+    prob.mask[0, H + 1, :] = 1
+    prob.wall_T[0, 0, :] = 300.0
+    prob.wall_T[0, H + 1, :] = 600.0
+    prob.T0[0] = np.linspace(320.0, 580.0, H + 2)[:, None]
+    return prob
+
+
+def _channel_mirror_images(H, nx, shift=0.0):
+    """Image points of every ghost of _ghost_channel at its axis mirror
+    across the half-way walls (y = 1/2 and H + 1/2), moved by `shift`
+    along y."""
+    cells, slots, ims = [], [], []
+    for x in range(nx):
+        for row, sg in ((1, -1), (2, -1), (H, 1), (H - 1, 1)):
+            wall = 0.5 if sg < 0 else H + 0.5
+            ms = (sg, 2 * sg) if row in (1, H) else (2 * sg,)
+            for m in ms:
+                j = {-2: 0, -1: 1, 1: 2, 2: 3}[m]
+                G = row + m
+                cells.append(row * nx + x)
+                slots.append(4 + j)
+                ims.append((x, 2 * wall - G + shift, 0.0))
+    return cells, slots, ims
+
+
+def test_image_points_on_mirror_nodes_equal_axis_mirror(oracle_mod):
+    """Ghost nodes behind straight half-way walls: image points listed at the
+    axis-mirror nodes reproduce the axis-mirror ghosts bit for bit (a node
+    at the image point takes the whole Shepard weight); moved off the nodes,
+    they change the result (the listed images are the ones used)."""
+    H, nx = 10, 6
+    a = oracle_mod.Oracle(_ghost_channel(H, nx))
+    b = oracle_mod.Oracle(_ghost_channel(H, nx))
+    b.set_image_points(*_channel_mirror_images(H, nx))
+    a.step(30)
+    b.step(30)
+    fa, fb = a.fields(), b.fields()
+    assert np.array_equal(fa["T"], fb["T"]) and np.array_equal(a.pops(), b.pops())
+    c = oracle_mod.Oracle(_ghost_channel(H, nx))
+    c.set_image_points(*_channel_mirror_images(H, nx, shift=0.3))
+    c.step(30)
+    assert np.abs(c.fields()["T"] - fa["T"]).max() > 1e-3
+
+
+def test_shepard_reconstruction_closed_forms(oracle_mod):
+    """Shepard inverse-distance weighting, p = 2, every fluid node within 4
+    cells (Sec. III.B).  For phi = |r - x|^2 the reconstruction at x is
+    sum_j w_j d_j^2 = N / sum_j d_j^-2 (N nodes, d_j their distances), which
+    fixes the exponent, the radius and the node set; constants are
+    reproduced (weights sum to one); a linear field is exact where the
+    node set is point-symmetric about x."""
+    H, nx = 16, 20
+    prob = _uniform_problem(nx, H)
+    prob.mask[0, 0, :] = 1             # a wall row and a solid block
+    prob.mask[0, 5:8, 9:12] = 2
+    fluid = prob.mask[0] == 0
+    yy, xx = np.mgrid[0:H, 0:nx]
+    for x in [(10.3, 3.6, 0.0), (4.0, 9.5, 0.0), (15.25, 10.0, 0.0), (1.2, 2.2, 0.0)]:
+        # every periodic copy of the fluid nodes within reach (the box is
+        # periodic along x and y)
+        pts, phi = [], np.full((H, nx), 300.0)
+        for ox in (-nx, 0, nx):
+            for oy in (-H, 0, H):
+                dd = (xx + ox - x[0]) ** 2 + (yy + oy - x[1]) ** 2
+                sel = fluid & (dd <= 16.0)
+                pts.append(dd[sel])
+                phi[sel] = 300.0 + dd[sel]   # phi = |r - x|^2 at the copy in reach
+        dd = np.concatenate(pts)
+        expect = len(dd) / np.sum(1.0 / dd)
+        prob.T0 = phi[None].astype(np.float64)
+        o = oracle_mod.Oracle(prob)
+        T, _, nnodes = o.image_value(x)
+        assert nnodes == len(dd)
+        assert abs((T - 300.0) - expect) < 1e-10 * expect, (x, T - 300.0, expect)
+    # constants and a linear field about a point-symmetric node set
+    prob = _uniform_problem(nx, H, T=420.0)
+    o = oracle_mod.Oracle(prob)
+    T, Y, _ = o.image_value((10.5, 8.5, 0.0))
+    assert abs(T - 420.0) < 1e-12 and np.allclose(Y, [0.5, 0.5], atol=1e-15)
+    prob.T0 = (300.0 + 3.0 * xx + 2.0 * yy)[None].astype(np.float64)
+    o = oracle_mod.Oracle(prob)
+    T, _, n = o.image_value((10.5, 8.5, 0.0))
+    assert abs(T - (300.0 + 3.0 * 10.5 + 2.0 * 8.5)) < 1e-10 and n == 52
