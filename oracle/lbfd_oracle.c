@@ -454,6 +454,15 @@ void lbo_chemistry(const lbo_params *p, double T, const double *Y,
                 incY[k] += r->nu[k] * rr;
             incT += r->q * rr;
         }
+        /* q is the temperature rise per unit mass at c_p,ref; with       */
+        /* species heat capacities it is divided by c_p(Y) / c_p,ref      */
+        /* (Eq. 7: omega_T / (rho c_p)) at the sub-step's composition     */
+        if (p->transport == LBO_MIXTURE_AVERAGED) {
+            double cpm = 0.0;
+            for (int k = 0; k < ns; ++k)
+                cpm += Yc[k] * p->cp[k];
+            incT /= cpm;
+        }
         /* positivity limiter (reading for stiff mechanisms): scale the    */
         /* sub-step so that no mass fraction is consumed below zero; it is */
         /* 1, i.e. plain explicit Euler, whenever nothing would go negative */
@@ -701,6 +710,75 @@ static void axis_stencil(const lbo_state *s, const int *pc, long pidx, int d,
 }
 
 /* ------------------------------------------------------------------ */
+/* Mixture-averaged transport (Sec. II.A).                             */
+/* Species: -(1/rho) div(rho Y_k V_k) with Eq. (2),                    */
+/*   Y_k V_k = -D_k G_k + Y_k V_c,  G_k = (W_k/W) grad X_k             */
+/*           = grad Y_k + Y_k grad ln W,  V_c = sum_k D_k G_k,         */
+/* D_k = alpha / Le_k.  Energy, Eq. (7) over rho c_p with the          */
+/* conductivity lambda = rho c_p alpha (constant Prandtl number at the */
+/* local c_p = sum_k Y_k c_pk):                                        */
+/*   alpha [lap T + (grad rho / rho + grad c_p / c_p) . grad T]        */
+/*   - (1/c_p) (sum_k c_pk Y_k V_k) . grad T.                          */
+/* Reading (discretisation): the divergences are expanded by the       */
+/* product rule, every derivative is the fourth-order central D1 / D2  */
+/* along its axis of the ghost-extended stencil values (of Y_k, T, rho,*/
+/* M = 1/W = sum_k Y_k / W_k and c_p), and the products are formed at  */
+/* the cell: with l1 = -D1(M)/M = d ln W and l2 = -D2(M)/M + l1^2 =    */
+/* d2 ln W per axis,                                                   */
+/*   div G_k = sum_axes [D2 Y_k + D1 Y_k l1 + Y_k l2],                 */
+/*   rhs_k = D_k (div G_k + grad rho . G_k / rho) - V_c . grad Y_k     */
+/*           - Y_k (div V_c + V_c . grad rho / rho).                   */
+/* With all Le_k = 1 and equal c_pk this is, to rounding, the Fickian  */
+/* alpha (lap Y_k + grad rho . grad Y_k / rho) of the unity-Lewis path. */
+/* ------------------------------------------------------------------ */
+static void mixture_transport(const lbo_params *p, int D, double rho, double T, const double *Y, double alpha,
+                              const double *grad_rho, const double *dT1, const double *dT2,
+                              double y1[3][LBO_MAXSP], double y2[3][LBO_MAXSP], const double *dM1,
+                              const double *dM2, const double *dcp, double *diffT, double *diffY)
+{
+    (void)T;
+    int ns = p->n_species;
+    double M = 0.0, cpm = 0.0, Dk[LBO_MAXSP];
+    for (int k = 0; k < ns; ++k) {
+        M += Y[k] / p->W[k];
+        cpm += Y[k] * p->cp[k];
+        Dk[k] = alpha / p->lewis[k];
+    }
+    double G[3][LBO_MAXSP], Vc[3] = {0.0, 0.0, 0.0}, divG[LBO_MAXSP], divVc = 0.0;
+    for (int k = 0; k < ns; ++k)
+        divG[k] = 0.0;
+    for (int d = 0; d < D; ++d) {
+        double l1 = -dM1[d] / M;
+        double l2 = -dM2[d] / M + l1 * l1;
+        for (int k = 0; k < ns; ++k) {
+            G[d][k] = y1[d][k] + Y[k] * l1;
+            divG[k] += y2[d][k] + y1[d][k] * l1 + Y[k] * l2;
+            Vc[d] += Dk[k] * G[d][k];
+        }
+    }
+    for (int k = 0; k < ns; ++k)
+        divVc += Dk[k] * divG[k];
+    for (int k = 0; k < ns; ++k) {
+        double gG = 0.0, vY = 0.0, vR = 0.0;
+        for (int d = 0; d < D; ++d) {
+            gG += grad_rho[d] * G[d][k];
+            vY += Vc[d] * y1[d][k];
+            vR += Vc[d] * grad_rho[d];
+        }
+        diffY[k] = Dk[k] * (divG[k] + gG / rho) - vY - Y[k] * (divVc + vR / rho);
+    }
+    double cond = 0.0, enth = 0.0;
+    for (int d = 0; d < D; ++d) {
+        cond += dT2[d] + (grad_rho[d] / rho + dcp[d] / cpm) * dT1[d];
+        double flux = 0.0;                       /* sum_k c_pk Y_k V_k along d */
+        for (int k = 0; k < ns; ++k)
+            flux += p->cp[k] * (-Dk[k] * G[d][k] + Y[k] * Vc[d]);
+        enth += flux * dT1[d];
+    }
+    *diffT = alpha * cond - enth / cpm;
+}
+
+/* ------------------------------------------------------------------ */
 /* Per-cell evaluation at the current level                            */
 /* ------------------------------------------------------------------ */
 typedef struct {
@@ -738,12 +816,26 @@ static void eval_cell(const lbo_state *s, int x, int y, int z, cell_eval_t *o)
     /* finite-difference operators per axis (Sec. II.D) */
     double alpha = CS2 * (p->tau - 0.5) / p->prandtl;
     double diffT = 0.0, diffY[LBO_MAXSP], convT[3], convY[3][LBO_MAXSP], grad_rho[3] = {0.0, 0.0, 0.0};
+    /* first and second derivatives per axis for the mixture-averaged form */
+    double dT1[3], dT2[3], y1[3][LBO_MAXSP], y2[3][LBO_MAXSP], dM1[3], dM2[3], dcp[3];
     for (int k = 0; k < ns; ++k)
         diffY[k] = 0.0;
     for (int d = 0; d < D; ++d) {
         scal st[5];
         int near = 0;
         axis_stencil(s, pc, idx, d, st, &near);
+        double phM[5], phC[5];
+        for (int m = 0; m < 5; ++m) {
+            phM[m] = 0.0;   /* 1 / W, linear in the Y_k */
+            phC[m] = 0.0;   /* c_p / c_p,ref */
+            for (int k = 0; k < ns; ++k) {
+                phM[m] += st[m].Y[k] / p->W[k];
+                phC[m] += st[m].Y[k] * p->cp[k];
+            }
+        }
+        dM1[d] = lbo_d1(phM);
+        dM2[d] = lbo_d2(phM);
+        dcp[d] = lbo_d1(phC);
         double phT[5], phR[5], phY[5];
         for (int m = 0; m < 5; ++m) {
             phT[m] = st[m].T;
@@ -751,6 +843,8 @@ static void eval_cell(const lbo_state *s, int x, int y, int z, cell_eval_t *o)
         }
         double d1r = lbo_d1(phR);
         grad_rho[d] = d1r;
+        dT1[d] = lbo_d1(phT);
+        dT2[d] = lbo_d2(phT);
         diffT += lbo_d2(phT) + d1r * lbo_d1(phT) / rho;
         /* centred second-order convection next to non-fluid points */
         convT[d] = near ? 0.5 * (phT[3] - phT[1]) : lbo_weno3(phT, u[d]);
@@ -758,12 +852,16 @@ static void eval_cell(const lbo_state *s, int x, int y, int z, cell_eval_t *o)
             for (int m = 0; m < 5; ++m)
                 phY[m] = st[m].Y[k];
             diffY[k] += lbo_d2(phY) + d1r * lbo_d1(phY) / rho;
+            y1[d][k] = lbo_d1(phY);
+            y2[d][k] = lbo_d2(phY);
             convY[d][k] = near ? 0.5 * (phY[3] - phY[1]) : lbo_weno3(phY, u[d]);
         }
     }
     diffT *= alpha;
     for (int k = 0; k < ns; ++k)
         diffY[k] *= alpha;
+    if (p->transport == LBO_MIXTURE_AVERAGED)
+        mixture_transport(p, D, rho, T, Y, alpha, grad_rho, dT1, dT2, y1, y2, dM1, dM2, dcp, &diffT, diffY);
 
     /* chemistry */
     double srcT, srcY[LBO_MAXSP];
@@ -1287,6 +1385,13 @@ lbo_state *lbo_create(const lbo_params *p, const uint8_t *mask,
     int D = p->Q == 9 ? 2 : 3;
     double alpha = CS2 * (p->tau - 0.5) / p->prandtl;
     if (alpha > (D == 2 ? 3.0 / 16.0 : 1.0 / 8.0)) FAIL("diffusivity above the explicit stability bound");
+    if (p->transport != LBO_UNITY_LEWIS && p->transport != LBO_MIXTURE_AVERAGED) FAIL("bad transport model");
+    if (p->transport == LBO_MIXTURE_AVERAGED)
+        for (int k = 0; k < p->n_species; ++k) {
+            if (!(p->lewis[k] > 0.0) || !(p->cp[k] > 0.0)) FAIL("Lewis numbers and heat capacities must be positive");
+            if (alpha / p->lewis[k] > (D == 2 ? 3.0 / 16.0 : 1.0 / 8.0))
+                FAIL("species diffusivity above the explicit stability bound");
+        }
     long N = (long)p->nx * p->ny * p->nz;
     long nfluid = 0;
     for (long idx = 0; idx < N; ++idx) {

@@ -63,7 +63,17 @@ typedef struct {
     double body_force[3];   /* oracle-only test fixture (0 in every workload) */
     double T_u, T_b;        /* progress-variable temperatures (diagnostics) */
     int collision;          /* LBO_CENTRAL_MOMENTS or LBO_CUMULANTS */
+    int transport;          /* LBO_UNITY_LEWIS or LBO_MIXTURE_AVERAGED */
+    double lewis[LBO_MAXSP];/* Le_k = alpha / D_k (mixture-averaged transport) */
+    double cp[LBO_MAXSP];   /* c_pk / c_p,ref (mixture-averaged transport) */
 } lbo_params;
+
+/* Species transport (Sec. II.A): Fick's law with D_k = alpha and equal
+   c_pk, or the mixture-averaged diffusion velocities of Eq. (2) with the
+   correction velocity, D_k = alpha / Le_k, and the species enthalpy flux of
+   Eq. (7) with c_p = sum_k Y_k c_pk. */
+#define LBO_UNITY_LEWIS 0
+#define LBO_MIXTURE_AVERAGED 1
 
 /* Collision operators (Sec. II.C): relaxation of central moments (every
    order), or of cumulants for the orders >= 4 (orders 2, 3: the two coincide

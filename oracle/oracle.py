@@ -65,6 +65,9 @@ class _Params(C.Structure):
         ("T_u", C.c_double),
         ("T_b", C.c_double),
         ("collision", C.c_int),
+        ("transport", C.c_int),
+        ("lewis", C.c_double * 16),
+        ("cp", C.c_double * 16),
     ]
 
 
@@ -176,6 +179,12 @@ def make_params(prob, **over) -> _Params:
     p.chem_substeps_max = prob.chem_substeps_max
     p.T_u, p.T_b = prob.T_u, prob.T_b
     p.collision = {"central_moments": 0, "cumulants": 1}[getattr(prob, "collision", "central_moments")]
+    p.transport = {"unity_lewis": 0, "mixture_averaged": 1}[getattr(prob, "transport", "unity_lewis")]
+    le = tuple(getattr(prob, "lewis", ()) or ())
+    cp = tuple(getattr(prob, "cp", ()) or ())
+    for k in range(len(prob.W)):
+        p.lewis[k] = le[k] if k < len(le) else 1.0
+        p.cp[k] = cp[k] if k < len(cp) else 1.0
     bf = over.pop("body_force", (0.0, 0.0, 0.0))
     for d in range(3):
         p.body_force[d] = bf[d]

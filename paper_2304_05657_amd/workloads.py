@@ -75,6 +75,9 @@ class Problem:
     eq_discrete: bool = False
     chem_substeps_max: int = 1
     collision: str = "central_moments"  # or "cumulants" (orders >= 4 relaxed as cumulants)
+    transport: str = "unity_lewis"  # or "mixture_averaged" (Lewis numbers and heat capacities below)
+    lewis: tuple = ()  # Le_k = alpha / D_k per species (empty: all 1)
+    cp: tuple = ()  # c_pk / c_p,ref per species (empty: all 1)
     T_u: float = 300.0
     T_b: float = 1800.0
     steps: int = 0

@@ -933,3 +933,105 @@ def test_shepard_reconstruction_closed_forms(oracle_mod):
     o = oracle_mod.Oracle(prob)
     T, _, n = o.image_value((10.5, 8.5, 0.0))
     assert abs(T - (300.0 + 3.0 * 10.5 + 2.0 * 8.5)) < 1e-10 and n == 52
+
+
+# ----------------------------------------- mixture-averaged transport
+LE4 = (0.8, 1.1, 1.4, 1.0)      # synthetic Lewis numbers of F, O, P, N
+CP4 = (2.0, 0.9, 1.3, 1.0)      # synthetic c_pk / c_p,ref
+
+
+def _smooth_1d(L):
+    """Periodic 1-D row of L cells (D2Q9, ny = 1) at rest with smooth T and
+    four mass fractions (W = 16, 32, 80/3, 28), no reaction."""
+    x = np.arange(L, dtype=np.float64)
+    th = 2.0 * np.pi * x / L
+    T = 400.0 + 60.0 * np.sin(th)
+    Y = np.stack([0.05 + 0.02 * np.sin(th + 0.3), 0.20 + 0.03 * np.cos(th), 0.10 - 0.01 * np.sin(2 * th)])
+    Y = np.vstack([Y, 1.0 - Y.sum(axis=0)])
+    prob = _uniform_problem(L, 1, Y=(0.25,) * 4, Wk=(16.0, 32.0, 80.0 / 3.0, 28.0))
+    prob.T0 = T.reshape(1, 1, L)
+    prob.Y0 = Y.reshape(4, 1, 1, L)
+    return prob.replace(transport="mixture_averaged", lewis=LE4, cp=CP4), T, Y
+
+
+def _spectral_rhs(T, Y, Wk, alpha, T_ref=300.0, W_ref=28.0):
+    """Eq. (2) and Eq. (7) (no source) on a periodic row, derivatives by
+    FFT: returns (dT/dt, dY_k/dt) of the transport terms alone."""
+    L = T.shape[0]
+    kw = 2.0 * np.pi * np.fft.fftfreq(L)
+
+    def dx(f):
+        return np.real(np.fft.ifft(1j * kw * np.fft.fft(f)))
+
+    Wk = np.asarray(Wk)[:, None]
+    W = 1.0 / (Y / Wk).sum(axis=0)
+    rho = (T_ref / T) * (W / W_ref)
+    X = Y * W / Wk
+    Dk = alpha / np.asarray(LE4)[:, None]
+    Jd = np.stack([Dk[k] * (Wk[k] / W) * dx(X[k]) for k in range(4)])   # D_k W_k / W dX_k
+    YV = -Jd + Y * Jd.sum(axis=0)                                       # Y_k V_k
+    rhsY = np.stack([-dx(rho * YV[k]) / rho for k in range(4)])
+    cpk = np.asarray(CP4)[:, None]
+    cp = (Y * cpk).sum(axis=0)
+    lam = rho * cp * alpha
+    rhsT = dx(lam * dx(T)) / (rho * cp) - (cpk * YV).sum(axis=0) * dx(T) / cp
+    return rhsT, rhsY
+
+
+def test_mixture_transport_converges_to_the_pde(oracle_mod):
+    """Mixture-averaged diffusion velocities with the correction velocity
+    (Eq. 2), D_k = alpha/Le_k, and the energy equation with the species
+    enthalpy flux and lambda = rho c_p alpha (Eq. 7): one step from rest,
+    whose increments are the discrete transport terms, against the same
+    terms of the PDE evaluated spectrally on a smooth periodic state.  The
+    difference falls at fourth order (the central stencils' order)."""
+    errs = []
+    for L in (24, 48):
+        prob, T, Y = _smooth_1d(L)
+        alpha = CS2 * (prob.tau - 0.5) / prob.prandtl
+        o = oracle_mod.Oracle(prob)
+        o.step(1)
+        f = o.fields()
+        dT = f["T"].reshape(-1) - T
+        dY = f["Y"].reshape(4, -1) - Y
+        rT, rY = _spectral_rhs(T, Y, prob.W, alpha)
+        eT = np.abs(dT - rT).max() / np.abs(rT).max()
+        eY = max(np.abs(dY[k] - rY[k]).max() / np.abs(rY[k]).max() for k in range(4))
+        errs.append((eT, eY))
+    (t1, y1), (t2, y2) = errs
+    assert t2 < 2e-4 and y2 < 2e-4, errs
+    assert t1 / t2 > 12.0 and y1 / y2 > 12.0, errs
+
+
+def test_mixture_transport_unity_lewis_is_fick(oracle_mod):
+    """With every Le_k = 1 and c_pk = c_p,ref the mixture-averaged form is,
+    to rounding, the Fickian unity-Lewis path (a flame with walls and an
+    inlet, 20 steps)."""
+    prob = W.cylinder_burner(nx=160, ny=64, x_begin=40, x_end=120, front_x=80.0, name="le1")
+    a = oracle_mod.Oracle(prob)
+    b = oracle_mod.Oracle(prob.replace(transport="mixture_averaged", lewis=(1.0,) * 4, cp=(1.0,) * 4))
+    a.step(20)
+    b.step(20)
+    fa, fb = a.fields(), b.fields()
+    fl = prob.mask == 0
+    assert np.abs(fa["T"][fl] - fb["T"][fl]).max() < 1e-9 * prob.T_b
+    assert np.abs(fa["Y"][:, fl] - fb["Y"][:, fl]).max() < 1e-11
+    assert np.abs(fa["u"][:, fl] - fb["u"][:, fl]).max() < 1e-12
+
+
+def test_mixture_transport_conserves_mass_fractions(oracle_mod):
+    """The correction velocity makes the diffusive fluxes sum to zero: with
+    unequal Lewis numbers the mass fractions of every cell still sum to one
+    (a burning channel flame, 200 steps)."""
+    prob = W.cylinder_burner(nx=160, ny=64, x_begin=40, x_end=120, front_x=80.0, name="le_mass")
+    prob = prob.replace(transport="mixture_averaged", lewis=LE4, cp=CP4)
+    o = oracle_mod.Oracle(prob)
+    o.step(200)
+    f = o.fields()
+    fl = prob.mask == 0
+    s = f["Y"][:, fl].sum(axis=0)
+    assert np.abs(s - 1.0).max() < 1e-12, np.abs(s - 1.0).max()
+    # and the transport model changes the flame
+    ref = oracle_mod.Oracle(W.cylinder_burner(nx=160, ny=64, x_begin=40, x_end=120, front_x=80.0, name="le_ref"))
+    ref.step(200)
+    assert np.abs(ref.fields()["T"][fl] - f["T"][fl]).max() > 1.0
