@@ -241,6 +241,9 @@ def main():
                     help="relaxation of the orders >= 4: central moments (default) or cumulants")
     ap.add_argument("--wall-links", action="store_true",
                     help="interpolated bounce-back on the links crossing the workload's cylinders / spheres")
+    ap.add_argument("--transport", default="unity_lewis", choices=("unity_lewis", "mixture_averaged"),
+                    help="species transport: Fick with unity Lewis numbers (default) or mixture-averaged "
+                         "diffusion with synthetic Lewis numbers and heat capacities")
     ap.add_argument("--image-points", action="store_true",
                     help="Shepard-reconstructed image points for the ghost nodes inside the workload's "
                          "cylinders / spheres")
@@ -263,6 +266,8 @@ def main():
     from paper_2304_05657_amd import workloads as W
 
     prob = W.named(args.workload).replace(collision=args.collision)
+    if args.transport == "mixture_averaged":
+        prob = W.mixture_transport(prob)
     links = W.wall_links(prob) if args.wall_links else None
     images = W.image_points(prob) if args.image_points else None
     if args.accuracy_steps is None:
@@ -319,7 +324,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": prob.name, "lattice": "D2Q9" if prob.lattice == 9 else "D3Q27", "cells": prob.N, "fluid_cells": prob.n_fluid,
                    "species": prob.n_species, "reactions": len(prob.reactions), "storage": precs[0],
-                   "collision": prob.collision, "wall_links": links is not None,
+                   "collision": prob.collision, "transport": prob.transport, "wall_links": links is not None,
                    "image_points": images is not None},
         "roofline": roofline(head, precs[0], prob.name),
         "cpu_baseline": cpu,

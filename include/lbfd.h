@@ -71,6 +71,18 @@ enum { LBFD_FP64 = 0, LBFD_MIXED_FP32 = 1, LBFD_MIXED_FP16 = 2 };
  * c_s^2 per squared axis; cumulants 0). */
 enum { LBFD_CENTRAL_MOMENTS = 0, LBFD_CUMULANTS = 1 };
 
+/* Species transport (Sec. II.A).  UNITY_LEWIS: Fick's law with every D_k
+ * equal to the thermal diffusivity alpha = cs^2 (tau - 1/2) / Pr and equal
+ * species heat capacities (Eq. 2 then reduces to -D grad Y_k and the species
+ * enthalpy flux of Eq. 7 vanishes).  MIXTURE_AVERAGED: the diffusion
+ * velocities of Eq. 2 with the correction velocity, D_k = alpha / lewis[k],
+ * and Eq. 7 with c_p = sum_k Y_k cp[k] (cp[k] = c_pk / c_p,ref), the
+ * conductivity lambda = rho c_p alpha and the species enthalpy flux; the
+ * reactions' temperature rise q_over_cp (at c_p,ref) is divided by
+ * c_p / c_p,ref.  The divergences are expanded by the product rule with the
+ * fourth-order central differences of Y_k, T, rho, 1/W and c_p. */
+enum { LBFD_UNITY_LEWIS = 0, LBFD_MIXTURE_AVERAGED = 1 };
+
 /* Face kinds.  WALL: isothermal no-slip wall at face_T (bounce-back, and a
  * Dirichlet ghost for T).  WALL_ADIABATIC: no-slip, Neumann ghost for T.
  * INFLOW: velocity inlet at u_in with Dirichlet T_in, Y_in (Eq. 31).
@@ -126,6 +138,9 @@ typedef struct {
     int check_every;         /* steps between NaN/Inf checks; 0 = never */
     double T_u, T_b;         /* progress variable theta = (T-T_u)/(T_b-T_u) */
     int collision;           /* LBFD_CENTRAL_MOMENTS or LBFD_CUMULANTS */
+    int transport;           /* LBFD_UNITY_LEWIS or LBFD_MIXTURE_AVERAGED */
+    double lewis[LBFD_MAX_SPECIES]; /* Le_k (MIXTURE_AVERAGED), > 0 */
+    double cp[LBFD_MAX_SPECIES];    /* c_pk / c_p,ref (MIXTURE_AVERAGED), > 0 */
 } lbfd_params;
 
 /* Diagnostics of the state at one level (plain sums over fluid cells in

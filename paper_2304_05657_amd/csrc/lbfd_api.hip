@@ -163,6 +163,16 @@ static int validate(const lbfd_params *p, const uint8_t *mask, const double *T0,
     if (p->check_every < 0) return fail(LBFD_EINVAL, "check_every must be >= 0");
     if (p->collision != LBFD_CENTRAL_MOMENTS && p->collision != LBFD_CUMULANTS)
         return fail(LBFD_EINVAL, "bad collision kind %d", p->collision);
+    if (p->transport != LBFD_UNITY_LEWIS && p->transport != LBFD_MIXTURE_AVERAGED)
+        return fail(LBFD_EINVAL, "bad transport model %d", p->transport);
+    if (p->transport == LBFD_MIXTURE_AVERAGED)
+        for (int k = 0; k < p->n_species; ++k) {
+            if (!(p->lewis[k] > 0.0) || !std::isfinite(p->lewis[k]) || !(p->cp[k] > 0.0) || !std::isfinite(p->cp[k]))
+                return fail(LBFD_EINVAL, "species %d: Lewis number and heat capacity must be positive", k);
+            if (alpha / p->lewis[k] > (D == 2 ? 3.0 / 16.0 : 1.0 / 8.0))
+                return fail(LBFD_EINVAL, "species %d: diffusivity %g above the explicit stability bound", k,
+                            alpha / p->lewis[k]);
+        }
     const long long N = (long long)p->nx * p->ny * p->nz;
     long long nfluid = 0;
     for (long long i = 0; i < N; ++i) {
@@ -420,6 +430,11 @@ static KParams make_kparams(const lbfd_ctx *c)
     k.T_u = p.T_u;
     k.T_b = p.T_b;
     k.collision = p.collision;
+    k.transport = p.transport;
+    for (int s = 0; s < c->nsp; ++s) {
+        k.dk[s] = p.transport == LBFD_MIXTURE_AVERAGED ? 1.0 / p.lewis[s] : 1.0;
+        k.cpk[s] = p.transport == LBFD_MIXTURE_AVERAGED ? p.cp[s] : 1.0;
+    }
     return k;
 }
 
@@ -1158,6 +1173,8 @@ int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwall
     if (c->prec != LBFD_FP64) return fail(LBFD_EINVAL, "the adjoint needs FP64 precision");
     if (c->p.collision != LBFD_CENTRAL_MOMENTS)
         return fail(LBFD_EINVAL, "the adjoint differentiates the central-moment collision only");
+    if (c->p.transport != LBFD_UNITY_LEWIS)
+        return fail(LBFD_EINVAL, "the adjoint differentiates the unity-Lewis transport only");
     if (c->bq || c->bimg)
         return fail(LBFD_EINVAL, "the adjoint differentiates half-way bounce-back and axis-mirror ghosts only");
     if (!adjoint_supported(c->Q, c->nsp))

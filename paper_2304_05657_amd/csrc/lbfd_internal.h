@@ -80,6 +80,9 @@ struct KParams {
     const double *inflow_u;  // [2 x faces][3][nz][ny] inlet velocity of the cells next to an x face
     double T_u, T_b;
     int collision;  // LBFD_CENTRAL_MOMENTS or LBFD_CUMULANTS
+    int transport;  // LBFD_UNITY_LEWIS or LBFD_MIXTURE_AVERAGED
+    double dk[kMaxSp];   // D_k / alpha = 1 / Le_k (mixture-averaged transport)
+    double cpk[kMaxSp];  // c_pk / c_p,ref (mixture-averaged transport)
 };
 
 // Kernel modes.

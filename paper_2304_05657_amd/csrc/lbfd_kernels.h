@@ -431,7 +431,7 @@ __device__ __forceinline__ double rate_coeff(const lbfd_reaction &r, double dt, 
     return r.A * dt * tb * exp(-r.Ta * rcp(T));
 }
 
-template <int NSP>
+template <int NSP, bool LE = false>
 __device__ __forceinline__ void chemistry(const KParams &P, double T, const double (&Y)[NSP], double &srcT,
                                           double (&srcY)[NSP])
 {
@@ -467,6 +467,14 @@ __device__ __forceinline__ void chemistry(const KParams &P, double T, const doub
 #pragma unroll
             for (int k = 0; k < NSP; ++k) incY[k] += r.nu_mass[k] * rr;
             incT += r.q_over_cp * rr;
+        }
+        if constexpr (LE) {
+            // q_over_cp is the rise at c_p,ref: divide by c_p(Y) / c_p,ref
+            // at the sub-step's composition (Eq. 7: omega_T / (rho c_p))
+            double cpm = 0.0;
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) cpm += Yc[k] * P.cpk[k];
+            incT *= rcp(cpm);
         }
         // positivity limiter: scale the sub-step so that no mass fraction
         // is consumed below zero (1, i.e. plain Euler, otherwise)
@@ -687,7 +695,7 @@ __device__ __forceinline__ void block_reduce_diag(double (&a)[kNDiag], double *o
 // source, Lambda (Eq. 6), Euler update, P_h (Eq. 13a), source Xi_i (Eq. 9),
 // central-moment collision (Eqs. 14, 19, 21), diagnostics, stores.
 // diffT, diffY already carry the factor alpha.
-template <int Q, int NSP, int PREC, int MODE>
+template <int Q, int NSP, int PREC, int MODE, bool LE = false>
 __device__ __forceinline__ void finish_cell(const KParams &P, long long idx, const typename Prec<PREC>::calc (&g)[Q],
                                             const Pt<NSP, typename Prec<PREC>::calc> &ctr,
                                             const typename Prec<PREC>::calc (&u)[3],
@@ -707,7 +715,7 @@ __device__ __forceinline__ void finish_cell(const KParams &P, long long idx, con
     double Yd[NSP], srcT, srcY[NSP];
 #pragma unroll
     for (int k = 0; k < NSP; ++k) Yd[k] = (double)ctr.Y[k];
-    chemistry<NSP>(P, (double)ctr.T, Yd, srcT, srcY);
+    chemistry<NSP, LE>(P, (double)ctr.T, Yd, srcT, srcY);
 
     // material derivatives, Lambda (Eq. 6), Euler update, P_h (Eq. 13a)
     const C DtT = diffT + (C)srcT;
@@ -820,7 +828,7 @@ template <int D> struct TileShape {
 // interpolated bounce-back of P.bq and the Shepard image points of P.bimg (a
 // separate instantiation, so that contexts without them keep the registers
 // of plain bounce-back and axis-mirror ghosts).
-template <int Q, int NSP, int PREC, int MODE, bool FAST, bool CW = false>
+template <int Q, int NSP, int PREC, int MODE, bool FAST, bool CW = false, bool LE = false>
 __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int bz, int tx, int ty, int tz,
                                            long long slot)
 {
@@ -925,21 +933,67 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
 #pragma unroll
         for (int k = 0; k < NSP; ++k) diffY[k] = CY[k] = 0;
         double wallq = 0.0;
+        // mixture-averaged transport (Sec. II.A, Eq. 2 and Eq. 7): the cell's
+        // 1/W, c_p and their reciprocals; div V_c summed over the axes
+        C Mc = 0, cpc = 0, divVc = 0;
+        if constexpr (LE) {
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) {
+                Mc += ctr.Y[k] * (C)P.invW[k];
+                cpc += ctr.Y[k] * (C)P.cpk[k];
+            }
+        }
+        const C inv_M = LE ? rcp(Mc) : (C)0, inv_cp = LE ? rcp(cpc) : (C)0;
         auto axis_terms = [&](auto &&val, const C (&r5)[5], bool near, C ud) -> C {
             // val(f, m): field f (0 = T, 2 + k = Y_k) at offset m = -2..2
             const C d1r = d1(r5[0], r5[1], r5[2], r5[3], r5[4]);
+            C t1, t2;
             {
                 const C a = val(0, -2), b = val(0, -1), c = ctr.T, e = val(0, 1), f = val(0, 2);
-                diffT += d2(a, b, c, e, f) + d1r * d1(a, b, c, e, f) * inv_rho;
+                t1 = d1(a, b, c, e, f);
+                t2 = d2(a, b, c, e, f);
+                if constexpr (!LE) diffT += t2 + d1r * t1 * inv_rho;
                 CT += ud * (near ? (C)0.5 * (e - b) : weno3(a, b, c, e, f, ud));
             }
-            C cY[NSP], sumc = 0;
+            C cY[NSP], sumc = 0, y1[NSP], y2[NSP];
 #pragma unroll
             for (int k = 0; k < NSP; ++k) {
                 const C a = val(2 + k, -2), b = val(2 + k, -1), c = ctr.Y[k], e = val(2 + k, 1), f = val(2 + k, 2);
-                diffY[k] += d2(a, b, c, e, f) + d1r * d1(a, b, c, e, f) * inv_rho;
+                y1[k] = d1(a, b, c, e, f);
+                y2[k] = d2(a, b, c, e, f);
+                if constexpr (!LE) diffY[k] += y2[k] + d1r * y1[k] * inv_rho;
                 cY[k] = near ? (C)0.5 * (e - b) : weno3(a, b, c, e, f, ud);
                 sumc += cY[k];
+            }
+            if constexpr (LE) {
+                // along this axis, in units of alpha: d ln W = l1, d2 ln W = l2
+                // (from 1/W = sum Y_k / W_k, linear in Y_k), G_k = (W_k/W) dX_k
+                // = dY_k + Y_k l1, V_c = sum D_k G_k, and sum_k c_pk Y_k V_k
+                C M1 = 0, M2 = 0, cp1 = 0;
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) {
+                    M1 += y1[k] * (C)P.invW[k];
+                    M2 += y2[k] * (C)P.invW[k];
+                    cp1 += y1[k] * (C)P.cpk[k];
+                }
+                const C l1 = -M1 * inv_M;
+                const C l2 = l1 * l1 - M2 * inv_M;
+                const C rr = d1r * inv_rho;
+                C Vc = 0, H = 0;
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) {
+                    const C Dk = (C)P.dk[k];
+                    const C G = y1[k] + ctr.Y[k] * l1;
+                    const C dG = y2[k] + y1[k] * l1 + ctr.Y[k] * l2;
+                    diffY[k] += Dk * (dG + rr * G);
+                    Vc += Dk * G;
+                    divVc += Dk * dG;
+                    H -= (C)P.cpk[k] * Dk * G;
+                }
+                H += cpc * Vc;
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) diffY[k] -= Vc * (y1[k] + ctr.Y[k] * rr);
+                diffT += t2 + (rr + cp1 * inv_cp) * t1 - H * inv_cp * t1;
             }
             // mass-conserving correction of the convection (Eq. 26)
 #pragma unroll
@@ -1046,12 +1100,16 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
             grad[1] = d == 1 ? d1r : grad[1];
             grad[2] = d == 2 ? d1r : grad[2];
         }
+        if constexpr (LE) {
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) diffY[k] -= ctr.Y[k] * divVc;
+        }
         const C alpha = (C)P.alpha;
         diffT *= alpha;
 #pragma unroll
         for (int k = 0; k < NSP; ++k) diffY[k] *= alpha;
 
-        finish_cell<Q, NSP, PREC, MODE>(P, idx, g, ctr, u, m, sg, inv_rc, diffT, diffY, CT, CY, grad, wallq, acc);
+        finish_cell<Q, NSP, PREC, MODE, LE>(P, idx, g, ctr, u, m, sg, inv_rc, diffT, diffY, CT, CY, grad, wallq, acc);
         if constexpr (MODE != kModeFields) {
             if constexpr (!FAST && D == 2) {
                 // outlet (Eq. 32): g_i(r) <- g_i(r-n)(cs - u.n) + g_i(r)(1 - cs + u.n)
@@ -1104,9 +1162,14 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
 // (168 VGPRs) in FP64 and four (128) in the mixed forms -- the boundary
 // path, which needs more, spills instead of lowering the tiles' occupancy.
 // 3-D FP64 boundary cells with up to 4 species: two waves (256 VGPRs).
-// Otherwise the allocator is left free (1).
-template <int Q, int NSP, int PREC, int PART> struct StepWaves {
-    static constexpr int value = (Q == 9 && NSP <= 4)                                     ? (PREC == LBFD_FP64 ? 3 : 4)
+// Otherwise the allocator is left free (1), and so it is for the launches
+// with diagnostics or fields (MODE != kModeStep), which run once per check
+// or read: the 2-D FP64 fields launch with curved walls and mixture-averaged
+// transport returned wrong velocities at the three-wave budget (spilling)
+// and exact ones without it.
+template <int Q, int NSP, int PREC, int PART, int MODE = kModeStep> struct StepWaves {
+    static constexpr int value = MODE != kModeStep                                        ? 1
+                                 : (Q == 9 && NSP <= 4)                                     ? (PREC == LBFD_FP64 ? 3 : 4)
                                  : (Q == 27 && NSP <= 4 && PART == 2 && PREC == LBFD_FP64) ? 2
                                                                                            : 1;
 };
@@ -1122,15 +1185,15 @@ template <int Q, int NSP, int PREC, int PART> struct StepWaves {
 // renumbered to give each XCD one contiguous band of the box;
 // boundary_blocks is a multiple of 8, which keeps the XCD of a tile block
 // equal to its index modulo 8.
-template <int Q, int NSP, int PREC, int MODE, int PART, bool CW = false>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepWaves<Q, NSP, PREC, PART>::value)))
+template <int Q, int NSP, int PREC, int MODE, int PART, bool CW = false, bool LE = false>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StepWaves<Q, NSP, PREC, PART, MODE>::value)))
 step_kernel(const KParams P)
 {
     using TS = TileShape<Lat<Q>::D>;
     const long long b = (long long)blockIdx.x + P.block_begin;
     if constexpr (PART != 1) {
         if (b < P.boundary_blocks) {
-            step_block<Q, NSP, PREC, MODE, false, CW>(P, (int)b, 0, 0, (int)threadIdx.x, 0, 0,
+            step_block<Q, NSP, PREC, MODE, false, CW, LE>(P, (int)b, 0, 0, (int)threadIdx.x, 0, 0,
                                                   P.interior_blocks + b);
             return;
         }
@@ -1146,7 +1209,7 @@ step_kernel(const KParams P)
         const int tx = (int)threadIdx.x % TS::X;
         const int ty = ((int)threadIdx.x / TS::X) % TS::Y;
         const int tz = (int)threadIdx.x / (TS::X * TS::Y);
-        step_block<Q, NSP, PREC, MODE, true>(P, bx, by, bz, tx, ty, tz, tile);
+        step_block<Q, NSP, PREC, MODE, true, false, LE>(P, bx, by, bz, tx, ty, tz, tile);
     }
 }
 
@@ -1305,21 +1368,30 @@ __global__ void __launch_bounds__(kBlock) init_kernel(const KParams P, const dou
 // One step: the boundary blocks and the interior tiles (both read level n
 // and write disjoint cells of level n+1), on the context stream, then for
 // D3Q27 the outlet update.
+template <int Q, int NSP, int PREC, int MODE, int PART, bool LE>
+hipError_t launch_range_t(const KParams &kp, long long count, hipStream_t s)
+{
+    if constexpr (PART != 1) {
+        // boundary cells with curved-wall links or image points
+        if (kp.bq != nullptr || kp.bimg != nullptr) {
+            step_kernel<Q, NSP, PREC, MODE, PART, true, LE><<<dim3((unsigned)count), dim3(kBlock), 0, s>>>(kp);
+            return hipGetLastError();
+        }
+    }
+    step_kernel<Q, NSP, PREC, MODE, PART, false, LE><<<dim3((unsigned)count), dim3(kBlock), 0, s>>>(kp);
+    return hipGetLastError();
+}
+
 template <int Q, int NSP, int PREC, int MODE, int PART>
 hipError_t launch_range(const KParams &kp0, long long begin, long long count, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
     KParams kp = kp0;
     kp.block_begin = begin;
-    if constexpr (PART != 1) {
-        // boundary cells with curved-wall links or image points
-        if (kp.bq != nullptr || kp.bimg != nullptr) {
-            step_kernel<Q, NSP, PREC, MODE, PART, true><<<dim3((unsigned)count), dim3(kBlock), 0, s>>>(kp);
-            return hipGetLastError();
-        }
-    }
-    step_kernel<Q, NSP, PREC, MODE, PART, false><<<dim3((unsigned)count), dim3(kBlock), 0, s>>>(kp);
-    return hipGetLastError();
+    // the mixture-averaged transport is a separate instantiation, so that
+    // unity-Lewis steps keep their registers
+    if (kp.transport == LBFD_MIXTURE_AVERAGED) return launch_range_t<Q, NSP, PREC, MODE, PART, true>(kp, count, s);
+    return launch_range_t<Q, NSP, PREC, MODE, PART, false>(kp, count, s);
 }
 
 template <int Q, int NSP, int PREC, int MODE>

@@ -30,6 +30,8 @@ EXPORTS = ("lbfd_init", "lbfd_step", "lbfd_sync", "lbfd_level", "lbfd_read_field
            "lbfd_objective", "lbfd_adjoint", "lbfd_set_inflow", "lbfd_hold_flame", "lbfd_set_wall_links",
            "lbfd_set_image_points", "lbfd_destroy",
            "lbfd_strerror", "lbfd_last_error")
+# species transport models (lbfd_params.transport)
+TRANSPORTS = {"unity_lewis": 0, "mixture_averaged": 1}
 # collision operators (lbfd_params.collision)
 COLLISIONS = {"central_moments": 0, "cumulants": 1}
 # objective kinds (lbfd_set_objective)
@@ -59,6 +61,7 @@ class Params(C.Structure):
         ("Y_in", C.c_double * MAX_SPECIES), ("omega3", C.c_double), ("omega4", C.c_double),
         ("chem_substeps_max", C.c_int), ("check_every", C.c_int),
         ("T_u", C.c_double), ("T_b", C.c_double), ("collision", C.c_int),
+        ("transport", C.c_int), ("lewis", C.c_double * 16), ("cp", C.c_double * 16),
     ]
 
 
@@ -168,6 +171,12 @@ def make_params(prob, precision="fp64", check_every: int = 0):
     p.check_every = check_every
     p.T_u, p.T_b = prob.T_u, prob.T_b
     p.collision = COLLISIONS[getattr(prob, "collision", "central_moments")]
+    p.transport = TRANSPORTS[getattr(prob, "transport", "unity_lewis")]
+    le = tuple(getattr(prob, "lewis", ()) or ())
+    cp = tuple(getattr(prob, "cp", ()) or ())
+    for k in range(len(prob.W)):
+        p.lewis[k] = le[k] if k < len(le) else 1.0
+        p.cp[k] = cp[k] if k < len(cp) else 1.0
     if prob.eq_discrete:
         raise ValueError("the GPU library relaxes toward Maxwellian central moments only")
     return p, rx

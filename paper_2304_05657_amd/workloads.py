@@ -182,6 +182,22 @@ def flame_channel(nx: int = 512, ny: int = 34, u_mean: float = 0.002, front_x: f
     return prob.replace(u0=u0)
 
 
+def mixture_transport(prob, seed: int = 2304):
+    """The problem with mixture-averaged species transport and synthetic
+    property data (no property database is available): for the 4-species
+    F / O / P / N set Lewis numbers (0.8, 1.1, 1.4, 1.0) and heat capacities
+    c_pk / c_p,ref (2.0, 0.9, 1.3, 1.0), of the order of methane, oxygen,
+    combustion products and nitrogen; for other species counts seeded
+    values with Le_k in [0.7, 1.6] and c_pk / c_p,ref in [0.8, 2.2]."""
+    ns = prob.n_species
+    if ns == 4:
+        le, cp = (0.8, 1.1, 1.4, 1.0), (2.0, 0.9, 1.3, 1.0)
+    else:
+        rng = np.random.default_rng(seed)
+        le, cp = tuple(rng.uniform(0.7, 1.6, ns)), tuple(rng.uniform(0.8, 2.2, ns))
+    return prob.replace(transport="mixture_averaged", lewis=le, cp=cp)
+
+
 def wall_links(prob):
     """Wall distances of the links that cross the curved walls of the
     problem's shapes (prob.notes["shapes"]: cylinders (cx, cy, 0, r) of a

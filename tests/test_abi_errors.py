@@ -84,3 +84,13 @@ def test_configuration_without_a_kernel():
     p = p.replace(W=(16.0, 32.0), Y_in=(0.5, 0.5), reactions=[two],
                   Y0=np.stack([np.full(p.mask.shape, 0.5), np.full(p.mask.shape, 0.5)]))
     _reject(p, "no kernel built", precision="fp16")
+
+
+def test_mixture_transport_parameters():
+    p = _small().replace(transport="mixture_averaged", lewis=(1.0, 0.0, 1.0, 1.0))
+    _reject(p, "Lewis number and heat capacity must be positive")
+    p = _small().replace(transport="mixture_averaged", cp=(1.0, 1.0, -2.0, 1.0))
+    _reject(p, "Lewis number and heat capacity must be positive")
+    # alpha = 0.0476 at tau 0.6: Le 0.2 puts D_k above 3/16
+    p = _small().replace(transport="mixture_averaged", lewis=(0.2, 1.0, 1.0, 1.0))
+    _reject(p, "above the explicit stability bound")
