@@ -419,6 +419,36 @@ __device__ __forceinline__ C weno3(C m2, C m1, C c0, C p1, C p2, C u)
     return neg ? -conv : conv;
 }
 
+// The three finite-difference operators of one scalar along one axis from
+// its five stencil values, written on the forward differences
+// D0 = m1 - m2, D1 = c0 - m1, D2 = p1 - c0, D3 = p2 - p1:
+//   D1 (4th order) = (7 (D1 + D2) - (D0 + D3)) / 12,
+//   D2 (4th order) = (15 (D2 - D1) - (D3 - D0)) / 12,
+//   conv2 = twice the WENO3 convective derivative of weno3() (the caller
+//   folds the 1/2 into u): with (a, b, c) = (D0, D1, D2) for u >= 0 and
+//   (D3, D2, D1) for u < 0 (the mirrored stencil, whose negation cancels the
+//   sign of its differences), conv2 = (b + c) + w+ (b - c) - w- (a - b),
+//   w+ = eC^2 / (eC^2 + 2 eB^2), w- = eB^2 / (eB^2 + 2 eA^2), eX = eps + X^2,
+//   both weights from one reciprocal; next to walls (near) the centred
+//   difference b + c.
+template <class C>
+__device__ __forceinline__ void axis5(C m2, C m1, C c0, C p1, C p2, C u, bool near, C &d1o, C &d2o, C &conv2)
+{
+    const C D0 = m1 - m2, D1 = c0 - m1, D2 = p1 - c0, D3 = p2 - p1;
+    const C s12 = D1 + D2;
+    d1o = ((C)7 * s12 - (D0 + D3)) * (C)(1.0 / 12.0);
+    d2o = ((C)15 * (D2 - D1) - (D3 - D0)) * (C)(1.0 / 12.0);
+    const bool neg = u < (C)0;
+    const C a = neg ? D3 : D0, b = neg ? D2 : D1, c = neg ? D1 : D2;
+    const C eps = (C)1e-6;
+    const C eA = eps + a * a, eB = eps + b * b, eC = eps + c * c;
+    const C eA2 = eA * eA, eB2 = eB * eB, eC2 = eC * eC;
+    const C den_p = eC2 + (C)2 * eB2, den_m = eB2 + (C)2 * eA2;
+    const C inv = rcp(den_p * den_m);
+    const C X = (eC2 * (b - c)) * den_m - (eB2 * (a - b)) * den_p;
+    conv2 = near ? s12 : s12 + X * inv;
+}
+
 // ------------------------------------------------------------ chemistry
 // Arrhenius source over one step in double precision (per reaction
 // r = A dt T^b exp(-Ta/T) prod Y_react; species nu_k r, temperature q r):
@@ -947,22 +977,20 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
         auto axis_terms = [&](auto &&val, const C (&r5)[5], bool near, C ud) -> C {
             // val(f, m): field f (0 = T, 2 + k = Y_k) at offset m = -2..2
             const C d1r = d1(r5[0], r5[1], r5[2], r5[3], r5[4]);
+            const C uh = (C)0.5 * ud;  // the conv2 values are twice the derivatives
             C t1, t2;
             {
-                const C a = val(0, -2), b = val(0, -1), c = ctr.T, e = val(0, 1), f = val(0, 2);
-                t1 = d1(a, b, c, e, f);
-                t2 = d2(a, b, c, e, f);
+                C tc;
+                axis5(val(0, -2), val(0, -1), ctr.T, val(0, 1), val(0, 2), ud, near, t1, t2, tc);
                 if constexpr (!LE) diffT += t2 + d1r * t1 * inv_rho;
-                CT += ud * (near ? (C)0.5 * (e - b) : weno3(a, b, c, e, f, ud));
+                CT += uh * tc;
             }
             C cY[NSP], sumc = 0, y1[NSP], y2[NSP];
 #pragma unroll
             for (int k = 0; k < NSP; ++k) {
-                const C a = val(2 + k, -2), b = val(2 + k, -1), c = ctr.Y[k], e = val(2 + k, 1), f = val(2 + k, 2);
-                y1[k] = d1(a, b, c, e, f);
-                y2[k] = d2(a, b, c, e, f);
+                axis5(val(2 + k, -2), val(2 + k, -1), ctr.Y[k], val(2 + k, 1), val(2 + k, 2), ud, near, y1[k], y2[k],
+                      cY[k]);
                 if constexpr (!LE) diffY[k] += y2[k] + d1r * y1[k] * inv_rho;
-                cY[k] = near ? (C)0.5 * (e - b) : weno3(a, b, c, e, f, ud);
                 sumc += cY[k];
             }
             if constexpr (LE) {
@@ -997,7 +1025,7 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
             }
             // mass-conserving correction of the convection (Eq. 26)
 #pragma unroll
-            for (int k = 0; k < NSP; ++k) CY[k] += ud * (cY[k] - ctr.Y[k] * sumc);
+            for (int k = 0; k < NSP; ++k) CY[k] += uh * (cY[k] - ctr.Y[k] * sumc);
             return d1r;
         };
 #pragma unroll 1
