@@ -894,23 +894,42 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
     // 2-D interior kernel: T, Y_k and rho of the block's 64 x 4 cells and a
     // 2-cell halo staged once in LDS (field-major planes of 68 x 8 points);
     // every finite-difference point is then an LDS read at a fixed offset.
-    // Halo points outside the box are left unset: only interior cells,
-    // whose stencils stay inside the box, read the tile.
+    // Halo points outside the box hold the nearest in-box point's values and
+    // are never read: only interior cells, whose stencils stay inside the
+    // box, read the tile.
     constexpr int kTX = 64, kTY = 4, kHX = kTX + 4, kHY = kTY + 4, kNP = kHX * kHY;
     constexpr bool TILE = FAST && D == 2;
     __shared__ C tile[TILE ? (NSP + 2) * kNP : 1];
+    C g[Q];
     if constexpr (TILE) {
+        // the cell's pull loads go out first, so that their latency overlaps
+        // the staging of the tile
+        if (active)
+            sfor<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                g[i] = pop_load<Q, PREC, i>(P.pop_in, P.N, idx - (L::cx(i) + sy * L::cy(i)));
+            });
+        // staging: every thread loads its (at most three) halo points at
+        // addresses clamped into the box before storing any, so that all the
+        // loads are in flight together (clamped points are never read)
         const int tid = tx + kTX * ty;
         const int gx0 = bx * kTX - 2, gy0 = by * kTY - 2;
-        for (int i = tid; i < kNP; i += kBlock) {
-            const int gx = gx0 + i % kHX, gy = gy0 + i / kHX;
-            if ((unsigned)gx < (unsigned)P.nx && (unsigned)gy < (unsigned)P.ny) {
-                Pt<NSP, C> pt;
-                load_point<NSP, PREC>(P, (long long)gy * P.nx + gx, pt);
-                tile[i] = pt.T;
-                tile[kNP + i] = pt.rho;
+        constexpr int kRounds = (kNP + kBlock - 1) / kBlock;
+        Pt<NSP, C> pt[kRounds];
 #pragma unroll
-                for (int k = 0; k < NSP; ++k) tile[(2 + k) * kNP + i] = pt.Y[k];
+        for (int r = 0; r < kRounds; ++r) {
+            const int i = tid + r * kBlock;
+            const int gx = min(max(gx0 + i % kHX, 0), P.nx - 1), gy = min(max(gy0 + i / kHX, 0), P.ny - 1);
+            load_point<NSP, PREC>(P, (long long)gy * P.nx + gx, pt[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const int i = tid + r * kBlock;
+            if (i < kNP) {
+                tile[i] = pt[r].T;
+                tile[kNP + i] = pt[r].rho;
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) tile[(2 + k) * kNP + i] = pt[r].Y[k];
             }
         }
         __syncthreads();
@@ -924,15 +943,15 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
     };
 
     if (active) {
-        // streaming with boundary conditions (pull)
-        C g[Q];
-        sfor<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            if constexpr (FAST)
-                g[i] = pop_load<Q, PREC, i>(P.pop_in, P.N, idx - (L::cx(i) + sy * L::cy(i) + sz * L::cz(i)));
-            else
-                g[i] = desc_pull<Q, PREC, i, CW>(P, tb, P.n_boundary, idx, x, y, z);
-        });
+        // streaming with boundary conditions (pull; already issued for tiles)
+        if constexpr (!TILE)
+            sfor<0, Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                if constexpr (FAST)
+                    g[i] = pop_load<Q, PREC, i>(P.pop_in, P.N, idx - (L::cx(i) + sy * L::cy(i) + sz * L::cz(i)));
+                else
+                    g[i] = desc_pull<Q, PREC, i, CW>(P, tb, P.n_boundary, idx, x, y, z);
+            });
         Pt<NSP, C> ctr;
         if constexpr (TILE)
             tile_point(0, 0, ctr);
