@@ -51,7 +51,7 @@ def _errors(gf, of, sel, prob):
     return out
 
 
-def _check(prob, mixed, seed):
+def _check(prob, mixed, seed, links=False):
     import oracle
     from paper_2304_05657_amd.lbfd import Solver
     need_gpu()
@@ -59,6 +59,10 @@ def _check(prob, mixed, seed):
                                                            prob.lattice, STEPS))
     sel = _sample(prob, seed)
     o = oracle.Oracle(prob, threads=oracle_threads())
+    wl = W.wall_links(prob) if links else None
+    if links:
+        say("  %d wall links" % len(wl[0]))
+        o.set_wall_links(wl[0], wl[1], wl[2].astype(np.float32).astype(np.float64))
     o.step_sampled(sel, STEPS)
     of = o.fields()
     del o
@@ -66,6 +70,8 @@ def _check(prob, mixed, seed):
     for precision in ("fp64", mixed):
         say("  gpu %s, %d steps, %d sampled cells" % (precision, STEPS, int(sel.sum())))
         g = Solver(prob, precision=precision)
+        if links:
+            g.set_wall_links(*wl)
         g.step(STEPS)
         gf = g.fields()
         g.close()
@@ -89,3 +95,9 @@ def test_porous_mechanism_512x256x256_sampled():
     """512 x 256 x 256, D3Q27, 9 species / 20 reactions (sub-cycled FP64
     source): FP64 and FP32 population storage."""
     _check(W.porous_3d_mech(), "fp32", seed=22)
+
+
+def test_porous_256_cubed_mixture_curved_sampled():
+    """256^3, D3Q27, 4 species with mixture-averaged transport and the
+    interpolated bounce-back on every link into a sphere: FP64 and FP32."""
+    _check(W.mixture_transport(W.porous_3d()), "fp32", seed=23, links=True)
