@@ -234,7 +234,9 @@ int lbfd_set_wall_links(lbfd_ctx *c, int64_t n, const int64_t *cell, const int32
  * normalised to sum to one (a node at I takes the whole weight), instead
  * of the axis-mirror image; unlisted ghosts keep the axis mirror.  The
  * weights are computed here, once, in double precision and held on the
- * device (4 + 8 bytes per node).  Replaces the previous set; n = 0 clears.
+ * device (4 + 8 bytes per list entry, and (2 + n_species) doubles per
+ * distinct node, packed once per step).  Replaces the previous set; n = 0
+ * clears.
  * LBFD_EINVAL for a slot that is not a ghost behind a wall, a repeated
  * ghost, or an image point with no fluid node within four cells;
  * LBFD_ENOMEM when the tables do not fit. */

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <thread>
 #include <vector>
 
 #include "lbfd_internal.h"
@@ -95,6 +96,9 @@ struct lbfd_ctx {
     int *img_idx = nullptr;             //   their fluid nodes
     double *img_w = nullptr;            //   and weights
     double *img_val = nullptr;          //   reconstructed values of the current level
+    long long n_sup = 0;                //   distinct nodes of the Shepard lists
+    int *sup_idx = nullptr;             //   their cells
+    double *sup_val = nullptr;          //   and their packed (T, rho, Y_k) of the current level
     std::vector<uint8_t> bwk_host;      // host copy of the ghost kinds of the descriptors
     std::vector<double> inflow_host;   // host copy
     size_t outlet_n = 0;
@@ -114,7 +118,7 @@ static void free_ctx(lbfd_ctx *c)
     if (!c) return;
     void *ptrs[] = {c->pop[0], c->pop[1], c->sc[0], c->sc[1], c->mask, c->code, c->boundary, c->bsrc, c->bpt, c->bwk,
                     c->btw, c->wall_T, c->outlet, c->outlet_un, c->inflow_u, c->inflow_du, c->bq,
-                    c->bimg, c->img_rng, c->img_idx, c->img_w, c->img_val,
+                    c->bimg, c->img_rng, c->img_idx, c->img_w, c->img_val, c->sup_idx, c->sup_val,
                     c->fields, c->partials, c->diag_dev, c->bad_dev, c->rx_dev};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -407,6 +411,9 @@ static KParams make_kparams(const lbfd_ctx *c)
     k.img_idx = c->img_idx;
     k.img_w = c->img_w;
     k.img_val = c->img_val;
+    k.n_sup = c->n_sup;
+    k.sup_idx = c->sup_idx;
+    k.sup_val = c->sup_val;
     k.fields = c->fields;
     k.partials = c->partials;
     k.rx = c->rx_dev;
@@ -756,9 +763,15 @@ int lbfd_set_wall_links(lbfd_ctx *c, int64_t n, const int64_t *cell, const int32
 
 static void clear_image_points(lbfd_ctx *c)
 {
-    void *ptrs[] = {c->bimg, c->img_rng, c->img_idx, c->img_w, c->img_val};
+    void *ptrs[] = {c->bimg, c->img_rng, c->img_idx, c->img_w, c->img_val, c->sup_idx, c->sup_val};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    c->sup_idx = nullptr;
+    c->sup_val = nullptr;
+    c->n_sup = 0;
+    c->base.sup_idx = nullptr;
+    c->base.sup_val = nullptr;
+    c->base.n_sup = 0;
     c->bimg = nullptr;
     c->img_rng = nullptr;
     c->img_idx = nullptr;
@@ -787,10 +800,8 @@ int lbfd_set_image_points(lbfd_ctx *c, int64_t n, const int64_t *cell, const int
     std::vector<int> pos(N, -1);  // cell -> position in the boundary list
     for (long long t = 0; t < nb; ++t) pos[c->boundary_host[t]] = (int)t;
     if (n > (int64_t)INT32_MAX) return fail(LBFD_EINVAL, "too many image points");
+    // validation, in entry order (the first bad entry is the one reported)
     std::vector<int> which((size_t)12 * nb, -1);
-    std::vector<int2> range((size_t)n);
-    std::vector<int> nodes;
-    std::vector<double> wts;
     for (int64_t k = 0; k < n; ++k) {
         const long long i = cell[k];
         const int s = slot[k];
@@ -805,45 +816,128 @@ int lbfd_set_image_points(lbfd_ctx *c, int64_t n, const int64_t *cell, const int
             return fail(LBFD_EINVAL, "image point %lld: its stencil point is not a ghost node behind a wall",
                         (long long)k);
         if (which[r] >= 0) return fail(LBFD_EINVAL, "image point %lld repeats a ghost node", (long long)k);
-        // Shepard weights: every fluid node within four cells of the image
-        // point, weight d^-2 normalised; a node at distance zero takes all
-        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-        for (int d = 0; d < D; ++d) {
-            lo[d] = (int)std::ceil(xi[d] - 4.0);
-            hi[d] = (int)std::floor(xi[d] + 4.0);
-        }
-        const size_t begin = nodes.size();
-        double wsum = 0.0;
-        bool exact = false;
-        for (int z = lo[2]; z <= hi[2] && !exact; ++z)
-            for (int y = lo[1]; y <= hi[1] && !exact; ++y)
-                for (int x = lo[0]; x <= hi[0]; ++x) {
-                    const double dx = x - xi[0], dy = y - xi[1], dz = D == 3 ? z - xi[2] : 0.0;
-                    const double d2 = dx * dx + dy * dy + dz * dz;
-                    if (d2 > 16.0) continue;
-                    const HostNb h = host_classify(p, mask, wT, x, y, z);
-                    if (h.kind != kFluid) continue;
-                    if (d2 == 0.0) {
-                        nodes.resize(begin);
-                        wts.resize(begin);
-                        nodes.push_back((int)h.idx);
-                        wts.push_back(1.0);
-                        exact = true;
-                        break;
-                    }
-                    nodes.push_back((int)h.idx);
-                    wts.push_back(1.0 / d2);
-                    wsum += 1.0 / d2;
-                }
-        if (nodes.size() == begin)
-            return fail(LBFD_EINVAL, "image point %lld has no fluid node within four cells", (long long)k);
-        if (!exact)
-            for (size_t e = begin; e < nodes.size(); ++e) wts[e] /= wsum;
-        if (nodes.size() > (size_t)INT32_MAX) return fail(LBFD_EINVAL, "too many Shepard nodes");
-        range[k] = make_int2((int)begin, (int)(nodes.size() - begin));
         which[r] = (int)k;
     }
-    if (hipMalloc((void **)&c->bimg, which.size() * sizeof(int)) != hipSuccess ||
+    // Shepard weights, on up to 16 host threads over contiguous ranges of
+    // entries: every fluid node within four cells of the image point, weight
+    // d^-2 normalised; a node at distance zero takes the whole weight
+    struct Part {
+        std::vector<int> nodes, count;
+        std::vector<double> wts;
+        int64_t bad = -1;  // first entry of the range without a fluid node
+        bool oom = false;
+    };
+    const int nth = (int)std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(),
+                                                                 (n + 4095) / 4096}));
+    std::vector<Part> parts(nth);
+    auto work = [&](int w) {
+        Part &pt = parts[w];
+        const int64_t k0 = n * w / nth, k1 = n * (w + 1) / nth;
+        try {
+            pt.count.reserve(k1 - k0);
+            for (int64_t k = k0; k < k1; ++k) {
+                const double *xi = image + 3 * k;
+                int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+                for (int d = 0; d < D; ++d) {
+                    lo[d] = (int)std::ceil(xi[d] - 4.0);
+                    hi[d] = (int)std::floor(xi[d] + 4.0);
+                }
+                const size_t begin = pt.nodes.size();
+                double wsum = 0.0;
+                bool exact = false;
+                for (int z = lo[2]; z <= hi[2] && !exact; ++z)
+                    for (int y = lo[1]; y <= hi[1] && !exact; ++y)
+                        for (int x = lo[0]; x <= hi[0]; ++x) {
+                            const double dx = x - xi[0], dy = y - xi[1], dz = D == 3 ? z - xi[2] : 0.0;
+                            const double d2 = dx * dx + dy * dy + dz * dz;
+                            if (d2 > 16.0) continue;
+                            const HostNb h = host_classify(p, mask, wT, x, y, z);
+                            if (h.kind != kFluid) continue;
+                            if (d2 == 0.0) {
+                                pt.nodes.resize(begin);
+                                pt.wts.resize(begin);
+                                pt.nodes.push_back((int)h.idx);
+                                pt.wts.push_back(1.0);
+                                exact = true;
+                                break;
+                            }
+                            pt.nodes.push_back((int)h.idx);
+                            pt.wts.push_back(1.0 / d2);
+                            wsum += 1.0 / d2;
+                        }
+                if (pt.nodes.size() == begin && pt.bad < 0) pt.bad = k;
+                if (!exact)
+                    for (size_t e = begin; e < pt.nodes.size(); ++e) pt.wts[e] /= wsum;
+                pt.count.push_back((int)(pt.nodes.size() - begin));
+            }
+        } catch (const std::bad_alloc &) {
+            pt.oom = true;
+        }
+    };
+    {
+        std::vector<std::thread> pool;
+        std::vector<int> here;  // ranges whose thread could not be started
+        for (int w = 1; w < nth; ++w) {
+            try {
+                pool.emplace_back(work, w);
+            } catch (...) {
+                here.push_back(w);
+            }
+        }
+        work(0);
+        for (int w : here) work(w);
+        for (std::thread &t : pool) t.join();
+    }
+    size_t total = 0;
+    for (const Part &pt : parts)
+        if (pt.oom) return fail(LBFD_ENOMEM, "host memory for the Shepard weights exhausted");
+    for (const Part &pt : parts) {
+        if (pt.bad >= 0)
+            return fail(LBFD_EINVAL, "image point %lld has no fluid node within four cells", (long long)pt.bad);
+        total += pt.nodes.size();
+    }
+    if (total > (size_t)INT32_MAX) return fail(LBFD_EINVAL, "too many Shepard nodes");
+    std::vector<int2> range;
+    std::vector<int> nodes;
+    std::vector<double> wts;
+    try {
+        range.resize((size_t)n);
+        nodes.reserve(total);
+        wts.reserve(total);
+    } catch (const std::bad_alloc &) {
+        return fail(LBFD_ENOMEM, "host memory for the Shepard weights exhausted");
+    }
+    for (int w = 0; w < nth; ++w) {
+        const int64_t k0 = n * w / nth;
+        const size_t base = nodes.size();
+        size_t off = 0;
+        for (size_t q = 0; q < parts[w].count.size(); ++q) {
+            range[k0 + q] = make_int2((int)(base + off), parts[w].count[q]);
+            off += (size_t)parts[w].count[q];
+        }
+        nodes.insert(nodes.end(), parts[w].nodes.begin(), parts[w].nodes.end());
+        wts.insert(wts.end(), parts[w].wts.begin(), parts[w].wts.end());
+        std::vector<int>().swap(parts[w].nodes);  // release as the tables grow
+        std::vector<double>().swap(parts[w].wts);
+    }
+    // the support: distinct nodes in cell order; list entries become
+    // positions in it
+    std::vector<int> sup;
+    try {
+        std::vector<int> at((size_t)N, -1);
+        for (int v : nodes) at[v] = 0;
+        for (long long i = 0; i < N; ++i)
+            if (at[i] == 0) {
+                at[i] = (int)sup.size();
+                sup.push_back((int)i);
+            }
+        for (int &v : nodes) v = at[v];
+    } catch (const std::bad_alloc &) {
+        return fail(LBFD_ENOMEM, "host memory for the Shepard support exhausted");
+    }
+    if (hipMalloc((void **)&c->sup_idx, sup.size() * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&c->sup_val, (size_t)(2 + c->nsp) * sup.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&c->bimg, which.size() * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->img_rng, range.size() * sizeof(int2)) != hipSuccess ||
         hipMalloc((void **)&c->img_idx, nodes.size() * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->img_w, wts.size() * sizeof(double)) != hipSuccess ||
@@ -855,6 +949,11 @@ int lbfd_set_image_points(lbfd_ctx *c, int64_t n, const int64_t *cell, const int
     HIP_TRY(hipMemcpy(c->img_rng, range.data(), range.size() * sizeof(int2), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->img_idx, nodes.data(), nodes.size() * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->img_w, wts.data(), wts.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->sup_idx, sup.data(), sup.size() * sizeof(int), hipMemcpyHostToDevice));
+    c->n_sup = (long long)sup.size();
+    c->base.n_sup = c->n_sup;
+    c->base.sup_idx = c->sup_idx;
+    c->base.sup_val = c->sup_val;
     // lanes per row: about two nodes per lane on average
     const double mean = (double)nodes.size() / (double)n;
     c->img_lpp = mean <= 32.0 ? 16 : mean <= 64.0 ? 32 : 64;

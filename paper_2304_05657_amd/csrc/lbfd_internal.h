@@ -52,8 +52,11 @@ struct KParams {
     long long n_img;            // image points:
     int img_lpp;                //   lanes per Shepard row (16, 32 or 64)
     const int2 *img_rng;        //   [n_img] {begin, count} of the Shepard list
-    const int *img_idx;         //   fluid nodes of the lists
+    const int *img_idx;         //   entries of the lists: positions in the support
     const double *img_w;        //   and their normalised weights
+    long long n_sup;            // support: the distinct fluid nodes of the lists,
+    const int *sup_idx;         //   [n_sup] their cells
+    double *sup_val;            //   [n_sup][2 + n_species] T, rho, Y_k (this level)
     double *img_val;            //   [2 + n_species][n_img] T, rho, Y_k at the image points (this level)
     // block list of a step launch: boundary_blocks (a multiple of 8) blocks
     // of 256 boundary cells, then interior_blocks tiles of tiles_x x tiles_y
@@ -95,7 +98,7 @@ constexpr bool fused_step(int Q) { return Q == 9; }
 
 inline int step_launches(int Q, const KParams &kp)
 {
-    const int images = kp.bimg != nullptr && kp.n_img > 0 ? 1 : 0;
+    const int images = kp.bimg != nullptr && kp.n_img > 0 ? 2 : 0;
     if (fused_step(Q)) return (kp.boundary_blocks + kp.interior_blocks > 0 ? 1 : 0) + images;
     const bool outlet = kp.n_boundary > 0 && (kp.face[0] == LBFD_FACE_OUTFLOW || kp.face[1] == LBFD_FACE_OUTFLOW);
     return (kp.boundary_blocks > 0) + (kp.interior_blocks > 0) + (outlet ? 1 : 0) + images;

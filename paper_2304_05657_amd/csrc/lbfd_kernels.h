@@ -1264,10 +1264,28 @@ step_kernel(const KParams P)
 // Shepard reconstruction at the image points of curved-wall ghost nodes
 // (Sec. III.B) for the current level: T, rho, Y_k averaged over the listed
 // fluid nodes within four cells with the normalised inverse-square-distance
-// weights -- a sparse matrix-vector product, one row per image point.  LPP
-// lanes share a row (chosen at set-up from the mean row length), stride over
-// its nodes and combine their sums with a butterfly inside the group; the
-// result is written before the step launches that read it.
+// weights -- a sparse matrix-vector product, one row per image point.  The
+// distinct nodes of all rows (the support) are first packed, once each, into
+// records of (T, rho, Y_k) (support_kernel), so that a row entry is one
+// contiguous record read rather than 1 + N_sp scattered loads and a density
+// evaluation.  LPP lanes share a row (chosen at set-up from the mean row
+// length), stride over its entries and combine their sums with a butterfly
+// inside the group; the result is written before the step launches read it.
+template <int NSP, int PREC>
+__global__ void __launch_bounds__(kBlock) support_kernel(const KParams P)
+{
+    using C = typename Prec<PREC>::calc;
+    const long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= P.n_sup) return;
+    Pt<NSP, C> pt;
+    load_point<NSP, PREC>(P, P.sup_idx[s], pt);
+    double *rec = P.sup_val + s * (2 + NSP);
+    rec[0] = (double)pt.T;
+    rec[1] = (double)pt.rho;
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) rec[2 + k] = (double)pt.Y[k];
+}
+
 template <int NSP, int PREC, int LPP>
 __global__ void __launch_bounds__(kBlock) image_kernel(const KParams P)
 {
@@ -1281,13 +1299,10 @@ __global__ void __launch_bounds__(kBlock) image_kernel(const KParams P)
     for (int f = 0; f < 2 + NSP; ++f) acc[f] = 0;
 #pragma unroll 2
     for (int e = r.x + lane; e < r.x + r.y; e += LPP) {
-        Pt<NSP, C> pt;
-        load_point<NSP, PREC>(P, P.img_idx[e], pt);
+        const double *rec = P.sup_val + (long long)P.img_idx[e] * (2 + NSP);
         const C w = (C)P.img_w[e];
-        acc[0] += w * pt.T;
-        acc[1] += w * pt.rho;
 #pragma unroll
-        for (int q = 0; q < NSP; ++q) acc[2 + q] += w * pt.Y[q];
+        for (int f = 0; f < 2 + NSP; ++f) acc[f] += w * (C)rec[f];
     }
 #pragma unroll
     for (int f = 0; f < 2 + NSP; ++f) {
@@ -1301,6 +1316,9 @@ __global__ void __launch_bounds__(kBlock) image_kernel(const KParams P)
 template <int NSP, int PREC>
 hipError_t launch_images(const KParams &kp, hipStream_t s)
 {
+    support_kernel<NSP, PREC><<<dim3((unsigned)((kp.n_sup + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(kp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const int lpp = kp.img_lpp;
     const unsigned nb = (unsigned)((kp.n_img * lpp + kBlock - 1) / kBlock);
     if (lpp == 16)

@@ -266,7 +266,11 @@ def image_points(prob):
     v = G - c (nearest periodic image).  Returns (cell [n] int64, slot [n]
     int32 = 4 a + j for m = (-2, -1, 1, 2)[j], image [n, 3] float64 in
     lattice coordinates unwrapped from p), sorted by cell then slot.
-    Ghosts in solids of no shape are not listed."""
+    Ghosts in solids of no shape are not listed, nor ghosts whose image point
+    is not certain to have a fluid node within four cells (where overlapping
+    shapes put it deep in solid: |I - g| + the distance from the grid point
+    g nearest to I to the nearest fluid cell must not exceed 4); those keep
+    the axis mirror."""
     shapes = prob.notes.get("shapes", [])
     x0, x1 = prob.notes.get("slab", (0, prob.nx))
     D = 2 if prob.lattice == 9 else 3
@@ -289,6 +293,11 @@ def image_points(prob):
         sel = (dep >= 0.0) & (dep < depth[Zw, Yw, X])
         depth[Zw[sel], Yw[sel], X[sel]] = dep[sel]
         label[Zw[sel], Yw[sel], X[sel]] = k
+    # distance from every cell centre to the nearest fluid cell centre
+    from scipy import ndimage
+    pad = [(6, 6) if periodic[2 - ax] and mask.shape[ax] > 1 else (0, 0) for ax in range(3)]
+    fd = ndimage.distance_transform_edt(np.pad(mask != FLUID, pad, mode="wrap"))
+    fd = fd[tuple(slice(w[0], w[0] + m) for w, m in zip(pad, mask.shape))]
     fz, fy, fx = np.nonzero(mask == FLUID)
     pc = [fx, fy, fz]
     cell = (fz.astype(np.int64) * ny + fy) * nx + fx
@@ -333,6 +342,17 @@ def image_points(prob):
                 dv = np.sqrt((v * v).sum(axis=1))
                 ok = dv > 0.0
                 img = G + 2.0 * ((rad[lab[sel]] - dv) / np.where(ok, dv, 1.0))[:, None] * v
+                # a fluid node within four cells of the image point, for sure
+                gi = np.rint(img).astype(np.int64)
+                for ax in range(3):
+                    gi[:, ax] = gi[:, ax] % n[ax] if periodic[ax] else np.clip(gi[:, ax], 0, n[ax] - 1)
+                if D == 2:
+                    gi[:, 2] = 0
+                gu = img.copy()   # g unwrapped next to the image point
+                for ax in range(3):
+                    gu[:, ax] = gi[:, ax] + (n[ax] * np.round((img[:, ax] - gi[:, ax]) / n[ax]) if periodic[ax] else 0)
+                reach = np.sqrt(((img - gu) ** 2).sum(axis=1)) + fd[gi[:, 2], gi[:, 1], gi[:, 0]]
+                ok &= reach <= 4.0
                 out_c.append(cell[sel][ok])
                 out_s.append(np.full(int(ok.sum()), 4 * a + j, np.int32))
                 out_i.append(img[ok])
