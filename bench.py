@@ -46,9 +46,9 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_05657_amd", "csrc", f)
 # SHA-256 (kernel_sha) is given (profiles/traffic_step_kernels_burner_2048x512.md).
 TRAFFIC_WORKLOAD = "cylinder_burner_2048x512"
 TRAFFIC = {
-    "fp64": {"kernel_sha256": "26d58a509865f8960ef6caf1f6e38d0f7cec700e4be09bc5e66da6d1ed6d3682", "bytes_per_launch": 267.3e6},
-    "fp32": {"kernel_sha256": "26d58a509865f8960ef6caf1f6e38d0f7cec700e4be09bc5e66da6d1ed6d3682", "bytes_per_launch": 171.9e6},
-    "fp16": {"kernel_sha256": "26d58a509865f8960ef6caf1f6e38d0f7cec700e4be09bc5e66da6d1ed6d3682", "bytes_per_launch": 128.9e6},
+    "fp64": {"kernel_sha256": "1553de4e773e68d2c74098f422ec83b997fdd6f7b0a3e6acef88ef7a5f6a54d3", "bytes_per_launch": 269.0e6},
+    "fp32": {"kernel_sha256": "1553de4e773e68d2c74098f422ec83b997fdd6f7b0a3e6acef88ef7a5f6a54d3", "bytes_per_launch": 172.5e6},
+    "fp16": {"kernel_sha256": "1553de4e773e68d2c74098f422ec83b997fdd6f7b0a3e6acef88ef7a5f6a54d3", "bytes_per_launch": 129.7e6},
 }
 POP_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 SCALAR_BYTES = {"fp64": 8, "fp32": 4, "fp16": 4}
