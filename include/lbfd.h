@@ -218,7 +218,8 @@ int lbfd_diagnostics(lbfd_ctx *c, lbfd_diag *d);
  *   q >= 1/2:  g*_i(r) / (2q) + (2q - 1)/(2q) g*_opp(r);
  * every other wall link bounces back half-way (q = 1/2).  Replaces the
  * previous set; n = 0 clears it.  q is stored in single precision.
- * LBFD_EINVAL for a link that does not run from a fluid cell to a wall. */
+ * LBFD_EINVAL for a link that does not run from a fluid cell to a wall (the
+ * previous set is then kept). */
 int lbfd_set_wall_links(lbfd_ctx *c, int64_t n, const int64_t *cell, const int32_t *dir, const double *q);
 
 /* Curved walls for the finite differences (image/ghost nodes, Sec. III.B,
@@ -238,8 +239,9 @@ int lbfd_set_wall_links(lbfd_ctx *c, int64_t n, const int64_t *cell, const int32
  * distinct node, packed once per step).  Replaces the previous set; n = 0
  * clears.
  * LBFD_EINVAL for a slot that is not a ghost behind a wall, a repeated
- * ghost, or an image point with no fluid node within four cells;
- * LBFD_ENOMEM when the tables do not fit. */
+ * ghost, or an image point with no fluid node within four cells (the
+ * previous set is then kept); LBFD_ENOMEM when the tables do not fit (no
+ * image points are then set). */
 int lbfd_set_image_points(lbfd_ctx *c, int64_t n, const int64_t *cell, const int32_t *slot, const double *image);
 
 /* Inlet velocity profile of the x face `face` (0: -x, 1: +x), which must

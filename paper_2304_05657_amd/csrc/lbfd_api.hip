@@ -790,8 +790,10 @@ int lbfd_set_image_points(lbfd_ctx *c, int64_t n, const int64_t *cell, const int
 {
     if (!c || n < 0 || (n > 0 && (!cell || !slot || !image))) return fail(LBFD_EINVAL, "bad arguments");
     HIP_TRY(hipStreamSynchronize(c->stream));
-    clear_image_points(c);
-    if (n == 0) return LBFD_OK;
+    if (n == 0) {
+        clear_image_points(c);
+        return LBFD_OK;
+    }
     const lbfd_params &p = c->p;
     const long long nb = c->n_boundary, N = c->N;
     const int D = c->D;
@@ -935,6 +937,8 @@ int lbfd_set_image_points(lbfd_ctx *c, int64_t n, const int64_t *cell, const int
     } catch (const std::bad_alloc &) {
         return fail(LBFD_ENOMEM, "host memory for the Shepard support exhausted");
     }
+    // everything checked: the new set replaces the previous one
+    clear_image_points(c);
     if (hipMalloc((void **)&c->sup_idx, sup.size() * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&c->sup_val, (size_t)(2 + c->nsp) * sup.size() * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&c->bimg, which.size() * sizeof(int)) != hipSuccess ||

@@ -164,3 +164,15 @@ def test_image_points_validation_and_clear():
     fa, fb = a.fields(), b.fields()
     for k in ("u", "T", "Ph"):
         assert np.array_equal(fa[k], fb[k]), k
+    # a rejected set leaves the previous one in place
+    c, d = Solver(prob), Solver(prob)
+    c.set_image_points(cells, slots, im)
+    d.set_image_points(cells, slots, im)
+    with pytest.raises(LbfdError):
+        d.set_image_points(cells[:1], [9], im[:1])
+    c.step(10)
+    d.step(10)
+    fc, fd = c.fields(), d.fields()
+    for k in ("u", "T", "Ph"):
+        assert np.array_equal(fc[k], fd[k]), k
+    assert not np.array_equal(fc["T"], fa["T"])
