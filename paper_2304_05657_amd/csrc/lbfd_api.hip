@@ -949,11 +949,15 @@ int lbfd_set_image_points(lbfd_ctx *c, int64_t n, const int64_t *cell, const int
         clear_image_points(c);
         return fail(LBFD_ENOMEM, "hipMalloc of the image-point tables failed");
     }
-    HIP_TRY(hipMemcpy(c->bimg, which.data(), which.size() * sizeof(int), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->img_rng, range.data(), range.size() * sizeof(int2), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->img_idx, nodes.data(), nodes.size() * sizeof(int), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->img_w, wts.data(), wts.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->sup_idx, sup.data(), sup.size() * sizeof(int), hipMemcpyHostToDevice));
+    hipError_t e = hipMemcpy(c->bimg, which.data(), which.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->img_rng, range.data(), range.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->img_idx, nodes.data(), nodes.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->img_w, wts.data(), wts.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->sup_idx, sup.data(), sup.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        clear_image_points(c);
+        return fail(LBFD_EDEVICE, "upload of the image-point tables failed: %s", hipGetErrorString(e));
+    }
     c->n_sup = (long long)sup.size();
     c->base.n_sup = c->n_sup;
     c->base.sup_idx = c->sup_idx;
