@@ -1035,3 +1035,30 @@ def test_mixture_transport_conserves_mass_fractions(oracle_mod):
     ref = oracle_mod.Oracle(W.cylinder_burner(nx=160, ny=64, x_begin=40, x_end=120, front_x=80.0, name="le_ref"))
     ref.step(200)
     assert np.abs(ref.fields()["T"][fl] - f["T"][fl]).max() > 1.0
+
+
+def test_shepard_reconstruction_closed_form_3d(oracle_mod):
+    """The p = 2 closed form N / sum_j d_j^-2 for phi = |r - x|^2 in a D3Q27
+    box with a solid block (spherical reach of four cells, periodic copies
+    enumerated by brute force)."""
+    n = 12
+    prob = _uniform_problem(n, n, lattice=27, nz=n)
+    prob.mask[4:7, 5:8, 3:6] = 1
+    fluid = prob.mask == 0
+    zz, yy, xx = np.mgrid[0:n, 0:n, 0:n]
+    for x in [(6.3, 2.6, 8.1), (1.5, 10.2, 0.4), (5.0, 6.0, 5.5)]:
+        pts, phi = [], np.full((n, n, n), 300.0)
+        for oz in (-n, 0, n):
+            for oy in (-n, 0, n):
+                for ox in (-n, 0, n):
+                    dd = (xx + ox - x[0]) ** 2 + (yy + oy - x[1]) ** 2 + (zz + oz - x[2]) ** 2
+                    sel = fluid & (dd <= 16.0)
+                    pts.append(dd[sel])
+                    phi[sel] = 300.0 + dd[sel]
+        dd = np.concatenate(pts)
+        prob.T0 = phi
+        o = oracle_mod.Oracle(prob)
+        T, _, nnodes = o.image_value(x)
+        assert nnodes == len(dd)
+        expect = len(dd) / np.sum(1.0 / dd)
+        assert abs((T - 300.0) - expect) < 1e-10 * expect, (x, T - 300.0, expect)
