@@ -183,6 +183,15 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T,
               const double *T0, const double *Y0, const double *u0,
               const double *Ph0, void *hip_stream, lbfd_ctx **out);
 
+/* lbfd_init with every array argument a device pointer (same layouts and
+ * optional arguments; e.g. the storage of torch tensors).  The arrays are
+ * copied to the host for validation and the host-side set-up, then as in
+ * lbfd_init; the caller keeps ownership.  Any work queued on hip_stream is
+ * waited for first. */
+int lbfd_init_dev(const lbfd_params *p, const uint8_t *mask, const double *wall_T,
+                  const double *T0, const double *Y0, const double *u0,
+                  const double *Ph0, void *hip_stream, lbfd_ctx **out);
+
 /* Queue nsteps coupled steps (asynchronous).  Every check_every levels
  * the step also reduces the diagnostics; a non-finite value is reported
  * by the next lbfd_sync. */
@@ -202,6 +211,12 @@ int64_t lbfd_level(const lbfd_ctx *c);
  * Synchronous. */
 int lbfd_read_fields(lbfd_ctx *c, double *rho, double *u, double *T,
                      double *Y, double *Ph);
+
+/* lbfd_read_fields into caller-owned device buffers of the same layouts
+ * (double; mixed-precision T, Y are widened on the device), queued on the
+ * context stream.  Synchronous. */
+int lbfd_read_fields_dev(lbfd_ctx *c, double *rho, double *u, double *T,
+                         double *Y, double *Ph);
 
 /* Diagnostics of the current level (synchronous). */
 int lbfd_diagnostics(lbfd_ctx *c, lbfd_diag *d);
@@ -322,6 +337,11 @@ int lbfd_objective(lbfd_ctx *c, int64_t nsteps, double *J);
  * the last bits between runs. */
 int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwallT, double *dJ_dA,
                  double *dJ_dTa);
+
+/* lbfd_adjoint with dJ_dwallT a device pointer ([N] doubles, caller-owned;
+ * e.g. a torch tensor's storage); J, dJ_dA, dJ_dTa stay on the host. */
+int lbfd_adjoint_dev(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwallT, double *dJ_dA,
+                     double *dJ_dTa);
 
 /* Per-part timing: queue nsteps steps with the interior-cell part and the
  * boundary-cell part launched separately on the context stream, each

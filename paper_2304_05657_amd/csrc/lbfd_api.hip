@@ -618,6 +618,41 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     return LBFD_OK;
 }
 
+int lbfd_init_dev(const lbfd_params *p, const uint8_t *mask, const double *wall_T, const double *T0,
+                  const double *Y0, const double *u0, const double *Ph0, void *hip_stream, lbfd_ctx **out)
+{
+    if (!out) return fail(LBFD_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!p || !mask || !T0 || !Y0) return fail(LBFD_EINVAL, "null argument");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBFD_EINVAL, "grid sizes must be positive");
+    if (p->n_species < 1 || p->n_species > LBFD_MAX_SPECIES) return fail(LBFD_EINVAL, "bad species count");
+    if (p->lattice != LBFD_D2Q9 && p->lattice != LBFD_D3Q27) return fail(LBFD_EINVAL, "lattice must be 9 or 27");
+    const size_t N = (size_t)p->nx * p->ny * p->nz, D = p->lattice == LBFD_D2Q9 ? 2 : 3;
+    // the inputs are validated and laid out on the host: bring them over
+    std::vector<uint8_t> hm;
+    std::vector<double> hw, hT, hY, hu, hP;
+    try {
+        hm.resize(N);
+        hT.resize(N);
+        hY.resize((size_t)p->n_species * N);
+        if (wall_T) hw.resize(N);
+        if (u0) hu.resize(D * N);
+        if (Ph0) hP.resize(N);
+    } catch (const std::bad_alloc &) {
+        return fail(LBFD_ENOMEM, "host staging of the initial state failed");
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemcpy(hm.data(), mask, N, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hT.data(), T0, N * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hY.data(), Y0, hY.size() * sizeof(double), hipMemcpyDeviceToHost));
+    if (wall_T) HIP_TRY(hipMemcpy(hw.data(), wall_T, N * sizeof(double), hipMemcpyDeviceToHost));
+    if (u0) HIP_TRY(hipMemcpy(hu.data(), u0, hu.size() * sizeof(double), hipMemcpyDeviceToHost));
+    if (Ph0) HIP_TRY(hipMemcpy(hP.data(), Ph0, N * sizeof(double), hipMemcpyDeviceToHost));
+    return lbfd_init(p, hm.data(), wall_T ? hw.data() : nullptr, hT.data(), hY.data(), u0 ? hu.data() : nullptr,
+                     Ph0 ? hP.data() : nullptr, hip_stream, out);
+}
+
 int lbfd_step(lbfd_ctx *c, int64_t nsteps)
 {
     if (!c || nsteps < 0) return fail(LBFD_EINVAL, "bad arguments");
@@ -668,32 +703,50 @@ static int evaluate(lbfd_ctx *c)
     return LBFD_OK;
 }
 
-int lbfd_read_fields(lbfd_ctx *c, double *rho, double *u, double *T, double *Y, double *Ph)
+// Fields of the current level into host (dev = false) or device buffers.
+static int read_fields(lbfd_ctx *c, double *rho, double *u, double *T, double *Y, double *Ph, bool dev)
 {
     if (!c) return fail(LBFD_EINVAL, "null context");
     int rc = evaluate(c);
     if (rc) return rc;
     const long long N = c->N;
-    if (rho) HIP_TRY(hipMemcpy(rho, c->fields, N * sizeof(double), hipMemcpyDeviceToHost));
-    if (u) HIP_TRY(hipMemcpy(u, c->fields + N, (size_t)c->D * N * sizeof(double), hipMemcpyDeviceToHost));
-    if (Ph) HIP_TRY(hipMemcpy(Ph, c->fields + 4 * N, N * sizeof(double), hipMemcpyDeviceToHost));
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (rho) HIP_TRY(hipMemcpyAsync(rho, c->fields, N * sizeof(double), kind, c->stream));
+    if (u) HIP_TRY(hipMemcpyAsync(u, c->fields + N, (size_t)c->D * N * sizeof(double), kind, c->stream));
+    if (Ph) HIP_TRY(hipMemcpyAsync(Ph, c->fields + 4 * N, N * sizeof(double), kind, c->stream));
     if (T || Y) {
         const size_t n = (size_t)(1 + c->nsp) * N;
         if (c->prec == LBFD_FP64) {
-            if (T) HIP_TRY(hipMemcpy(T, c->sc[c->cur], N * sizeof(double), hipMemcpyDeviceToHost));
+            if (T) HIP_TRY(hipMemcpyAsync(T, c->sc[c->cur], N * sizeof(double), kind, c->stream));
             if (Y)
-                HIP_TRY(hipMemcpy(Y, (double *)c->sc[c->cur] + N, (size_t)c->nsp * N * sizeof(double),
-                                  hipMemcpyDeviceToHost));
+                HIP_TRY(hipMemcpyAsync(Y, (double *)c->sc[c->cur] + N, (size_t)c->nsp * N * sizeof(double), kind,
+                                       c->stream));
+        } else if (dev) {
+            // mixed storage: widened to double on the device
+            if (T) HIP_TRY(launch_widen((const float *)c->sc[c->cur], T, (size_t)N, c->stream));
+            if (Y) HIP_TRY(launch_widen((const float *)c->sc[c->cur] + N, Y, (size_t)c->nsp * N, c->stream));
         } else {
             std::vector<float> tmp(n);
-            HIP_TRY(hipMemcpy(tmp.data(), c->sc[c->cur], n * sizeof(float), hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpyAsync(tmp.data(), c->sc[c->cur], n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
             if (T)
                 for (long long i = 0; i < N; ++i) T[i] = tmp[i];
             if (Y)
                 for (size_t i = 0; i < (size_t)c->nsp * N; ++i) Y[i] = tmp[N + i];
         }
     }
+    HIP_TRY(hipStreamSynchronize(c->stream));
     return LBFD_OK;
+}
+
+int lbfd_read_fields(lbfd_ctx *c, double *rho, double *u, double *T, double *Y, double *Ph)
+{
+    return read_fields(c, rho, u, T, Y, Ph, false);
+}
+
+int lbfd_read_fields_dev(lbfd_ctx *c, double *rho, double *u, double *T, double *Y, double *Ph)
+{
+    return read_fields(c, rho, u, T, Y, Ph, true);
 }
 
 int lbfd_diagnostics(lbfd_ctx *c, lbfd_diag *d)
@@ -1273,8 +1326,8 @@ int lbfd_objective(lbfd_ctx *c, int64_t nsteps, double *J)
     return LBFD_OK;
 }
 
-int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwallT, double *dJ_dA,
-                 double *dJ_dTa)
+static int adjoint_impl(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwallT, double *dJ_dA,
+                        double *dJ_dTa, bool wall_dev)
 {
     if (!c || nsteps < 1 || K < 1) return fail(LBFD_EINVAL, "bad arguments");
     if (c->prec != LBFD_FP64) return fail(LBFD_EINVAL, "the adjoint needs FP64 precision");
@@ -1369,12 +1422,24 @@ int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwall
     double hP[2 * LBFD_MAX_REACTIONS];
     HIP_TRY(hipMemcpy(hP, dP, sizeof(hP), hipMemcpyDeviceToHost));
     if (J) HIP_TRY(hipMemcpy(J, Jd, sizeof(double), hipMemcpyDeviceToHost));
-    if (dJ_dwallT) HIP_TRY(hipMemcpy(dJ_dwallT, dW, N * sizeof(double), hipMemcpyDeviceToHost));
+    if (dJ_dwallT)
+        HIP_TRY(hipMemcpy(dJ_dwallT, dW, N * sizeof(double), wall_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
     for (int j = 0; j < nrx; ++j) {
         if (dJ_dA) dJ_dA[j] = hP[2 * j];
         if (dJ_dTa) dJ_dTa[j] = hP[2 * j + 1];
     }
     return LBFD_OK;
+}
+
+int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwallT, double *dJ_dA, double *dJ_dTa)
+{
+    return adjoint_impl(c, nsteps, K, J, dJ_dwallT, dJ_dA, dJ_dTa, false);
+}
+
+int lbfd_adjoint_dev(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwallT, double *dJ_dA,
+                     double *dJ_dTa)
+{
+    return adjoint_impl(c, nsteps, K, J, dJ_dwallT, dJ_dA, dJ_dTa, true);
 }
 
 int lbfd_cell_counts(const lbfd_ctx *c, int64_t *n_fluid, int64_t *n_boundary)

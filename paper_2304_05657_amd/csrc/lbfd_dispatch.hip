@@ -120,4 +120,18 @@ hipError_t launch_finalize(const double *partials, int nblocks, double *out, lon
     return hipGetLastError();
 }
 
+// Widening copy of single-precision scalars into caller double buffers.
+__global__ void __launch_bounds__(kBlock) widen_kernel(const float *src, double *dst, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) dst[i] = (double)src[i];
+}
+
+hipError_t launch_widen(const float *src, double *dst, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    widen_kernel<<<dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(src, dst, n);
+    return hipGetLastError();
+}
+
 }  // namespace lbfd

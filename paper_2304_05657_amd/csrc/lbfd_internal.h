@@ -130,6 +130,8 @@ bool adjoint_supported(int Q, int nsp);
 hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_pop_next, const double *lam_sc_next,
                           double *lam_pop, double *lam_sc, double *dwallT, double *dparam, int obj_kind,
                           double obj_w, hipStream_t s);
+// dst[i] = src[i] for i < n (float to double, on the stream).
+hipError_t launch_widen(const float *src, double *dst, size_t n, hipStream_t s);
 // *acc += a * diag[slot] + b (one thread).
 hipError_t launch_accumulate(double *acc, const double *diag, int slot, double a, double b, hipStream_t s);
 

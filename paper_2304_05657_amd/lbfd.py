@@ -28,7 +28,8 @@ EXPORTS = ("lbfd_init", "lbfd_step", "lbfd_sync", "lbfd_level", "lbfd_read_field
            "lbfd_save_state", "lbfd_load_state", "lbfd_time_steps", "lbfd_time_kernels",
            "lbfd_cell_counts", "lbfd_step_launches", "lbfd_set_reaction", "lbfd_set_objective",
            "lbfd_objective", "lbfd_adjoint", "lbfd_set_inflow", "lbfd_hold_flame", "lbfd_set_wall_links",
-           "lbfd_set_image_points", "lbfd_destroy",
+           "lbfd_set_image_points", "lbfd_init_dev", "lbfd_read_fields_dev", "lbfd_adjoint_dev",
+           "lbfd_destroy",
            "lbfd_strerror", "lbfd_last_error")
 # species transport models (lbfd_params.transport)
 TRANSPORTS = {"unity_lewis": 0, "mixture_averaged": 1}
@@ -99,6 +100,9 @@ def load_library():
     lib.lbfd_level.argtypes = [vp]
     lib.lbfd_level.restype = C.c_int64
     lib.lbfd_read_fields.argtypes = [vp, dp, dp, dp, dp, dp]
+    lib.lbfd_init_dev.argtypes = [C.POINTER(Params), vp, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]
+    lib.lbfd_read_fields_dev.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.lbfd_adjoint_dev.argtypes = [vp, C.c_int64, C.c_int, dp, vp, dp, dp]
     lib.lbfd_diagnostics.argtypes = [vp, C.POINTER(Diag)]
     lib.lbfd_set_wall_temperature.argtypes = [vp, dp]
     lib.lbfd_state_size.argtypes = [vp, C.POINTER(C.c_size_t)]
@@ -189,7 +193,7 @@ class Solver:
     torch stream of the current device is used when torch is importable,
     else the null stream."""
 
-    def __init__(self, prob, precision="fp64", check_every: int = 0, stream=None):
+    def __init__(self, prob, precision="fp64", check_every: int = 0, stream=None, from_device: bool = False):
         lib = load_library()
         if stream is None:
             stream = _torch_stream()
@@ -208,8 +212,15 @@ class Solver:
             np.asarray(prob.u0, dtype=np.float64)[: self.dim]).reshape(-1)
         Ph0 = None if prob.Ph0 is None else np.ascontiguousarray(prob.Ph0, dtype=np.float64).reshape(-1)
         h = C.c_void_p()
-        rc = lib.lbfd_init(C.byref(self._params), mask.ctypes.data, _dp(wall_T), _dp(T0), _dp(Y0),
-                           _dp(u0), _dp(Ph0), C.c_void_p(stream or 0), C.byref(h))
+        if from_device:
+            # the same arrays as torch tensors on the current device (lbfd_init_dev)
+            import torch
+            dev = [None if a is None else torch.from_numpy(a).cuda() for a in (mask, wall_T, T0, Y0, u0, Ph0)]
+            ptr = [None if t is None else C.c_void_p(t.data_ptr()) for t in dev]
+            rc = lib.lbfd_init_dev(C.byref(self._params), *ptr, C.c_void_p(stream or 0), C.byref(h))
+        else:
+            rc = lib.lbfd_init(C.byref(self._params), mask.ctypes.data, _dp(wall_T), _dp(T0), _dp(Y0),
+                               _dp(u0), _dp(Ph0), C.c_void_p(stream or 0), C.byref(h))
         _check(lib, rc)
         self._h = h
         self._lib = lib
@@ -271,22 +282,42 @@ class Solver:
         _check(self._lib, self._lib.lbfd_objective(self._h, int(nsteps), C.byref(J)))
         return J.value
 
-    def adjoint(self, nsteps: int, K: int):
+    def adjoint(self, nsteps: int, K: int, device: bool = False):
         """(J, dJ/dwall_T [nz, ny, nx], dJ/dA [n_rx], dJ/dTa [n_rx]) over the next
-        nsteps levels, checkpointing every K steps."""
+        nsteps levels, checkpointing every K steps; device=True returns
+        dJ/dwall_T as a torch tensor on the current device (lbfd_adjoint_dev)."""
         pr = self.prob
         J = C.c_double()
-        gW = np.zeros(self.N)
         nrx = max(1, len(pr.reactions))
         gA, gTa = np.zeros(nrx), np.zeros(nrx)
-        _check(self._lib, self._lib.lbfd_adjoint(self._h, int(nsteps), int(K), C.byref(J), _dp(gW), _dp(gA),
-                                                 _dp(gTa)))
+        if device:
+            import torch
+            gW = torch.zeros(self.N, dtype=torch.float64, device="cuda")
+            _check(self._lib, self._lib.lbfd_adjoint_dev(self._h, int(nsteps), int(K), C.byref(J),
+                                                         C.c_void_p(gW.data_ptr()), _dp(gA), _dp(gTa)))
+        else:
+            gW = np.zeros(self.N)
+            _check(self._lib, self._lib.lbfd_adjoint(self._h, int(nsteps), int(K), C.byref(J), _dp(gW), _dp(gA),
+                                                     _dp(gTa)))
         return J.value, gW.reshape((pr.nz, pr.ny, pr.nx)), gA[: len(pr.reactions)], gTa[: len(pr.reactions)]
 
-    def fields(self) -> dict:
+    def fields(self, device: bool = False) -> dict:
+        """rho, u [3], T, Y [n_species], Ph of the current level (FP64): numpy
+        arrays, or with device=True torch tensors on the current device
+        (lbfd_read_fields_dev)."""
         pr = self.prob
         shp = (pr.nz, pr.ny, pr.nx)
         N = self.N
+        if device:
+            import torch
+            out = {k: torch.empty(n * N, dtype=torch.float64, device="cuda")
+                   for k, n in (("rho", 1), ("u", self.dim), ("T", 1), ("Y", self.nsp), ("Ph", 1))}
+            _check(self._lib, self._lib.lbfd_read_fields_dev(self._h, *(C.c_void_p(out[k].data_ptr())
+                                                                      for k in ("rho", "u", "T", "Y", "Ph"))))
+            u3 = torch.zeros((3,) + shp, dtype=torch.float64, device="cuda")
+            u3[: self.dim] = out["u"].reshape((self.dim,) + shp)
+            return {"rho": out["rho"].reshape(shp), "u": u3, "T": out["T"].reshape(shp),
+                    "Y": out["Y"].reshape((self.nsp,) + shp), "Ph": out["Ph"].reshape(shp)}
         rho, T, Ph = np.empty(N), np.empty(N), np.empty(N)
         u = np.empty(self.dim * N)
         Y = np.empty(self.nsp * N)
@@ -388,8 +419,10 @@ def wall_heat_flux_objective(solver: Solver, state: bytes, nsteps: int, K: int, 
             solver.set_wall_temperature(wall_T.detach().to(torch.float64).cpu().numpy())
             r = solver.prob.reactions[0]
             solver.set_reaction(0, float(A), r.b, float(Ta))
-            J, gW, gA, gTa = solver.adjoint(nsteps, K)
-            ctx.save_for_backward(torch.from_numpy(gW).to(wall_T.dtype), torch.tensor(gA[0], dtype=A.dtype),
+            on_gpu = wall_T.is_cuda
+            J, gW, gA, gTa = solver.adjoint(nsteps, K, device=on_gpu)
+            gW = gW if on_gpu else torch.from_numpy(gW)
+            ctx.save_for_backward(gW.to(wall_T.dtype), torch.tensor(gA[0], dtype=A.dtype),
                                   torch.tensor(gTa[0], dtype=Ta.dtype))
             return torch.tensor(J, dtype=torch.float64)
 
