@@ -46,9 +46,9 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_05657_amd", "csrc", f)
 # SHA-256 (kernel_sha) is given (profiles/traffic_step_kernels_burner_2048x512.md).
 TRAFFIC_WORKLOAD = "cylinder_burner_2048x512"
 TRAFFIC = {
-    "fp64": {"kernel_sha256": "447c7ffcd8bd1273ff2edb11de8aaff3e5769440864131f1e7bd32ecef0e5185", "bytes_per_launch": 269.2e6},
-    "fp32": {"kernel_sha256": "447c7ffcd8bd1273ff2edb11de8aaff3e5769440864131f1e7bd32ecef0e5185", "bytes_per_launch": 172.4e6},
-    "fp16": {"kernel_sha256": "447c7ffcd8bd1273ff2edb11de8aaff3e5769440864131f1e7bd32ecef0e5185", "bytes_per_launch": 129.7e6},
+    "fp64": {"kernel_sha256": "1c365bf59528639c5a2517102153e6cdb4bbff545e98fd637ad797ba3652c333", "bytes_per_launch": 269.2e6},
+    "fp32": {"kernel_sha256": "1c365bf59528639c5a2517102153e6cdb4bbff545e98fd637ad797ba3652c333", "bytes_per_launch": 172.6e6},
+    "fp16": {"kernel_sha256": "1c365bf59528639c5a2517102153e6cdb4bbff545e98fd637ad797ba3652c333", "bytes_per_launch": 129.8e6},
 }
 POP_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 SCALAR_BYTES = {"fp64": 8, "fp32": 4, "fp16": 4}
