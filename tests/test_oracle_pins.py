@@ -1062,3 +1062,27 @@ def test_shepard_reconstruction_closed_form_3d(oracle_mod):
         assert nnodes == len(dd)
         expect = len(dd) / np.sum(1.0 / dd)
         assert abs((T - 300.0) - expect) < 1e-10 * expect, (x, T - 300.0, expect)
+
+
+def test_zero_d_reactor_species_heat_capacities(oracle_mod):
+    """Homogeneous periodic box with mixture-averaged transport: no
+    diffusion, and the temperature rises by q r / (c_p / c_p,ref) with
+    c_p = sum_k Y_k c_pk at the current composition (Eq. 7 at u = 0: the
+    heat release over rho c_p); the mass fractions follow nu r as before."""
+    prob = W.channel_flame(nx=4, ny=4)
+    prob.mask[:] = 0
+    Yu = np.array(W.Y_UNBURNT_STOICH)
+    cpk = np.array([2.0, 0.9, 1.3, 1.0])
+    prob = prob.replace(T0=np.full((1, 4, 4), 1500.0), Y0=np.stack([np.full((1, 4, 4), v) for v in Yu]),
+                        transport="mixture_averaged", lewis=(0.8, 1.1, 1.4, 1.0), cp=tuple(cpk))
+    o = oracle_mod.Oracle(prob)
+    T, Y = 1500.0, Yu.copy()
+    for n in range(30):
+        f = o.fields()
+        assert np.allclose(f["T"], T, rtol=1e-12)
+        assert np.allclose(f["Y"][:, 0, 0, 0], Y, rtol=1e-11, atol=1e-15)
+        r = 1e9 * 7.5e-8 * math.exp(-15000.0 / T) * Y[0] * Y[1]
+        T += 3e4 * r / float((Y * cpk).sum())
+        Y = Y + np.array([-1.0, -4.0, 5.0, 0.0]) * r
+        o.step(1)
+    assert T > 1520.0  # the heat release is visible
