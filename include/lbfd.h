@@ -178,7 +178,9 @@ typedef struct lbfd_ctx lbfd_ctx;
  * or NULL (rest), Ph0 [N] or NULL (0).  The initial populations are the
  * pressure-based equilibrium g_i = w_i (P_h - rho cs^2) + cs^2 f_i^eq
  * (Eq. 12).  hip_stream: a hipStream_t on which all work of the context is
- * queued (NULL: the null stream).  On success *out receives the context. */
+ * queued (NULL: the null stream).  On success *out receives the context.
+ * Boxes of 2^29 cells or more are rejected (LBFD_EINVAL) before any array
+ * is read: every field is addressed with 32-bit byte offsets. */
 int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T,
               const double *T0, const double *Y0, const double *u0,
               const double *Ph0, void *hip_stream, lbfd_ctx **out);

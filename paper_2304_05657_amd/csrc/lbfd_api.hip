@@ -130,6 +130,8 @@ static int validate(const lbfd_params *p, const uint8_t *mask, const double *T0,
     if (!p || !mask || !T0 || !Y0) return fail(LBFD_EINVAL, "null argument");
     if (p->lattice != LBFD_D2Q9 && p->lattice != LBFD_D3Q27) return fail(LBFD_EINVAL, "lattice must be 9 or 27");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBFD_EINVAL, "grid sizes must be positive");
+    if ((long long)p->nx * p->ny * p->nz >= (1LL << 29))
+        return fail(LBFD_EINVAL, "box too large (at most 2^29 cells: 32-bit byte offsets per field)");
     if (p->lattice == LBFD_D2Q9 && p->nz != 1) return fail(LBFD_EINVAL, "D2Q9 needs nz == 1");
     if (p->precision < LBFD_FP64 || p->precision > LBFD_MIXED_FP16) return fail(LBFD_EINVAL, "bad precision");
     if (p->n_species < 1 || p->n_species > LBFD_MAX_SPECIES) return fail(LBFD_EINVAL, "bad species count");
@@ -625,6 +627,8 @@ int lbfd_init_dev(const lbfd_params *p, const uint8_t *mask, const double *wall_
     *out = nullptr;
     if (!p || !mask || !T0 || !Y0) return fail(LBFD_EINVAL, "null argument");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBFD_EINVAL, "grid sizes must be positive");
+    if ((long long)p->nx * p->ny * p->nz >= (1LL << 29))
+        return fail(LBFD_EINVAL, "box too large (at most 2^29 cells: 32-bit byte offsets per field)");
     if (p->n_species < 1 || p->n_species > LBFD_MAX_SPECIES) return fail(LBFD_EINVAL, "bad species count");
     if (p->lattice != LBFD_D2Q9 && p->lattice != LBFD_D3Q27) return fail(LBFD_EINVAL, "lattice must be 9 or 27");
     const size_t N = (size_t)p->nx * p->ny * p->nz, D = p->lattice == LBFD_D2Q9 ? 2 : 3;

@@ -94,3 +94,25 @@ def test_mixture_transport_parameters():
     # alpha = 0.0476 at tau 0.6: Le 0.2 puts D_k above 3/16
     p = _small().replace(transport="mixture_averaged", lewis=(0.2, 1.0, 1.0, 1.0))
     _reject(p, "above the explicit stability bound")
+
+
+def test_box_beyond_the_maximum_size():
+    """Boxes of 2^29 cells or more are rejected before any input array is
+    read (the arrays passed here are those of a small box)."""
+    import ctypes as C
+    from paper_2304_05657_amd import lbfd as L
+    lib = L.load_library()
+    prob = _small()
+    p, rx = L.make_params(prob)
+    p.lattice, p.nx, p.ny, p.nz = 27, 1024, 512, 1024
+    mask = np.zeros(prob.N, np.uint8)
+    T0 = np.full(prob.N, 300.0)
+    Y0 = np.full(4 * prob.N, 0.25)
+    h = C.c_void_p()
+    rc = lib.lbfd_init(C.byref(p), mask.ctypes.data, None, L._dp(T0), L._dp(Y0), None, None, None, C.byref(h))
+    assert rc == EINVAL and not h.value
+    assert "box too large" in lib.lbfd_last_error().decode()
+    rc = lib.lbfd_init_dev(C.byref(p), mask.ctypes.data, None, T0.ctypes.data, Y0.ctypes.data, None, None, None,
+                           C.byref(h))
+    assert rc == EINVAL and not h.value
+    assert "box too large" in lib.lbfd_last_error().decode()
