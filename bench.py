@@ -46,9 +46,9 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_05657_amd", "csrc", f)
 # SHA-256 (kernel_sha) is given (profiles/traffic_step_kernels_burner_2048x512.md).
 TRAFFIC_WORKLOAD = "cylinder_burner_2048x512"
 TRAFFIC = {
-    "fp64": {"kernel_sha256": "08567a115aa828050deaa737bdb19125fe468331399580a8d18eed641bccd0d7", "bytes_per_launch": 269.2e6},
-    "fp32": {"kernel_sha256": "08567a115aa828050deaa737bdb19125fe468331399580a8d18eed641bccd0d7", "bytes_per_launch": 171.7e6},
-    "fp16": {"kernel_sha256": "08567a115aa828050deaa737bdb19125fe468331399580a8d18eed641bccd0d7", "bytes_per_launch": 130.2e6},
+    "fp64": {"kernel_sha256": "9d1349d250e5324bb86203a936403069b8b3797f96b9c2043a72caf81abe6588", "bytes_per_launch": 267.0e6},
+    "fp32": {"kernel_sha256": "9d1349d250e5324bb86203a936403069b8b3797f96b9c2043a72caf81abe6588", "bytes_per_launch": 168.1e6},
+    "fp16": {"kernel_sha256": "9d1349d250e5324bb86203a936403069b8b3797f96b9c2043a72caf81abe6588", "bytes_per_launch": 125.3e6},
 }
 POP_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 SCALAR_BYTES = {"fp64": 8, "fp32": 4, "fp16": 4}

@@ -461,14 +461,26 @@ __device__ __forceinline__ double rate_coeff(const lbfd_reaction &r, double dt, 
     return r.A * dt * tb * exp(-r.Ta * rcp(T));
 }
 
+// The same rate coefficient from ln T and 1/T shared by every reaction:
+// A dt exp(b ln T - Ta / T), one exponential per reaction (with b = 0 it is
+// A dt exp(-Ta / T) bit for bit).
+__device__ __forceinline__ double rate_coeff_l(const lbfd_reaction &r, double dt, double lnT, double invT)
+{
+    return r.A * dt * exp(r.b * lnT - r.Ta * invT);
+}
+
 template <int NSP, bool LE = false>
 __device__ __forceinline__ void chemistry(const KParams &P, double T, const double (&Y)[NSP], double &srcT,
                                           double (&srcY)[NSP])
 {
+    // ln T is needed only when a temperature exponent is not zero
+    bool anyb = false;
+    for (int j = 0; j < P.n_rx; ++j) anyb |= P.rx[j].b != 0.0;
     int nsub = 1;
     if (P.chem_substeps_max > 1) {
+        const double lnT = anyb ? log(T) : 0.0, invT = rcp(T);
         double kmax = 0.0;
-        for (int j = 0; j < P.n_rx; ++j) kmax = fmax(kmax, rate_coeff(P.rx[j], P.dt_phys, T));
+        for (int j = 0; j < P.n_rx; ++j) kmax = fmax(kmax, rate_coeff_l(P.rx[j], P.dt_phys, lnT, invT));
         double want = ceil(kmax / 0.1);
         nsub = want < 1.0 ? 1 : want > (double)P.chem_substeps_max ? P.chem_substeps_max : (int)want;
     }
@@ -484,9 +496,10 @@ __device__ __forceinline__ void chemistry(const KParams &P, double T, const doub
         double incT = 0.0, incY[NSP];
 #pragma unroll
         for (int k = 0; k < NSP; ++k) incY[k] = 0.0;
+        const double lnTc = anyb ? log(Tc) : 0.0, invTc = rcp(Tc);
         for (int j = 0; j < P.n_rx; ++j) {
             const lbfd_reaction &r = P.rx[j];
-            double rr = rate_coeff(r, P.dt_phys, Tc) * inv_nsub;
+            double rr = rate_coeff_l(r, P.dt_phys, lnTc, invTc) * inv_nsub;
             for (int m = 0; m < r.n_react; ++m) {
                 int kr = r.react[m];
                 double yv = 0.0;
