@@ -414,9 +414,12 @@ double lbo_weno3(const double *phi5, double u)
 /* capped at chem_substeps_max (one sub-step is the plain Euler source);*/
 /* each sub-step is scaled down if it would drive a Y_k below zero.     */
 /* ------------------------------------------------------------------ */
+/* k = A dt T^b exp(-Ta/T), with T^b exp(-Ta/T) written as the one        */
+/* exponential exp(b ln T - Ta/T) (the form every implementation of the   */
+/* step uses; with b = 0 it is exp(-Ta/T) exactly).                       */
 static double rate_coeff(const lbo_reaction *r, double dt_phys, double T)
 {
-    return r->A * dt_phys * pow(T, r->b) * exp(-r->Ta / T);
+    return r->A * dt_phys * exp(r->b * log(T) - r->Ta / T);
 }
 
 void lbo_chemistry(const lbo_params *p, double T, const double *Y,

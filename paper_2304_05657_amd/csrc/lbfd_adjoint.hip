@@ -9,9 +9,10 @@
 // adjoint recursion is lambda^N = 0,
 //   lambda^n = (dF/ds^n)^T lambda^{n+1} + (dq/ds^n)^T,
 //   dJ/dtheta = sum_n (dF/dtheta)^T lambda^{n+1} + dq^n/dtheta.
-// One thread per fluid cell c evaluates the cell's update (the same
-// formulas and device functions as the forward kernels, general geometry
-// path) in dual numbers, once per input slot of the cell (pull source,
+// One thread per fluid cell c evaluates the cell's update (the forward
+// step's formulas, in the general geometry path: neighbours classified on
+// the fly, each stencil point and density evaluated separately) in dual
+// numbers, once per input slot of the cell (pull source,
 // stencil scalar, wall temperature, Arrhenius parameter) with a unit tangent
 // on that slot; the tangent of the outputs dotted with the cell's output
 // adjoint is that slot's contribution, added atomically to the adjoint of
@@ -58,12 +59,8 @@ __device__ inline Dual dexp(Dual a)
     return Dual(e, e * a.d);
 }
 __device__ inline double dexp(double a) { return exp(a); }
-__device__ inline Dual dpow(Dual a, double b)
-{
-    const double p = pow(a.v, b);
-    return Dual(p, b * pow(a.v, b - 1.0) * a.d);
-}
-__device__ inline double dpow(double a, double b) { return pow(a, b); }
+__device__ inline Dual dlog(Dual a) { return Dual(log(a.v), a.d * rcp(a.v)); }
+__device__ inline double dlog(double a) { return log(a); }
 __device__ inline double val(Dual a) { return a.v; }
 __device__ inline double val(double a) { return a; }
 __device__ inline double tan_(Dual a) { return a.d; }
@@ -278,14 +275,20 @@ __device__ void cell_eval(const KParams &P, const CellIn<Q, NSP> &in, int seed, 
     // Arrhenius source (same sub-stepping and limiter as the forward)
     A srcT = 0.0, srcY[NSP];
     {
+        // rate coefficients k_j = A_j dt exp(b_j ln T - Ta_j / T), ln T and
+        // 1/T shared by the reactions, as in the forward chemistry()
         const A Tc0 = T[0];
+        bool anyb = false;
+        for (int j = 0; j < P.n_rx; ++j) anyb |= P.rx[j].b != 0.0;
         int nsub = 1;
         if (P.chem_substeps_max > 1) {
+            const double lnT = anyb ? log(val(Tc0)) : 0.0, invT = rcp(val(Tc0));
             double kmax = 0.0;
-            for (int j = 0; j < P.n_rx; ++j) kmax = fmax(kmax, rate_coeff(P.rx[j], P.dt_phys, val(Tc0)));
+            for (int j = 0; j < P.n_rx; ++j) kmax = fmax(kmax, rate_coeff_l(P.rx[j], P.dt_phys, lnT, invT));
             const double want = ceil(kmax / 0.1);
             nsub = want < 1.0 ? 1 : want > (double)P.chem_substeps_max ? P.chem_substeps_max : (int)want;
         }
+        const double inv_nsub = nsub == 1 ? 1.0 : rcp((double)nsub);
         A dT = 0.0, dY[NSP];
         for (int k = 0; k < NSP; ++k) dY[k] = 0.0;
         for (int s = 0; s < nsub; ++s) {
@@ -295,11 +298,11 @@ __device__ void cell_eval(const KParams &P, const CellIn<Q, NSP> &in, int seed, 
                 Yc[k] = Y[0][k] + dY[k];
                 incY[k] = 0.0;
             }
+            const A lnTc = anyb ? dlog(Tc) : A(0.0), invTc = rcp(Tc);
             for (int j = 0; j < P.n_rx; ++j) {
                 const lbfd_reaction &r = P.rx[j];
                 const A Aj = mk(r.A, S::param + 2 * j), Taj = mk(r.Ta, S::param + 2 * j + 1);
-                const A tb = r.b == 0.0 ? A(1.0) : dpow(Tc, r.b);
-                A rr = Aj * A(P.dt_phys) * tb * dexp(-Taj / Tc) / A((double)nsub);
+                A rr = Aj * A(P.dt_phys) * dexp(A(r.b) * lnTc - Taj * invTc) * A(inv_nsub);
                 for (int mm = 0; mm < r.n_react; ++mm) rr *= Yc[r.react[mm]];
                 for (int k = 0; k < NSP; ++k) incY[k] += A(r.nu_mass[k]) * rr;
                 incT += A(r.q_over_cp) * rr;

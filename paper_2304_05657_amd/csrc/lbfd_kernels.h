@@ -455,15 +455,9 @@ __device__ __forceinline__ void axis5(C m2, C m1, C c0, C p1, C p2, C u, bool ne
 // one explicit Euler step, or, with chem_substeps_max > 1, N sub-steps
 // with N = ceil(max_j k_j / 0.1) capped at chem_substeps_max; a sub-step
 // that would consume a mass fraction below zero is scaled down.
-__device__ __forceinline__ double rate_coeff(const lbfd_reaction &r, double dt, double T)
-{
-    const double tb = r.b == 0.0 ? 1.0 : pow(T, r.b);
-    return r.A * dt * tb * exp(-r.Ta * rcp(T));
-}
-
-// The same rate coefficient from ln T and 1/T shared by every reaction:
-// A dt exp(b ln T - Ta / T), one exponential per reaction (with b = 0 it is
-// A dt exp(-Ta / T) bit for bit).
+// The rate coefficient A dt T^b exp(-Ta/T) from ln T and 1/T shared by
+// every reaction: A dt exp(b ln T - Ta / T), one exponential per reaction
+// (with b = 0 it is A dt exp(-Ta / T) bit for bit).
 __device__ __forceinline__ double rate_coeff_l(const lbfd_reaction &r, double dt, double lnT, double invT)
 {
     return r.A * dt * exp(r.b * lnT - r.Ta * invT);

@@ -1,0 +1,417 @@
+"""More pins of the FP64 oracle against closed forms and brute force:
+
+* the outlet rule of Sec. III.A (Eq. 32), through the reflection of a weak
+  plane pressure pulse, against the coefficient of the linear analysis of
+  the rule as read (derivation below);
+* the Arrhenius rate law with temperature exponents b != 0 and a seeded
+  9-species / 20-reaction mechanism with sub-cycling (Sec. II.A), against a
+  scalar Python recurrence written with math.pow;
+* the wall-heat-flux diagnostic (Sec. IV.A) on each wall of steady
+  conduction against the closed-form conductive flux, and the flame
+  position (Sec. IV.A / IV.C) of a tanh front against its closed form;
+* the Gaussian heat kernel (Sec. II.D: fourth-order central diffusion with
+  explicit Euler).
+
+Runs on CPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2304_05657_amd import workloads as W
+
+CS2 = 1.0 / 3.0
+CS = math.sqrt(CS2)
+
+
+# ------------------------------------------------------------- outlet rule
+# Linear analysis of the outlet (Eq. 32 as read:
+#   g_i(r) <- g_i(r - n)(cs - u.n) + g_i(r)(1 - cs + u.n)
+# for the populations entering through the face, post-streaming values of
+# the current level).  Rewritten, g_i(r, t+1) - g_i(r, t) =
+# a (g_i(r - n, t) - g_i(r, t)) with a = cs - u.n: the first-order upwind
+# form of d_t g_i + a d_n g_i = 0 at the face.  For long waves the
+# populations are at equilibrium, g_i = w_i P_h + w_i rho c_i.u +
+# w_i rho ((c_i.u)^2 / (2 cs^2) - u.u / 2) (Eq. 12), and the macroscopic
+# equations of the pressure-based scheme at constant rho are
+# d_t P + rho cs^2 d_x u = 0, d_t(rho u) + d_x(P + rho u^2) = 0.  About a
+# mean flow u0 along the outward normal x the characteristic speeds are
+# lam = u0 +- sqrt(u0^2 + cs^2), with u' = lam P' / (rho cs^2).  The sum of
+# the entering populations (c_x = -1, weights summing to 1/6) is
+# G = (P' - rho u'(1 - 2 u0)) / 6 = alpha(lam) P', alpha(lam) =
+# (1 - lam (1 - 2 u0) / cs^2) / 6.  With an outgoing wave P_R(x - lam_R t)
+# and a reflected one P_L(x - lam_L t), the face condition
+# d_t G + a d_x G = 0 gives (a - lam_R) alpha_R P_R' + (a - lam_L) alpha_L
+# P_L' = 0, and the ratio of the reflected to the incident pressure as seen
+# at the face, R = lam_L P_L' / (lam_R P_R'), is
+#   R = -(lam_L / lam_R) (a - lam_R) alpha_R / ((a - lam_L) alpha_L).
+# At rest (a = cs = lam_R) R = 0: the rule passes a plane acoustic wave with
+# a reflection that vanishes at first order in the wave number.  The
+# non-equilibrium parts add O(1 / width) to R.
+def outlet_reflection_theory(u0, a=None):
+    lr = u0 + math.sqrt(u0 * u0 + CS2)
+    ll = u0 - math.sqrt(u0 * u0 + CS2)
+    a = CS - u0 if a is None else a
+    al = lambda lam: (1.0 - lam * (1.0 - 2.0 * u0) / CS2) / 6.0
+    return -(ll / lr) * (a - lr) * al(lr) / ((a - ll) * al(ll))
+
+
+def _pulse_run(oracle_mod, nx, sig, x0, u0, steps):
+    """A right-going plane pressure pulse P = 1e-4 exp(-((x - x0)/sig)^2),
+    u = u0 + lam_R P / (rho cs^2), in a one-row D2Q9 box with a velocity
+    inlet at -x (u0) and the outlet at +x; uniform T, Y (rho = 1, no
+    reaction, Xi = 0).  Returns P_h after `steps` steps."""
+    shape = (1, 1, nx)
+    Y = (0.5, 0.5)
+    lr = u0 + math.sqrt(u0 * u0 + CS2)
+    x = np.arange(nx, dtype=np.float64)
+    P = 1e-4 * np.exp(-((x - x0) / sig) ** 2)
+    u = np.zeros((3,) + shape)
+    u[0] = u0 + (lr / CS2) * P
+    prob = W.Problem(
+        name="pulse", lattice=9, nx=nx, ny=1, nz=1,
+        faces=("inflow", "outflow", "periodic", "periodic", "periodic", "periodic"), face_T=(300.0,) * 6,
+        tau=0.6, prandtl=0.7, dt_phys=7.5e-8, T_ref=300.0, W_ref=28.0, W=(28.0, 28.0), reactions=[],
+        u_in=(u0, 0.0, 0.0), T_in=300.0, Y_in=Y, mask=np.zeros(shape, np.uint8),
+        wall_T=np.full(shape, 300.0), T0=np.full(shape, 300.0),
+        Y0=np.stack([np.full(shape, v) for v in Y]), u0=u, Ph0=P.reshape(shape).copy())
+    o = oracle_mod.Oracle(prob)
+    o.step(steps)
+    return o.fields()["Ph"][0, 0]
+
+
+def outlet_reflection(oracle_mod, sig, u0):
+    """Measured R: the box with the outlet at x = L against a box twice as
+    long (the free run) at the time the incident pulse has left through the
+    outlet: their difference inside the short box is the reflected pulse;
+    its signed extremum over the free run's (incident) peak."""
+    x0 = 4 * sig + 10
+    L = int(x0 + 8 * sig + 40)
+    lr = u0 + math.sqrt(u0 * u0 + CS2)
+    t1 = int((L - x0 + 4 * sig) / lr)
+    Pb = _pulse_run(oracle_mod, L, sig, x0, u0, t1)
+    Pf = _pulse_run(oracle_mod, 2 * L + 200, sig, x0, u0, t1)
+    d = Pb - Pf[:L]
+    i = int(np.argmax(np.abs(d[:L - 2])))
+    return float(d[i] / np.abs(Pf).max())
+
+
+@pytest.mark.parametrize("u0", [0.0, 0.05])
+def test_outlet_reflection_matches_linear_theory(oracle_mod, u0):
+    """Sec. III.A, Eq. 32: the reflection of a plane pressure pulse at the
+    outlet, extrapolated to long waves (R(sig) = R0 + C / sig, widths 16 and
+    32), equals the coefficient of the linear analysis above: 0 at rest,
+    0.0234 against a mean outflow of 0.05.  A swapped split of the two
+    weights (advection speed 1 - cs + u.n) gives 0.041 / 0.038, a wrong sign
+    of u.n 0 / 0.0005."""
+    r16 = outlet_reflection(oracle_mod, 16, u0)
+    r32 = outlet_reflection(oracle_mod, 32, u0)
+    r0 = 2.0 * r32 - r16
+    want = outlet_reflection_theory(u0)
+    assert abs(r0 - want) < 1.5e-3, (r16, r32, r0, want)
+    if u0 == 0.0:
+        # first order in 1 / width, toward zero
+        assert 0.0 < r32 < 0.6 * r16, (r16, r32)
+    # the two plausible misreadings are far from the measurement
+    assert abs(r0 - outlet_reflection_theory(u0, a=1.0 - CS + u0)) > 0.01
+    if u0 != 0.0:
+        assert abs(r0 - outlet_reflection_theory(u0, a=CS + u0)) > 0.01
+
+
+# ---------------------------------------------------------------- rate law
+def _rate(r, dt, T):
+    """k_j = A_j dt T^b_j exp(-Ta_j / T), the paper's law per lattice step."""
+    return r.A * dt * math.pow(T, r.b) * math.exp(-r.Ta / T)
+
+
+def _chem_python(rx, dt, T, Y, cap):
+    """The Arrhenius source of one step as a scalar recurrence: N sub-steps,
+    N = ceil(max_j k_j / 0.1) capped at `cap` (one sub-step when cap is 1),
+    each sub-step's increment scaled by the largest lam <= 1 that keeps every
+    mass fraction >= 0."""
+    ns = len(Y)
+    nsub = 1
+    if cap > 1:
+        kmax = max(_rate(r, dt, T) for r in rx)
+        nsub = int(min(cap, max(1.0, math.ceil(kmax / 0.1))))
+    dT, dY = 0.0, [0.0] * ns
+    for _ in range(nsub):
+        Tc = T + dT
+        Yc = [Y[k] + dY[k] for k in range(ns)]
+        incT, incY = 0.0, [0.0] * ns
+        for r in rx:
+            rr = _rate(r, dt, Tc) / nsub
+            for kr in r.reactants:
+                rr *= Yc[kr]
+            for k in range(ns):
+                incY[k] += r.nu[k] * rr
+            incT += r.q * rr
+        lam = 1.0
+        for k in range(ns):
+            if incY[k] < 0.0 and Yc[k] + incY[k] < 0.0:
+                lam = min(lam, max(Yc[k], 0.0) / (-incY[k]))
+        dT += lam * incT
+        for k in range(ns):
+            dY[k] += lam * incY[k]
+    return dT, dY
+
+
+@pytest.mark.parametrize("b", [-0.7, 0.7])
+def test_rate_with_temperature_exponent(oracle_mod, b):
+    """Sec. II.A: r = A dt T^b exp(-Ta/T) Y_F Y_O with b != 0 (one step, one
+    reaction): the closed form at four temperatures; where r would exceed
+    the fuel (stoichiometric mixture, b = 0.7 at 2400 K) the positivity
+    limiter consumes exactly the fuel and the oxidiser."""
+    prob = W.channel_flame(nx=8, ny=6)
+    prob = prob.replace(reactions=[W.one_step_reaction(b=b)])
+    p = oracle_mod.oracle.make_params(prob)
+    Y = np.array(W.Y_UNBURNT_STOICH)
+    for T in (300.0, 900.0, 1500.0, 1800.0):
+        sT, sY = oracle_mod.single.chemistry(p, T, Y)
+        r = 1e9 * 7.5e-8 * T ** b * math.exp(-15000.0 / T) * Y[0] * Y[1]
+        assert r < Y[0]
+        assert -sY[0] == pytest.approx(r, rel=1e-13)
+        assert sT == pytest.approx(3e4 * r, rel=1e-13)
+    if b > 0:
+        T = 2400.0
+        assert 1e9 * 7.5e-8 * T ** b * math.exp(-15000.0 / T) * Y[0] * Y[1] > Y[0]
+        sT, sY = oracle_mod.single.chemistry(p, T, Y)
+        assert Y[0] + sY[0] == pytest.approx(0.0, abs=1e-17)
+        assert Y[1] + sY[1] == pytest.approx(0.0, abs=1e-16)
+        assert sT == pytest.approx(3e4 * Y[0], rel=1e-14)
+
+
+def test_substeps_converge_with_temperature_exponent(oracle_mod):
+    """Sub-cycling of a stiff rate with b = 0.7 at constant T (no heat
+    release): the source approaches the exact solution of
+    dY_F/dt = -k Y_F Y_O over one step, k = A dt T^b, and more sub-steps get
+    closer (lean mixture, Y_O - 4 Y_F constant)."""
+    prob = W.channel_flame(nx=8, ny=6)
+    prob = prob.replace(reactions=[W.Reaction([0, 1], 2e7, 0.7, 0.0, [-1.0, -4.0, 5.0, 0.0], 0.0)])
+    Y = np.array(W.Y_UNBURNT_LEAN)
+    T = 1500.0
+    k = 2e7 * 7.5e-8 * T ** 0.7
+    F0, O0 = Y[0], Y[1]
+    cc = O0 - 4 * F0
+    F1 = cc * F0 / ((4 * F0 + cc) * math.exp(k * cc) - 4 * F0)
+    errs = []
+    for cap in (100, 400, 1600):
+        p = oracle_mod.oracle.make_params(prob, chem_substeps_max=cap)
+        _, sY = oracle_mod.single.chemistry(p, T, Y)
+        errs.append(abs(Y[0] + sY[0] - F1) / F0)
+    assert errs[2] < 2e-3 and errs[0] > errs[1] > errs[2], errs
+
+
+def test_zero_d_reactor_mechanism_brute_force(oracle_mod):
+    """A homogeneous periodic box with the seeded 9-species / 20-reaction
+    mechanism (b in [-1, 1], sub-cycling capped at 64, positivity limiter)
+    and unequal molar masses: T, Y_k and P_h follow the scalar recurrence
+    T += src_T, Y += src_Y, S += rho cs^2 Lambda, P_h = S + rho cs^2 Lambda / 2
+    (Eqs. 6, 9, 13a at u = 0), the sources from the Python recurrence above."""
+    ns = 9
+    rx = W.synthetic_mechanism(ns, 20, seed=2305)
+    assert any(abs(r.b) > 0.5 for r in rx)
+    Wk = np.array([16.0, 32.0, 28.0, 18.0, 44.0, 30.0, 2.0, 17.0, 28.0])
+    Y0 = np.array([0.05, 0.2, 0.01, 0.02, 0.0, 0.03, 0.001, 0.0, 0.0])
+    Y0[8] = 1.0 - Y0[:8].sum()
+    n = 3
+    shape = (n, n, n)
+    prob = W.Problem(
+        name="reactor9", lattice=27, nx=n, ny=n, nz=n, faces=("periodic",) * 6, face_T=(300.0,) * 6,
+        tau=0.6, prandtl=0.7, dt_phys=1e-7, T_ref=300.0, W_ref=28.0, W=tuple(Wk), reactions=rx,
+        u_in=(0.0, 0.0, 0.0), T_in=300.0, Y_in=tuple(Y0), mask=np.zeros(shape, np.uint8),
+        wall_T=np.full(shape, 300.0), T0=np.full(shape, 1100.0),
+        Y0=np.stack([np.full(shape, v) for v in Y0]), chem_substeps_max=64)
+    o = oracle_mod.Oracle(prob)
+    T, Y, S = 1100.0, list(Y0), 0.0
+    nsubs = []
+    for step in range(25):
+        f = o.fields()
+        kmax = max(_rate(r, 1e-7, T) for r in rx)
+        nsubs.append(min(64, max(1, math.ceil(kmax / 0.1))))
+        srcT, srcY = _chem_python(rx, 1e-7, T, Y, 64)
+        Wm = 1.0 / sum(Y[k] / Wk[k] for k in range(ns))
+        rho = (300.0 / T) * Wm / 28.0
+        Lam = srcT / T + sum((Wm / Wk[k]) * srcY[k] for k in range(ns))
+        Ph = S + 0.5 * rho * CS2 * Lam
+        assert np.allclose(f["T"], T, rtol=1e-12), step
+        for k in range(ns):
+            assert np.allclose(f["Y"][k], Y[k], rtol=1e-10, atol=1e-15), (step, k)
+        assert np.allclose(f["Ph"], Ph, rtol=1e-9, atol=1e-15), step
+        T += srcT
+        Y = [Y[k] + srcY[k] for k in range(ns)]
+        S += rho * CS2 * Lam
+        o.step(1)
+    # sub-cycling active, below and at the cap, and heat released
+    assert max(nsubs) > 1 and T > 1100.0 + 1.0, (nsubs, T)
+
+
+# ------------------------------------------------------------- diagnostics
+def _one_wall_conduction(oracle_mod, H, wall_bottom):
+    """Steady conduction across H fluid rows (periodic in x, 4 columns):
+    one isothermal solid row (the wall whose flux the diagnostic counts) and
+    a Dirichlet face (a velocity inlet at rest, T_in) on the other side, at
+    T1 = 300 K below and T2 = 600 K above.  Starts from the closed form and
+    runs ~2 diffusion times; returns the wall-heat-flux diagnostic."""
+    T1, T2 = 300.0, 600.0
+    nx = 4
+    ny = H + 1
+    shape = (1, ny, nx)
+    mask = np.zeros(shape, np.uint8)
+    wall_T = np.full(shape, 300.0)
+    Y = (0.5, 0.5)
+    if wall_bottom:
+        mask[0, 0, :] = 1
+        wall_T[0, 0, :] = T1
+        y = np.arange(ny) - 0.5  # distance above the bottom wall
+        faces = ("periodic", "periodic", "periodic", "inflow", "periodic", "periodic")
+        T_in = T2
+    else:
+        mask[0, H, :] = 1
+        wall_T[0, H, :] = T2
+        y = np.arange(ny) + 0.5  # distance above the inflow face
+        faces = ("periodic", "periodic", "inflow", "periodic", "periodic", "periodic")
+        T_in = T1
+    T0 = T1 * (T2 / T1) ** (y / H)
+    T0 = np.broadcast_to(T0[None, :, None], shape).copy()
+    T0[mask != 0] = wall_T[mask != 0]
+    prob = W.Problem(
+        name="cond1", lattice=9, nx=nx, ny=ny, nz=1, faces=faces, face_T=(300.0,) * 6,
+        tau=0.6, prandtl=0.7, dt_phys=7.5e-8, T_ref=300.0, W_ref=28.0, W=(28.0, 28.0), reactions=[],
+        u_in=(0.0, 0.0, 0.0), T_in=T_in, Y_in=Y, mask=mask, wall_T=wall_T, T0=T0,
+        Y0=np.stack([np.full(shape, v) for v in Y]))
+    o = oracle_mod.Oracle(prob)
+    alpha = CS2 * 0.1 / 0.7
+    o.step(int(2 * H * H / alpha))
+    return o.diagnostics()["wall_q"], alpha
+
+
+@pytest.mark.parametrize("wall_bottom", [True, False])
+def test_wall_heat_flux_steady_conduction(oracle_mod, wall_bottom):
+    """Sec. IV.A wall heat flux (per wall link 2 alpha rho(T_w, Y)(T - T_w),
+    summed over the links): in steady conduction rho alpha dT/dy is the
+    constant T_ref alpha ln(T2/T1) / H (rho = T_ref / T, W = W_ref), so the
+    wall of nx links carries q = +-nx T_ref alpha ln(T2/T1) / H (into the
+    cold wall, out of the hot one).  The link formula is a one-sided
+    difference across half a cell, so q converges to it at first order:
+    q / q_exact - 1 = C / H + O(H^-2), halving from H = 8 to 16.  A factor
+    error, a sign error, the kinematic viscosity in place of alpha or a unit
+    wall density (the hot wall has rho_B = 1/2) miss the limit."""
+    rr = math.log(2.0)
+    e = {}
+    for H in (8, 16):
+        q, alpha = _one_wall_conduction(oracle_mod, H, wall_bottom)
+        q_exact = 4 * 300.0 * alpha * rr / H * (1.0 if wall_bottom else -1.0)
+        e[H] = q / q_exact - 1.0
+    assert abs(e[16]) < 0.2 / 16, e
+    assert 1.8 < e[8] / e[16] < 2.2, e
+
+
+@pytest.mark.parametrize("wall_bottom", [True, False])
+def test_wall_heat_flux_definition_on_given_fields(oracle_mod, wall_bottom):
+    """The same diagnostic at level 0, on the given initial fields: per
+    link 2 alpha rho(T_w, Y(I)) (T(I) - T_w), rho(T, Y) = T_ref W / (T W_ref)
+    with the wall's temperature and the fluid cell's composition (R20)."""
+    H = 8
+    T1, T2 = 300.0, 600.0
+    alpha = CS2 * 0.1 / 0.7
+    nx, ny = 4, H + 1
+    shape = (1, ny, nx)
+    rng = np.random.default_rng(3)
+    mask = np.zeros(shape, np.uint8)
+    wall_T = np.full(shape, 300.0)
+    row = 0 if wall_bottom else H
+    mask[0, row, :] = 1
+    wall_T[0, row, :] = T1 if wall_bottom else T2
+    T0 = rng.uniform(350.0, 550.0, shape)
+    T0[mask != 0] = wall_T[mask != 0]
+    Wk = (16.0, 32.0)
+    Y0 = np.zeros((2,) + shape)
+    Y0[0] = rng.uniform(0.1, 0.9, shape)
+    Y0[1] = 1.0 - Y0[0]
+    faces = ("periodic", "periodic") + (("periodic", "inflow") if wall_bottom else ("inflow", "periodic")) + (
+        "periodic", "periodic")
+    prob = W.Problem(
+        name="cond0", lattice=9, nx=nx, ny=ny, nz=1, faces=faces, face_T=(300.0,) * 6,
+        tau=0.6, prandtl=0.7, dt_phys=7.5e-8, T_ref=300.0, W_ref=28.0, W=Wk, reactions=[],
+        u_in=(0.0, 0.0, 0.0), T_in=450.0, Y_in=(0.5, 0.5), mask=mask, wall_T=wall_T, T0=T0, Y0=Y0)
+    o = oracle_mod.Oracle(prob)
+    q = o.diagnostics()["wall_q"]
+    fr = 1 if wall_bottom else H - 1
+    Tw = wall_T[0, row, 0]
+    want = 0.0
+    for x in range(nx):
+        Wm = 1.0 / (Y0[0, 0, fr, x] / Wk[0] + Y0[1, 0, fr, x] / Wk[1])
+        rho_b = (300.0 / Tw) * Wm / 28.0
+        want += 2.0 * alpha * rho_b * (T0[0, fr, x] - Tw)
+    assert q == pytest.approx(want, rel=1e-13)
+
+
+def test_flame_position_of_tanh_front(oracle_mod):
+    """Flame position x_f = nx - sum(theta) / (fluid cells per column),
+    theta = (T - T_u)/(T_b - T_u): for the level-0 channel flame,
+    theta = (1 + tanh((x - x0)/4))/2 at the cell indices x, the sum over
+    x = 0..nx-1 equals the integral over [-1/2, nx - 1/2] up to
+    exponentially small terms (Poisson summation), so x_f = x0 + 1/2."""
+    for x0 in (64.0, 100.3):
+        prob = W.channel_flame(nx=256, ny=64, front_x=x0)
+        o = oracle_mod.Oracle(prob)
+        d = o.diagnostics()
+        xf = prob.nx - d["sum_theta"] / (prob.n_fluid / prob.nx)
+        assert abs(xf - (x0 + 0.5)) < 1e-9, (x0, xf)
+        J = o.objective(1, kind="flame_x")
+        assert abs(J - (x0 + 0.5)) < 1e-9, (x0, J)
+
+
+# ------------------------------------------------------- Gaussian heat kernel
+def _gaussian_run(oracle_mod, sig, c=0.25):
+    """A passive species Gaussian Y_0 = 0.1 exp(-r^2/sig^2) + 0.2 in a
+    periodic 8 sig x 8 sig D2Q9 box (equal molar masses: rho uniform, u = 0),
+    run to t = c sig^2 / alpha.  Returns the discrete field, the closed form
+    0.1 (s^2/(s^2 + 4 alpha t)) exp(-r^2/(s^2 + 4 alpha t)) + 0.2 and the
+    spectral solution of explicit Euler without spatial error,
+    (1 - alpha k^2)^n per Fourier mode."""
+    n = 8 * sig
+    alpha = CS2 * 0.1 / 0.7
+    steps = int(round(c * sig * sig / alpha))
+    x = np.arange(n) - n / 2
+    X, Yy = np.meshgrid(x, x, indexing="xy")
+    r2 = X ** 2 + Yy ** 2
+    g0 = 0.1 * np.exp(-r2 / sig ** 2)
+    shape = (1, n, n)
+    Y0 = np.zeros((2,) + shape)
+    Y0[0, 0] = g0 + 0.2
+    Y0[1] = 1.0 - Y0[0]
+    prob = W.Problem(
+        name="gauss", lattice=9, nx=n, ny=n, nz=1, faces=("periodic",) * 6, face_T=(300.0,) * 6,
+        tau=0.6, prandtl=0.7, dt_phys=7.5e-8, T_ref=300.0, W_ref=28.0, W=(28.0, 28.0), reactions=[],
+        u_in=(0.0, 0.0, 0.0), T_in=300.0, Y_in=(0.5, 0.5), mask=np.zeros(shape, np.uint8),
+        wall_T=np.full(shape, 300.0), T0=np.full(shape, 300.0), Y0=Y0)
+    o = oracle_mod.Oracle(prob)
+    o.step(steps)
+    got = o.fields()["Y"][0, 0] - 0.2
+    s2 = sig ** 2 + 4 * alpha * steps
+    exact = 0.1 * (sig ** 2 / s2) * np.exp(-r2 / s2)
+    k = 2 * np.pi * np.fft.fftfreq(n)
+    KX, KY = np.meshgrid(k, k, indexing="xy")
+    spec = np.real(np.fft.ifft2(np.fft.fft2(g0) * (1.0 - alpha * (KX ** 2 + KY ** 2)) ** steps))
+    return got, exact, spec
+
+
+def test_gaussian_heat_kernel(oracle_mod):
+    """Sec. II.D: the heat kernel of a Gaussian passive species.  At a fixed
+    t alpha / sig^2 the error against the closed form falls as sig^-2 (first
+    order in the time step, dt ~ dx^2 at fixed lattice alpha); the error
+    against the time-discrete spectral solution, the spatial error alone,
+    falls as sig^-4 (fourth-order central D2)."""
+    e_tot, e_sp = [], []
+    for sig in (3, 6, 12):
+        got, exact, spec = _gaussian_run(oracle_mod, sig)
+        e_tot.append(np.abs(got - exact).max() / 0.1)
+        e_sp.append(np.abs(got - spec).max() / 0.1)
+    o_tot = [math.log2(e_tot[i] / e_tot[i + 1]) for i in range(2)]
+    o_sp = [math.log2(e_sp[i] / e_sp[i + 1]) for i in range(2)]
+    # second order, approached from below (1.79, 1.93 from sig = 3 to 12)
+    assert 1.7 < o_tot[0] < o_tot[1] < 2.2, (e_tot, o_tot)
+    assert min(o_sp) > 3.6, (e_sp, o_sp)
