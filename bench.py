@@ -1,27 +1,37 @@
 """Benchmark of the coupled LB/FD step on one MI355X.
 
-Default workload: the pseudo 2-D porous burner, D2Q9, 2048 x 512 cells,
-staggered cylinders (radius 20, pitch 64) at 400 K, lean inflow at
-u = 0.02, outflow, 4 species / 1 reaction -- synthetic, seeded inputs built
-by ``paper_2304_05657_amd.workloads.cylinder_burner``.  ``--workload``
-selects another of ``workloads.named`` (``porous``: D3Q27 256^3 sphere
-packing; ``porous_mech``: D3Q27 512 x 256^2, 9 species / 20 reactions).
+Default workload: the 3-D porous medium with the synthetic mechanism,
+D3Q27, 512 x 256 x 256 cells, seeded overlapping spheres of radius 6-12 to
+porosity 0.85, 9 species / 20 reactions with FP64 sub-cycled Arrhenius
+sources (``paper_2304_05657_amd.workloads.porous_3d_mech``) -- the largest
+single-GPU configuration.  ``--workload`` selects another of
+``workloads.named`` (``porous``: D3Q27 256^3, 4 species; ``burner``: D2Q9
+2048 x 512; ``channel``).  ``--also`` adds further workloads to the same
+line (default: the 256^3 packing, FP64 and FP16 populations).
 
-Prints one JSON line.  ``value`` is the FP64 step's throughput in MLUPS
-(all cells of the box per second), with every input resident in HBM before
-the timed region; the mixed-precision forms are reported beside it.
-``roofline`` is for the dominant kernel (the single step launch in 2-D, the
-interior-cell launch in 3-D): algorithmic flops per launch against the
-vector-ALU peak, with the algorithmic bytes per launch (per fluid cell
-2 Q b_pop + 2 (1 + N_sp) b_scalar, plus 1 byte of mask per cell) beside
-them, over the launch duration measured with HIP events on the stream the
-kernel runs on.  ``cpu_baseline`` times the FP64 oracle (test infrastructure) on the
-host cores for a bounded number of steps of the same workload.
+Prints one JSON line.  ``value`` is the first precision's (FP64) step
+throughput in MLUPS (all cells of the box per second) with every input
+resident in HBM before the timed region; the timed region is exactly
+``--steps`` steps with the FP64 conservation / non-finite reductions every
+``--check-every`` steps, bracketed by HIP events on the solver's stream.
+The mixed-precision forms are reported beside it, each with its step HBM
+fraction (algorithmic bytes per step over the step time over 8 TB/s) and
+its error against the FP64 run at a common level.
+
+``roofline`` is for the dominant kernel (the launch with the longest
+duration per step, timed separately with HIP events on the solver's
+stream): its algorithmic flops and bytes per launch over its duration; the
+bound is the one its arithmetic intensity selects against the ridge of the
+FP64/FP32 vector peak (78.6 TFLOP/s without packed FP32) and 8 TB/s, and
+``frac`` is the fraction of that peak; both fractions are given.
+``cpu_baseline`` times the FP64 oracle (test infrastructure) on the host
+cores for one step of a bounded slab of the same box.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -33,50 +43,53 @@ if ROOT not in sys.path:
 METRIC = "MLUPS of coupled LBM+FD step and % HBM roofline, FP64 vs mixed precision"
 HBM_PEAK_GBS = 8000.0
 # Vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
-# Both FP64 and FP32 issue at this rate: packed FP32 is not used.
+# FP64 and FP32 issue at this rate: packed FP32 is not used.
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# sources that fix what the step kernel reads and writes (device code, the
+RIDGE = VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)  # flop per byte
+# sources that fix what the launches read and write (device code, the
 # host-side launch plan and the boundary-cell list)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_05657_amd", "csrc", f)
                   for f in ("lbfd_kernels.h", "lbfd_internal.h", "lbfd_api.hip")]
-# HBM bytes per launch of the dominant kernel on this workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by
-# the same counters on a plain 512 MiB device copy (FETCH_SIZE reads 0.5x,
-# WRITE_SIZE 1.0x the copied bytes), valid for the kernel sources whose
-# SHA-256 (kernel_sha) is given (profiles/traffic_step_kernels_burner_2048x512.md).
-TRAFFIC_WORKLOAD = "cylinder_burner_2048x512"
-TRAFFIC = {
-    "fp64": {"kernel_sha256": "9d1349d250e5324bb86203a936403069b8b3797f96b9c2043a72caf81abe6588", "bytes_per_launch": 267.0e6},
-    "fp32": {"kernel_sha256": "9d1349d250e5324bb86203a936403069b8b3797f96b9c2043a72caf81abe6588", "bytes_per_launch": 168.1e6},
-    "fp16": {"kernel_sha256": "9d1349d250e5324bb86203a936403069b8b3797f96b9c2043a72caf81abe6588", "bytes_per_launch": 125.3e6},
-}
+# HBM bytes per launch of a kernel on a workload, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by the same
+# counters on a plain device copy of known size, valid for the kernel
+# sources whose SHA-256 is given (summaries under profiles/).
+TRAFFIC = {}
 POP_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 SCALAR_BYTES = {"fp64": 8, "fp32": 4, "fp16": 4}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16": "f32"}
+CHEM_PASS_MIN_SPECIES = 5  # mechanisms of more than four species: chemistry launch
+
+
+def chem_pass(prob) -> bool:
+    return prob.n_species >= CHEM_PASS_MIN_SPECIES
+
+
+def step_bytes_per_fluid(prob, precision: str) -> int:
+    """Algorithmic bytes of one fluid cell's step: each population and
+    scalar read and written once."""
+    return 2 * prob.lattice * POP_BYTES[precision] + 2 * (1 + prob.n_species) * SCALAR_BYTES[precision]
 
 
 def algorithmic_bytes(prob, precision: str) -> float:
-    """Minimum HBM bytes of one step: each population and scalar of a fluid
-    cell read and written once, one mask byte per cell."""
-    per_fluid = 2 * prob.lattice * POP_BYTES[precision] + 2 * (1 + prob.n_species) * SCALAR_BYTES[precision]
-    return float(prob.n_fluid * per_fluid + prob.N)
+    """Minimum HBM bytes of one step: per fluid cell 2 Q b_pop +
+    2 (1 + N_sp) b_scalar, plus one mask byte per cell."""
+    return float(prob.n_fluid * step_bytes_per_fluid(prob, precision) + prob.N)
 
 
-def algorithmic_flops_per_cell(prob) -> int:
+def step_flops_per_cell(prob) -> int:
     """Floating-point operations of one coupled step for one fluid cell
-    (FMA = 2, add/mul/div/exp = 1), counted from the minimal form of each
-    operation: moments, density, FD operators with WENO3 on 1 + N_sp scalars
-    per axis, Arrhenius source, Lambda, Euler update, P_h, source Xi and
-    pre-conditioning, per-axis central-moment transforms, relaxation."""
+    without the Arrhenius source (FMA = 2, add/mul/div = 1), counted from
+    the minimal form of each operation: moments, density, FD operators with
+    WENO3 on 1 + N_sp scalars per axis, Lambda, Euler update, P_h, source Xi
+    and pre-conditioning, per-axis central-moment transforms, relaxation."""
     Q = prob.lattice
     D = 2 if Q == 9 else 3
     ns = prob.n_species
-    nrx = len(prob.reactions)
     moments = (Q - 1) + D * (2 * Q // 3 - 1)
     density = 2 * ns + 1
     velocity = 2 + D + 1
     fd = D * (6 + 56 * (1 + ns) + 5 * ns + 1) + (1 + ns)
-    chem = nrx * (10 + 2 * ns)
     lam = 6 * ns + 2
     euler = 2 + 2 * ns
     ph = 3
@@ -85,8 +98,33 @@ def algorithmic_flops_per_cell(prob) -> int:
     transforms = 2 * 12 * D * Q // 3
     relax = 3 * (Q - 1 - D)
     out = 4 * Q + 1
-    return (moments + density + velocity + fd + chem + lam + euler + ph + xi + shift + transforms + relax
-            + out)
+    return moments + density + velocity + fd + lam + euler + ph + xi + shift + transforms + relax + out
+
+
+def chem_flops_per_substep(prob) -> int:
+    """Flops of one chemistry sub-step of one cell (exp and log count 1):
+    per reaction the exponent b ln T - Ta/T (3), exp, prefactor and 1/N (2),
+    the reactant product (n_react), nu_k r for every species (2 N_sp) and
+    q r (2); per sub-step the current state (1 + N_sp), ln T and 1/T (2), the
+    limiter (3 N_sp) and the accumulation (2 + 2 N_sp)."""
+    ns = prob.n_species
+    per_rx = sum(3 + 1 + 2 + len(r.reactants) + 2 * ns + 2 for r in prob.reactions)
+    return per_rx + (1 + ns) + 2 + 3 * ns + 2 + 2 * ns
+
+
+def mean_substeps(prob, T_sample) -> float:
+    """Mean number of chemistry sub-steps over a sample of cell
+    temperatures: N = ceil(max_j k_j / 0.1) capped at chem_substeps_max
+    (1 without sub-cycling)."""
+    import numpy as np
+    if prob.chem_substeps_max <= 1 or not prob.reactions:
+        return 1.0
+    T = np.asarray(T_sample, dtype=np.float64)
+    kmax = np.zeros_like(T)
+    for r in prob.reactions:
+        kmax = np.maximum(kmax, r.A * prob.dt_phys * np.exp(r.b * np.log(T) - r.Ta / T))
+    n = np.clip(np.ceil(kmax / 0.1), 1, prob.chem_substeps_max)
+    return float(n.mean())
 
 
 def kernel_sha() -> str:
@@ -112,130 +150,146 @@ def accuracy(ref: dict, ref_diag: dict, fields: dict, diag: dict, prob) -> dict:
     umag_r = np.sqrt(sum(ref["u"][d][fl] ** 2 for d in range(dims)))
     du = np.sqrt(sum((fields["u"][d][fl] - ref["u"][d][fl]) ** 2 for d in range(dims)))
     dT = np.abs(fields["T"][fl] - ref["T"][fl]) / (prob.T_b - prob.T_u)
-    return {"u_max_rel": float(du.max() / umag_r.max()), "u_rms_rel": float(np.sqrt((du ** 2).mean()) / umag_r.max()),
-            "T_max_rel": float(dT.max()), "T_rms_rel": float(np.sqrt((dT ** 2).mean())),
-            "flame_dx_cells": float(flame_position(diag, prob) - flame_position(ref_diag, prob))}
+    out = {"u_max_rel": float(du.max() / umag_r.max()), "u_rms_rel": float(np.sqrt((du ** 2).mean()) / umag_r.max()),
+           "T_max_rel": float(dT.max()), "T_rms_rel": float(np.sqrt((dT ** 2).mean())),
+           "flame_dx_cells": float(flame_position(diag, prob) - flame_position(ref_diag, prob))}
+    dY = max(float(np.abs(fields["Y"][k][fl] - ref["Y"][k][fl]).max()) for k in range(prob.n_species))
+    out["Y_max_abs"] = dY
+    return out
 
 
-def run_gpu(prob, precision: str, steps: int, warmup: int, links=None, images=None) -> dict:
+def kernel_record(name, cells, ms, flops, nbytes):
+    t = ms * 1e-3
+    tf = flops / t / 1e12
+    gbs = nbytes / t / 1e9
+    intensity = flops / nbytes if nbytes else float("inf")
+    return {"kernel": name, "cells": cells, "ms_per_launch": ms, "flops": flops, "algorithmic_bytes": nbytes,
+            "intensity_flop_per_byte": intensity, "TFLOPs": tf, "alu_frac": tf / VALU_PEAK_TFLOPS, "GBs": gbs,
+            "hbm_frac": gbs / HBM_PEAK_GBS, "bound": "alu" if intensity > RIDGE else "hbm"}
+
+
+def run_gpu(prob, precision: str, steps: int, warmup: int, check_every: int, links=None, images=None):
+    import numpy as np
     import torch
     from paper_2304_05657_amd.lbfd import Solver
 
-    s = Solver(prob, precision=precision, stream=int(torch.cuda.current_stream().cuda_stream))
+    s = Solver(prob, precision=precision, check_every=check_every,
+               stream=int(torch.cuda.current_stream().cuda_stream))
     if links is not None:
         s.set_wall_links(*links)
     if images is not None:
         s.set_image_points(*images)
     s.step(warmup)
     s.sync()
+    # sub-step counts of the chemistry at the level the timed region starts
+    # from (a random sample of fluid cells), for the chemistry's flop count
+    nsub = 1.0
+    if prob.reactions and prob.chem_substeps_max > 1:
+        T = s.fields()["T"][prob.mask == 0]
+        rng = np.random.default_rng(0)
+        nsub = mean_substeps(prob, rng.choice(T, size=min(200000, T.size), replace=False))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ms = s.time_steps(steps)  # HIP events on the solver's stream around exactly `steps` launches
+    ms = s.time_steps(steps)  # HIP events on the solver's stream around exactly `steps` steps
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     s.sync()
-    f = s.fields()
-    import numpy as np
-    fluid = prob.mask == 0
-    ok = bool(np.isfinite(f["T"][fluid]).all() and np.isfinite(f["u"]).all())
     per_step_s = ms * 1e-3 / steps
     nbytes = algorithmic_bytes(prob, precision)
-    achieved = nbytes / per_step_s / 1e9
-    # the dominant kernel alone: interior cells, launches serialised and
-    # bracketed by HIP events on the solver's stream
+    # each launch alone, serialised and bracketed by HIP events on the
+    # solver's stream (after the timed region; the state advances)
     n_fluid, n_boundary = s.cell_counts()
     n_int = n_fluid - n_boundary
-    kms_i, kms_b = s.time_kernels(steps)
-    t_int = kms_i * 1e-3 / steps
-    per_fluid = algorithmic_bytes(prob, precision) - prob.N
-    per_fluid /= prob.n_fluid
-    int_bytes = n_int * per_fluid + prob.N
-    int_flops = n_int * algorithmic_flops_per_cell(prob)
+    kms_i, kms_b, kms_c = s.time_kernels(steps)
     launches = s.step_launches()
-    fpc = algorithmic_flops_per_cell(prob)
-    if launches == 1:
-        # one launch per step: the step kernel is the whole step, and its
-        # average launch duration is the event-timed step above
-        dominant = {"kernel": "step_kernel (one launch per step: boundary and interior cells)",
-                    "cells": n_fluid, "ms_per_launch": ms / steps, "flops": n_fluid * fpc,
-                    "algorithmic_bytes": nbytes}
+    per_fluid = step_bytes_per_fluid(prob, precision)
+    sfl = step_flops_per_cell(prob)
+    cfl = chem_flops_per_substep(prob) * nsub
+    kernels = []
+    if chem_pass(prob):
+        nsc = (1 + prob.n_species) * SCALAR_BYTES[precision]
+        kernels.append(kernel_record("chem_kernel (FP64 Arrhenius source, one thread per cell)", n_fluid,
+                                     kms_c / steps, n_fluid * cfl, float(n_fluid * 2 * nsc + prob.N)))
+        step_fl = sfl
     else:
-        dominant = {"kernel": "step_kernel (interior cells)", "cells": n_int, "ms_per_launch": kms_i / steps,
-                    "flops": int_flops, "algorithmic_bytes": int_bytes}
-    t_dom = dominant["ms_per_launch"] * 1e-3
-    dominant.update({"flops_per_cell": fpc, "TFLOPs": dominant["flops"] / t_dom / 1e12,
-                     "alu_frac": dominant["flops"] / t_dom / 1e12 / VALU_PEAK_TFLOPS,
-                     "GBs": dominant["algorithmic_bytes"] / t_dom / 1e9,
-                     "hbm_frac": dominant["algorithmic_bytes"] / t_dom / 1e9 / HBM_PEAK_GBS})
+        step_fl = sfl + cfl
+    if prob.lattice == 9:
+        kernels.append(kernel_record("step_kernel (one launch: boundary and interior cells)", n_fluid,
+                                     (kms_i + kms_b) / steps, n_fluid * step_fl, float(n_fluid * per_fluid + prob.N)))
+    else:
+        kernels.append(kernel_record("step_kernel (interior cells)", n_int, kms_i / steps, n_int * step_fl,
+                                     float(n_int * per_fluid + prob.N)))
+        kernels.append(kernel_record("step_kernel (boundary cells) + outlet_kernel", n_boundary, kms_b / steps,
+                                     n_boundary * step_fl, float(n_boundary * per_fluid)))
+    dominant = max(kernels, key=lambda k: k["ms_per_launch"])
+    f = s.fields()
+    fluid = prob.mask == 0
+    ok = bool(np.isfinite(f["T"][fluid]).all() and np.isfinite(f["u"]).all())
     out = {
         "precision": precision, "ms_per_step": ms / steps, "wall_ms_per_step": wall * 1e3 / steps,
-        "launches_per_step": launches, "dominant_kernel": dominant,
+        "check_every": check_every, "launches_per_step": launches,
         "mlups": prob.N / per_step_s / 1e6, "mflups": prob.n_fluid / per_step_s / 1e6,
-        "algorithmic_bytes_per_step": nbytes, "achieved_GBs": achieved,
-        "hbm_frac": achieved / HBM_PEAK_GBS, "finite": ok,
-        "interior_kernel": {"cells": n_int, "ms_per_launch": kms_i / steps, "flops_per_cell":
-                            algorithmic_flops_per_cell(prob), "TFLOPs": int_flops / t_int / 1e12,
-                            "alu_frac": int_flops / t_int / 1e12 / VALU_PEAK_TFLOPS,
-                            "algorithmic_bytes": int_bytes, "GBs": int_bytes / t_int / 1e9,
-                            "hbm_frac": int_bytes / t_int / 1e9 / HBM_PEAK_GBS},
-        "boundary_kernel": {"cells": n_boundary, "ms_per_launch": kms_b / steps},
+        "algorithmic_bytes_per_step": nbytes, "achieved_GBs": nbytes / per_step_s / 1e9,
+        "step_hbm_frac": nbytes / per_step_s / 1e9 / HBM_PEAK_GBS, "finite": ok,
+        "chem_mean_substeps": nsub, "kernels": kernels, "dominant_kernel": dominant["kernel"],
     }
     return out, s
 
 
 def run_cpu_baseline(prob, budget_s: float) -> dict:
+    """The FP64 oracle on the host cores, one step from the initial state
+    over a slab of z planes of the same box (every cell of the slab
+    computed, the rest of the box inactive), sized from a one-plane
+    calibration to about `budget_s` seconds; MLUPS = slab cells / time."""
+    import numpy as np
     import oracle
 
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     o = oracle.Oracle(prob, threads=threads)
-    o.step(1)  # first-touch
-    n, t0 = 0, time.perf_counter()
-    while True:
+    plane = prob.nx * prob.ny
+
+    def slab(z0, z1):
+        a = np.zeros((prob.nz, prob.ny, prob.nx), np.uint8)
+        a[z0:z1] = 1
+        return a
+
+    if prob.nz == 1:
+        o.step(1)  # first touch
+        n, t0 = 0, time.perf_counter()
+        while True:
+            o.step(1)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or n >= 200:
+                break
+        cells, what = prob.N * n, "%d FP64 steps of the whole box" % n
+    else:
+        o.set_active(slab(0, 1))
+        t0 = time.perf_counter()
         o.step(1)
-        n += 1
+        t1 = time.perf_counter() - t0
+        k = int(max(1, min(prob.nz - 1, budget_s / max(t1, 1e-3))))
+        o.set_active(slab(1, 1 + k))
+        t0 = time.perf_counter()
+        o.step(1)
         el = time.perf_counter() - t0
-        if el >= budget_s or n >= 200:
-            break
-    # the same oracle on one core, continuing the run, for a quarter of the budget
-    o.set_threads(1)
-    n1, t1 = 0, time.perf_counter()
-    while True:
-        o.step(1)
-        n1 += 1
-        el1 = time.perf_counter() - t1
-        if el1 >= budget_s / 4 or n1 >= 50:
-            break
-    return {"value": prob.N * n / el / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": "%d FP64 steps of the same workload (%s) from its initial state (after one untimed "
-                      "step), %.1f s" % (n, prob.name, el),
-            "single_core": {"value": prob.N * n1 / el1 / 1e6, "unit": "MLUPS", "cores": 1,
-                            "sample": "the next %d steps of that run on one thread, %.1f s" % (n1, el1)}}
-
-
-def roofline(res: dict, precision: str, workload: str) -> dict:
-    """Roofline of the dominant kernel (the one step launch in 2-D, the
-    interior-cell launch in 3-D): it is bound by the vector ALU (instruction
-    issue), so achieved is algorithmic TFLOP/s against the VALU peak; its
-    HBM rate is given beside it."""
-    dk = res["dominant_kernel"]
-    t = TRAFFIC.get(precision) if workload == TRAFFIC_WORKLOAD else None
-    traffic = t["bytes_per_launch"] if t and t.get("kernel_sha256") == kernel_sha() else None
-    return {"kernel": dk["kernel"], "bound": "alu", "achieved": dk["TFLOPs"],
-            "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": dk["alu_frac"], "traffic": traffic,
-            "hbm_achieved_GBs": dk["GBs"], "hbm_peak_GBs": HBM_PEAK_GBS, "hbm_frac": dk["hbm_frac"],
-            "launch_ms": dk["ms_per_launch"], "cells_per_launch": dk["cells"],
-            "algorithmic_flops_per_cell": dk["flops_per_cell"],
-            "algorithmic_bytes_per_launch": dk["algorithmic_bytes"]}
+        cells, what = plane * k, "one FP64 step of the z planes 1..%d (%d cells, the rest of the box inactive)" % (k, plane * k)
+    res = {"value": cells / el / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": "%s of %s, %.1f s" % (what, prob.name, el)}
+    del o
+    return res
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--check-every", type=int, default=10,
+                    help="FP64 reductions (conservation, non-finite check) every this many steps, in the timed region")
     ap.add_argument("--precisions", default="fp64,fp32,fp16",
                     help="first entry is the headline value, the others are reported beside it")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--collision", default="central_moments", choices=("central_moments", "cumulants"),
                     help="relaxation of the orders >= 4: central moments (default) or cumulants")
@@ -247,16 +301,18 @@ def main():
     ap.add_argument("--image-points", action="store_true",
                     help="Shepard-reconstructed image points for the ghost nodes inside the workload's "
                          "cylinders / spheres")
-    ap.add_argument("--workload", default="burner",
-                    help="burner (default), channel, porous or porous_mech")
+    ap.add_argument("--workload", default="porous_mech",
+                    help="porous_mech (default), porous, burner or channel")
     ap.add_argument("--accuracy-steps", type=int, default=None,
                     help="level at which the mixed-precision runs are compared with the FP64 run "
-                         "(0: skip; default 20000 for the burner, 2000 otherwise)")
+                         "(0: skip; default 200 for porous_mech, 20000 for the burner, 5000 for porous)")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also run one plain 512 MiB device copy (calibrates HBM byte counters)")
+                    help="also run one plain 512 MiB device copy (calibrates the HBM byte counters)")
+    ap.add_argument("--also", default="porous:fp64,fp16",
+                    help="further workloads on the same line, 'name:prec,prec;name:...' ('none' for none)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU sharding is a design note, "
+        print("bench.py: this build runs on one GPU only; the multi-GPU slab sharding is a design note, "
               "not an executable path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
@@ -265,36 +321,54 @@ def main():
         sys.exit(3)
     from paper_2304_05657_amd import workloads as W
 
-    prob = W.named(args.workload).replace(collision=args.collision)
-    if args.transport == "mixture_averaged":
-        prob = W.mixture_transport(prob)
-    links = W.wall_links(prob) if args.wall_links else None
-    images = W.image_points(prob) if args.image_points else None
-    if args.accuracy_steps is None:
-        args.accuracy_steps = 20000 if args.workload == "burner" else 2000
+    default_acc = {"porous_mech": 200, "burner": 20000, "porous": 5000, "channel": 2000}
+
+    def bench_workload(name, precs, acc_steps, links_flag, images_flag):
+        prob = W.named(name).replace(collision=args.collision)
+        if args.transport == "mixture_averaged":
+            prob = W.mixture_transport(prob)
+        links = W.wall_links(prob) if links_flag else None
+        images = W.image_points(prob) if images_flag else None
+        results, ref = {}, None
+        for p in precs:
+            print("[bench] %s %s: %d warmup + %d timed steps" % (prob.name, p, args.warmup, args.steps),
+                  file=sys.stderr, flush=True)
+            results[p], solver = run_gpu(prob, p, args.steps, args.warmup, args.check_every, links, images)
+            print("[bench] %s %s: %s" % (prob.name, p, json.dumps(results[p])), file=sys.stderr, flush=True)
+            if acc_steps > 0:
+                # continue the same run (outside the timed region) to the
+                # comparison level and compare with the FP64 run
+                solver.step(max(0, acc_steps - solver.level))
+                solver.sync()
+                f, d = solver.fields(), solver.diagnostics()
+                results[p]["level"] = solver.level
+                results[p]["finite_at_level"] = d["nonfinite"] == 0
+                results[p]["flame_x_cells"] = flame_position(d, prob)
+                if p == "fp64":
+                    ref = (f, d)
+                elif ref is not None:
+                    results[p]["error_vs_fp64"] = accuracy(ref[0], ref[1], f, d, prob)
+                    print("[bench] %s vs fp64 at level %d: %s" % (p, solver.level,
+                          json.dumps(results[p]["error_vs_fp64"])), file=sys.stderr, flush=True)
+            solver.close()
+            del solver
+        return prob, results, links is not None, images is not None
+
     precs = [p.strip() for p in args.precisions.split(",") if p.strip()]
-    results = {}
-    ref = None
-    for p in precs:
-        print("[bench] %s: %d warmup + %d timed steps" % (p, args.warmup, args.steps), file=sys.stderr, flush=True)
-        results[p], solver = run_gpu(prob, p, args.steps, args.warmup, links, images)
-        print("[bench] %s: %s" % (p, json.dumps(results[p])), file=sys.stderr, flush=True)
-        if args.accuracy_steps > 0:
-            # continue the same run (outside the timed region) to the
-            # comparison level and compare with the FP64 run
-            solver.step(max(0, args.accuracy_steps - solver.level))
-            solver.sync()
-            f, d = solver.fields(), solver.diagnostics()
-            results[p]["level"] = solver.level
-            results[p]["finite_at_level"] = d["nonfinite"] == 0
-            results[p]["flame_x_cells"] = flame_position(d, prob)
-            if p == "fp64":
-                ref = (f, d)
-            elif ref is not None:
-                results[p]["error_vs_fp64"] = accuracy(ref[0], ref[1], f, d, prob)
-                print("[bench] %s vs fp64 at level %d: %s" % (p, solver.level, json.dumps(results[p]["error_vs_fp64"])),
-                      file=sys.stderr, flush=True)
-        solver.close()
+    acc = args.accuracy_steps if args.accuracy_steps is not None else default_acc.get(args.workload, 2000)
+    prob, results, has_links, has_images = bench_workload(args.workload, precs, acc, args.wall_links,
+                                                          args.image_points)
+    others = {}
+    for item in [x for x in args.also.split(";") if x.strip() and x.strip() not in ("none", "''", '""')]:
+        name, _, pl = item.partition(":")
+        ops = [p.strip() for p in (pl or "fp64").split(",") if p.strip()]
+        oprob, ores, _, _ = bench_workload(name.strip(), ops, default_acc.get(name.strip(), 2000), False, False)
+        others[oprob.name] = {"lattice": "D2Q9" if oprob.lattice == 9 else "D3Q27", "cells": oprob.N,
+                              "fluid_cells": oprob.n_fluid, "species": oprob.n_species,
+                              "reactions": len(oprob.reactions),
+                              "precisions": {p: {k: v for k, v in r.items() if k != "precision"}
+                                             for p, r in ores.items()}}
+        del oprob
     if args.copy_probe:
         src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -305,6 +379,21 @@ def main():
               file=sys.stderr, flush=True)
         del src, dst
     head = results[precs[0]]
+    dk = max(head["kernels"], key=lambda k: k["ms_per_launch"])
+    bound = dk["bound"]
+    tkey = (prob.name, precs[0], dk["kernel"].split(" ")[0])
+    t = TRAFFIC.get(tkey)
+    traffic = t["bytes_per_launch"] if t and t.get("kernel_sha256") == kernel_sha() else None
+    roof = {"kernel": dk["kernel"], "bound": bound,
+            "achieved": dk["TFLOPs"] if bound == "alu" else dk["GBs"],
+            "peak": VALU_PEAK_TFLOPS if bound == "alu" else HBM_PEAK_GBS,
+            "unit": "TFLOP/s" if bound == "alu" else "GB/s",
+            "frac": dk["alu_frac"] if bound == "alu" else dk["hbm_frac"],
+            "traffic": traffic, "intensity_flop_per_byte": dk["intensity_flop_per_byte"], "ridge_flop_per_byte": RIDGE,
+            "alu_frac": dk["alu_frac"], "hbm_frac": dk["hbm_frac"], "launch_ms": dk["ms_per_launch"],
+            "cells_per_launch": dk["cells"], "algorithmic_flops_per_launch": dk["flops"],
+            "algorithmic_bytes_per_launch": dk["algorithmic_bytes"],
+            "step_hbm_frac": head["step_hbm_frac"]}
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, %.0f s budget)" % args.cpu_seconds, file=sys.stderr, flush=True)
@@ -322,13 +411,15 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[precs[0]],
         "data": "synthetic",
-        "config": {"workload": prob.name, "lattice": "D2Q9" if prob.lattice == 9 else "D3Q27", "cells": prob.N, "fluid_cells": prob.n_fluid,
-                   "species": prob.n_species, "reactions": len(prob.reactions), "storage": precs[0],
-                   "collision": prob.collision, "transport": prob.transport, "wall_links": links is not None,
-                   "image_points": images is not None},
-        "roofline": roofline(head, precs[0], prob.name),
+        "config": {"workload": prob.name, "lattice": "D2Q9" if prob.lattice == 9 else "D3Q27", "cells": prob.N,
+                   "fluid_cells": prob.n_fluid, "species": prob.n_species, "reactions": len(prob.reactions),
+                   "chem_substeps_max": prob.chem_substeps_max, "storage": precs[0],
+                   "check_every": args.check_every, "collision": prob.collision, "transport": prob.transport,
+                   "wall_links": has_links, "image_points": has_images},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "precisions": {p: {k: v for k, v in r.items() if k != "precision"} for p, r in results.items()},
+        "other_workloads": others,
     }
     print(json.dumps(line), flush=True)
 

@@ -194,9 +194,15 @@ int lbfd_init_dev(const lbfd_params *p, const uint8_t *mask, const double *wall_
                   const double *T0, const double *Y0, const double *u0,
                   const double *Ph0, void *hip_stream, lbfd_ctx **out);
 
-/* Queue nsteps coupled steps (asynchronous).  Every check_every levels
- * the step also reduces the diagnostics; a non-finite value is reported
- * by the next lbfd_sync. */
+/* Queue nsteps coupled steps (asynchronous).  One step n -> n+1, every
+ * term at level n: streaming of the lattice-Boltzmann equation with the
+ * source Xi_i (Sec. II.B, Eqs. 8-9) and the boundary rules of Sec. III.A
+ * (Eqs. 28, 31, 32), the central-moment collision (Sec. II.C, Eqs. 14, 19,
+ * 21), the finite-difference advection-diffusion-reaction terms of T and
+ * Y_k with ghost nodes (Sec. II.D, Eq. 26; Sec. III.B, Eq. 34), the
+ * coupling term Lambda (Eq. 6) and the explicit Euler update of T and Y_k
+ * (Sec. II.D).  Every check_every levels the step also reduces the
+ * diagnostics; a non-finite value is reported by the next lbfd_sync. */
 int lbfd_step(lbfd_ctx *c, int64_t nsteps);
 
 /* Wait for queued work.  Returns LBFD_ENONFINITE if a periodic check saw
@@ -220,7 +226,12 @@ int lbfd_read_fields(lbfd_ctx *c, double *rho, double *u, double *T,
 int lbfd_read_fields_dev(lbfd_ctx *c, double *rho, double *u, double *T,
                          double *Y, double *Ph);
 
-/* Diagnostics of the current level (synchronous). */
+/* Diagnostics of the current level (synchronous): the sums of lbfd_diag.
+ * The wall heat flux is the conductive flux through the ghost-node walls of
+ * Sec. III.B (Eq. 34) that the heat-loss study of Sec. IV.A measures; the
+ * progress-variable sum gives the flame position followed in Secs. IV.A
+ * and IV.C (flame position = nx - sum_theta / (n_fluid / nx)); the fuel rate
+ * gives the consumption speed of Sec. IV.C. */
 int lbfd_diagnostics(lbfd_ctx *c, lbfd_diag *d);
 
 /* Curved walls (interpolated bounce-back, the post-collision form of the
@@ -283,7 +294,11 @@ int lbfd_set_inflow(lbfd_ctx *c, int face, const double *u);
 int lbfd_hold_flame(lbfd_ctx *c, int64_t nsteps, int every, double x_target, double gain, double *u_mean,
                     double *x_flame);
 
-/* Replace the wall temperature of isothermal solid cells (host [N]). */
+/* Replace the wall temperature of isothermal solid cells (host [N]): the
+ * T_w of the Dirichlet ghost values 2 T_w - T(I) of Sec. III.B (Eq. 34) and
+ * of the wall density rho(T_w, Y(I)) of the density ghosts; entries of
+ * other cells are ignored.  Takes effect from the next step (the queued
+ * work is waited for first). */
 int lbfd_set_wall_temperature(lbfd_ctx *c, const double *wall_T);
 
 /* Checkpoint: the whole state (populations, scalars, outlet buffer,
@@ -323,8 +338,11 @@ int lbfd_set_objective(lbfd_ctx *c, int kind, int64_t t_begin, int64_t t_end);
  * lbfd_adjoint). */
 int lbfd_objective(lbfd_ctx *c, int64_t nsteps, double *J);
 
-/* Discrete adjoint of the FP64 step (the paper's differentiation use of the
- * solver).  Starting from the current level L, runs nsteps steps and
+/* Discrete adjoint of the FP64 step.  Not a method of the paper: the paper
+ * has no differentiation; this entry point serves gradient-based uses of
+ * the step (sensitivities of wall heat flux and flame position with respect
+ * to wall temperatures and Arrhenius parameters).  Starting from the
+ * current level L, runs nsteps steps and
  * computes the objective J selected by lbfd_set_objective and its exact
  * derivatives with respect to the
  * wall temperature of every isothermal solid cell (dJ_dwallT [N], host, may
@@ -345,11 +363,15 @@ int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwall
 int lbfd_adjoint_dev(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwallT, double *dJ_dA,
                      double *dJ_dTa);
 
-/* Per-part timing: queue nsteps steps with the interior-cell part and the
- * boundary-cell part launched separately on the context stream, each
- * bracketed by HIP events; wait and return their summed durations in
- * milliseconds.  The state advances exactly as with lbfd_step. */
-int lbfd_time_kernels(lbfd_ctx *c, int64_t nsteps, double *ms_interior, double *ms_boundary);
+/* Per-part timing: queue nsteps steps with their parts launched separately
+ * on the context stream, each bracketed by HIP events -- the chemistry
+ * launch (mechanisms of more than four species; 0 otherwise), the
+ * interior-cell part, and the boundary-cell part (with the image-point and
+ * outlet launches) -- wait and return their summed durations in
+ * milliseconds (ms_chemistry may be NULL).  The state advances exactly as
+ * with lbfd_step. */
+int lbfd_time_kernels(lbfd_ctx *c, int64_t nsteps, double *ms_interior, double *ms_boundary,
+                      double *ms_chemistry);
 
 /* Cell counts of the context's geometry: fluid cells, and the fluid cells
  * handled by the boundary-cell path (every other fluid cell is interior: all
@@ -360,7 +382,9 @@ int lbfd_cell_counts(const lbfd_ctx *c, int64_t *n_fluid, int64_t *n_boundary);
 /* Kernel launches queued by one lbfd_step level without diagnostics: 1 for
  * D2Q9 (one launch covers boundary and interior cells); for D3Q27 the
  * boundary cells, the interior cells and, with an outflow face, the outlet
- * update (Eq. 32) are separate launches.  Negative on a null context. */
+ * update (Eq. 32) are separate launches; plus one for the chemistry launch
+ * of a mechanism of more than four species, and two for image points.
+ * Negative on a null context. */
 int lbfd_step_launches(const lbfd_ctx *c);
 
 void lbfd_destroy(lbfd_ctx *c);

@@ -42,11 +42,24 @@ def _obj(src: str) -> str:
     return os.path.join(BUILD, rel + ".o")
 
 
+def _asm(src: str) -> str:
+    """The device assembly the compile of src leaves beside its object."""
+    base = os.path.splitext(os.path.basename(src))[0]
+    return os.path.join(BUILD, base + "-hip-amdgcn-amd-amdhsa-gfx950.s")
+
+
 def _compile(src: str) -> tuple[str, int, str]:
     obj = _obj(src)
     tmp = obj + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", tmp]
+    # -save-temps=obj keeps the device assembly (for the check below) in
+    # the build folder; the other intermediate files are removed
+    cmd = [HIPCC] + FLAGS + ["-save-temps=obj", "-c", src, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
+    base = os.path.splitext(os.path.basename(src))[0]
+    for f in glob.glob(os.path.join(BUILD, base + "-hip-*")) + glob.glob(os.path.join(BUILD, base + "-host-*")) + \
+            glob.glob(os.path.join(BUILD, base + ".hip-hip-*")):
+        if f != _asm(src):
+            os.remove(f)
     if r.returncode == 0:
         os.replace(tmp, obj)
     out = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
@@ -76,6 +89,21 @@ def build(force: bool = False, jobs: int | None = None, verbose: bool = True) ->
                     failed.append(src)
     if failed:
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
+    # every kernel's assembly is checked for copies that only some lanes of
+    # a divergent branch receive (a miscompilation of the register
+    # allocator; see isa_check.py); a library holding one is not linked
+    from . import isa_check
+    missing = [s for s in sources() if not os.path.exists(_asm(s))]
+    if missing:
+        raise RuntimeError("device assembly missing for: " + ", ".join(missing) + " (rebuild with force=True)")
+    bad = isa_check.check([_asm(s) for s in sources()])
+    if bad:
+        for path, name, ins in bad[:20]:
+            print("[lbfd build] %s: %s: %s" % (os.path.basename(path), name, ins), flush=True)
+        raise RuntimeError("%d one-sided register copies in divergent code (isa_check.py); the library is not "
+                           "linked" % len(bad))
+    if verbose:
+        print("[lbfd build] assembly of %d units checked: no one-sided copies" % len(sources()), flush=True)
     objs = [_obj(s) for s in sources()]
     if force or todo or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(o) for o in objs):
         tmp = LIB + ".tmp%d" % os.getpid()

@@ -53,12 +53,13 @@ __device__ inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
 __device__ inline bool operator>(Dual a, Dual b) { return a.v > b.v; }
 __device__ inline bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
 __device__ inline bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
+// the exponential of the forward chemistry (exp_tab)
 __device__ inline Dual dexp(Dual a)
 {
-    const double e = exp(a.v);
+    const double e = exp_tab(a.v, kExp2Tab);
     return Dual(e, e * a.d);
 }
-__device__ inline double dexp(double a) { return exp(a); }
+__device__ inline double dexp(double a) { return exp_tab(a, kExp2Tab); }
 __device__ inline Dual dlog(Dual a) { return Dual(log(a.v), a.d * rcp(a.v)); }
 __device__ inline double dlog(double a) { return log(a); }
 __device__ inline double val(Dual a) { return a.v; }
@@ -278,13 +279,12 @@ __device__ void cell_eval(const KParams &P, const CellIn<Q, NSP> &in, int seed, 
         // rate coefficients k_j = A_j dt exp(b_j ln T - Ta_j / T), ln T and
         // 1/T shared by the reactions, as in the forward chemistry()
         const A Tc0 = T[0];
-        bool anyb = false;
-        for (int j = 0; j < P.n_rx; ++j) anyb |= P.rx[j].b != 0.0;
+        const bool anyb = P.chem_anyb != 0;
         int nsub = 1;
         if (P.chem_substeps_max > 1) {
             const double lnT = anyb ? log(val(Tc0)) : 0.0, invT = rcp(val(Tc0));
             double kmax = 0.0;
-            for (int j = 0; j < P.n_rx; ++j) kmax = fmax(kmax, rate_coeff_l(P.rx[j], P.dt_phys, lnT, invT));
+            for (int j = 0; j < P.n_rx; ++j) kmax = fmax(kmax, rate_coeff_l(P.rxk[j], lnT, invT, kExp2Tab));
             const double want = ceil(kmax / 0.1);
             nsub = want < 1.0 ? 1 : want > (double)P.chem_substeps_max ? P.chem_substeps_max : (int)want;
         }

@@ -76,6 +76,7 @@ struct lbfd_ctx {
     uint8_t *code = nullptr;
     int *boundary = nullptr;
     long long n_boundary = 0;
+    int *fluid = nullptr;               // fluid-cell list (contexts with a chemistry launch)
     std::vector<int> boundary_host;
     std::vector<uint8_t> mask_host;
     std::vector<double> wall_T_host;
@@ -108,6 +109,7 @@ struct lbfd_ctx {
     double *diag_dev = nullptr;
     long long *bad_dev = nullptr;
     lbfd_reaction *rx_dev = nullptr;
+    ChemRx *rxk_dev = nullptr;
     int64_t level = 0;
     dim3 grid, block;
     KParams base;
@@ -119,7 +121,7 @@ static void free_ctx(lbfd_ctx *c)
     void *ptrs[] = {c->pop[0], c->pop[1], c->sc[0], c->sc[1], c->mask, c->code, c->boundary, c->bsrc, c->bpt, c->bwk,
                     c->btw, c->wall_T, c->outlet, c->outlet_un, c->inflow_u, c->inflow_du, c->bq,
                     c->bimg, c->img_rng, c->img_idx, c->img_w, c->img_val, c->sup_idx, c->sup_val,
-                    c->fields, c->partials, c->diag_dev, c->bad_dev, c->rx_dev};
+                    c->fields, c->partials, c->diag_dev, c->bad_dev, c->rx_dev, c->rxk_dev, c->fluid};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete c;
@@ -392,6 +394,8 @@ static KParams make_kparams(const lbfd_ctx *c)
     k.code = c->code;
     k.boundary = c->boundary;
     k.n_boundary = c->n_boundary;
+    k.fluid = c->fluid;
+    k.n_fluid = c->n_fluid;
     k.boundary_blocks = c->nblocks - c->nblocks_interior;
     k.interior_blocks = c->nblocks_interior;
     k.block_begin = 0;
@@ -419,6 +423,7 @@ static KParams make_kparams(const lbfd_ctx *c)
     k.fields = c->fields;
     k.partials = c->partials;
     k.rx = c->rx_dev;
+    k.rxk = c->rxk_dev;
     k.n_rx = p.n_reactions;
     k.chem_substeps_max = p.chem_substeps_max;
     k.omega2 = 1.0 / p.tau;
@@ -445,6 +450,34 @@ static KParams make_kparams(const lbfd_ctx *c)
         k.cpk[s] = p.transport == LBFD_MIXTURE_AVERAGED ? p.cp[s] : 1.0;
     }
     return k;
+}
+
+// The reactions of the context on the device, in both forms the kernels
+// read (the ABI struct for the adjoint, ChemRx for the chemistry: A dt_phys
+// formed once here), and whether a temperature exponent is in use.
+static int upload_reactions(lbfd_ctx *c)
+{
+    const lbfd_params &p = c->p;
+    ChemRx h[LBFD_MAX_REACTIONS];
+    memset(h, 0, sizeof(h));
+    int anyb = 0;
+    for (int j = 0; j < p.n_reactions; ++j) {
+        const lbfd_reaction &r = c->rx[j];
+        h[j].adt = r.A * p.dt_phys;
+        h[j].b = r.b;
+        h[j].ta = r.Ta;
+        h[j].q = r.q_over_cp;
+        h[j].n_react = r.n_react;
+        for (int m = 0; m < 4; ++m) h[j].react[m] = m < r.n_react ? r.react[m] : 0;
+        for (int k = 0; k < c->nsp; ++k) h[j].nu[k] = r.nu_mass[k];
+        anyb |= r.b != 0.0;
+    }
+    if (p.n_reactions > 0) {
+        HIP_TRY(hipMemcpy(c->rx_dev, c->rx, sizeof(lbfd_reaction) * p.n_reactions, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->rxk_dev, h, sizeof(ChemRx) * p.n_reactions, hipMemcpyHostToDevice));
+    }
+    c->base.chem_anyb = anyb;
+    return LBFD_OK;
 }
 
 // Convert and upload a double host array into a device scalar buffer.
@@ -541,6 +574,8 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     ALLOC(c->diag_dev, kNDiag * sizeof(double));
     ALLOC(c->bad_dev, sizeof(long long));
     ALLOC(c->rx_dev, sizeof(lbfd_reaction) * LBFD_MAX_REACTIONS);
+    ALLOC(c->rxk_dev, sizeof(ChemRx) * LBFD_MAX_REACTIONS);
+    if (chem_pass(c->nsp)) ALLOC(c->fluid, sizeof(int) * (size_t)c->n_fluid);
 #undef ALLOC
 
 #define TRY_OR_FREE(expr)            \
@@ -582,16 +617,22 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
         c->wall_T_host.assign(N, 300.0);
     HIP_OR_FREE(hipMemcpy(c->wall_T, c->wall_T_host.data(), N * sizeof(double), hipMemcpyHostToDevice));
     c->boundary_host = boundary;
+    if (c->fluid) {
+        std::vector<int> fl;
+        fl.reserve((size_t)c->n_fluid);
+        for (long long i = 0; i < N; ++i)
+            if (mask[i] == LBFD_FLUID) fl.push_back((int)i);
+        HIP_OR_FREE(hipMemcpy(c->fluid, fl.data(), fl.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
     TRY_OR_FREE(build_descriptors(c));
     long long minus1 = -1;
     HIP_OR_FREE(hipMemcpy(c->bad_dev, &minus1, sizeof(minus1), hipMemcpyHostToDevice));
-    if (p->n_reactions > 0)
-        HIP_OR_FREE(hipMemcpy(c->rx_dev, c->rx, sizeof(lbfd_reaction) * p->n_reactions, hipMemcpyHostToDevice));
     TRY_OR_FREE(upload_scalars(c, c->sc[0], T0, Y0));
     TRY_OR_FREE(upload_scalars(c, c->sc[1], T0, Y0));
 
     c->streams.main = c->stream;
     c->base = make_kparams(c);
+    TRY_OR_FREE(upload_reactions(c));
     double *u0_dev = nullptr, *Ph0_dev = nullptr;
     if (u0) {
         HIP_OR_FREE(hipMalloc((void **)&u0_dev, (size_t)c->D * N * sizeof(double)));
@@ -701,6 +742,9 @@ static int evaluate(lbfd_ctx *c)
     KParams k = c->base;
     k.pop_in = c->pop[c->cur];
     k.sc_in = c->sc[c->cur];
+    // the next level's scalar buffer holds the chemistry launch's source
+    // (it is overwritten by the next step)
+    k.sc_out = c->sc[1 - c->cur];
     HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeFields, k, c->streams));
     HIP_TRY(launch_finalize(c->partials, c->nblocks, c->diag_dev, nullptr, c->level, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1198,44 +1242,42 @@ int lbfd_time_steps(lbfd_ctx *c, int64_t nsteps, double *ms)
     return rc;
 }
 
-int lbfd_time_kernels(lbfd_ctx *c, int64_t nsteps, double *ms_interior, double *ms_boundary)
+int lbfd_time_kernels(lbfd_ctx *c, int64_t nsteps, double *ms_interior, double *ms_boundary,
+                      double *ms_chemistry)
 {
     if (!c || !ms_interior || !ms_boundary || nsteps < 0) return fail(LBFD_EINVAL, "bad arguments");
-    hipEvent_t e0, e1, e2;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventCreate(&e2));
-    double ti = 0.0, tb = 0.0;
-    int rc = LBFD_OK;
-    for (int64_t s = 0; s < nsteps && rc == LBFD_OK; ++s) {
+    hipEvent_t ev[4];
+    for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&ev[i]));
+    double ti = 0.0, tb = 0.0, tc = 0.0;
+    for (int64_t s = 0; s < nsteps; ++s) {
         KParams k = c->base;
         k.pop_in = c->pop[c->cur];
         k.pop_out = c->pop[1 - c->cur];
         k.sc_in = c->sc[c->cur];
         k.sc_out = c->sc[1 - c->cur];
         Streams st = c->streams;
-        HIP_TRY(hipEventRecord(e0, c->stream));
-        st.part = 1;
-        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStep, k, st));
-        HIP_TRY(hipEventRecord(e1, c->stream));
-        st.part = 2;
-        HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStep, k, st));
-        HIP_TRY(hipEventRecord(e2, c->stream));
-        HIP_TRY(hipEventSynchronize(e2));
-        float a = 0.0f, b = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&a, e0, e1));
-        HIP_TRY(hipEventElapsedTime(&b, e1, e2));
-        ti += a;
-        tb += b;
+        // chemistry launch (if any) first: the step reads its source
+        const int parts[3] = {3, 1, 2};
+        HIP_TRY(hipEventRecord(ev[0], c->stream));
+        for (int i = 0; i < 3; ++i) {
+            st.part = parts[i];
+            HIP_TRY(launch_step(c->Q, c->nsp, c->prec, kModeStep, k, st));
+            HIP_TRY(hipEventRecord(ev[i + 1], c->stream));
+        }
+        HIP_TRY(hipEventSynchronize(ev[3]));
+        float t[3] = {0.0f, 0.0f, 0.0f};
+        for (int i = 0; i < 3; ++i) HIP_TRY(hipEventElapsedTime(&t[i], ev[i], ev[i + 1]));
+        tc += t[0];
+        ti += t[1];
+        tb += t[2];
         c->cur ^= 1;
         c->level += 1;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipEventDestroy(e2);
+    for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
     *ms_interior = ti;
     *ms_boundary = tb;
-    return rc;
+    if (ms_chemistry) *ms_chemistry = tc;
+    return LBFD_OK;
 }
 
 int lbfd_set_reaction(lbfd_ctx *c, int j, double A, double b, double Ta)
@@ -1245,8 +1287,7 @@ int lbfd_set_reaction(lbfd_ctx *c, int j, double A, double b, double Ta)
     c->rx[j].A = A;
     c->rx[j].b = b;
     c->rx[j].Ta = Ta;
-    HIP_TRY(hipMemcpy(c->rx_dev + j, &c->rx[j], sizeof(lbfd_reaction), hipMemcpyHostToDevice));
-    return LBFD_OK;
+    return upload_reactions(c);
 }
 
 namespace {
@@ -1324,7 +1365,9 @@ int lbfd_objective(lbfd_ctx *c, int64_t nsteps, double *J)
         c->cur ^= 1;
         c->level += 1;
     }
-    if (e == hipSuccess) e = hipMemcpy(J, Jd, sizeof(double), hipMemcpyDeviceToHost);
+    // the context stream may be a non-blocking one: copy on it and wait
+    if (e == hipSuccess) e = hipMemcpyAsync(J, Jd, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(Jd);
     if (e != hipSuccess) return fail(LBFD_EDEVICE, "objective: %s", hipGetErrorString(e));
     return LBFD_OK;
@@ -1457,7 +1500,7 @@ int lbfd_cell_counts(const lbfd_ctx *c, int64_t *n_fluid, int64_t *n_boundary)
 int lbfd_step_launches(const lbfd_ctx *c)
 {
     if (!c) return fail(LBFD_EINVAL, "null context");
-    return step_launches(c->Q, c->base);
+    return step_launches(c->Q, c->nsp, c->base);
 }
 
 void lbfd_destroy(lbfd_ctx *c)

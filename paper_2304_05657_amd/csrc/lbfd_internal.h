@@ -29,6 +29,21 @@ enum { kSrcBounce = -1, kSrcInflow = -2, kSrcOutlet = -3 };
 // Kind of what a neighbour coordinate lands on.
 enum NbKind { kFluid = 0, kIso = 1, kAdia = 2, kInflow = 3, kOutflow = 4 };
 
+// One reaction as the chemistry reads it: A dt_phys (the rate coefficient's
+// prefactor per lattice step), b, Ta, the temperature rise q_over_cp, the
+// reactant indices and the mass coefficients.
+struct ChemRx {
+    double adt, b, ta, q;
+    int n_react, react[4];
+    double nu[kMaxSp];
+};
+
+// Mechanisms of more than four species take their FP64 Arrhenius source in
+// a launch of its own ahead of the step (chem_kernel), which leaves it in
+// the step's output scalars for the step kernel to read back; smaller ones
+// evaluate it inside the step kernel.
+constexpr bool chem_pass(int nsp) { return nsp > 4; }
+
 // Everything a step kernel reads; passed by value (kernarg segment, read
 // through the scalar cache).
 struct KParams {
@@ -40,6 +55,8 @@ struct KParams {
     const uint8_t *code;        // CellCode per cell
     const int *boundary;        // boundary fluid cells, increasing index
     long long n_boundary;
+    const int *fluid;           // every fluid cell, increasing index (chemistry launch)
+    long long n_fluid;
     // per boundary cell t (structure of arrays, stride n_boundary):
     const int *bsrc;            // [Q][nb] pull source index, or kSrcBounce / kSrcInflow / kSrcOutlet
     const int *bpt;             // [3*4][nb] finite-difference point (or ghost image) index, axis-major, m = -2,-1,1,2
@@ -73,7 +90,9 @@ struct KParams {
     double *fields;       // [5][N]: rho, u_x, u_y, u_z, P_h  (fields mode)
     double *partials;     // [interior_blocks + boundary_blocks][kNDiag]  (diagnostics modes)
     const lbfd_reaction *rx;
+    const ChemRx *rxk;  // the same reactions as the chemistry reads them
     int n_rx;
+    int chem_anyb;      // some reaction has a temperature exponent b != 0
     int chem_substeps_max;
     double omega2, omega3, omega4, alpha;
     double dt_phys;
@@ -88,7 +107,9 @@ struct KParams {
     double cpk[kMaxSp];  // c_pk / c_p,ref (mixture-averaged transport)
 };
 
-// Kernel modes.
+// Launch modes: the step; the step with the reductions of the level; the
+// evaluation of the current level (fields and reductions, nothing of the
+// state written).
 enum { kModeStep = 0, kModeStepDiag = 1, kModeFields = 2 };
 
 // D2Q9 steps are one launch over boundary blocks and interior tiles;
@@ -96,16 +117,18 @@ enum { kModeStep = 0, kModeStepDiag = 1, kModeFields = 2 };
 // the 3-D interior tiles), plus the outlet update with an outflow face.
 constexpr bool fused_step(int Q) { return Q == 9; }
 
-inline int step_launches(int Q, const KParams &kp)
+inline int step_launches(int Q, int nsp, const KParams &kp)
 {
     const int images = kp.bimg != nullptr && kp.n_img > 0 ? 2 : 0;
-    if (fused_step(Q)) return (kp.boundary_blocks + kp.interior_blocks > 0 ? 1 : 0) + images;
+    const int chem = chem_pass(nsp) ? 1 : 0;
+    if (fused_step(Q)) return (kp.boundary_blocks + kp.interior_blocks > 0 ? 1 : 0) + images + chem;
     const bool outlet = kp.n_boundary > 0 && (kp.face[0] == LBFD_FACE_OUTFLOW || kp.face[1] == LBFD_FACE_OUTFLOW);
-    return (kp.boundary_blocks > 0) + (kp.interior_blocks > 0) + (outlet ? 1 : 0) + images;
+    return (kp.boundary_blocks > 0) + (kp.interior_blocks > 0) + (outlet ? 1 : 0) + images + chem;
 }
 
-// Where a step is launched: the context stream, and which blocks (0: all,
-// 1: interior tiles only, 2: boundary blocks only -- for per-part timing).
+// Where a step is launched: the context stream, and which launches (0: all;
+// for per-part timing 1: interior tiles only, 2: boundary blocks, image
+// points and outlet, 3: the chemistry launch only).
 struct Streams {
     hipStream_t main;
     int part;

@@ -291,8 +291,42 @@ __device__ __forceinline__ void ghost(const KParams &P, const Nb &w, const Pt<NS
     o.rho = iso || inf ? (C)2 * rho_b - img.rho : img.rho;
 }
 
+// Population I or its opposite (same lattice weight, hence the same scale
+// in the mixed forms) of cell idx, the direction chosen per lane.
+template <int Q, int PREC, int I>
+__device__ __forceinline__ typename Prec<PREC>::calc pop_load_pair(const void *base, long long N, bool opp,
+                                                                   uint32_t idx)
+{
+    using T = typename Prec<PREC>::pop;
+    constexpr int OPP = Q - 1 - I;
+    static_assert(Lat<Q>::w(I) == Lat<Q>::w(OPP), "opposite directions share a weight");
+    const size_t dir = opp ? (size_t)OPP : (size_t)I;
+    const char *b = (const char *)base + dir * (size_t)N * sizeof(T);
+    const uint32_t off = idx * (uint32_t)sizeof(T);
+    if constexpr (PREC == LBFD_FP64) {
+        return ldo<double>(b, off);
+    } else if constexpr (PREC == LBFD_MIXED_FP32) {
+        constexpr float s = (float)(Lat<Q>::w(I) * kCs2);
+        return ldo<float>(b, off) * s;
+    } else {
+        constexpr float s = (float)(Lat<Q>::w(I) * kCs2);
+        return __half2float(ldo<__half>(b, off)) * s;
+    }
+}
+
+// A zero that a lane loads in place of an entry it does not need.
+static __constant__ double kZeroEntry[1] = {0.0};
+
 // Boundary cells: pull and stencil from the per-cell descriptors built at
 // init (same rules as gather / axis_stencil, resolved once on the host).
+// The pull keeps every lane on one path: the source population is one load
+// whose direction and cell are selected per lane, and the rarer inlet,
+// outlet and interpolated-wall terms are evaluated under wave-uniform
+// conditions (some lane of the wave needs them) for every lane, each lane
+// keeping its own by selection.  (Per-lane branches here let the register
+// allocator of the toolchain place copies of values that live through the
+// branch in the join block, where only one side's lanes are active, so
+// that the other side's lanes later read stale registers.)
 template <int Q, int PREC, int I, bool CW>
 __device__ __forceinline__ typename Prec<PREC>::calc desc_pull(const KParams &P, long long t, long long nb,
                                                                long long idx, int x, int y, int z)
@@ -304,31 +338,56 @@ __device__ __forceinline__ typename Prec<PREC>::calc desc_pull(const KParams &P,
         return pop_load<Q, PREC, I>(P.pop_in, P.N, (uint32_t)idx);
     } else {
         const int src = P.bsrc[I * nb + t];
-        if (src >= 0) return pop_load<Q, PREC, I>(P.pop_in, P.N, (uint32_t)src);
-        if (src == kSrcInflow) {
-            const double cu = inflow_cu<Q, I>(P, x, y, z);
-            return pop_load<Q, PREC, OPP>(P.pop_in, P.N, (uint32_t)idx) + (C)(2.0 * L::w(I) * P.rho_in * cu);
+        const bool fluid = src >= 0;
+        // the source cell's population I, or this cell's opposite one
+        // (half-way bounce-back, and the base of the inlet rule)
+        C g = pop_load_pair<Q, PREC, I>(P.pop_in, P.N, !fluid, fluid ? (uint32_t)src : (uint32_t)idx);
+        const bool inflow = src == kSrcInflow, outlet = src == kSrcOutlet;
+        if (__any(inflow)) {
+            // inlet (Eq. 31): + 2 w_I rho_in c_I.u_in; an x face carries the
+            // per-cell profile indexed by the cell's (y, z)
+            constexpr int cx = L::cx(I), cy = L::cy(I), cz = L::cz(I);
+            const int f = (cx == 1 && x == 0 && P.face[0] == LBFD_FACE_INFLOW)               ? 0
+                          : (cx == -1 && x == P.nx - 1 && P.face[1] == LBFD_FACE_INFLOW) ? 1
+                                                                                         : -1;
+            const bool prof = inflow && f >= 0;
+            const long long s3 = (long long)P.ny * P.nz;
+            const double *ub = prof ? P.inflow_u : kZeroEntry;
+            const long long o = prof ? 3 * s3 * f + (long long)z * P.ny + y : 0;
+            const double ux = ub[o], uy = ub[prof ? o + s3 : 0], uz = ub[prof ? o + 2 * s3 : 0];
+            const double cu = prof ? cx * ux + cy * uy + cz * uz : cx * P.u_in[0] + cy * P.u_in[1] + cz * P.u_in[2];
+            g = inflow ? g + (C)(2.0 * L::w(I) * P.rho_in * cu) : g;
         }
-        if (src == kSrcOutlet) return (C)P.outlet[outlet_index(P, L::cx(I) < 0 ? 1 : 0, I, Q, y, z)];
-        const C gb = pop_load<Q, PREC, OPP>(P.pop_in, P.N, (uint32_t)idx);
+        if (__any(outlet)) {
+            // outlet value kept in the outlet buffer
+            const double *ob = outlet ? P.outlet : kZeroEntry;
+            const C ov = (C)ob[outlet ? outlet_index(P, L::cx(I) < 0 ? 1 : 0, I, Q, y, z) : 0];
+            g = outlet ? ov : g;
+        }
         if constexpr (CW) {
             // linearly interpolated bounce-back (post-collision form) for a
             // wall met at the fraction q of the link toward it (direction OPP)
-            const float qs = P.bq ? P.bq[I * nb + t] : __builtin_nanf("");
-            if (qs == qs) {
-                const C q2 = (C)2 * (C)qs;  // weights in the arithmetic precision
-                if (qs < 0.5f) {
-                    // the far node r + c_I is the pull source of direction OPP
+            if (P.bq != nullptr) {
+                const float qraw = P.bq[I * nb + t];
+                const float qs = src == kSrcBounce ? qraw : __builtin_nanf("");
+                const bool interp = qs == qs;
+                if (__any(interp)) {
+                    const C q2 = (C)2 * (C)qs;  // weights in the arithmetic precision
+                    // q < 1/2: the far node r + c_I is the pull source of
+                    // direction OPP (when it is a fluid cell)
                     const int far = P.bsrc[OPP * nb + t];
-                    if (far >= 0)
-                        return q2 * gb + ((C)1 - q2) * pop_load<Q, PREC, OPP>(P.pop_in, P.N, (uint32_t)far);
-                } else {
-                    const C iq = (C)1 / q2;
-                    return gb * iq + (q2 - (C)1) * iq * pop_load<Q, PREC, I>(P.pop_in, P.N, (uint32_t)idx);
+                    const bool near_half = qs < 0.5f;
+                    const bool use_far = interp && near_half && far >= 0;
+                    const C gfar = pop_load_pair<Q, PREC, I>(P.pop_in, P.N, true, use_far ? (uint32_t)far : (uint32_t)idx);
+                    const C gown = pop_load<Q, PREC, I>(P.pop_in, P.N, (uint32_t)idx);
+                    const C lo = q2 * g + ((C)1 - q2) * gfar;
+                    const C iq = (C)1 / (interp && !near_half ? q2 : (C)1);
+                    const C hi = g * iq + (q2 - (C)1) * iq * gown;
+                    g = use_far ? lo : (interp && !near_half) ? hi : g;
                 }
             }
         }
-        return gb;
+        return g;
     }
 }
 
@@ -449,32 +508,80 @@ __device__ __forceinline__ void axis5(C m2, C m1, C c0, C p1, C p2, C u, bool ne
     conv2 = near ? s12 : s12 + X * inv;
 }
 
+// ------------------------------------------------------------ exponential
+// 2^(j/64), j = 0..63, each the double nearest to the exact value (computed
+// with 60-digit decimal arithmetic).
+static __constant__ double kExp2Tab[64] = {
+    0x1.0000000000000p+0, 0x1.02c9a3e778061p+0, 0x1.059b0d3158574p+0, 0x1.0874518759bc8p+0,
+    0x1.0b5586cf9890fp+0, 0x1.0e3ec32d3d1a2p+0, 0x1.11301d0125b51p+0, 0x1.1429aaea92de0p+0,
+    0x1.172b83c7d517bp+0, 0x1.1a35beb6fcb75p+0, 0x1.1d4873168b9aap+0, 0x1.2063b88628cd6p+0,
+    0x1.2387a6e756238p+0, 0x1.26b4565e27cddp+0, 0x1.29e9df51fdee1p+0, 0x1.2d285a6e4030bp+0,
+    0x1.306fe0a31b715p+0, 0x1.33c08b26416ffp+0, 0x1.371a7373aa9cbp+0, 0x1.3a7db34e59ff7p+0,
+    0x1.3dea64c123422p+0, 0x1.4160a21f72e2ap+0, 0x1.44e086061892dp+0, 0x1.486a2b5c13cd0p+0,
+    0x1.4bfdad5362a27p+0, 0x1.4f9b2769d2ca7p+0, 0x1.5342b569d4f82p+0, 0x1.56f4736b527dap+0,
+    0x1.5ab07dd485429p+0, 0x1.5e76f15ad2148p+0, 0x1.6247eb03a5585p+0, 0x1.6623882552225p+0,
+    0x1.6a09e667f3bcdp+0, 0x1.6dfb23c651a2fp+0, 0x1.71f75e8ec5f74p+0, 0x1.75feb564267c9p+0,
+    0x1.7a11473eb0187p+0, 0x1.7e2f336cf4e62p+0, 0x1.82589994cce13p+0, 0x1.868d99b4492edp+0,
+    0x1.8ace5422aa0dbp+0, 0x1.8f1ae99157736p+0, 0x1.93737b0cdc5e5p+0, 0x1.97d829fde4e50p+0,
+    0x1.9c49182a3f090p+0, 0x1.a0c667b5de565p+0, 0x1.a5503b23e255dp+0, 0x1.a9e6b5579fdbfp+0,
+    0x1.ae89f995ad3adp+0, 0x1.b33a2b84f15fbp+0, 0x1.b7f76f2fb5e47p+0, 0x1.bcc1e904bc1d2p+0,
+    0x1.c199bdd85529cp+0, 0x1.c67f12e57d14bp+0, 0x1.cb720dcef9069p+0, 0x1.d072d4a07897cp+0,
+    0x1.d5818dcfba487p+0, 0x1.da9e603db3285p+0, 0x1.dfc97337b9b5fp+0, 0x1.e502ee78b3ff6p+0,
+    0x1.ea4afa2a490dap+0, 0x1.efa1bee615a27p+0, 0x1.f50765b6e4540p+0, 0x1.fa7c1819e90d8p+0,
+};
+
+// exp(x) by table-driven argument reduction (P. T. P. Tang, Table-driven
+// implementation of the exponential function in IEEE floating-point
+// arithmetic, ACM TOMS 15, 1989): x = (64 m + j) ln2/64 + r, |r| <= ln2/128,
+// with ln2/64 split into a 32-bit head (n times it is exact) and a tail;
+// exp(x) = 2^m 2^(j/64) (1 + p(r)), p the degree-5 Taylor polynomial of
+// exp(r) - 1 (truncation below 4e-17 relative).  About one ulp from the
+// correctly rounded value; x is clamped to [-1000, 1000] (exp underflows to
+// 0 and overflows to infinity well inside it).  `tab` holds kExp2Tab (in
+// LDS in the chemistry launch, the constant table elsewhere).
+__device__ __forceinline__ double exp_tab(double x, const double *tab)
+{
+    constexpr double kInvLn2_64 = 0x1.71547652b82fep+6;   // 64 / ln 2
+    constexpr double kLn2_64_hi = 0x1.62e42fee00000p-7;   // ln 2 / 64, head
+    constexpr double kLn2_64_lo = 0x1.a39ef35793c76p-39;  // and tail
+    x = fmin(fmax(x, -1000.0), 1000.0);
+    const double n = __builtin_rint(x * kInvLn2_64);
+    const double r = fma(-n, kLn2_64_lo, fma(-n, kLn2_64_hi, x));
+    const int ni = (int)n;
+    double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    p = fma(r, p, 1.0 / 6.0);
+    p = fma(r, p, 0.5);
+    p = fma(r, p, 1.0);
+    p *= r;
+    const double t = tab[ni & 63];
+    return __builtin_ldexp(fma(t, p, t), ni >> 6);
+}
+
 // ------------------------------------------------------------ chemistry
 // Arrhenius source over one step in double precision (per reaction
 // r = A dt T^b exp(-Ta/T) prod Y_react; species nu_k r, temperature q r):
 // one explicit Euler step, or, with chem_substeps_max > 1, N sub-steps
 // with N = ceil(max_j k_j / 0.1) capped at chem_substeps_max; a sub-step
 // that would consume a mass fraction below zero is scaled down.
-// The rate coefficient A dt T^b exp(-Ta/T) from ln T and 1/T shared by
-// every reaction: A dt exp(b ln T - Ta / T), one exponential per reaction
-// (with b = 0 it is A dt exp(-Ta / T) bit for bit).
-__device__ __forceinline__ double rate_coeff_l(const lbfd_reaction &r, double dt, double lnT, double invT)
+// The rate coefficient A dt T^b exp(-Ta/T) is formed from ln T and 1/T
+// shared by every reaction as (A dt) exp(b ln T - Ta / T), one exponential
+// per reaction (with b = 0 it is A dt exp(-Ta / T)).
+__device__ __forceinline__ double rate_coeff_l(const ChemRx &r, double lnT, double invT, const double *tab)
 {
-    return r.A * dt * exp(r.b * lnT - r.Ta * invT);
+    return r.adt * exp_tab(r.b * lnT - r.ta * invT, tab);
 }
 
 template <int NSP, bool LE = false>
-__device__ __forceinline__ void chemistry(const KParams &P, double T, const double (&Y)[NSP], double &srcT,
-                                          double (&srcY)[NSP])
+__device__ __forceinline__ void chemistry(const KParams &P, const double *tab, double T, const double (&Y)[NSP],
+                                          double &srcT, double (&srcY)[NSP])
 {
     // ln T is needed only when a temperature exponent is not zero
-    bool anyb = false;
-    for (int j = 0; j < P.n_rx; ++j) anyb |= P.rx[j].b != 0.0;
+    const bool anyb = P.chem_anyb != 0;
     int nsub = 1;
     if (P.chem_substeps_max > 1) {
         const double lnT = anyb ? log(T) : 0.0, invT = rcp(T);
         double kmax = 0.0;
-        for (int j = 0; j < P.n_rx; ++j) kmax = fmax(kmax, rate_coeff_l(P.rx[j], P.dt_phys, lnT, invT));
+        for (int j = 0; j < P.n_rx; ++j) kmax = fmax(kmax, rate_coeff_l(P.rxk[j], lnT, invT, tab));
         double want = ceil(kmax / 0.1);
         nsub = want < 1.0 ? 1 : want > (double)P.chem_substeps_max ? P.chem_substeps_max : (int)want;
     }
@@ -483,7 +590,7 @@ __device__ __forceinline__ void chemistry(const KParams &P, double T, const doub
 #pragma unroll
     for (int k = 0; k < NSP; ++k) dY[k] = 0.0;
     for (int s = 0; s < nsub; ++s) {
-        double Tc = T + dT;
+        const double Tc = T + dT;
         double Yc[NSP];
 #pragma unroll
         for (int k = 0; k < NSP; ++k) Yc[k] = Y[k] + dY[k];
@@ -491,20 +598,27 @@ __device__ __forceinline__ void chemistry(const KParams &P, double T, const doub
 #pragma unroll
         for (int k = 0; k < NSP; ++k) incY[k] = 0.0;
         const double lnTc = anyb ? log(Tc) : 0.0, invTc = rcp(Tc);
-        for (int j = 0; j < P.n_rx; ++j) {
-            const lbfd_reaction &r = P.rx[j];
-            double rr = rate_coeff_l(r, P.dt_phys, lnTc, invTc) * inv_nsub;
-            for (int m = 0; m < r.n_react; ++m) {
-                int kr = r.react[m];
-                double yv = 0.0;
+        // one reaction's progress over the sub-step and its increments;
+        // the reactant indices are the same for every lane, so Yc is
+        // indexed through the register file (no private memory)
+        auto apply = [&](const ChemRx &r, double k) {
+            double rr = k * inv_nsub;
+            for (int m = 0; m < r.n_react; ++m) rr *= Yc[r.react[m]];
 #pragma unroll
-                for (int k = 0; k < NSP; ++k) yv = (k == kr) ? Yc[k] : yv;
-                rr *= yv;
-            }
+            for (int k2 = 0; k2 < NSP; ++k2) incY[k2] += r.nu[k2] * rr;
+            incT += r.q * rr;
+        };
+        // reactions four at a time: the four exponentials are independent
+        // and interleave, the increments follow in reaction order
+        int j = 0;
+        for (; j + 4 <= P.n_rx; j += 4) {
+            double k4[4];
 #pragma unroll
-            for (int k = 0; k < NSP; ++k) incY[k] += r.nu_mass[k] * rr;
-            incT += r.q_over_cp * rr;
+            for (int u = 0; u < 4; ++u) k4[u] = rate_coeff_l(P.rxk[j + u], lnTc, invTc, tab);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) apply(P.rxk[j + u], k4[u]);
         }
+        for (; j < P.n_rx; ++j) apply(P.rxk[j], rate_coeff_l(P.rxk[j], lnTc, invTc, tab));
         if constexpr (LE) {
             // q_over_cp is the rise at c_p,ref: divide by c_p(Y) / c_p,ref
             // at the sub-step's composition (Eq. 7: omega_T / (rho c_p))
@@ -518,7 +632,7 @@ __device__ __forceinline__ void chemistry(const KParams &P, double T, const doub
         double lam = 1.0;
 #pragma unroll
         for (int k = 0; k < NSP; ++k)
-            if (incY[k] < 0.0 && Yc[k] + incY[k] < 0.0) lam = fmin(lam, fmax(Yc[k], 0.0) / (-incY[k]));
+            if (incY[k] < 0.0 && Yc[k] + incY[k] < 0.0) lam = fmin(lam, fmax(Yc[k], 0.0) * rcp(-incY[k]));
         dT += lam * incT;
 #pragma unroll
         for (int k = 0; k < NSP; ++k) dY[k] += lam * incY[k];
@@ -748,11 +862,22 @@ __device__ __forceinline__ void finish_cell(const KParams &P, long long idx, con
     using S = typename Prec<PREC>::scal;
     constexpr bool DIAG = MODE != kModeStep;
     const C rho = ctr.rho;
-    // Arrhenius source (double)
-    double Yd[NSP], srcT, srcY[NSP];
+    // Arrhenius source (double): computed here, or read back from this
+    // step's output scalars where the chemistry launch left it
+    double srcT, srcY[NSP];
+    if constexpr (chem_pass(NSP)) {
+        const char *so = (const char *)P.sc_out;
+        const size_t fstride = (size_t)P.N * sizeof(S);
+        const uint32_t off = (uint32_t)idx * (uint32_t)sizeof(S);
+        srcT = (double)ldo<S>(so, off);
 #pragma unroll
-    for (int k = 0; k < NSP; ++k) Yd[k] = (double)ctr.Y[k];
-    chemistry<NSP, LE>(P, (double)ctr.T, Yd, srcT, srcY);
+        for (int k = 0; k < NSP; ++k) srcY[k] = (double)ldo<S>(so + (size_t)(1 + k) * fstride, off);
+    } else {
+        double Yd[NSP];
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) Yd[k] = (double)ctr.Y[k];
+        chemistry<NSP, LE>(P, kExp2Tab, (double)ctr.T, Yd, srcT, srcY);
+    }
 
     // material derivatives, Lambda (Eq. 6), Euler update, P_h (Eq. 13a)
     const C DtT = diffT + (C)srcT;
@@ -1337,6 +1462,53 @@ hipError_t launch_images(const KParams &kp, hipStream_t s)
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ chemistry launch
+// Mechanisms of many species (chem_pass): the FP64 Arrhenius source of every
+// fluid cell as a launch of its own ahead of the step, one thread per fluid
+// cell of the fluid-cell list (index order, so that solid cells occupy no
+// lane), written into this step's output scalars (the slots of T
+// and Y_k), where the cell's step thread reads it back before overwriting
+// them with the cell's new state.  The sub-stepped source then runs at the
+// occupancy of its own registers, not of the step's populations and
+// stencils; the exponential's table is staged in LDS.  In the mixed forms
+// the stored source is rounded to single precision, as the step kernel
+// rounds it when it adds it.
+template <int NSP, int PREC, bool LE>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) chem_kernel(const KParams P)
+{
+    using S = typename Prec<PREC>::scal;
+    __shared__ double tab[64];
+    if (threadIdx.x < 64) tab[threadIdx.x] = kExp2Tab[threadIdx.x];
+    __syncthreads();
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= P.n_fluid) return;
+    const long long idx = P.fluid[t];
+    const char *si = (const char *)P.sc_in;
+    char *so = (char *)P.sc_out;
+    const size_t fstride = (size_t)P.N * sizeof(S);
+    const uint32_t off = (uint32_t)idx * (uint32_t)sizeof(S);
+    double Y[NSP], srcT, srcY[NSP];
+    const double T = (double)ldo<S>(si, off);
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) Y[k] = (double)ldo<S>(si + (size_t)(1 + k) * fstride, off);
+    chemistry<NSP, LE>(P, tab, T, Y, srcT, srcY);
+    sto<S>(so, off, (S)srcT);
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) sto<S>(so + (size_t)(1 + k) * fstride, off, (S)srcY[k]);
+}
+
+template <int NSP, int PREC>
+hipError_t launch_chem(const KParams &kp, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((kp.n_fluid + kBlock - 1) / kBlock);
+    if (nb == 0) return hipSuccess;
+    if (kp.transport == LBFD_MIXTURE_AVERAGED)
+        chem_kernel<NSP, PREC, true><<<dim3(nb), dim3(kBlock), 0, s>>>(kp);
+    else
+        chem_kernel<NSP, PREC, false><<<dim3(nb), dim3(kBlock), 0, s>>>(kp);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ outlet
 // Outlet (Eq. 32): for every fluid cell of an outflow face whose inner
 // neighbour is fluid, the populations entering through the face become
@@ -1469,9 +1641,15 @@ hipError_t launch_range(const KParams &kp0, long long begin, long long count, hi
 template <int Q, int NSP, int PREC, int MODE>
 hipError_t launch_pair(const KParams &kp, const Streams &st)
 {
-    // st.part 0: every block; 1: interior tiles only; 2: boundary blocks only
+    // st.part 0: every launch; 1: interior tiles only; 2: boundary blocks,
+    // image points and outlet; 3: the chemistry launch only
     const long long nbb = kp.boundary_blocks, nti = kp.interior_blocks;
     hipError_t e = hipSuccess;
+    if constexpr (chem_pass(NSP)) {
+        if ((st.part == 0 || st.part == 3) && (e = launch_chem<NSP, PREC>(kp, st.main)) != hipSuccess)
+            return e;
+    }
+    if (st.part == 3) return hipSuccess;
     if (kp.bimg != nullptr && kp.n_img > 0 && st.part != 1)
         if ((e = launch_images<NSP, PREC>(kp, st.main)) != hipSuccess) return e;
     if constexpr (fused_step(Q)) {

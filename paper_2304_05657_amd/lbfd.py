@@ -109,7 +109,7 @@ def load_library():
     lib.lbfd_save_state.argtypes = [vp, vp, C.c_size_t]
     lib.lbfd_load_state.argtypes = [vp, vp, C.c_size_t]
     lib.lbfd_time_steps.argtypes = [vp, C.c_int64, dp]
-    lib.lbfd_time_kernels.argtypes = [vp, C.c_int64, dp, dp]
+    lib.lbfd_time_kernels.argtypes = [vp, C.c_int64, dp, dp, dp]
     lib.lbfd_cell_counts.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.lbfd_step_launches.argtypes = [vp]
     lib.lbfd_step_launches.restype = C.c_int
@@ -249,10 +249,11 @@ class Solver:
         return ms.value
 
     def time_kernels(self, n: int) -> tuple:
-        """(ms interior kernel, ms boundary kernel) summed over n serialised steps."""
-        a, b = C.c_double(), C.c_double()
-        _check(self._lib, self._lib.lbfd_time_kernels(self._h, int(n), C.byref(a), C.byref(b)))
-        return a.value, b.value
+        """(ms interior kernel, ms boundary kernel, ms chemistry launch)
+        summed over n serialised steps."""
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        _check(self._lib, self._lib.lbfd_time_kernels(self._h, int(n), C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
 
     def cell_counts(self) -> tuple:
         """(fluid cells, cells on the boundary-cell path)."""
