@@ -338,6 +338,21 @@ int lbfd_set_objective(lbfd_ctx *c, int kind, int64_t t_begin, int64_t t_end);
  * lbfd_adjoint). */
 int lbfd_objective(lbfd_ctx *c, int64_t nsteps, double *J);
 
+/* lbfd_objective for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same objective from the same kernels, with the objective's
+ * accumulator, the final diagnostics and the per-block partial diagnostics
+ * of its steps in a static device array of the library (16 MiB, one per GPU,
+ * held until the process ends) instead of library-allocated memory; no
+ * hipMalloc, hipFree or allocating library call is made.  The accumulator
+ * is cleared by a fill kernel at the start of every call.  Every call on a
+ * GPU shares that GPU's array and leaves its contents there: calls that
+ * overlap on one GPU (from several threads or streams) race and must be
+ * serialised by the caller.  LBFD_EINVAL when the context's step needs more
+ * than the array holds (512 + 104 bytes per step block: boxes up to about
+ * 161,000 blocks of 256 cells); J is a host pointer; synchronous. */
+int lbfd_objective_static(lbfd_ctx *c, int64_t nsteps, double *J);
+
 /* Discrete adjoint of the FP64 step.  Not a method of the paper: the paper
  * has no differentiation; this entry point serves gradient-based uses of
  * the step (sensitivities of wall heat flux and flame position with respect

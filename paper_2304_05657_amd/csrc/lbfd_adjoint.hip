@@ -450,6 +450,19 @@ hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_p
     return hipGetLastError();
 }
 
+__global__ void fill_kernel(double *dst, int n, double v)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) dst[i] = v;
+}
+
+hipError_t launch_fill(double *dst, int n, double v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    fill_kernel<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(dst, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_accumulate(double *acc, const double *diag, int slot, double a, double b, hipStream_t s)
 {
     accumulate_kernel<<<1, 1, 0, s>>>(acc, diag, slot, a, b);

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -39,6 +40,37 @@ int fail(int code, const char *fmt, ...)
 
 constexpr double kCs2 = 1.0 / 3.0;
 constexpr uint32_t kMagic = 0x4c424644u;  // "LBFD"
+
+// Device memory of lbfd_objective_static, which allocates nothing: the
+// objective's accumulator, the final diagnostics and the per-block partial
+// diagnostics of its steps.  One copy per GPU, held until the process ends;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// on that device (the array's name is a host-side stand-in).
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+constexpr size_t kScratchAcc = 0, kScratchDiag = 256, kScratchPartials = 512;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// The scratch array's device address on the current device, looked up once
+// per device (called from lbfd_init).
+int scratch_address(void **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBFD_EDEVICE, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(LBFD_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBFD_OK;
+}
 
 struct StateHeader {
     uint32_t magic;
@@ -110,6 +142,7 @@ struct lbfd_ctx {
     long long *bad_dev = nullptr;
     lbfd_reaction *rx_dev = nullptr;
     ChemRx *rxk_dev = nullptr;
+    unsigned char *scratch = nullptr;   // this device's static scratch (lbfd_objective_static)
     int64_t level = 0;
     dim3 grid, block;
     KParams base;
@@ -633,6 +666,11 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     c->streams.main = c->stream;
     c->base = make_kparams(c);
     TRY_OR_FREE(upload_reactions(c));
+    {
+        void *sp = nullptr;
+        TRY_OR_FREE(scratch_address(&sp));
+        c->scratch = (unsigned char *)sp;
+    }
     double *u0_dev = nullptr, *Ph0_dev = nullptr;
     if (u0) {
         HIP_OR_FREE(hipMalloc((void **)&u0_dev, (size_t)c->D * N * sizeof(double)));
@@ -1369,6 +1407,37 @@ int lbfd_objective(lbfd_ctx *c, int64_t nsteps, double *J)
     if (e == hipSuccess) e = hipMemcpyAsync(J, Jd, sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(Jd);
+    if (e != hipSuccess) return fail(LBFD_EDEVICE, "objective: %s", hipGetErrorString(e));
+    return LBFD_OK;
+}
+
+int lbfd_objective_static(lbfd_ctx *c, int64_t nsteps, double *J)
+{
+    if (!c || !J || nsteps < 0) return fail(LBFD_EINVAL, "bad arguments");
+    const size_t need = kScratchPartials + (size_t)c->nblocks * kNDiag * sizeof(double);
+    if (need > kScratchBytes)
+        return fail(LBFD_EINVAL, "lbfd_objective_static: this box needs %zu bytes of scratch, the static array "
+                    "holds %zu (use lbfd_objective)", need, kScratchBytes);
+    double *acc = (double *)(c->scratch + kScratchAcc);
+    double *diag = (double *)(c->scratch + kScratchDiag);
+    double *partials = (double *)(c->scratch + kScratchPartials);
+    hipError_t e = launch_fill(acc, 1, 0.0, c->stream);
+    for (int64_t n = 0; n < nsteps && e == hipSuccess; ++n) {
+        KParams k = c->base;
+        k.pop_in = c->pop[c->cur];
+        k.pop_out = c->pop[1 - c->cur];
+        k.sc_in = c->sc[c->cur];
+        k.sc_out = c->sc[1 - c->cur];
+        k.partials = partials;
+        const ObjTerm o = objective_term(c, n);
+        e = launch_step(c->Q, c->nsp, c->prec, o.on ? kModeStepDiag : kModeStep, k, c->streams);
+        if (e == hipSuccess && o.on) e = launch_finalize(partials, c->nblocks, diag, c->bad_dev, c->level, c->stream);
+        if (e == hipSuccess && o.on) e = launch_accumulate(acc, diag, o.slot, o.a, o.b, c->stream);
+        c->cur ^= 1;
+        c->level += 1;
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(J, acc, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(LBFD_EDEVICE, "objective: %s", hipGetErrorString(e));
     return LBFD_OK;
 }

@@ -157,5 +157,8 @@ hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_p
 hipError_t launch_widen(const float *src, double *dst, size_t n, hipStream_t s);
 // *acc += a * diag[slot] + b (one thread).
 hipError_t launch_accumulate(double *acc, const double *diag, int slot, double a, double b, hipStream_t s);
+// dst[i] = v for i < n (a fill kernel, so that callers capturing a graph
+// record no memset node).
+hipError_t launch_fill(double *dst, int n, double v, hipStream_t s);
 
 }  // namespace lbfd

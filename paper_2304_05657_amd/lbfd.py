@@ -29,6 +29,7 @@ EXPORTS = ("lbfd_init", "lbfd_step", "lbfd_sync", "lbfd_level", "lbfd_read_field
            "lbfd_cell_counts", "lbfd_step_launches", "lbfd_set_reaction", "lbfd_set_objective",
            "lbfd_objective", "lbfd_adjoint", "lbfd_set_inflow", "lbfd_hold_flame", "lbfd_set_wall_links",
            "lbfd_set_image_points", "lbfd_init_dev", "lbfd_read_fields_dev", "lbfd_adjoint_dev",
+           "lbfd_objective_static",
            "lbfd_destroy",
            "lbfd_strerror", "lbfd_last_error")
 # species transport models (lbfd_params.transport)
@@ -120,6 +121,7 @@ def load_library():
     lib.lbfd_set_image_points.argtypes = [vp, C.c_int64, vp, vp, dp]
     lib.lbfd_hold_flame.argtypes = [vp, C.c_int64, C.c_int, C.c_double, C.c_double, dp, dp]
     lib.lbfd_objective.argtypes = [vp, C.c_int64, dp]
+    lib.lbfd_objective_static.argtypes = [vp, C.c_int64, dp]
     lib.lbfd_adjoint.argtypes = [vp, C.c_int64, C.c_int, dp, dp, dp, dp]
     lib.lbfd_destroy.argtypes = [vp]
     lib.lbfd_destroy.restype = None
@@ -281,6 +283,13 @@ class Solver:
         """The selected objective over the next nsteps levels (forward only)."""
         J = C.c_double()
         _check(self._lib, self._lib.lbfd_objective(self._h, int(nsteps), C.byref(J)))
+        return J.value
+
+    def objective_static(self, nsteps: int) -> float:
+        """objective() through lbfd_objective_static: no device allocation,
+        the library's static per-GPU scratch array instead."""
+        J = C.c_double()
+        _check(self._lib, self._lib.lbfd_objective_static(self._h, int(nsteps), C.byref(J)))
         return J.value
 
     def adjoint(self, nsteps: int, K: int, device: bool = False):
