@@ -305,7 +305,8 @@ def main():
                     help="porous_mech (default), porous, burner or channel")
     ap.add_argument("--accuracy-steps", type=int, default=None,
                     help="level at which the mixed-precision runs are compared with the FP64 run "
-                         "(0: skip; default 200 for porous_mech, 20000 for the burner, 5000 for porous)")
+                         "(0: skip, also for the --also workloads; default 200 for porous_mech, 20000 for the "
+                         "burner, 5000 for porous)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 512 MiB device copy (calibrates the HBM byte counters)")
     ap.add_argument("--also", default="porous:fp64,fp16",
@@ -362,7 +363,8 @@ def main():
     for item in [x for x in args.also.split(";") if x.strip() and x.strip() not in ("none", "''", '""')]:
         name, _, pl = item.partition(":")
         ops = [p.strip() for p in (pl or "fp64").split(",") if p.strip()]
-        oprob, ores, _, _ = bench_workload(name.strip(), ops, default_acc.get(name.strip(), 2000), False, False)
+        oacc = args.accuracy_steps if args.accuracy_steps == 0 else default_acc.get(name.strip(), 2000)
+        oprob, ores, _, _ = bench_workload(name.strip(), ops, oacc, False, False)
         others[oprob.name] = {"lattice": "D2Q9" if oprob.lattice == 9 else "D3Q27", "cells": oprob.N,
                               "fluid_cells": oprob.n_fluid, "species": oprob.n_species,
                               "reactions": len(oprob.reactions),

@@ -397,8 +397,10 @@ int lbfd_cell_counts(const lbfd_ctx *c, int64_t *n_fluid, int64_t *n_boundary);
 /* Kernel launches queued by one lbfd_step level without diagnostics: 1 for
  * D2Q9 (one launch covers boundary and interior cells); for D3Q27 the
  * boundary cells, the interior cells and, with an outflow face, the outlet
- * update (Eq. 32) are separate launches; plus one for the chemistry launch
- * of a mechanism of more than four species, and two for image points.
+ * update (Eq. 32) are separate launches; plus three for the chemistry of a
+ * mechanism of more than four species (clearing the ordering's counters,
+ * ordering the fluid cells by their previous sub-step count, the sources),
+ * and two for image points.
  * Negative on a null context. */
 int lbfd_step_launches(const lbfd_ctx *c);
 

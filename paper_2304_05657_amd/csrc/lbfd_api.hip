@@ -109,6 +109,9 @@ struct lbfd_ctx {
     int *boundary = nullptr;
     long long n_boundary = 0;
     int *fluid = nullptr;               // fluid-cell list (contexts with a chemistry launch)
+    int *chem_order = nullptr;          // its per-step order for the chemistry launch
+    unsigned char *chem_heavy = nullptr;
+    int *chem_count = nullptr;
     std::vector<int> boundary_host;
     std::vector<uint8_t> mask_host;
     std::vector<double> wall_T_host;
@@ -154,7 +157,8 @@ static void free_ctx(lbfd_ctx *c)
     void *ptrs[] = {c->pop[0], c->pop[1], c->sc[0], c->sc[1], c->mask, c->code, c->boundary, c->bsrc, c->bpt, c->bwk,
                     c->btw, c->wall_T, c->outlet, c->outlet_un, c->inflow_u, c->inflow_du, c->bq,
                     c->bimg, c->img_rng, c->img_idx, c->img_w, c->img_val, c->sup_idx, c->sup_val,
-                    c->fields, c->partials, c->diag_dev, c->bad_dev, c->rx_dev, c->rxk_dev, c->fluid};
+                    c->fields, c->partials, c->diag_dev, c->bad_dev, c->rx_dev, c->rxk_dev, c->fluid,
+                    c->chem_order, c->chem_heavy, c->chem_count};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete c;
@@ -429,6 +433,9 @@ static KParams make_kparams(const lbfd_ctx *c)
     k.n_boundary = c->n_boundary;
     k.fluid = c->fluid;
     k.n_fluid = c->n_fluid;
+    k.chem_order = c->chem_order;
+    k.chem_heavy = c->chem_heavy;
+    k.chem_count = c->chem_count;
     k.boundary_blocks = c->nblocks - c->nblocks_interior;
     k.interior_blocks = c->nblocks_interior;
     k.block_begin = 0;
@@ -501,7 +508,8 @@ static int upload_reactions(lbfd_ctx *c)
         h[j].ta = r.Ta;
         h[j].q = r.q_over_cp;
         h[j].n_react = r.n_react;
-        for (int m = 0; m < 4; ++m) h[j].react[m] = m < r.n_react ? r.react[m] : 0;
+        // unused reactant slots index the chemistry's constant-1 entry
+        for (int m = 0; m < 4; ++m) h[j].react[m] = m < r.n_react ? r.react[m] : c->nsp;
         for (int k = 0; k < c->nsp; ++k) h[j].nu[k] = r.nu_mass[k];
         anyb |= r.b != 0.0;
     }
@@ -608,7 +616,12 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
     ALLOC(c->bad_dev, sizeof(long long));
     ALLOC(c->rx_dev, sizeof(lbfd_reaction) * LBFD_MAX_REACTIONS);
     ALLOC(c->rxk_dev, sizeof(ChemRx) * LBFD_MAX_REACTIONS);
-    if (chem_pass(c->nsp)) ALLOC(c->fluid, sizeof(int) * (size_t)c->n_fluid);
+    if (chem_pass(c->nsp)) {
+        ALLOC(c->fluid, sizeof(int) * (size_t)c->n_fluid);
+        ALLOC(c->chem_order, sizeof(int) * (size_t)c->n_fluid);
+        ALLOC(c->chem_heavy, (size_t)N);
+        ALLOC(c->chem_count, 2 * sizeof(int));
+    }
 #undef ALLOC
 
 #define TRY_OR_FREE(expr)            \
@@ -656,6 +669,9 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
         for (long long i = 0; i < N; ++i)
             if (mask[i] == LBFD_FLUID) fl.push_back((int)i);
         HIP_OR_FREE(hipMemcpy(c->fluid, fl.data(), fl.size() * sizeof(int), hipMemcpyHostToDevice));
+        // every cell starts as light (the first step's order is the list's)
+        HIP_OR_FREE(hipMemset(c->chem_heavy, 0, (size_t)N));
+        HIP_OR_FREE(hipMemset(c->chem_count, 0, 2 * sizeof(int)));
     }
     TRY_OR_FREE(build_descriptors(c));
     long long minus1 = -1;

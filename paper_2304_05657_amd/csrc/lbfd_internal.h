@@ -34,7 +34,7 @@ enum NbKind { kFluid = 0, kIso = 1, kAdia = 2, kInflow = 3, kOutflow = 4 };
 // reactant indices and the mass coefficients.
 struct ChemRx {
     double adt, b, ta, q;
-    int n_react, react[4];
+    int n_react, react[4];  // react[m >= n_react] = n_species (a factor 1)
     double nu[kMaxSp];
 };
 
@@ -56,6 +56,10 @@ struct KParams {
     const int *boundary;        // boundary fluid cells, increasing index
     long long n_boundary;
     const int *fluid;           // every fluid cell, increasing index (chemistry launch)
+    int *chem_order;            // [n_fluid] fluid cells in the chemistry launch's order: cells whose last
+                                //   source took few sub-steps first, the others from the back
+    unsigned char *chem_heavy;  // [N] the cell's last source took more than kChemLight sub-steps
+    int *chem_count;            // [2] cells placed at the front / back by this step's ordering
     long long n_fluid;
     // per boundary cell t (structure of arrays, stride n_boundary):
     const int *bsrc;            // [Q][nb] pull source index, or kSrcBounce / kSrcInflow / kSrcOutlet
@@ -120,7 +124,7 @@ constexpr bool fused_step(int Q) { return Q == 9; }
 inline int step_launches(int Q, int nsp, const KParams &kp)
 {
     const int images = kp.bimg != nullptr && kp.n_img > 0 ? 2 : 0;
-    const int chem = chem_pass(nsp) ? 1 : 0;
+    const int chem = chem_pass(nsp) && kp.n_fluid > 0 ? 3 : 0;  // counter clear, ordering, sources
     if (fused_step(Q)) return (kp.boundary_blocks + kp.interior_blocks > 0 ? 1 : 0) + images + chem;
     const bool outlet = kp.n_boundary > 0 && (kp.face[0] == LBFD_FACE_OUTFLOW || kp.face[1] == LBFD_FACE_OUTFLOW);
     return (kp.boundary_blocks > 0) + (kp.interior_blocks > 0) + (outlet ? 1 : 0) + images + chem;

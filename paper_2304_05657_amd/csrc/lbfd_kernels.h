@@ -571,9 +571,10 @@ __device__ __forceinline__ double rate_coeff_l(const ChemRx &r, double lnT, doub
     return r.adt * exp_tab(r.b * lnT - r.ta * invT, tab);
 }
 
+// Returns the number of sub-steps taken.
 template <int NSP, bool LE = false>
-__device__ __forceinline__ void chemistry(const KParams &P, const double *tab, double T, const double (&Y)[NSP],
-                                          double &srcT, double (&srcY)[NSP])
+__device__ __forceinline__ int chemistry(const KParams &P, const double *tab, double T, const double (&Y)[NSP],
+                                         double &srcT, double (&srcY)[NSP])
 {
     // ln T is needed only when a temperature exponent is not zero
     const bool anyb = P.chem_anyb != 0;
@@ -591,19 +592,26 @@ __device__ __forceinline__ void chemistry(const KParams &P, const double *tab, d
     for (int k = 0; k < NSP; ++k) dY[k] = 0.0;
     for (int s = 0; s < nsub; ++s) {
         const double Tc = T + dT;
-        double Yc[NSP];
+        // Yc[NSP] = 1 is the factor of the unused reactant slots
+        double Yc[NSP + 1];
 #pragma unroll
         for (int k = 0; k < NSP; ++k) Yc[k] = Y[k] + dY[k];
+        Yc[NSP] = 1.0;
         double incT = 0.0, incY[NSP];
 #pragma unroll
         for (int k = 0; k < NSP; ++k) incY[k] = 0.0;
         const double lnTc = anyb ? log(Tc) : 0.0, invTc = rcp(Tc);
         // one reaction's progress over the sub-step and its increments;
         // the reactant indices are the same for every lane, so Yc is
-        // indexed through the register file (no private memory)
+        // indexed through the register file (no private memory).  The four
+        // reactant slots are all multiplied in (the unused ones index the
+        // constant 1): a fixed count lets the four indices arrive in one
+        // scalar load ahead of the products instead of one dependent load
+        // per reactant
         auto apply = [&](const ChemRx &r, double k) {
             double rr = k * inv_nsub;
-            for (int m = 0; m < r.n_react; ++m) rr *= Yc[r.react[m]];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) rr *= Yc[r.react[m]];
 #pragma unroll
             for (int k2 = 0; k2 < NSP; ++k2) incY[k2] += r.nu[k2] * rr;
             incT += r.q * rr;
@@ -640,6 +648,7 @@ __device__ __forceinline__ void chemistry(const KParams &P, const double *tab, d
     srcT = dT;
 #pragma unroll
     for (int k = 0; k < NSP; ++k) srcY[k] = dY[k];
+    return nsub;
 }
 
 // ------------------------------------------------- central-moment transform
@@ -1465,14 +1474,85 @@ hipError_t launch_images(const KParams &kp, hipStream_t s)
 // ------------------------------------------------------------ chemistry launch
 // Mechanisms of many species (chem_pass): the FP64 Arrhenius source of every
 // fluid cell as a launch of its own ahead of the step, one thread per fluid
-// cell of the fluid-cell list (index order, so that solid cells occupy no
-// lane), written into this step's output scalars (the slots of T
-// and Y_k), where the cell's step thread reads it back before overwriting
-// them with the cell's new state.  The sub-stepped source then runs at the
-// occupancy of its own registers, not of the step's populations and
-// stencils; the exponential's table is staged in LDS.  In the mixed forms
-// the stored source is rounded to single precision, as the step kernel
-// rounds it when it adds it.
+// cell, written into this step's output scalars (the slots of T and Y_k),
+// where the cell's step thread reads it back before overwriting them with
+// the cell's new state.  The sub-stepped source then runs at the occupancy
+// of its own registers, not of the step's populations and stencils; the
+// exponential's table is staged in LDS.  In the mixed forms the stored
+// source is rounded to single precision, as the step kernel rounds it when
+// it adds it.
+//
+// A wave takes as long as its lane with the most sub-steps, and the counts
+// are bimodal (cold gas 1, burning gas up to the cap), so the cells are
+// ordered first (chem_order_kernel): those whose previous source took at
+// most kChemLight sub-steps from the front of chem_order, the others from
+// the back, runs of the fluid-cell list kept in list order within a wave.
+// The previous step's count only decides where a cell goes; every cell's
+// source is computed alike wherever it lands, so the results do not depend
+// on the order (which the atomics make vary from run to run).
+constexpr int kChemLight = 8;
+constexpr int kChemChunk = 16;  // fluid-list positions per thread of the ordering
+
+template <int NSP>
+__global__ void __launch_bounds__(kBlock) chem_order_kernel(const KParams P)
+{
+    __shared__ int cnt[2], base[2];
+    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const long long n = P.n_fluid;
+    const long long t0 = (long long)blockIdx.x * kBlock * kChemChunk;
+    const int lane = (int)(threadIdx.x & 63);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    // this block's light and heavy cells
+    int nh = 0, nl = 0;
+    for (int r = 0; r < kChemChunk; ++r) {
+        const long long t = t0 + (long long)r * kBlock + threadIdx.x;
+        if (t < n) {
+            const bool h = P.chem_heavy[P.fluid[t]] != 0;
+            nh += h;
+            nl += !h;
+        }
+    }
+    atomicAdd(&cnt[0], nl);
+    atomicAdd(&cnt[1], nh);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        base[0] = atomicAdd(&P.chem_count[0], cnt[0]);
+        base[1] = atomicAdd(&P.chem_count[1], cnt[1]);
+        cnt[0] = cnt[1] = 0;
+    }
+    __syncthreads();
+    // places: per round and wave one run per class, in list order
+    for (int r = 0; r < kChemChunk; ++r) {
+        const long long t = t0 + (long long)r * kBlock + threadIdx.x;
+        const bool valid = t < n;
+        const int idx = valid ? P.fluid[t] : 0;
+        const bool h = valid && P.chem_heavy[idx] != 0;
+        const bool l = valid && !h;
+        const unsigned long long bh = __ballot(h), bl = __ballot(l);
+        int wh = 0, wl = 0;
+        if (lane == 0) {
+            wh = atomicAdd(&cnt[1], __popcll(bh));
+            wl = atomicAdd(&cnt[0], __popcll(bl));
+        }
+        wh = __shfl(wh, 0, 64);
+        wl = __shfl(wl, 0, 64);
+        // (the counts of both passes agree, so every place is in [0, n))
+        const long long ph = n - 1 - (base[1] + wh + __popcll(bh & below));
+        const long long pl = base[0] + wl + __popcll(bl & below);
+        if (h && ph >= 0) P.chem_order[ph] = idx;
+        if (l && pl < n) P.chem_order[pl] = idx;
+    }
+}
+
+// The ordering's two counters, cleared ahead of it (a kernel, so that a
+// captured step records no memset node).
+template <int NSP>
+__global__ void chem_count_clear_kernel(int *count)
+{
+    if (threadIdx.x < 2) count[threadIdx.x] = 0;
+}
+
 template <int NSP, int PREC, bool LE>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) chem_kernel(const KParams P)
 {
@@ -1482,7 +1562,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     __syncthreads();
     const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= P.n_fluid) return;
-    const long long idx = P.fluid[t];
+    const long long idx = P.chem_order[t];
     const char *si = (const char *)P.sc_in;
     char *so = (char *)P.sc_out;
     const size_t fstride = (size_t)P.N * sizeof(S);
@@ -1491,7 +1571,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     const double T = (double)ldo<S>(si, off);
 #pragma unroll
     for (int k = 0; k < NSP; ++k) Y[k] = (double)ldo<S>(si + (size_t)(1 + k) * fstride, off);
-    chemistry<NSP, LE>(P, tab, T, Y, srcT, srcY);
+    const int nsub = chemistry<NSP, LE>(P, tab, T, Y, srcT, srcY);
+    P.chem_heavy[idx] = nsub > kChemLight;
     sto<S>(so, off, (S)srcT);
 #pragma unroll
     for (int k = 0; k < NSP; ++k) sto<S>(so + (size_t)(1 + k) * fstride, off, (S)srcY[k]);
@@ -1502,6 +1583,11 @@ hipError_t launch_chem(const KParams &kp, hipStream_t s)
 {
     const unsigned nb = (unsigned)((kp.n_fluid + kBlock - 1) / kBlock);
     if (nb == 0) return hipSuccess;
+    const long long per = (long long)kBlock * kChemChunk;
+    chem_count_clear_kernel<NSP><<<dim3(1), dim3(64), 0, s>>>(kp.chem_count);
+    chem_order_kernel<NSP><<<dim3((unsigned)((kp.n_fluid + per - 1) / per)), dim3(kBlock), 0, s>>>(kp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     if (kp.transport == LBFD_MIXTURE_AVERAGED)
         chem_kernel<NSP, PREC, true><<<dim3(nb), dim3(kBlock), 0, s>>>(kp);
     else

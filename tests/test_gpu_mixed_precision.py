@@ -21,6 +21,7 @@ pytestmark = pytest.mark.gpu
 # steps fp32 (5.9e-7, 8.8e-6), fp16 (5.9e-6, 3.5e-4).
 CHANNEL_BOUNDS = {"fp32": (1e-4, 5e-4, 5e-3), "fp16": (5e-3, 2e-1, 5e-2)}
 POROUS_BOUNDS = {"fp32": (5e-6, 5e-5), "fp16": (5e-5, 2e-3)}
+MECH_BOUNDS = {"fp32": (1e-3, 1e-3, 1e-2), "fp16": (1e-2, 1e-2, 1e-1)}
 
 
 def _flame_x(d, prob):
@@ -71,3 +72,29 @@ def test_porous_3d_mixed_vs_oracle(precision):
     say("  %s: T_max_rel=%.3e u_max_rel=%.3e" % (precision, eT, eu))
     bT, bu = POROUS_BOUNDS[precision]
     assert eT <= bT and eu <= bu, (eT, eu)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_porous_mechanism_mixed_vs_oracle(precision):
+    """The 9-species / 20-reaction mechanism (FP64 sub-cycled sources, FP32
+    arithmetic elsewhere), 200 steps."""
+    import oracle
+    from paper_2304_05657_amd.lbfd import Solver
+    need_gpu()
+    prob = W.porous_3d_mech(nx=32, ny=12, nz=12, porosity=0.9, radius=(2.0, 4.0), margin=6,
+                            name="porous3d_mech_32x12x12")
+    steps = 200
+    say("case porous3d_mech_32x12x12 %s steps=%d" % (precision, steps))
+    g = Solver(prob, precision=precision)
+    o = oracle.Oracle(prob, threads=oracle_threads())
+    g.step(steps)
+    o.step(steps)
+    gf, of = g.fields(), o.fields()
+    fl = prob.mask == 0
+    eT = np.abs(gf["T"][fl] - of["T"][fl]).max() / (prob.T_b - prob.T_u)
+    eY = np.abs(gf["Y"][:, fl] - of["Y"][:, fl]).max()
+    umax = np.abs(of["u"][:, fl]).max()
+    eu = np.abs(gf["u"][:, fl] - of["u"][:, fl]).max() / umax
+    say("  %s: T_max_rel=%.3e Y_max_abs=%.3e u_max_rel=%.3e" % (precision, eT, eY, eu))
+    bT, bY, bu = MECH_BOUNDS[precision]
+    assert eT <= bT and eY <= bY and eu <= bu, (eT, eY, eu)

@@ -124,6 +124,26 @@ def test_porous_3d_mechanism_fp64():
     _assert_tol(errs, TOL64)
 
 
+def test_porous_3d_fp64_500_steps():
+    """A longer 3-D horizon: D3Q27 packing 64x32x32 (58,029 fluid cells),
+    inflow / outflow, 4 species, 500 FP64 steps with the reductions every
+    10 steps, compared at levels 1, 100 and 500."""
+    prob = W.porous_3d(nx=64, ny=32, nz=32, porosity=0.85, radius=4.0, margin=8, seed=11,
+                       name="porous3d_64x32x32")
+    _, _, errs = _run_pair(prob, 500, checkpoints=[1, 100], check_every=10)
+    _assert_tol(errs, TOL64)
+
+
+def test_porous_3d_mechanism_fp64_400_steps():
+    """A longer horizon of the stiff mechanism: 9 species / 20 reactions with
+    temperature exponents and sub-cycled FP64 sources, 400 steps, compared at
+    levels 1, 40, 200 and 400."""
+    prob = W.porous_3d_mech(nx=32, ny=12, nz=12, porosity=0.9, radius=(2.0, 4.0), margin=6,
+                            name="porous3d_mech_32x12x12")
+    _, _, errs = _run_pair(prob, 400, checkpoints=[1, 40, 200], check_every=10)
+    _assert_tol(errs, TOL64)
+
+
 def test_closed_3d_budget_and_diagnostics():
     """D3Q27 closed periodic box with a sphere: GPU diagnostics equal the
     oracle's and the population budget closes."""
