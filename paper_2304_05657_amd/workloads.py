@@ -508,23 +508,45 @@ def porous_3d(nx: int = 256, ny: int = 256, nz: int = 256, porosity: float = 0.8
     )
 
 
+def synthetic_enthalpies(n_species: int = 9, seed: int = 2305, h_top: float = 2000.0) -> list:
+    """Chemical enthalpy levels (K per unit mass fraction) of the synthetic
+    mechanism's species: species 0 and 1 (fuel and oxidiser) at h_top, the
+    intermediates 2 .. n_species - 2 at seeded levels in (0.05, 0.9) h_top,
+    the last species (inert) at 0."""
+    rng = np.random.default_rng([seed, 1])
+    h = [h_top, h_top] + [float(v) for v in rng.uniform(0.05, 0.9, n_species - 3) * h_top] + [0.0]
+    return h
+
+
 def synthetic_mechanism(n_species: int = 9, n_reactions: int = 20, seed: int = 2305,
                         log10A=(6.0, 13.0), Ta=(5000.0, 25000.0), b=(-1.0, 1.0),
-                        q=(0.0, 1.0e3)) -> list:
-    """Seeded synthetic mechanism: per reaction two distinct reactants and
-    one or two distinct products among the species; mass coefficients:
-    reactants lose fractions that sum to 1 over the reactants, products gain
-    the same total, so that the coefficients sum to zero.  Heat releases
-    are uniform in `q` (K per unit progress): with rate coefficients up to
-    ~1e8 per step most reactions complete within one step, and larger heat
-    releases make the explicit coupled step diverge."""
+                        h_top: float = 2000.0) -> list:
+    """Seeded synthetic mechanism that conserves energy.  Species carry the
+    enthalpy levels of `synthetic_enthalpies`; the last species is inert
+    and takes part in no reaction.  Per reaction: two distinct reactants and
+    one or two distinct products, every product below both reactants in
+    enthalpy (the first reaction burns the fuel with the oxidiser); mass
+    coefficients: the reactants lose fractions a, 1 - a that sum to 1, the
+    products gain the same total; the heat release per unit progress is
+    the enthalpy the reaction gives up, q = sum_r a_r h_r - sum_p c_p h_p > 0
+    (K).  Then T + sum_k h_k Y_k is invariant under the sources, so no cycle
+    of reactions can heat the gas without bound.  Rate parameters: log10 A,
+    Ta and b uniform in the given ranges."""
     rng = np.random.default_rng(seed)
+    h = synthetic_enthalpies(n_species, seed, h_top)
+    reactive = list(range(n_species - 1))
     rx = []
-    for _ in range(n_reactions):
-        perm = rng.permutation(n_species)
-        reac = [int(perm[0]), int(perm[1])]
-        nprod = int(rng.integers(1, 3))
-        prods = [int(p) for p in perm[2:2 + nprod]]
+    while len(rx) < n_reactions:
+        if not rx:
+            reac = [0, 1]
+        else:
+            reac = [int(v) for v in rng.choice(reactive, 2, replace=False)]
+        lo = min(h[reac[0]], h[reac[1]])
+        below = [k for k in reactive if h[k] < lo and k not in reac]
+        if not below:
+            continue
+        nprod = min(int(rng.integers(1, 3)), len(below))
+        prods = [int(v) for v in rng.choice(below, nprod, replace=False)]
         nu = [0.0] * n_species
         a = float(rng.uniform(0.2, 0.8))
         nu[reac[0]] = -a
@@ -535,9 +557,9 @@ def synthetic_mechanism(n_species: int = 9, n_reactions: int = 20, seed: int = 2
             c = float(rng.uniform(0.2, 0.8))
             nu[prods[0]] = c
             nu[prods[1]] = 1.0 - c
+        q = -sum(nu[k] * h[k] for k in range(n_species))
         rx.append(Reaction(reactants=reac, A=float(10.0 ** rng.uniform(*log10A)),
-                           b=float(rng.uniform(*b)), Ta=float(rng.uniform(*Ta)), nu=nu,
-                           q=float(rng.uniform(*q))))
+                           b=float(rng.uniform(*b)), Ta=float(rng.uniform(*Ta)), nu=nu, q=q))
     return rx
 
 

@@ -4,7 +4,7 @@ FP64 Arrhenius source and reductions) against the FP64 oracle.
 These are accuracy reports with stated bounds, not bit-parity: the storage
 rounding (2^-24 relative for float, 2^-11 for half, on g / (w_i cs^2)) and
 float arithmetic (2^-24 per operation) accumulate over the run.  The bounds
-below are about 5x the errors measured on MI355X for the same runs.
+below are about twice the errors measured on MI355X for the same runs.
 """
 import numpy as np
 import pytest
@@ -16,12 +16,16 @@ from .gpu_util import need_gpu, oracle_threads, say
 pytestmark = pytest.mark.gpu
 
 # bounds on max |T - T_oracle| / (T_b - T_u), max |u - u_oracle| / max |u_oracle|
-# and the flame-position shift in cells.  Measured on MI355X: channel 2000
-# steps fp32 (1.8e-5, 9.9e-5, 8e-4), fp16 (9.0e-4, 3.9e-2, 9e-5); porous 60
-# steps fp32 (5.9e-7, 8.8e-6), fp16 (5.9e-6, 3.5e-4).
-CHANNEL_BOUNDS = {"fp32": (1e-4, 5e-4, 5e-3), "fp16": (5e-3, 2e-1, 5e-2)}
-POROUS_BOUNDS = {"fp32": (5e-6, 5e-5), "fp16": (5e-5, 2e-3)}
-MECH_BOUNDS = {"fp32": (1e-3, 1e-3, 1e-2), "fp16": (1e-2, 1e-2, 1e-1)}
+# (and max |Y - Y_oracle| for the mechanism) and the flame-position shift in
+# cells, at about twice the errors measured on MI355X for the same runs:
+# channel 2000 steps fp32 (2.26e-5, 1.23e-4, 1.02e-3 cells), fp16 (7.7e-4,
+# 4.64e-2, 4.2e-4); porous 60 steps fp32 (6.3e-7, 8.4e-6), fp16 (6.9e-6,
+# 3.46e-4); mechanism 200 steps fp32 (T 3.26e-6, Y 1.39e-6, u 1.84e-5),
+# fp16 (T 1.07e-5, Y 1.48e-6, u 5.5e-4).  Both sides are deterministic, so
+# the margin covers toolchain-level rounding changes, not run-to-run noise.
+CHANNEL_BOUNDS = {"fp32": (5e-5, 2.5e-4, 2.5e-3), "fp16": (1.6e-3, 1e-1, 1e-3)}
+POROUS_BOUNDS = {"fp32": (1.3e-6, 1.7e-5), "fp16": (1.4e-5, 7e-4)}
+MECH_BOUNDS = {"fp32": (7e-6, 3e-6, 4e-5), "fp16": (2.2e-5, 3e-6, 1.1e-3)}
 
 
 def _flame_x(d, prob):

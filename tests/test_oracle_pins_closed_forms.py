@@ -247,6 +247,45 @@ def test_zero_d_reactor_mechanism_brute_force(oracle_mod):
     assert max(nsubs) > 1 and T > 1100.0 + 1.0, (nsubs, T)
 
 
+def test_mechanism_conserves_energy(oracle_mod):
+    """The synthetic mechanism's heat releases are the enthalpy its
+    reactions give up, so T + sum_k h_k Y_k stays constant under the oracle's
+    sub-cycled sources (explicit Euler sub-steps and the limiter change only
+    how far each reaction goes, never this sum) in a homogeneous box over
+    400 steps from burnt, fresh and hot-fresh states, and the temperature
+    stays below the bound T_0 + sum_k h_k Y_k(0).  (The generator's first
+    version drew reactants and products without enthalpy levels: its
+    reaction cycles, which also consumed the inert, heated the burnt state
+    of such a box from 1800 K to 3077 K in 2000 steps.)"""
+    ns = 9
+    rx = W.synthetic_mechanism(ns, 20, seed=2305)
+    h = np.array(W.synthetic_enthalpies(ns, 2305))
+    assert all(r.q > 0 for r in rx) and all(v == 0.0 for r in rx for v in [r.nu[ns - 1]])
+    n = 3
+    shape = (n, n, n)
+    states = [((0.0, 0.0, 0.05, 0.05, 0.05, 0.05, 0.0, 0.05, 0.75), 1800.0),
+              ((0.05, 0.2) + (0.0,) * 6 + (0.75,), 1800.0),
+              ((0.02, 0.1, 0.03, 0.0, 0.04, 0.0, 0.01, 0.05, 0.75), 1400.0)]
+    for Y0, T0 in states:
+        prob = W.Problem(
+            name="reactor9e", lattice=27, nx=n, ny=n, nz=n, faces=("periodic",) * 6, face_T=(300.0,) * 6,
+            tau=0.6, prandtl=0.7, dt_phys=1e-7, T_ref=300.0, W_ref=28.0, W=(28.0,) * ns, reactions=rx,
+            u_in=(0.0, 0.0, 0.0), T_in=300.0, Y_in=tuple(Y0), mask=np.zeros(shape, np.uint8),
+            wall_T=np.full(shape, 300.0), T0=np.full(shape, T0),
+            Y0=np.stack([np.full(shape, v) for v in Y0]), chem_substeps_max=64)
+        o = oracle_mod.Oracle(prob)
+        e0 = T0 + float(np.dot(h, Y0))
+        done = 0
+        for level in (100, 400):
+            o.step(level - done)
+            done = level
+            f = o.fields()
+            T = float(f["T"].mean())
+            Y = np.array([float(f["Y"][k].mean()) for k in range(ns)])
+            assert abs(T + float(np.dot(h, Y)) - e0) <= 1e-9 * e0, (Y0, level, T)
+            assert T <= e0 + 1e-9, (Y0, level, T)
+
+
 # ------------------------------------------------------------- diagnostics
 def _one_wall_conduction(oracle_mod, H, wall_bottom):
     """Steady conduction across H fluid rows (periodic in x, 4 columns):
