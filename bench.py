@@ -54,7 +54,16 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_05657_amd", "csrc", f)
 # runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by the same
 # counters on a plain device copy of known size, valid for the kernel
 # sources whose SHA-256 is given (summaries under profiles/).
-TRAFFIC = {}
+# HBM bytes per launch of the headline's dominant kernel from rocprofv3
+# FETCH_SIZE + WRITE_SIZE (each scaled by what a 512 MiB device copy reads
+# as), valid only for the kernel sources they were taken on
+# (profiles/traffic_porous_mech_512x256x256_and_porous_256.md)
+TRAFFIC = {
+    ("porous3d_mech_512x256x256", "fp64", "chem_kernel"): {
+        "bytes_per_launch": 6121.1e6,
+        "kernel_sha256": "38a08c641f024078a89bfd905882f544b06124bf7a41f2943225f627dcc21cc7",
+    },
+}
 POP_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 SCALAR_BYTES = {"fp64": 8, "fp32": 4, "fp16": 4}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16": "f32"}
