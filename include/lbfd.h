@@ -378,6 +378,34 @@ int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwall
 int lbfd_adjoint_dev(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwallT, double *dJ_dA,
                      double *dJ_dTa);
 
+/* The two derivatives of one FP64 step at the current state s^L, for the
+ * same contexts as lbfd_adjoint (LBFD_EINVAL otherwise); like lbfd_adjoint
+ * they are not methods of the paper.  Neither advances the context.  Host
+ * arrays in the state's layout: populations [Q][N] (the post-collision
+ * populations the step pulls from), scalars [1 + n_species][N] (T, then
+ * Y_k), wall temperatures [N], Arrhenius parameters [n_reactions]; entries
+ * of solid cells neither act on nor receive anything.  q is the
+ * per-level term of the objective selected by lbfd_set_objective (wall
+ * heat flux or flame position at level L).
+ *
+ * lbfd_step_tangent: the Jacobian-vector product.  Given tangents of the
+ * inputs (dpop, dsc; dwallT, dA, dTa may be NULL for zero), returns the
+ * tangents of the populations and scalars the step writes (dpop_out,
+ * dsc_out; zero at solid cells) and that of q (dq).  Evaluated in dual
+ * numbers, cell by cell, from the step's formulas.
+ *
+ * lbfd_step_adjoint: the vector-Jacobian product, one backward step of
+ * lbfd_adjoint.  Given the adjoint of the step's outputs (lam_pop, lam_sc)
+ * and a weight wq of q, returns lam_pop_in, lam_sc_in = (dF/ds)^T lam +
+ * wq (dq/ds)^T and, if not NULL, the same products for the wall
+ * temperatures (dJ_dwallT [N]) and A_j, Ta_j (dJ_dA, dJ_dTa).  For any
+ * tangent dx and adjoint lam the two satisfy <J dx, lam> = <dx, J^T lam>
+ * up to rounding.  Synchronous. */
+int lbfd_step_tangent(lbfd_ctx *c, const double *dpop, const double *dsc, const double *dwallT, const double *dA,
+                      const double *dTa, double *dpop_out, double *dsc_out, double *dq);
+int lbfd_step_adjoint(lbfd_ctx *c, const double *lam_pop, const double *lam_sc, double wq, double *lam_pop_in,
+                      double *lam_sc_in, double *dJ_dwallT, double *dJ_dA, double *dJ_dTa);
+
 /* Per-part timing: queue nsteps steps with their parts launched separately
  * on the context stream, each bracketed by HIP events -- the chemistry
  * launch (mechanisms of more than four species; 0 otherwise), the

@@ -1,4 +1,4 @@
-// lbfd_adjoint.hip -- discrete adjoint of the coupled step (FP64).
+// lbfd_adjoint.hip -- derivatives of the FP64 coupled step.
 //
 // The objective is J = sum_{n = 0}^{N-1} w_n q(s^n), w_n = 1 inside the
 // chosen window of levels, with q either the wall heat flux (the sum over
@@ -9,62 +9,114 @@
 // adjoint recursion is lambda^N = 0,
 //   lambda^n = (dF/ds^n)^T lambda^{n+1} + (dq/ds^n)^T,
 //   dJ/dtheta = sum_n (dF/dtheta)^T lambda^{n+1} + dq^n/dtheta.
-// One thread per fluid cell c evaluates the cell's update (the forward
-// step's formulas, in the general geometry path: neighbours classified on
-// the fly, each stencil point and density evaluated separately) in dual
-// numbers, once per input slot of the cell (pull source,
-// stencil scalar, wall temperature, Arrhenius parameter) with a unit tangent
-// on that slot; the tangent of the outputs dotted with the cell's output
-// adjoint is that slot's contribution, added atomically to the adjoint of
-// the variable behind the slot.  Steps are recomputed from checkpoints
-// taken every K steps (host side, lbfd_api.hip).
+// One thread per fluid cell c gathers the cell's inputs (pull sources,
+// the finite-difference stencil's scalars, ghost wall temperatures; in the
+// general geometry path: neighbours classified on the fly) and runs the
+// cell's update forward in FP64, then backward (cell_vjp): the reverse of
+// every operation, hand-derived, from the adjoint of the cell's outputs to
+// those of its inputs.  The sub-stepped Arrhenius source is differentiated
+// in forward mode instead (a 5 x 5 Jacobian carried through the sub-steps,
+// and one pass per reaction for A_j, Ta_j): its state is small and its
+// sub-step count data-dependent.  Each pulled population is read by exactly
+// one cell, so its adjoint is stored; the stencil scalars' and wall
+// temperatures' adjoints are added atomically.  Steps are recomputed from
+// checkpoints taken every K steps (host side, lbfd_api.hip).
+//
+// tangent_kernel evaluates the same update in dual numbers with a given
+// tangent of every input (the Jacobian-vector product of one step); the
+// identity <J dx, lambda> = <dx, J^T lambda> between the two checks the
+// reverse sweep.  Both evaluate the forward step's formulas in the general
+// geometry path; rate coefficients are formed as in the step's chemistry
+// (A dt exp(b ln T - Ta/T) with the step's exponential).
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "lbfd_kernels.h"
 
 namespace lbfd {
 
 // ----------------------------------------------------------- dual numbers
-struct Dual {
-    double v, d;
-    __host__ __device__ Dual() : v(0.0), d(0.0) {}
-    __host__ __device__ Dual(double x) : v(x), d(0.0) {}
-    __host__ __device__ Dual(double x, double dx) : v(x), d(dx) {}
-    __host__ __device__ explicit operator double() const { return v; }
-    __device__ Dual &operator+=(const Dual &b) { v += b.v; d += b.d; return *this; }
-    __device__ Dual &operator-=(const Dual &b) { v -= b.v; d -= b.d; return *this; }
-    __device__ Dual &operator*=(const Dual &b) { d = d * b.v + v * b.d; v *= b.v; return *this; }
+// Value and N tangents.
+template <int N>
+struct DualN {
+    double v;
+    double d[N];
+    __device__ DualN() : v(0.0)
+    {
+        for (int i = 0; i < N; ++i) d[i] = 0.0;
+    }
+    __device__ DualN(double x) : v(x)
+    {
+        for (int i = 0; i < N; ++i) d[i] = 0.0;
+    }
+    __device__ explicit operator double() const { return v; }
+    __device__ DualN &operator+=(const DualN &b)
+    {
+        v += b.v;
+        for (int i = 0; i < N; ++i) d[i] += b.d[i];
+        return *this;
+    }
+    __device__ DualN &operator-=(const DualN &b)
+    {
+        v -= b.v;
+        for (int i = 0; i < N; ++i) d[i] -= b.d[i];
+        return *this;
+    }
+    __device__ DualN &operator*=(const DualN &b)
+    {
+        for (int i = 0; i < N; ++i) d[i] = d[i] * b.v + v * b.d[i];
+        v *= b.v;
+        return *this;
+    }
 };
-__device__ inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
-__device__ inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
-__device__ inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
-__device__ inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
-__device__ inline Dual operator/(Dual a, Dual b)
+using Dual = DualN<1>;
+
+template <int N> __device__ inline DualN<N> operator+(DualN<N> a, const DualN<N> &b) { return a += b; }
+template <int N> __device__ inline DualN<N> operator-(DualN<N> a, const DualN<N> &b) { return a -= b; }
+template <int N> __device__ inline DualN<N> operator*(DualN<N> a, const DualN<N> &b) { return a *= b; }
+template <int N> __device__ inline DualN<N> operator-(const DualN<N> &a)
+{
+    DualN<N> r(-a.v);
+    for (int i = 0; i < N; ++i) r.d[i] = -a.d[i];
+    return r;
+}
+// (divisions, not a reciprocal: with b.v subnormal, 1 / b.v overflows and a
+// zero numerator would give 0 * inf)
+template <int N> __device__ inline DualN<N> operator/(const DualN<N> &a, const DualN<N> &b)
 {
     const double q = a.v / b.v;
-    return Dual(q, (a.d - q * b.d) / b.v);
+    DualN<N> r(q);
+    for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - q * b.d[i]) / b.v;
+    return r;
 }
-__device__ inline Dual rcp(Dual a)
+// f(a) with f(a.v) = fv and f'(a.v) = fd
+template <int N> __device__ inline DualN<N> chain(const DualN<N> &a, double fv, double fd)
+{
+    DualN<N> r(fv);
+    for (int i = 0; i < N; ++i) r.d[i] = fd * a.d[i];
+    return r;
+}
+template <int N> __device__ inline DualN<N> rcp(const DualN<N> &a)
 {
     const double r = rcp(a.v);
-    return Dual(r, -a.d * r * r);
+    return chain(a, r, -r * r);
 }
-__device__ inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
-__device__ inline bool operator>(Dual a, Dual b) { return a.v > b.v; }
-__device__ inline bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
-__device__ inline bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
+template <int N> __device__ inline bool operator<(const DualN<N> &a, const DualN<N> &b) { return a.v < b.v; }
+template <int N> __device__ inline bool operator>(const DualN<N> &a, const DualN<N> &b) { return a.v > b.v; }
+template <int N> __device__ inline bool operator>=(const DualN<N> &a, const DualN<N> &b) { return a.v >= b.v; }
+template <int N> __device__ inline bool operator<=(const DualN<N> &a, const DualN<N> &b) { return a.v <= b.v; }
 // the exponential of the forward chemistry (exp_tab)
-__device__ inline Dual dexp(Dual a)
+template <int N> __device__ inline DualN<N> dexp(const DualN<N> &a)
 {
     const double e = exp_tab(a.v, kExp2Tab);
-    return Dual(e, e * a.d);
+    return chain(a, e, e);
 }
 __device__ inline double dexp(double a) { return exp_tab(a, kExp2Tab); }
-__device__ inline Dual dlog(Dual a) { return Dual(log(a.v), a.d * rcp(a.v)); }
+template <int N> __device__ inline DualN<N> dlog(const DualN<N> &a) { return chain(a, log(a.v), rcp(a.v)); }
 __device__ inline double dlog(double a) { return log(a); }
-__device__ inline double val(Dual a) { return a.v; }
+template <int N> __device__ inline double val(const DualN<N> &a) { return a.v; }
 __device__ inline double val(double a) { return a; }
-__device__ inline double tan_(Dual a) { return a.d; }
 
 // ------------------------------------------------------------ cell inputs
 // Stencil slots: 0 = the cell, 1 + 4 d + j for axis d and m = -2, -1, 1, 2.
@@ -175,20 +227,72 @@ __device__ A density_a(const KParams &P, A T, const A (&Y)[NSP])
     return A(P.T_ref_over_W_ref) / (T * s);
 }
 
-// The cell's update in the number type A (double or Dual), seeded at slot
-// `seed`: outputs out[0..Q) = g*, out[Q] = T^{n+1}, out[Q+1+k] = Y_k^{n+1};
-// *qc = the cell's wall-heat-flux contribution at level n.
-template <int Q, int NSP, class A>
-__device__ void cell_eval(const KParams &P, const CellIn<Q, NSP> &in, int seed, A (&out)[Q + 1 + NSP], A &qc)
+// Arrhenius source of one cell over the step in the number type A (the
+// forward chemistry's sub-stepping, rate coefficients and limiter): from
+// the cell's T0, Y0 and the reactions' (A_j, Ta_j) = par(j) to (srcT, srcY).
+// The sub-step count and the limiter's choice follow the values.
+template <int NSP, class A, class Par>
+__device__ void chem_source(const KParams &P, const A &T0, const A (&Y0)[NSP], Par par, A &srcT, A (&srcY)[NSP])
 {
+    const bool anyb = P.chem_anyb != 0;
+    int nsub = 1;
+    if (P.chem_substeps_max > 1) {
+        const double lnT = anyb ? log(val(T0)) : 0.0, invT = rcp(val(T0));
+        double kmax = 0.0;
+        for (int j = 0; j < P.n_rx; ++j) kmax = fmax(kmax, rate_coeff_l(P.rxk[j], lnT, invT, kExp2Tab));
+        const double want = ceil(kmax / 0.1);
+        nsub = want < 1.0 ? 1 : want > (double)P.chem_substeps_max ? P.chem_substeps_max : (int)want;
+    }
+    const double inv_nsub = nsub == 1 ? 1.0 : rcp((double)nsub);
+    A dT = 0.0, dY[NSP];
+    for (int k = 0; k < NSP; ++k) dY[k] = 0.0;
+    for (int s = 0; s < nsub; ++s) {
+        const A Tc = T0 + dT;
+        A Yc[NSP], incT = 0.0, incY[NSP];
+        for (int k = 0; k < NSP; ++k) {
+            Yc[k] = Y0[k] + dY[k];
+            incY[k] = 0.0;
+        }
+        const A lnTc = anyb ? dlog(Tc) : A(0.0), invTc = rcp(Tc);
+        for (int j = 0; j < P.n_rx; ++j) {
+            const lbfd_reaction &r = P.rx[j];
+            A Aj, Taj;
+            par(j, Aj, Taj);
+            A rr = Aj * A(P.dt_phys) * dexp(A(r.b) * lnTc - Taj * invTc) * A(inv_nsub);
+            for (int mm = 0; mm < r.n_react; ++mm) rr *= Yc[r.react[mm]];
+            for (int k = 0; k < NSP; ++k) incY[k] += A(r.nu_mass[k]) * rr;
+            incT += A(r.q_over_cp) * rr;
+        }
+        // positivity limiter (value-based choice, differentiable scale)
+        A lam = 1.0;
+        for (int k = 0; k < NSP; ++k)
+            if (val(incY[k]) < 0.0 && val(Yc[k] + incY[k]) < 0.0) {
+                const A l = (val(Yc[k]) > 0.0 ? Yc[k] : A(0.0)) / (-incY[k]);
+                if (val(l) < val(lam)) lam = l;
+            }
+        dT += lam * incT;
+        for (int k = 0; k < NSP; ++k) dY[k] += lam * incY[k];
+    }
+    srcT = dT;
+    for (int k = 0; k < NSP; ++k) srcY[k] = dY[k];
+}
+
+// The cell's update in dual numbers with the tangent tan[slot] of every
+// input slot (Slots numbering): outputs out[0..Q) = g*, out[Q] = T^{n+1},
+// out[Q+1+k] = Y_k^{n+1}; *qc = the cell's wall-heat-flux contribution at
+// level n.
+template <int Q, int NSP>
+__device__ void cell_eval(const KParams &P, const CellIn<Q, NSP> &in, const double *tan, Dual (&out)[Q + 1 + NSP],
+                          Dual &qc)
+{
+    using A = Dual;
     using L = Lat<Q>;
     using S = Slots<Q, NSP>;
     constexpr int D = L::D;
     auto mk = [&](double v, int slot) -> A {
-        if constexpr (std::is_same<A, Dual>::value)
-            return Dual(v, slot == seed ? 1.0 : 0.0);
-        else
-            return v;
+        A r(v);
+        r.d[0] = tan[slot];
+        return r;
     };
     A g[Q];
     for (int i = 0; i < Q; ++i) g[i] = mk(in.g[i], S::pull + i) + A(in.corr[i]);
@@ -228,9 +332,8 @@ __device__ void cell_eval(const KParams &P, const CellIn<Q, NSP> &in, int seed, 
         }
     }
     const A rho = R[0];
-    A sg = 0.0, m[3] = {0.0, 0.0, 0.0};
+    A m[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < Q; ++i) {
-        sg += g[i];
         m[0] += A((double)L::cx(i)) * g[i];
         m[1] += A((double)L::cy(i)) * g[i];
         m[2] += A((double)L::cz(i)) * g[i];
@@ -273,53 +376,15 @@ __device__ void cell_eval(const KParams &P, const CellIn<Q, NSP> &in, int seed, 
     diffT *= alpha;
     for (int k = 0; k < NSP; ++k) diffY[k] *= alpha;
 
-    // Arrhenius source (same sub-stepping and limiter as the forward)
-    A srcT = 0.0, srcY[NSP];
-    {
-        // rate coefficients k_j = A_j dt exp(b_j ln T - Ta_j / T), ln T and
-        // 1/T shared by the reactions, as in the forward chemistry()
-        const A Tc0 = T[0];
-        const bool anyb = P.chem_anyb != 0;
-        int nsub = 1;
-        if (P.chem_substeps_max > 1) {
-            const double lnT = anyb ? log(val(Tc0)) : 0.0, invT = rcp(val(Tc0));
-            double kmax = 0.0;
-            for (int j = 0; j < P.n_rx; ++j) kmax = fmax(kmax, rate_coeff_l(P.rxk[j], lnT, invT, kExp2Tab));
-            const double want = ceil(kmax / 0.1);
-            nsub = want < 1.0 ? 1 : want > (double)P.chem_substeps_max ? P.chem_substeps_max : (int)want;
-        }
-        const double inv_nsub = nsub == 1 ? 1.0 : rcp((double)nsub);
-        A dT = 0.0, dY[NSP];
-        for (int k = 0; k < NSP; ++k) dY[k] = 0.0;
-        for (int s = 0; s < nsub; ++s) {
-            const A Tc = Tc0 + dT;
-            A Yc[NSP], incT = 0.0, incY[NSP];
-            for (int k = 0; k < NSP; ++k) {
-                Yc[k] = Y[0][k] + dY[k];
-                incY[k] = 0.0;
-            }
-            const A lnTc = anyb ? dlog(Tc) : A(0.0), invTc = rcp(Tc);
-            for (int j = 0; j < P.n_rx; ++j) {
-                const lbfd_reaction &r = P.rx[j];
-                const A Aj = mk(r.A, S::param + 2 * j), Taj = mk(r.Ta, S::param + 2 * j + 1);
-                A rr = Aj * A(P.dt_phys) * dexp(A(r.b) * lnTc - Taj * invTc) * A(inv_nsub);
-                for (int mm = 0; mm < r.n_react; ++mm) rr *= Yc[r.react[mm]];
-                for (int k = 0; k < NSP; ++k) incY[k] += A(r.nu_mass[k]) * rr;
-                incT += A(r.q_over_cp) * rr;
-            }
-            // positivity limiter (value-based choice, differentiable scale)
-            A lam = 1.0;
-            for (int k = 0; k < NSP; ++k)
-                if (val(incY[k]) < 0.0 && val(Yc[k] + incY[k]) < 0.0) {
-                    const A l = (val(Yc[k]) > 0.0 ? Yc[k] : A(0.0)) / (-incY[k]);
-                    if (val(l) < val(lam)) lam = l;
-                }
-            dT += lam * incT;
-            for (int k = 0; k < NSP; ++k) dY[k] += lam * incY[k];
-        }
-        srcT = dT;
-        for (int k = 0; k < NSP; ++k) srcY[k] = dY[k];
-    }
+    A srcT, srcY[NSP], Y0[NSP];
+    for (int k = 0; k < NSP; ++k) Y0[k] = Y[0][k];
+    chem_source<NSP>(
+        P, T[0], Y0,
+        [&](int j, A &Aj, A &Taj) {
+            Aj = mk(P.rx[j].A, S::param + 2 * j);
+            Taj = mk(P.rx[j].Ta, S::param + 2 * j + 1);
+        },
+        srcT, srcY);
 
     const A DtT = diffT + srcT;
     A DtY[NSP], invW = 0.0;
@@ -355,12 +420,493 @@ __device__ void cell_eval(const KParams &P, const CellIn<Q, NSP> &in, int seed, 
     for (int i = 0; i < Q; ++i) out[i] = rc * (h[i] - A(L::w(i)) * sh) + A(0.5) * xi[i];
 }
 
+// ------------------------------------------------------- the reverse sweep
+// Adjoints of the cell's inputs.
+template <int Q, int NSP>
+struct CellAdj {
+    double g[Q];                  // pulled populations
+    double T[kSlots], Y[kSlots][NSP];  // stencil scalars (fluid slots)
+    double Tw[kSlots];            // ghost wall temperatures
+};
+
+// Reverse of cm_fwd_line at the input (a, b, d): (la, lb, ld) holds the
+// adjoints of (m0, m1, m2) and receives those of (a, b, d); returns the
+// contribution to the adjoint of u.
+__device__ __forceinline__ double cm_fwd_line_adj(double a, double b, double d, double u, double &la, double &lb,
+                                                  double &ld)
+{
+    const double m0 = a + b + d;
+    const double l0 = la, l1 = lb, l2 = ld;
+    la = l0 - (1.0 + u) * l1 + (1.0 + u) * (1.0 + u) * l2;
+    lb = l0 - u * l1 + u * u * l2;
+    ld = l0 + (1.0 - u) * l1 + (1.0 - u) * (1.0 - u) * l2;
+    return -m0 * l1 + (2.0 * (a - d) + 2.0 * u * m0) * l2;
+}
+
+// Reverse of cm_inv_line at the input moments (m0, m1, m2).
+__device__ __forceinline__ double cm_inv_line_adj(double m0, double m1, double m2, double u, double &la, double &lb,
+                                                  double &ld)
+{
+    const double uu = u * u;
+    const double A = la, B = lb, E = ld;
+    la = 0.5 * (uu - u) * A + (1.0 - uu) * B + 0.5 * (uu + u) * E;
+    lb = 0.5 * (2.0 * u - 1.0) * A - 2.0 * u * B + 0.5 * (2.0 * u + 1.0) * E;
+    ld = 0.5 * A - B + 0.5 * E;
+    (void)m2;
+    return 0.5 * (m0 * (2.0 * u - 1.0) + 2.0 * m1) * A - 2.0 * (u * m0 + m1) * B +
+           0.5 * (m0 * (2.0 * u + 1.0) + 2.0 * m1) * E;
+}
+
+// Reverse of relax(): the orders >= 2 were scaled by (1 - omega).
+template <int Q>
+__device__ __forceinline__ void relax_adj(double (&lk)[Q], double om2, double om3, double om4)
+{
+    sfor<0, Q>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        constexpr int p = j % 3, q = (j / 3) % 3, r = (Q == 27) ? j / 9 : 0;
+        constexpr int order = p + q + r;
+        if constexpr (order >= 2) lk[j] *= 1.0 - (order == 2 ? om2 : order == 3 ? om3 : om4);
+    });
+}
+
+// Reverse of weno3(m2, m1, c0, p1, p2, u) for the adjoint lam of its
+// result: adds the adjoints of the five stencil values to l[0..5) (u
+// enters through its sign only).
+__device__ __forceinline__ void weno3_adj(double m2, double m1, double c0, double p1, double p2, double u, double lam,
+                                          double (&l)[5])
+{
+    const bool neg = u < 0.0;
+    const double A = neg ? p2 : m2, B = neg ? p1 : m1, E = neg ? m1 : p1;
+    const double eps = 1e-6;
+    const double dA = B - A, dB = c0 - B, dE = E - c0;
+    const double eA = eps + dA * dA, eB = eps + dB * dB, eE = eps + dE * dE;
+    const double eA2 = eA * eA, eB2 = eB * eB, eE2 = eE * eE;
+    const double den_p = eE2 + 2.0 * eB2, den_m = eB2 + 2.0 * eA2;
+    const double ip = 1.0 / den_p, im = 1.0 / den_m;
+    const double w_p = eE2 * ip, w_m = eB2 * im;
+    const double q0p = 1.5 * c0 - 0.5 * B, q1p = 0.5 * (c0 + E);
+    const double q0m = 1.5 * B - 0.5 * A, q1m = 0.5 * (B + c0);
+    const double L = neg ? -lam : lam;
+    const double lq1p = L * (1.0 - w_p), lq0p = L * w_p, lw_p = L * (q0p - q1p);
+    const double lq1m = -L * (1.0 - w_m), lq0m = -L * w_m, lw_m = -L * (q0m - q1m);
+    const double leE2 = lw_p * 2.0 * eB2 * ip * ip;
+    const double leB2 = -lw_p * 2.0 * eE2 * ip * ip + lw_m * 2.0 * eA2 * im * im;
+    const double leA2 = -lw_m * 2.0 * eB2 * im * im;
+    const double ldA = leA2 * 4.0 * eA * dA, ldB = leB2 * 4.0 * eB * dB, ldE = leE2 * 4.0 * eE * dE;
+    const double lA = -ldA - 0.5 * lq0m;
+    const double lB = ldA - ldB - 0.5 * lq0p + 1.5 * lq0m + 0.5 * lq1m;
+    const double lC = ldB - ldE + 1.5 * lq0p + 0.5 * lq1p + 0.5 * lq1m;
+    const double lE = ldE + 0.5 * lq1p;
+    l[2] += lC;
+    if (neg) {
+        l[4] += lA;
+        l[3] += lB;
+        l[1] += lE;
+    } else {
+        l[0] += lA;
+        l[1] += lB;
+        l[3] += lE;
+    }
+}
+
+// The cell's update forward in FP64, then its reverse: from the adjoint lo
+// of the outputs (g*, T^{n+1}, Y^{n+1}), the weight wq of the cell's
+// wall-heat-flux term and the weight wT0 of its own T (the flame position's
+// linear term) to the adjoints of the inputs (a) and of the reactions'
+// (A_j, Ta_j), added to lam_param[2 j], lam_param[2 j + 1] (LDS).
+template <int Q, int NSP>
+__device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, const double (&lo)[Q + 1 + NSP], double wq,
+                         double wT0, CellAdj<Q, NSP> &a, double *lam_param)
+{
+    using L = Lat<Q>;
+    constexpr int D = L::D;
+    constexpr double c1[5] = {1.0 / 12.0, -8.0 / 12.0, 0.0, 8.0 / 12.0, -1.0 / 12.0};
+    constexpr double c2[5] = {-1.0 / 12.0, 16.0 / 12.0, -30.0 / 12.0, 16.0 / 12.0, -1.0 / 12.0};
+    const double c0 = P.T_ref_over_W_ref;
+
+    // ------------------------------------------------ forward (values)
+    double g[Q];
+    for (int i = 0; i < Q; ++i) g[i] = in.g[i] + in.corr[i];
+    double T[kSlots], Y[kSlots][NSP], R[kSlots], Sw[kSlots];  // Sw = sum_k Y_k / W_k
+    for (int s = 0; s < kSlots; ++s) {
+        if (in.kind[s] != kFluid) continue;
+        T[s] = in.T[s];
+        double sw = 0.0;
+        for (int k = 0; k < NSP; ++k) {
+            Y[s][k] = in.Y[k][s];
+            sw += Y[s][k] * P.invW[k];
+        }
+        Sw[s] = sw;
+        R[s] = c0 / (T[s] * sw);
+    }
+    for (int s = 0; s < kSlots; ++s) {
+        if (in.kind[s] == kFluid) continue;
+        const int im = in.img[s];
+        Sw[s] = Sw[im];
+        if (in.kind[s] == kIso) {
+            T[s] = 2.0 * in.Tw[s] - T[im];
+            for (int k = 0; k < NSP; ++k) Y[s][k] = Y[im][k];
+            R[s] = 2.0 * (c0 / (in.Tw[s] * Sw[im])) - R[im];
+        } else if (in.kind[s] == kInflow) {
+            T[s] = 2.0 * P.T_in - T[im];
+            for (int k = 0; k < NSP; ++k) Y[s][k] = 2.0 * P.Y_in[k] - Y[im][k];
+            R[s] = 2.0 * P.rho_in - R[im];
+        } else {
+            T[s] = T[im];
+            for (int k = 0; k < NSP; ++k) Y[s][k] = Y[im][k];
+            R[s] = R[im];
+        }
+    }
+    const double rho = R[0];
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+        m[0] += L::cx(i) * g[i];
+        m[1] += L::cy(i) * g[i];
+        m[2] += L::cz(i) * g[i];
+    }
+    const double inv_rc = 1.0 / (rho * kCs2);
+    const double u[3] = {m[0] * inv_rc, m[1] * inv_rc, m[2] * inv_rc};
+    const double inv_rho = 1.0 / rho;
+    double diffT = 0.0, grad[3] = {0.0, 0.0, 0.0}, diffY[NSP];
+    double cT[3] = {0.0, 0.0, 0.0}, cY[3][NSP], sumc[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < NSP; ++k) diffY[k] = 0.0;
+    for (int d = 0; d < D; ++d) {
+        const int sl[5] = {1 + 4 * d, 2 + 4 * d, 0, 3 + 4 * d, 4 + 4 * d};
+        bool near = false;
+        for (int j = 0; j < 5; ++j) near |= in.kind[sl[j]] != kFluid;
+        const double d1r = d1(R[sl[0]], R[sl[1]], R[sl[2]], R[sl[3]], R[sl[4]]);
+        {
+            const double p = T[sl[0]], b = T[sl[1]], c = T[sl[2]], e = T[sl[3]], f = T[sl[4]];
+            diffT += d2(p, b, c, e, f) + d1r * d1(p, b, c, e, f) * inv_rho;
+            cT[d] = near ? 0.5 * (e - b) : weno3(p, b, c, e, f, u[d]);
+        }
+        for (int k = 0; k < NSP; ++k) {
+            const double p = Y[sl[0]][k], b = Y[sl[1]][k], c = Y[sl[2]][k], e = Y[sl[3]][k], f = Y[sl[4]][k];
+            diffY[k] += d2(p, b, c, e, f) + d1r * d1(p, b, c, e, f) * inv_rho;
+            cY[d][k] = near ? 0.5 * (e - b) : weno3(p, b, c, e, f, u[d]);
+            sumc[d] += cY[d][k];
+        }
+        grad[d] = d1r;
+    }
+    diffT *= P.alpha;
+    for (int k = 0; k < NSP; ++k) diffY[k] *= P.alpha;
+
+    // the source and its Jacobian in (T0, Y0) by forward mode
+    constexpr int NS = 1 + NSP;
+    double srcT, srcY[NSP], Jc[NS][NS];  // Jc[o][i] = d src_o / d x_i, o, i over (T, Y_0 ...)
+    {
+        using V = DualN<NS>;
+        V T0(T[0]), Y0[NSP], sT, sY[NSP];
+        T0.d[0] = 1.0;
+        for (int k = 0; k < NSP; ++k) {
+            Y0[k] = V(Y[0][k]);
+            Y0[k].d[1 + k] = 1.0;
+        }
+        chem_source<NSP>(
+            P, T0, Y0,
+            [&](int j, V &Aj, V &Taj) {
+                Aj = V(P.rx[j].A);
+                Taj = V(P.rx[j].Ta);
+            },
+            sT, sY);
+        srcT = sT.v;
+        for (int i = 0; i < NS; ++i) Jc[0][i] = sT.d[i];
+        for (int k = 0; k < NSP; ++k) {
+            srcY[k] = sY[k].v;
+            for (int i = 0; i < NS; ++i) Jc[1 + k][i] = sY[k].d[i];
+        }
+    }
+    const double DtT = diffT + srcT;
+    double DtY[NSP], invWs = 0.0;
+    for (int k = 0; k < NSP; ++k) {
+        DtY[k] = diffY[k] + srcY[k];
+        invWs += Y[0][k] * P.invW[k];
+    }
+    const double Wm = 1.0 / invWs;
+    double Lam = DtT / T[0];
+    for (int k = 0; k < NSP; ++k) Lam += (Wm * P.invW[k]) * DtY[k];
+
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double xi[Q], feq[Q], proj[Q], h0[Q], pi = 0.0;
+    const double half_inv = 0.5 * inv_rc;
+    for (int i = 0; i < Q; ++i) {
+        const double wi = L::w(i);
+        const double cu = L::cx(i) * u[0] + L::cy(i) * u[1] + L::cz(i) * u[2];
+        feq[i] = wi * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        proj[i] = (L::cx(i) - u[0]) * grad[0] + (L::cy(i) - u[1]) * grad[1] + (L::cz(i) - u[2]) * grad[2];
+        xi[i] = kCs2 * (feq[i] - wi) * proj[i] + wi * rho * kCs2 * Lam;
+        h0[i] = g[i] * inv_rc + xi[i] * half_inv;
+        pi += h0[i];
+    }
+    const double sh = 1.0 - pi;
+    // the transforms, keeping the input of every pass
+    double hx[Q], hy[Q], hz[Q], kr[Q], iz[Q], iy[Q];
+    for (int i = 0; i < Q; ++i) hx[i] = h0[i] + L::w(i) * sh;
+    for (int i = 0; i < Q; ++i) hy[i] = hx[i];
+    for (int l = 0; l < Q / 3; ++l) cm_fwd_line(hy[3 * l], hy[3 * l + 1], hy[3 * l + 2], u[0]);
+    for (int i = 0; i < Q; ++i) hz[i] = hy[i];
+    for (int zp = 0; zp < Q / 9; ++zp)
+        for (int p = 0; p < 3; ++p) cm_fwd_line(hz[9 * zp + p], hz[9 * zp + p + 3], hz[9 * zp + p + 6], u[1]);
+    for (int i = 0; i < Q; ++i) kr[i] = hz[i];
+    if constexpr (Q == 27)
+        for (int r = 0; r < 9; ++r) cm_fwd_line(kr[r], kr[r + 9], kr[r + 18], u[2]);
+    relax<Q>(kr, P.omega2, P.omega3, P.omega4);
+    for (int i = 0; i < Q; ++i) iz[i] = kr[i];
+    if constexpr (Q == 27)
+        for (int r = 0; r < 9; ++r) cm_inv_line(iz[r], iz[r + 9], iz[r + 18], u[2]);
+    for (int i = 0; i < Q; ++i) iy[i] = iz[i];
+    for (int zp = 0; zp < Q / 9; ++zp)
+        for (int p = 0; p < 3; ++p) cm_inv_line(iy[9 * zp + p], iy[9 * zp + p + 3], iy[9 * zp + p + 6], u[1]);
+    double h3[Q];
+    for (int i = 0; i < Q; ++i) h3[i] = iy[i];
+    for (int l = 0; l < Q / 3; ++l) cm_inv_line(h3[3 * l], h3[3 * l + 1], h3[3 * l + 2], u[0]);
+    const double rc = rho * kCs2;
+
+    // ------------------------------------------------------ reverse
+    for (int i = 0; i < Q; ++i) a.g[i] = 0.0;
+    for (int s = 0; s < kSlots; ++s) {
+        a.T[s] = 0.0;
+        a.Tw[s] = 0.0;
+        for (int k = 0; k < NSP; ++k) a.Y[s][k] = 0.0;
+    }
+    double lR[kSlots];
+    for (int s = 0; s < kSlots; ++s) lR[s] = 0.0;
+    double lu[3] = {0.0, 0.0, 0.0}, lrho = 0.0, linv_rc = 0.0, linv_rho = 0.0;
+
+    // out[i] = rc (h3[i] - w_i sh) + xi[i] / 2
+    double lh[Q], lxi[Q], lrc = 0.0, lsh = 0.0;
+    for (int i = 0; i < Q; ++i) {
+        lh[i] = rc * lo[i];
+        lrc += lo[i] * (h3[i] - L::w(i) * sh);
+        lsh -= rc * L::w(i) * lo[i];
+        lxi[i] = 0.5 * lo[i];
+    }
+    // central_inv, reversed
+    for (int l = 0; l < Q / 3; ++l)
+        lu[0] += cm_inv_line_adj(iy[3 * l], iy[3 * l + 1], iy[3 * l + 2], u[0], lh[3 * l], lh[3 * l + 1], lh[3 * l + 2]);
+    for (int zp = 0; zp < Q / 9; ++zp)
+        for (int p = 0; p < 3; ++p) {
+            const int i0 = 9 * zp + p, i1 = i0 + 3, i2 = i0 + 6;
+            lu[1] += cm_inv_line_adj(iz[i0], iz[i1], iz[i2], u[1], lh[i0], lh[i1], lh[i2]);
+        }
+    if constexpr (Q == 27)
+        for (int r = 0; r < 9; ++r) lu[2] += cm_inv_line_adj(kr[r], kr[r + 9], kr[r + 18], u[2], lh[r], lh[r + 9], lh[r + 18]);
+    relax_adj<Q>(lh, P.omega2, P.omega3, P.omega4);
+    // central_fwd, reversed
+    if constexpr (Q == 27)
+        for (int r = 0; r < 9; ++r) lu[2] += cm_fwd_line_adj(hz[r], hz[r + 9], hz[r + 18], u[2], lh[r], lh[r + 9], lh[r + 18]);
+    for (int zp = 0; zp < Q / 9; ++zp)
+        for (int p = 0; p < 3; ++p) {
+            const int i0 = 9 * zp + p, i1 = i0 + 3, i2 = i0 + 6;
+            lu[1] += cm_fwd_line_adj(hy[i0], hy[i1], hy[i2], u[1], lh[i0], lh[i1], lh[i2]);
+        }
+    for (int l = 0; l < Q / 3; ++l)
+        lu[0] += cm_fwd_line_adj(hx[3 * l], hx[3 * l + 1], hx[3 * l + 2], u[0], lh[3 * l], lh[3 * l + 1], lh[3 * l + 2]);
+    // hx = h0 + w sh, sh = 1 - sum h0
+    for (int i = 0; i < Q; ++i) lsh += L::w(i) * lh[i];
+    double lLam = 0.0, lgrad[3] = {0.0, 0.0, 0.0}, luu = 0.0;
+    for (int i = 0; i < Q; ++i) {
+        const double lh0 = lh[i] - lsh;
+        // h0 = g inv_rc + xi inv_rc / 2
+        a.g[i] += inv_rc * lh0;
+        lxi[i] += half_inv * lh0;
+        linv_rc += lh0 * (g[i] + 0.5 * xi[i]);
+        // xi = cs2 (feq - w) proj + w rho cs2 Lam
+        const double wi = L::w(i);
+        const double lfeq = kCs2 * proj[i] * lxi[i];
+        const double lproj = kCs2 * (feq[i] - wi) * lxi[i];
+        lrho += wi * kCs2 * Lam * lxi[i];
+        lLam += wi * rho * kCs2 * lxi[i];
+        // proj = sum_d (c_d - u_d) grad_d
+        const double cd[3] = {(double)L::cx(i), (double)L::cy(i), (double)L::cz(i)};
+        for (int d = 0; d < 3; ++d) {
+            lgrad[d] += lproj * (cd[d] - u[d]);
+            lu[d] -= lproj * grad[d];
+        }
+        // feq = w (1 + 3 cu + 9/2 cu^2 - 3/2 uu)
+        const double cu = cd[0] * u[0] + cd[1] * u[1] + cd[2] * u[2];
+        const double lcu = wi * (3.0 + 9.0 * cu) * lfeq;
+        luu -= 1.5 * wi * lfeq;
+        for (int d = 0; d < 3; ++d) lu[d] += cd[d] * lcu;
+    }
+    for (int d = 0; d < 3; ++d) lu[d] += 2.0 * u[d] * luu;
+    lrho += kCs2 * lrc;
+
+    // scalar outputs: T' = T0 - CT + DtT, Y' = Y0 - CY + DtY
+    const double lTo = lo[Q];
+    a.T[0] += lTo + wT0;
+    const double lCT = -lTo;
+    double lDtT = lTo, lCY[NSP], lDtY[NSP];
+    for (int k = 0; k < NSP; ++k) {
+        a.Y[0][k] += lo[Q + 1 + k];
+        lCY[k] = -lo[Q + 1 + k];
+        lDtY[k] = lo[Q + 1 + k];
+    }
+    // Lam = DtT / T0 + sum_k Wm / W_k DtY_k, Wm = 1 / sum_k Y0_k / W_k
+    lDtT += lLam / T[0];
+    a.T[0] -= lLam * DtT / (T[0] * T[0]);
+    double lWm = 0.0;
+    for (int k = 0; k < NSP; ++k) {
+        lDtY[k] += lLam * Wm * P.invW[k];
+        lWm += lLam * P.invW[k] * DtY[k];
+    }
+    const double linvWs = -lWm * Wm * Wm;
+    for (int k = 0; k < NSP; ++k) a.Y[0][k] += linvWs * P.invW[k];
+    // Dt = alpha (diffusion) + source
+    {
+        double ls[NS];
+        ls[0] = lDtT;
+        for (int k = 0; k < NSP; ++k) ls[1 + k] = lDtY[k];
+        for (int i = 0; i < NS; ++i) {
+            double acc = 0.0;
+            for (int o = 0; o < NS; ++o) acc += Jc[o][i] * ls[o];
+            if (i == 0)
+                a.T[0] += acc;
+            else
+                a.Y[0][i - 1] += acc;
+        }
+        // (A_j, Ta_j): one forward-mode pass per reaction
+        using V = DualN<2>;
+        for (int jr = 0; jr < P.n_rx; ++jr) {
+            V T0(T[0]), Y0[NSP], sT, sY[NSP];
+            for (int k = 0; k < NSP; ++k) Y0[k] = V(Y[0][k]);
+            chem_source<NSP>(
+                P, T0, Y0,
+                [&](int j, V &Aj, V &Taj) {
+                    Aj = V(P.rx[j].A);
+                    Taj = V(P.rx[j].Ta);
+                    if (j == jr) {
+                        Aj.d[0] = 1.0;
+                        Taj.d[1] = 1.0;
+                    }
+                },
+                sT, sY);
+            double gA = ls[0] * sT.d[0], gTa = ls[0] * sT.d[1];
+            for (int k = 0; k < NSP; ++k) {
+                gA += ls[1 + k] * sY[k].d[0];
+                gTa += ls[1 + k] * sY[k].d[1];
+            }
+            atomicAdd(&lam_param[2 * jr], gA);
+            atomicAdd(&lam_param[2 * jr + 1], gTa);
+        }
+    }
+    const double ldT = P.alpha * lDtT;
+    double ldY[NSP];
+    for (int k = 0; k < NSP; ++k) ldY[k] = P.alpha * lDtY[k];
+
+    // the axes, reversed
+    for (int d = 0; d < D; ++d) {
+        const int sl[5] = {1 + 4 * d, 2 + 4 * d, 0, 3 + 4 * d, 4 + 4 * d};
+        bool near = false;
+        for (int j = 0; j < 5; ++j) near |= in.kind[sl[j]] != kFluid;
+        // wall heat flux q += 2 alpha rho(Tw, Y0) (T0 - Tw), rho(Tw, Y0) = c0 / (Tw Sw0)
+        for (int j = 1; j <= 3; j += 2)
+            if (in.kind[sl[j]] == kIso && wq != 0.0) {
+                const int s = sl[j];
+                const double Tw = in.Tw[s], rw = c0 / (Tw * Sw[0]), f = 2.0 * P.alpha * wq;
+                a.T[0] += f * rw;
+                a.Tw[s] += f * (-rw / Tw * (T[0] - Tw) - rw);
+                for (int k = 0; k < NSP; ++k) a.Y[0][k] += f * (T[0] - Tw) * (-rw * P.invW[k] / Sw[0]);
+            }
+        const double d1r = grad[d];
+        double ld1r = lgrad[d];
+        // diffusion: d2(phi) + d1r d1(phi) / rho
+        {
+            const double dT1 = d1(T[sl[0]], T[sl[1]], T[sl[2]], T[sl[3]], T[sl[4]]);
+            for (int j = 0; j < 5; ++j) a.T[sl[j]] += ldT * (c2[j] + d1r * inv_rho * c1[j]);
+            ld1r += ldT * dT1 * inv_rho;
+            linv_rho += ldT * d1r * dT1;
+        }
+        for (int k = 0; k < NSP; ++k) {
+            const double dY1 = d1(Y[sl[0]][k], Y[sl[1]][k], Y[sl[2]][k], Y[sl[3]][k], Y[sl[4]][k]);
+            for (int j = 0; j < 5; ++j) a.Y[sl[j]][k] += ldY[k] * (c2[j] + d1r * inv_rho * c1[j]);
+            ld1r += ldY[k] * dY1 * inv_rho;
+            linv_rho += ldY[k] * d1r * dY1;
+        }
+        // convection of T: CT += u_d cT_d
+        lu[d] += lCT * cT[d];
+        {
+            const double lc = lCT * u[d];
+            double l5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            if (near) {
+                l5[3] += 0.5 * lc;
+                l5[1] -= 0.5 * lc;
+            } else {
+                weno3_adj(T[sl[0]], T[sl[1]], T[sl[2]], T[sl[3]], T[sl[4]], u[d], lc, l5);
+            }
+            for (int j = 0; j < 5; ++j) a.T[sl[j]] += l5[j];
+        }
+        // convection of Y: CY_k += u_d (cY_k - Y0_k sumc)
+        double lsumc = 0.0;
+        for (int k = 0; k < NSP; ++k) {
+            lu[d] += lCY[k] * (cY[d][k] - Y[0][k] * sumc[d]);
+            a.Y[0][k] -= lCY[k] * u[d] * sumc[d];
+            lsumc -= lCY[k] * u[d] * Y[0][k];
+        }
+        for (int k = 0; k < NSP; ++k) {
+            const double lc = lCY[k] * u[d] + lsumc;
+            double l5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            if (near) {
+                l5[3] += 0.5 * lc;
+                l5[1] -= 0.5 * lc;
+            } else {
+                weno3_adj(Y[sl[0]][k], Y[sl[1]][k], Y[sl[2]][k], Y[sl[3]][k], Y[sl[4]][k], u[d], lc, l5);
+            }
+            for (int j = 0; j < 5; ++j) a.Y[sl[j]][k] += l5[j];
+        }
+        // d1r = d1(R)
+        for (int j = 0; j < 5; ++j) lR[sl[j]] += ld1r * c1[j];
+    }
+
+    // u = m / (rho cs2), inv_rho = 1 / rho
+    for (int d = 0; d < 3; ++d) {
+        const double lm = lu[d] * inv_rc;
+        linv_rc += lu[d] * m[d];
+        for (int i = 0; i < Q; ++i) {
+            const int c = d == 0 ? L::cx(i) : d == 1 ? L::cy(i) : L::cz(i);
+            if (c != 0) a.g[i] += c * lm;
+        }
+    }
+    lrho -= linv_rc * inv_rc / rho;
+    lrho -= linv_rho * inv_rho * inv_rho;
+    lR[0] += lrho;
+
+    // ghosts onto their images and wall temperatures
+    for (int s = 0; s < kSlots; ++s) {
+        if (in.kind[s] == kFluid) continue;
+        const int im = in.img[s];
+        if (in.kind[s] == kIso) {
+            const double Tw = in.Tw[s], rw = c0 / (Tw * Sw[im]);
+            a.Tw[s] += 2.0 * a.T[s] + 2.0 * lR[s] * (-rw / Tw);
+            a.T[im] -= a.T[s];
+            for (int k = 0; k < NSP; ++k) a.Y[im][k] += a.Y[s][k] + 2.0 * lR[s] * (-rw * P.invW[k] / Sw[im]);
+            lR[im] -= lR[s];
+        } else if (in.kind[s] == kInflow) {
+            a.T[im] -= a.T[s];
+            for (int k = 0; k < NSP; ++k) a.Y[im][k] -= a.Y[s][k];
+            lR[im] -= lR[s];
+        } else {
+            a.T[im] += a.T[s];
+            for (int k = 0; k < NSP; ++k) a.Y[im][k] += a.Y[s][k];
+            lR[im] += lR[s];
+        }
+        a.T[s] = 0.0;
+        for (int k = 0; k < NSP; ++k) a.Y[s][k] = 0.0;
+    }
+    // densities of the fluid slots: R = c0 / (T Sw)
+    for (int s = 0; s < kSlots; ++s) {
+        if (in.kind[s] != kFluid || lR[s] == 0.0) continue;
+        a.T[s] -= lR[s] * R[s] / T[s];
+        for (int k = 0; k < NSP; ++k) a.Y[s][k] -= lR[s] * R[s] * P.invW[k] / Sw[s];
+    }
+}
+
 struct AdjParams {
     KParams k;              // pop_in / sc_in: the state of level n
     const double *lam_pop_next;  // [Q][N] adjoint of the populations written by step n
     const double *lam_sc_next;   // [1+NSP][N]
-    double *lam_pop;        // [Q][N] adjoint of level n (accumulated)
-    double *lam_sc;         // [1+NSP][N]
+    double *lam_pop;        // [Q][N] adjoint of level n (cleared by the caller; stored)
+    double *lam_sc;         // [1+NSP][N] (cleared by the caller; accumulated)
     double *dwallT;         // [N] dJ/d wall_T (accumulated)
     double *dparam;         // [2 n_rx]: dJ/dA_j, dJ/dTa_j (accumulated)
     int obj_kind;           // LBFD_OBJ_*
@@ -370,7 +916,6 @@ struct AdjParams {
 template <int Q, int NSP>
 __global__ void __launch_bounds__(kBlock) adjoint_kernel(const AdjParams AP)
 {
-    using S = Slots<Q, NSP>;
     const KParams &P = AP.k;
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     __shared__ double red[2 * LBFD_MAX_REACTIONS];
@@ -380,43 +925,71 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(const AdjParams AP)
         const int x = (int)(idx % P.nx), y = (int)((idx / P.nx) % P.ny), z = (int)(idx / ((long long)P.nx * P.ny));
         CellIn<Q, NSP> in;
         gather_inputs<Q, NSP>(P, x, y, z, idx, in);
-        double lam_out[Q + 1 + NSP];
-        for (int i = 0; i < Q; ++i) lam_out[i] = AP.lam_pop_next[(long long)i * P.N + idx];
-        for (int k = 0; k < 1 + NSP; ++k) lam_out[Q + k] = AP.lam_sc_next[(long long)k * P.N + idx];
-        const int nslots = S::param + 2 * P.n_rx;
-        const int D = Lat<Q>::D;
-        for (int seed = 0; seed < nslots; ++seed) {
-            // skip slots with no variable behind them
-            if (seed >= S::scal && seed < S::wall) {
-                const int s = (seed - S::scal) / (1 + NSP);
-                if (in.kind[s] != kFluid || (s > 0 && (s - 1) / 4 >= D)) continue;
-            } else if (seed >= S::wall && seed < S::param) {
-                const int s = seed - S::wall;
-                if (in.kind[s] != kIso || in.wall[s] < 0) continue;
-            }
-            Dual out[Q + 1 + NSP], qc;
-            cell_eval<Q, NSP, Dual>(P, in, seed, out, qc);
-            // the objective's share: the wall heat flux through this cell's
-            // walls, or the flame position's linear term in the cell's own T
-            double contrib = AP.obj_kind == LBFD_OBJ_WALL_HEAT_FLUX ? AP.obj_w * qc.d
-                             : seed == S::scal                      ? AP.obj_w
-                                                                    : 0.0;
-            for (int o = 0; o < Q + 1 + NSP; ++o) contrib += lam_out[o] * out[o].d;
-            if (seed < S::scal) {
-                atomicAdd(&AP.lam_pop[(long long)in.tdir[seed] * P.N + in.tcell[seed]], contrib);
-            } else if (seed < S::wall) {
-                const int s = (seed - S::scal) / (1 + NSP), var = (seed - S::scal) % (1 + NSP);
-                atomicAdd(&AP.lam_sc[(long long)var * P.N + in.cell[s]], contrib);
-            } else if (seed < S::param) {
-                atomicAdd(&AP.dwallT[in.wall[seed - S::wall]], contrib);
-            } else {
-                atomicAdd(&red[seed - S::param], contrib);
+        double lo[Q + 1 + NSP];
+        for (int i = 0; i < Q; ++i) lo[i] = AP.lam_pop_next[(long long)i * P.N + idx];
+        for (int k = 0; k < 1 + NSP; ++k) lo[Q + k] = AP.lam_sc_next[(long long)k * P.N + idx];
+        const double wq = AP.obj_kind == LBFD_OBJ_WALL_HEAT_FLUX ? AP.obj_w : 0.0;
+        const double wT0 = AP.obj_kind == LBFD_OBJ_FLAME_POSITION ? AP.obj_w : 0.0;
+        CellAdj<Q, NSP> a;
+        cell_vjp<Q, NSP>(P, in, lo, wq, wT0, a, red);
+        // pull streaming reads every population entry at most once (the
+        // source cell's, or the cell's own opposite entry behind a wall)
+        for (int i = 0; i < Q; ++i) AP.lam_pop[(long long)in.tdir[i] * P.N + in.tcell[i]] = a.g[i];
+        constexpr int D = Lat<Q>::D;
+        for (int s = 0; s < kSlots; ++s) {
+            if (s > 0 && (s - 1) / 4 >= D) continue;
+            if (in.kind[s] == kFluid) {
+                const long long c = in.cell[s];
+                atomicAdd(&AP.lam_sc[c], a.T[s]);
+                for (int k = 0; k < NSP; ++k) atomicAdd(&AP.lam_sc[(long long)(1 + k) * P.N + c], a.Y[s][k]);
+            } else if (in.kind[s] == kIso && in.wall[s] >= 0) {
+                atomicAdd(&AP.dwallT[in.wall[s]], a.Tw[s]);
             }
         }
     }
     __syncthreads();
     for (int j = threadIdx.x; j < 2 * P.n_rx; j += blockDim.x)
         if (red[j] != 0.0) atomicAdd(&AP.dparam[j], red[j]);
+}
+
+struct TanParams {
+    KParams k;               // pop_in / sc_in: the state of level n
+    const double *dpop;      // [Q][N] tangent of the populations read by the step
+    const double *dsc;       // [1+NSP][N] tangent of T, Y
+    const double *dwallT;    // [N] tangent of the wall temperatures
+    const double *dparam;    // [2 n_rx] tangents of A_j, Ta_j
+    double *dpop_out;        // [Q][N] tangent of the populations written (fluid cells)
+    double *dsc_out;         // [1+NSP][N] tangent of T, Y written (fluid cells)
+    double *dq;              // tangent of this level's q (accumulated)
+    int obj_kind;
+    double obj_w;            // flame position: dq/dT of a cell
+};
+
+template <int Q, int NSP>
+__global__ void __launch_bounds__(kBlock) tangent_kernel(const TanParams TP)
+{
+    using S = Slots<Q, NSP>;
+    const KParams &P = TP.k;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= P.N || P.mask[idx] != LBFD_FLUID) return;
+    const int x = (int)(idx % P.nx), y = (int)((idx / P.nx) % P.ny), z = (int)(idx / ((long long)P.nx * P.ny));
+    CellIn<Q, NSP> in;
+    gather_inputs<Q, NSP>(P, x, y, z, idx, in);
+    double tan[S::param + 2 * LBFD_MAX_REACTIONS];
+    for (int i = 0; i < Q; ++i) tan[S::pull + i] = TP.dpop[(long long)in.tdir[i] * P.N + in.tcell[i]];
+    for (int s = 0; s < kSlots; ++s) {
+        const bool fl = in.kind[s] == kFluid;
+        for (int v = 0; v < 1 + NSP; ++v)
+            tan[S::scal + s * (1 + NSP) + v] = fl ? TP.dsc[(long long)v * P.N + in.cell[s]] : 0.0;
+        tan[S::wall + s] = (in.kind[s] == kIso && in.wall[s] >= 0) ? TP.dwallT[in.wall[s]] : 0.0;
+    }
+    for (int j = 0; j < 2 * P.n_rx; ++j) tan[S::param + j] = TP.dparam[j];
+    Dual out[Q + 1 + NSP], qc;
+    cell_eval<Q, NSP>(P, in, tan, out, qc);
+    for (int i = 0; i < Q; ++i) TP.dpop_out[(long long)i * P.N + idx] = out[i].d[0];
+    for (int k = 0; k < 1 + NSP; ++k) TP.dsc_out[(long long)k * P.N + idx] = out[Q + k].d[0];
+    const double dq = TP.obj_kind == LBFD_OBJ_WALL_HEAT_FLUX ? qc.d[0] : TP.obj_w * tan[S::scal];
+    if (dq != 0.0) atomicAdd(TP.dq, dq);
 }
 
 __global__ void accumulate_kernel(double *acc, const double *diag, int slot, double a, double b)
@@ -445,6 +1018,31 @@ hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_p
         adjoint_kernel<9, 4><<<nb, kBlock, 0, s>>>(ap);
     else if (Q == 27 && nsp == 4)
         adjoint_kernel<27, 4><<<nb, kBlock, 0, s>>>(ap);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_tangent(int Q, int nsp, const KParams &kp, const double *dpop, const double *dsc,
+                          const double *dwallT, const double *dparam, double *dpop_out, double *dsc_out, double *dq,
+                          int obj_kind, double obj_w, hipStream_t s)
+{
+    TanParams tp;
+    tp.k = kp;
+    tp.dpop = dpop;
+    tp.dsc = dsc;
+    tp.dwallT = dwallT;
+    tp.dparam = dparam;
+    tp.dpop_out = dpop_out;
+    tp.dsc_out = dsc_out;
+    tp.dq = dq;
+    tp.obj_kind = obj_kind;
+    tp.obj_w = obj_w;
+    const unsigned nb = (unsigned)((kp.N + kBlock - 1) / kBlock);
+    if (Q == 9 && nsp == 4)
+        tangent_kernel<9, 4><<<nb, kBlock, 0, s>>>(tp);
+    else if (Q == 27 && nsp == 4)
+        tangent_kernel<27, 4><<<nb, kBlock, 0, s>>>(tp);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -1458,10 +1458,10 @@ int lbfd_objective_static(lbfd_ctx *c, int64_t nsteps, double *J)
     return LBFD_OK;
 }
 
-static int adjoint_impl(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwallT, double *dJ_dA,
-                        double *dJ_dTa, bool wall_dev)
+// The contexts the adjoint and the tangent differentiate; LBFD_OK or the
+// reason (LBFD_EINVAL).
+static int derivative_check(const lbfd_ctx *c)
 {
-    if (!c || nsteps < 1 || K < 1) return fail(LBFD_EINVAL, "bad arguments");
     if (c->prec != LBFD_FP64) return fail(LBFD_EINVAL, "the adjoint needs FP64 precision");
     if (c->p.collision != LBFD_CENTRAL_MOMENTS)
         return fail(LBFD_EINVAL, "the adjoint differentiates the central-moment collision only");
@@ -1473,6 +1473,109 @@ static int adjoint_impl(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *d
         return fail(LBFD_EINVAL, "no adjoint kernel for lattice %d with %d species", c->Q, c->nsp);
     for (int f = 0; f < 6; ++f)
         if (c->p.face[f] == LBFD_FACE_OUTFLOW) return fail(LBFD_EINVAL, "the adjoint does not support OUTFLOW faces");
+    return LBFD_OK;
+}
+
+// dq/dT of one fluid cell for the flame position (its objective is linear in
+// the cells' T), 1 for the wall heat flux.
+static double objective_cell_weight(const lbfd_ctx *c)
+{
+    if (c->obj_kind != LBFD_OBJ_FLAME_POSITION) return 1.0;
+    const double per_col = (double)c->n_fluid / c->p.nx;
+    return -1.0 / (per_col * (c->p.T_b - c->p.T_u));
+}
+
+int lbfd_step_tangent(lbfd_ctx *c, const double *dpop, const double *dsc, const double *dwallT, const double *dA,
+                      const double *dTa, double *dpop_out, double *dsc_out, double *dq)
+{
+    if (!c || !dpop || !dsc || !dpop_out || !dsc_out || !dq) return fail(LBFD_EINVAL, "null argument");
+    const int rc0 = derivative_check(c);
+    if (rc0 != LBFD_OK) return rc0;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const long long N = c->N;
+    const int nrx = c->p.n_reactions;
+    const size_t pop_b = (size_t)c->Q * N * sizeof(double), sc_b = (size_t)(1 + c->nsp) * N * sizeof(double);
+    AdjBuffers mem;
+    double *d_in = (double *)mem.get(pop_b), *s_in = (double *)mem.get(sc_b);
+    double *d_out = (double *)mem.get(pop_b), *s_out = (double *)mem.get(sc_b);
+    double *w_in = (double *)mem.get(N * sizeof(double));
+    double *p_in = (double *)mem.get(2 * LBFD_MAX_REACTIONS * sizeof(double)), *q = (double *)mem.get(sizeof(double));
+    if (!d_in || !s_in || !d_out || !s_out || !w_in || !p_in || !q)
+        return fail(LBFD_ENOMEM, "tangent: device allocation failed");
+    std::vector<double> hp(2 * LBFD_MAX_REACTIONS, 0.0);
+    for (int j = 0; j < nrx; ++j) {
+        hp[2 * j] = dA ? dA[j] : 0.0;
+        hp[2 * j + 1] = dTa ? dTa[j] : 0.0;
+    }
+    HIP_TRY(hipMemcpy(d_in, dpop, pop_b, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s_in, dsc, sc_b, hipMemcpyHostToDevice));
+    if (dwallT)
+        HIP_TRY(hipMemcpy(w_in, dwallT, N * sizeof(double), hipMemcpyHostToDevice));
+    else
+        HIP_TRY(hipMemset(w_in, 0, N * sizeof(double)));
+    HIP_TRY(hipMemcpy(p_in, hp.data(), hp.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(d_out, 0, pop_b));
+    HIP_TRY(hipMemset(s_out, 0, sc_b));
+    HIP_TRY(hipMemset(q, 0, sizeof(double)));
+    KParams k = c->base;
+    k.pop_in = c->pop[c->cur];
+    k.sc_in = c->sc[c->cur];
+    HIP_TRY(launch_tangent(c->Q, c->nsp, k, d_in, s_in, w_in, p_in, d_out, s_out, q, c->obj_kind,
+                           objective_cell_weight(c), c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(dpop_out, d_out, pop_b, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(dsc_out, s_out, sc_b, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(dq, q, sizeof(double), hipMemcpyDeviceToHost));
+    return LBFD_OK;
+}
+
+int lbfd_step_adjoint(lbfd_ctx *c, const double *lam_pop, const double *lam_sc, double wq, double *lam_pop_in,
+                      double *lam_sc_in, double *dJ_dwallT, double *dJ_dA, double *dJ_dTa)
+{
+    if (!c || !lam_pop || !lam_sc || !lam_pop_in || !lam_sc_in) return fail(LBFD_EINVAL, "null argument");
+    const int rc0 = derivative_check(c);
+    if (rc0 != LBFD_OK) return rc0;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const long long N = c->N;
+    const int nrx = c->p.n_reactions;
+    const size_t pop_b = (size_t)c->Q * N * sizeof(double), sc_b = (size_t)(1 + c->nsp) * N * sizeof(double);
+    AdjBuffers mem;
+    double *l_next = (double *)mem.get(pop_b), *s_next = (double *)mem.get(sc_b);
+    double *l_out = (double *)mem.get(pop_b), *s_out = (double *)mem.get(sc_b);
+    double *dW = (double *)mem.get(N * sizeof(double));
+    double *dP = (double *)mem.get(2 * LBFD_MAX_REACTIONS * sizeof(double));
+    if (!l_next || !s_next || !l_out || !s_out || !dW || !dP)
+        return fail(LBFD_ENOMEM, "adjoint step: device allocation failed");
+    HIP_TRY(hipMemcpy(l_next, lam_pop, pop_b, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s_next, lam_sc, sc_b, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(l_out, 0, pop_b));
+    HIP_TRY(hipMemset(s_out, 0, sc_b));
+    HIP_TRY(hipMemset(dW, 0, N * sizeof(double)));
+    HIP_TRY(hipMemset(dP, 0, 2 * LBFD_MAX_REACTIONS * sizeof(double)));
+    KParams k = c->base;
+    k.pop_in = c->pop[c->cur];
+    k.sc_in = c->sc[c->cur];
+    HIP_TRY(launch_adjoint(c->Q, c->nsp, k, l_next, s_next, l_out, s_out, dW, dP, c->obj_kind,
+                           wq * objective_cell_weight(c), c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(lam_pop_in, l_out, pop_b, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(lam_sc_in, s_out, sc_b, hipMemcpyDeviceToHost));
+    if (dJ_dwallT) HIP_TRY(hipMemcpy(dJ_dwallT, dW, N * sizeof(double), hipMemcpyDeviceToHost));
+    double hP[2 * LBFD_MAX_REACTIONS];
+    HIP_TRY(hipMemcpy(hP, dP, sizeof(hP), hipMemcpyDeviceToHost));
+    for (int j = 0; j < nrx; ++j) {
+        if (dJ_dA) dJ_dA[j] = hP[2 * j];
+        if (dJ_dTa) dJ_dTa[j] = hP[2 * j + 1];
+    }
+    return LBFD_OK;
+}
+
+static int adjoint_impl(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwallT, double *dJ_dA,
+                        double *dJ_dTa, bool wall_dev)
+{
+    if (!c || nsteps < 1 || K < 1) return fail(LBFD_EINVAL, "bad arguments");
+    const int rc0 = derivative_check(c);
+    if (rc0 != LBFD_OK) return rc0;
     HIP_TRY(hipStreamSynchronize(c->stream));
     const long long N = c->N;
     const int Q = c->Q, ns = c->nsp, nrx = c->p.n_reactions;

@@ -157,6 +157,12 @@ bool adjoint_supported(int Q, int nsp);
 hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_pop_next, const double *lam_sc_next,
                           double *lam_pop, double *lam_sc, double *dwallT, double *dparam, int obj_kind,
                           double obj_w, hipStream_t s);
+// One forward-mode (Jacobian-vector) evaluation of the FP64 step at the
+// state kp.pop_in / kp.sc_in: tangents of the inputs in, tangents of the
+// outputs at fluid cells out; *dq accumulates the tangent of the level's q.
+hipError_t launch_tangent(int Q, int nsp, const KParams &kp, const double *dpop, const double *dsc,
+                          const double *dwallT, const double *dparam, double *dpop_out, double *dsc_out, double *dq,
+                          int obj_kind, double obj_w, hipStream_t s);
 // dst[i] = src[i] for i < n (float to double, on the stream).
 hipError_t launch_widen(const float *src, double *dst, size_t n, hipStream_t s);
 // *acc += a * diag[slot] + b (one thread).

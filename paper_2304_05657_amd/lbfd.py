@@ -29,7 +29,7 @@ EXPORTS = ("lbfd_init", "lbfd_step", "lbfd_sync", "lbfd_level", "lbfd_read_field
            "lbfd_cell_counts", "lbfd_step_launches", "lbfd_set_reaction", "lbfd_set_objective",
            "lbfd_objective", "lbfd_adjoint", "lbfd_set_inflow", "lbfd_hold_flame", "lbfd_set_wall_links",
            "lbfd_set_image_points", "lbfd_init_dev", "lbfd_read_fields_dev", "lbfd_adjoint_dev",
-           "lbfd_objective_static",
+           "lbfd_objective_static", "lbfd_step_tangent", "lbfd_step_adjoint",
            "lbfd_destroy",
            "lbfd_strerror", "lbfd_last_error")
 # species transport models (lbfd_params.transport)
@@ -123,6 +123,8 @@ def load_library():
     lib.lbfd_objective.argtypes = [vp, C.c_int64, dp]
     lib.lbfd_objective_static.argtypes = [vp, C.c_int64, dp]
     lib.lbfd_adjoint.argtypes = [vp, C.c_int64, C.c_int, dp, dp, dp, dp]
+    lib.lbfd_step_tangent.argtypes = [vp, dp, dp, dp, dp, dp, dp, dp, dp]
+    lib.lbfd_step_adjoint.argtypes = [vp, dp, dp, C.c_double, dp, dp, dp, dp, dp]
     lib.lbfd_destroy.argtypes = [vp]
     lib.lbfd_destroy.restype = None
     lib.lbfd_strerror.argtypes = [C.c_int]
@@ -310,6 +312,36 @@ class Solver:
             _check(self._lib, self._lib.lbfd_adjoint(self._h, int(nsteps), int(K), C.byref(J), _dp(gW), _dp(gA),
                                                      _dp(gTa)))
         return J.value, gW.reshape((pr.nz, pr.ny, pr.nx)), gA[: len(pr.reactions)], gTa[: len(pr.reactions)]
+
+    def step_tangent(self, dpop, dsc, dwallT=None, dA=None, dTa=None):
+        """Jacobian-vector product of one FP64 step at the current level
+        (lbfd_step_tangent): tangents dpop [Q, N], dsc [1 + n_species, N]
+        (T, Y_k), optional dwallT [N], dA, dTa [n_reactions] -> (dpop_out,
+        dsc_out, dq).  The context does not advance."""
+        pop = np.ascontiguousarray(dpop, dtype=np.float64)
+        sc = np.ascontiguousarray(dsc, dtype=np.float64)
+        opt = [None if v is None else np.ascontiguousarray(v, dtype=np.float64) for v in (dwallT, dA, dTa)]
+        po, so = np.zeros_like(pop), np.zeros_like(sc)
+        dq = C.c_double()
+        _check(self._lib, self._lib.lbfd_step_tangent(self._h, _dp(pop), _dp(sc),
+                                                      *(None if v is None else _dp(v) for v in opt),
+                                                      _dp(po), _dp(so), C.byref(dq)))
+        return po, so, dq.value
+
+    def step_adjoint(self, lam_pop, lam_sc, wq: float = 0.0):
+        """Vector-Jacobian product of one FP64 step at the current level
+        (lbfd_step_adjoint): adjoints of the step's outputs lam_pop [Q, N],
+        lam_sc [1 + n_species, N] and the weight wq of the level's objective
+        term -> (lam_pop_in, lam_sc_in, dJ/dwall_T [N], dJ/dA, dJ/dTa)."""
+        lp = np.ascontiguousarray(lam_pop, dtype=np.float64)
+        ls = np.ascontiguousarray(lam_sc, dtype=np.float64)
+        nrx = max(1, len(self.prob.reactions))
+        po, so, gW = np.zeros_like(lp), np.zeros_like(ls), np.zeros(self.N)
+        gA, gTa = np.zeros(nrx), np.zeros(nrx)
+        _check(self._lib, self._lib.lbfd_step_adjoint(self._h, _dp(lp), _dp(ls), C.c_double(wq), _dp(po), _dp(so),
+                                                      _dp(gW), _dp(gA), _dp(gTa)))
+        n = len(self.prob.reactions)
+        return po, so, gW, gA[:n], gTa[:n]
 
     def fields(self, device: bool = False) -> dict:
         """rho, u [3], T, Y [n_species], Ph of the current level (FP64): numpy
