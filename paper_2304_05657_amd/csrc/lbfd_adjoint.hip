@@ -119,20 +119,27 @@ template <int N> __device__ inline double val(const DualN<N> &a) { return a.v; }
 __device__ inline double val(double a) { return a; }
 
 // ------------------------------------------------------------ cell inputs
-// Stencil slots: 0 = the cell, 1 + 4 d + j for axis d and m = -2, -1, 1, 2.
-constexpr int kSlots = 13;
+// Stencil slots: 0 = the cell, 1 + 4 d + j for axis d < D and
+// m = -2, -1, 1, 2 (j = 0 .. 3).
+template <int Q> constexpr int n_slots() { return 1 + 4 * Lat<Q>::D; }
+
+// A ghost's image is a fluid slot: the cell for a first neighbour; the
+// cell or one of the axis's two first neighbours (slots img_lo, img_hi) for
+// a second neighbour.
+constexpr bool second_nb(int s) { return s > 0 && ((s - 1) % 4 == 0 || (s - 1) % 4 == 3); }
+constexpr int img_lo(int s) { return second_nb(s) ? s - (s - 1) % 4 + 1 : 0; }
+constexpr int img_hi(int s) { return second_nb(s) ? s - (s - 1) % 4 + 2 : 0; }
 
 template <int Q, int NSP>
 struct CellIn {
-    double g[Q];          // pulled populations (without the inlet correction)
-    double corr[Q];       // inlet correction added to the pull
+    static constexpr int S = n_slots<Q>();
+    double g[Q];          // pulled populations (with the inlet correction)
     int tdir[Q], tcell[Q];  // population entry each pull read
-    double T[kSlots], Y[NSP][kSlots];
-    int cell[kSlots];     // fluid slot: its cell; ghost slot: -1
-    int kind[kSlots];     // kFluid or the kind of the wall behind the ghost
-    int img[kSlots];      // ghost slot: slot of its image point
-    double Tw[kSlots];    // ghost slot: wall temperature
-    int wall[kSlots];     // ghost slot behind an isothermal in-box solid: its cell, else -1
+    int cell[S];          // fluid slot: its cell; ghost slot: -1
+    int kind[S];          // kFluid or the kind of the wall behind the ghost
+    int img[S];           // ghost slot: slot of its image point
+    double Tw[S];         // ghost slot: wall temperature
+    int wall[S];          // ghost slot behind an isothermal in-box solid: its cell, else -1
 };
 
 template <int Q, int NSP>
@@ -141,26 +148,22 @@ __device__ void gather_inputs(const KParams &P, int x, int y, int z, long long i
     using L = Lat<Q>;
     constexpr int D = L::D;
     const double *pop = (const double *)P.pop_in;
-    const double *sc = (const double *)P.sc_in;
+#pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = Q == 9 ? 0 : i / 9 - 1;
         const int opp = Q - 1 - i;
-        in.corr[i] = 0.0;
+        double corr = 0.0;
         if (cx == 0 && cy == 0 && cz == 0) {
             in.tdir[i] = i;
             in.tcell[i] = (int)idx;
         } else {
             const Nb s = classify(P, x - cx, y - cy, z - cz);
-            if (s.kind == kFluid) {
-                in.tdir[i] = i;
-                in.tcell[i] = (int)s.idx;
-            } else {
-                in.tdir[i] = opp;
-                in.tcell[i] = (int)idx;
-                if (s.kind == kInflow) in.corr[i] = 2.0 * L::w(i) * P.rho_in * inflow_cu_c(P, cx, cy, cz, x, y, z);
-            }
+            const bool fl = s.kind == kFluid;
+            in.tdir[i] = fl ? i : opp;
+            in.tcell[i] = fl ? (int)s.idx : (int)idx;
+            if (s.kind == kInflow) corr = 2.0 * L::w(i) * P.rho_in * inflow_cu_c(P, cx, cy, cz, x, y, z);
         }
-        in.g[i] = pop[(long long)in.tdir[i] * P.N + in.tcell[i]];
+        in.g[i] = pop[(long long)in.tdir[i] * P.N + in.tcell[i]] + corr;
     }
     auto load = [&](int s, long long c) {
         in.cell[s] = (int)c;
@@ -168,8 +171,6 @@ __device__ void gather_inputs(const KParams &P, int x, int y, int z, long long i
         in.img[s] = -1;
         in.Tw[s] = 0.0;
         in.wall[s] = -1;
-        in.T[s] = sc[c];
-        for (int k = 0; k < NSP; ++k) in.Y[k][s] = sc[(1 + k) * P.N + c];
     };
     auto ghost_slot = [&](int s, const Nb &w, int image) {
         in.cell[s] = -1;
@@ -177,19 +178,14 @@ __device__ void gather_inputs(const KParams &P, int x, int y, int z, long long i
         in.img[s] = image;
         in.Tw[s] = w.Tw;
         in.wall[s] = (w.kind == kIso && w.face < 0) ? (int)w.idx : -1;
-        in.T[s] = 0.0;
-        for (int k = 0; k < NSP; ++k) in.Y[k][s] = 0.0;
     };
     load(0, idx);
-    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+#pragma unroll
         for (int sg = -1; sg <= 1; sg += 2) {
             const int j1 = sg < 0 ? 1 : 2, j2 = sg < 0 ? 0 : 3;
             const int s1 = 1 + 4 * d + j1, s2 = 1 + 4 * d + j2, sm = 1 + 4 * d + (sg < 0 ? 2 : 1);
-            if (d >= D) {
-                load(s1, idx);
-                load(s2, idx);
-                continue;
-            }
             const int ox = d == 0, oy = d == 1, oz = d == 2;
             const Nb c1 = classify(P, x + sg * ox, y + sg * oy, z + sg * oz);
             if (c1.kind != kFluid) {
@@ -208,15 +204,32 @@ __device__ void gather_inputs(const KParams &P, int x, int y, int z, long long i
     }
 }
 
-// Input slot numbering for seeding: [0, Q) pulls; then kSlots x (1 + NSP)
-// stencil scalars (T, Y_k); then kSlots ghost wall temperatures; then
+// T and Y of the fluid slots (read from the state; 0 at ghost slots).
+template <int Q, int NSP>
+__device__ __forceinline__ void slot_scalars(const KParams &P, const CellIn<Q, NSP> &in, double (&T)[n_slots<Q>()],
+                                             double (&Y)[n_slots<Q>()][NSP])
+{
+    const double *sc = (const double *)P.sc_in;
+#pragma unroll
+    for (int s = 0; s < n_slots<Q>(); ++s) {
+        const bool fl = in.kind[s] == kFluid;
+        const long long c = fl ? in.cell[s] : in.cell[0];
+        T[s] = fl ? sc[c] : 0.0;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) Y[s][k] = fl ? sc[(1 + k) * P.N + c] : 0.0;
+    }
+}
+
+// Input slot numbering of the tangent: [0, Q) pulls; then S x (1 + NSP)
+// stencil scalars (T, Y_k); then S ghost wall temperatures; then
 // (A_j, Ta_j) per reaction.
 template <int Q, int NSP>
 struct Slots {
+    static constexpr int S = n_slots<Q>();
     static constexpr int pull = 0;
     static constexpr int scal = Q;
-    static constexpr int wall = Q + kSlots * (1 + NSP);
-    static constexpr int param = wall + kSlots;
+    static constexpr int wall = Q + S * (1 + NSP);
+    static constexpr int param = wall + S;
 };
 
 template <int NSP, class A>
@@ -259,7 +272,15 @@ __device__ void chem_source(const KParams &P, const A &T0, const A (&Y0)[NSP], P
             A Aj, Taj;
             par(j, Aj, Taj);
             A rr = Aj * A(P.dt_phys) * dexp(A(r.b) * lnTc - Taj * invTc) * A(inv_nsub);
-            for (int mm = 0; mm < r.n_react; ++mm) rr *= Yc[r.react[mm]];
+            // four reactant factors, Y of the reactant or 1 (react[m] = NSP)
+#pragma unroll
+            for (int mm = 0; mm < 4; ++mm) {
+                const int sp = P.rxk[j].react[mm];
+                A f = 1.0;
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) f = sp == k ? Yc[k] : f;
+                rr *= f;
+            }
             for (int k = 0; k < NSP; ++k) incY[k] += A(r.nu_mass[k]) * rr;
             incT += A(r.q_over_cp) * rr;
         }
@@ -295,22 +316,25 @@ __device__ void cell_eval(const KParams &P, const CellIn<Q, NSP> &in, const doub
         return r;
     };
     A g[Q];
-    for (int i = 0; i < Q; ++i) g[i] = mk(in.g[i], S::pull + i) + A(in.corr[i]);
-    A T[kSlots], Y[kSlots][NSP], R[kSlots], Tw[kSlots];
-    for (int s = 0; s < kSlots; ++s) {
+    for (int i = 0; i < Q; ++i) g[i] = mk(in.g[i], S::pull + i);
+    constexpr int NSL = n_slots<Q>();
+    double Tv[NSL], Yv[NSL][NSP];
+    slot_scalars<Q, NSP>(P, in, Tv, Yv);
+    A T[NSL], Y[NSL][NSP], R[NSL], Tw[NSL];
+    for (int s = 0; s < NSL; ++s) {
         Tw[s] = mk(in.Tw[s], S::wall + s);
         if (in.kind[s] == kFluid) {
-            T[s] = mk(in.T[s], S::scal + s * (1 + NSP));
+            T[s] = mk(Tv[s], S::scal + s * (1 + NSP));
             A Ys[NSP];
             for (int k = 0; k < NSP; ++k) {
-                Y[s][k] = mk(in.Y[k][s], S::scal + s * (1 + NSP) + 1 + k);
+                Y[s][k] = mk(Yv[s][k], S::scal + s * (1 + NSP) + 1 + k);
                 Ys[k] = Y[s][k];
             }
             R[s] = density_a<NSP>(P, T[s], Ys);
         }
     }
     // ghosts (Sec. III.B): images are fluid slots
-    for (int s = 0; s < kSlots; ++s) {
+    for (int s = 0; s < NSL; ++s) {
         if (in.kind[s] == kFluid) continue;
         const int im = in.img[s];
         if (in.kind[s] == kIso) {
@@ -421,14 +445,6 @@ __device__ void cell_eval(const KParams &P, const CellIn<Q, NSP> &in, const doub
 }
 
 // ------------------------------------------------------- the reverse sweep
-// Adjoints of the cell's inputs.
-template <int Q, int NSP>
-struct CellAdj {
-    double g[Q];                  // pulled populations
-    double T[kSlots], Y[kSlots][NSP];  // stencil scalars (fluid slots)
-    double Tw[kSlots];            // ghost wall temperatures
-};
-
 // Reverse of cm_fwd_line at the input (a, b, d): (la, lb, ld) holds the
 // adjoints of (m0, m1, m2) and receives those of (a, b, d); returns the
 // contribution to the adjoint of u.
@@ -497,68 +513,102 @@ __device__ __forceinline__ void weno3_adj(double m2, double m1, double c0, doubl
     const double lB = ldA - ldB - 0.5 * lq0p + 1.5 * lq0m + 0.5 * lq1m;
     const double lC = ldB - ldE + 1.5 * lq0p + 0.5 * lq1p + 0.5 * lq1m;
     const double lE = ldE + 0.5 * lq1p;
+    // selects on the values, not on the destination (an indexed store would
+    // put l in scratch memory)
+    l[0] += neg ? 0.0 : lA;
+    l[1] += neg ? lE : lB;
     l[2] += lC;
-    if (neg) {
-        l[4] += lA;
-        l[3] += lB;
-        l[1] += lE;
-    } else {
-        l[0] += lA;
-        l[1] += lB;
-        l[3] += lE;
-    }
+    l[3] += neg ? lB : lE;
+    l[4] += neg ? lA : 0.0;
 }
 
+// Where the reverse sweep puts the adjoints of a cell's inputs.
+struct AdjOut {
+    const double *lo_pop;  // [Q][N] adjoint of the populations the step writes
+    const double *lo_sc;   // [1+NSP][N] adjoint of the scalars the step writes
+    double *lam_pop;    // [Q][N]: stored (every entry is pulled by one cell)
+    double *lam_sc;     // [1+NSP][N]: accumulated atomically
+    double *dwallT;     // [N]: accumulated atomically
+    double *lam_param;  // [2 n_rx] in LDS: accumulated atomically
+};
+
 // The cell's update forward in FP64, then its reverse: from the adjoint lo
-// of the outputs (g*, T^{n+1}, Y^{n+1}), the weight wq of the cell's
+// of the outputs (g*, T^{n+1}, Y^{n+1}; read from out), the weight wq of the cell's
 // wall-heat-flux term and the weight wT0 of its own T (the flame position's
-// linear term) to the adjoints of the inputs (a) and of the reactions'
-// (A_j, Ta_j), added to lam_param[2 j], lam_param[2 j + 1] (LDS).
+// linear term) to the adjoints of the inputs, added to out.  The slots of
+// each axis are finished (ghosts onto their images, densities onto T and
+// Y) and scattered as soon as the axis's finite differences are reversed;
+// the cell's own slot last.
 template <int Q, int NSP>
-__device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, const double (&lo)[Q + 1 + NSP], double wq,
-                         double wT0, CellAdj<Q, NSP> &a, double *lam_param)
+__device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, double wq, double wT0, const AdjOut &out)
 {
     using L = Lat<Q>;
-    constexpr int D = L::D;
+    constexpr int D = L::D, S = n_slots<Q>(), NS = 1 + NSP;
     constexpr double c1[5] = {1.0 / 12.0, -8.0 / 12.0, 0.0, 8.0 / 12.0, -1.0 / 12.0};
     constexpr double c2[5] = {-1.0 / 12.0, 16.0 / 12.0, -30.0 / 12.0, 16.0 / 12.0, -1.0 / 12.0};
     const double c0 = P.T_ref_over_W_ref;
 
     // ------------------------------------------------ forward (values)
     double g[Q];
-    for (int i = 0; i < Q; ++i) g[i] = in.g[i] + in.corr[i];
-    double T[kSlots], Y[kSlots][NSP], R[kSlots], Sw[kSlots];  // Sw = sum_k Y_k / W_k
-    for (int s = 0; s < kSlots; ++s) {
-        if (in.kind[s] != kFluid) continue;
-        T[s] = in.T[s];
-        double sw = 0.0;
-        for (int k = 0; k < NSP; ++k) {
-            Y[s][k] = in.Y[k][s];
-            sw += Y[s][k] * P.invW[k];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = in.g[i];
+    // the stencil's T, Y, rho and sum_k Y_k / W_k, ghosts from their images
+    // (fluid slots: the cell or a first neighbour); filled for the forward
+    // finite differences and again for their reverse, so that the values are
+    // not held through the collision
+    double T[S], Y[S][NSP], R[S], Sw[S];
+    auto fill = [&]() {
+        slot_scalars<Q, NSP>(P, in, T, Y);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            double sw = 0.0;
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) sw += Y[s][k] * P.invW[k];
+            const bool fl = in.kind[s] == kFluid;
+            Sw[s] = fl ? sw : 1.0;
+            R[s] = fl ? c0 / (T[s] * Sw[s]) : 0.0;
         }
-        Sw[s] = sw;
-        R[s] = c0 / (T[s] * sw);
-    }
-    for (int s = 0; s < kSlots; ++s) {
-        if (in.kind[s] == kFluid) continue;
-        const int im = in.img[s];
-        Sw[s] = Sw[im];
-        if (in.kind[s] == kIso) {
-            T[s] = 2.0 * in.Tw[s] - T[im];
-            for (int k = 0; k < NSP; ++k) Y[s][k] = Y[im][k];
-            R[s] = 2.0 * (c0 / (in.Tw[s] * Sw[im])) - R[im];
-        } else if (in.kind[s] == kInflow) {
-            T[s] = 2.0 * P.T_in - T[im];
-            for (int k = 0; k < NSP; ++k) Y[s][k] = 2.0 * P.Y_in[k] - Y[im][k];
-            R[s] = 2.0 * P.rho_in - R[im];
-        } else {
-            T[s] = T[im];
-            for (int k = 0; k < NSP; ++k) Y[s][k] = Y[im][k];
-            R[s] = R[im];
+#pragma unroll
+        for (int s = 1; s < S; ++s) {
+            const int kd = in.kind[s];
+            if (kd == kFluid) continue;
+            const int im = in.img[s];
+            const int ca = img_lo(s), cb = img_hi(s);
+            const bool ia = im == ca, ib = !ia && im == cb;
+            // the image's values as an exact 0/1 blend of the three candidates
+            // (a select between array elements would become an indexed load
+            // and keep the arrays in scratch memory)
+            const double fa = ia ? 1.0 : 0.0, fb = ib ? 1.0 : 0.0, f0 = 1.0 - fa - fb;
+            auto blend = [&](double va, double vb, double v0) { return fa * va + fb * vb + f0 * v0; };
+            const double Ti = blend(T[ca], T[cb], T[0]);
+            const double Ri = blend(R[ca], R[cb], R[0]);
+            const double Swi = blend(Sw[ca], Sw[cb], Sw[0]);
+            double Yi[NSP];
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) Yi[k] = blend(Y[ca][k], Y[cb][k], Y[0][k]);
+            Sw[s] = Swi;
+            if (kd == kIso) {
+                T[s] = 2.0 * in.Tw[s] - Ti;
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) Y[s][k] = Yi[k];
+                R[s] = 2.0 * (c0 / (in.Tw[s] * Swi)) - Ri;
+            } else if (kd == kInflow) {
+                T[s] = 2.0 * P.T_in - Ti;
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) Y[s][k] = 2.0 * P.Y_in[k] - Yi[k];
+                R[s] = 2.0 * P.rho_in - Ri;
+            } else {
+                T[s] = Ti;
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) Y[s][k] = Yi[k];
+                R[s] = Ri;
+            }
         }
-    }
+    };
+    fill();
     const double rho = R[0];
     double m[3] = {0.0, 0.0, 0.0};
+#pragma unroll
     for (int i = 0; i < Q; ++i) {
         m[0] += L::cx(i) * g[i];
         m[1] += L::cy(i) * g[i];
@@ -569,156 +619,200 @@ __device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, const doubl
     const double inv_rho = 1.0 / rho;
     double diffT = 0.0, grad[3] = {0.0, 0.0, 0.0}, diffY[NSP];
     double cT[3] = {0.0, 0.0, 0.0}, cY[3][NSP], sumc[3] = {0.0, 0.0, 0.0};
+    bool near[3] = {false, false, false};
+#pragma unroll
     for (int k = 0; k < NSP; ++k) diffY[k] = 0.0;
+#pragma unroll
     for (int d = 0; d < D; ++d) {
         const int sl[5] = {1 + 4 * d, 2 + 4 * d, 0, 3 + 4 * d, 4 + 4 * d};
-        bool near = false;
-        for (int j = 0; j < 5; ++j) near |= in.kind[sl[j]] != kFluid;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) near[d] |= in.kind[sl[j]] != kFluid;
         const double d1r = d1(R[sl[0]], R[sl[1]], R[sl[2]], R[sl[3]], R[sl[4]]);
         {
             const double p = T[sl[0]], b = T[sl[1]], c = T[sl[2]], e = T[sl[3]], f = T[sl[4]];
             diffT += d2(p, b, c, e, f) + d1r * d1(p, b, c, e, f) * inv_rho;
-            cT[d] = near ? 0.5 * (e - b) : weno3(p, b, c, e, f, u[d]);
+            cT[d] = near[d] ? 0.5 * (e - b) : weno3(p, b, c, e, f, u[d]);
         }
+#pragma unroll
         for (int k = 0; k < NSP; ++k) {
             const double p = Y[sl[0]][k], b = Y[sl[1]][k], c = Y[sl[2]][k], e = Y[sl[3]][k], f = Y[sl[4]][k];
             diffY[k] += d2(p, b, c, e, f) + d1r * d1(p, b, c, e, f) * inv_rho;
-            cY[d][k] = near ? 0.5 * (e - b) : weno3(p, b, c, e, f, u[d]);
+            cY[d][k] = near[d] ? 0.5 * (e - b) : weno3(p, b, c, e, f, u[d]);
             sumc[d] += cY[d][k];
         }
         grad[d] = d1r;
     }
     diffT *= P.alpha;
+#pragma unroll
     for (int k = 0; k < NSP; ++k) diffY[k] *= P.alpha;
 
-    // the source and its Jacobian in (T0, Y0) by forward mode
-    constexpr int NS = 1 + NSP;
-    double srcT, srcY[NSP], Jc[NS][NS];  // Jc[o][i] = d src_o / d x_i, o, i over (T, Y_0 ...)
+    // the source (its derivatives are taken in the reverse, by forward mode)
+    double srcT, srcY[NSP];
     {
-        using V = DualN<NS>;
-        V T0(T[0]), Y0[NSP], sT, sY[NSP];
-        T0.d[0] = 1.0;
-        for (int k = 0; k < NSP; ++k) {
-            Y0[k] = V(Y[0][k]);
-            Y0[k].d[1 + k] = 1.0;
-        }
+        double Y0[NSP];
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) Y0[k] = Y[0][k];
         chem_source<NSP>(
-            P, T0, Y0,
-            [&](int j, V &Aj, V &Taj) {
-                Aj = V(P.rx[j].A);
-                Taj = V(P.rx[j].Ta);
+            P, T[0], Y0,
+            [&](int j, double &Aj, double &Taj) {
+                Aj = P.rx[j].A;
+                Taj = P.rx[j].Ta;
             },
-            sT, sY);
-        srcT = sT.v;
-        for (int i = 0; i < NS; ++i) Jc[0][i] = sT.d[i];
-        for (int k = 0; k < NSP; ++k) {
-            srcY[k] = sY[k].v;
-            for (int i = 0; i < NS; ++i) Jc[1 + k][i] = sY[k].d[i];
-        }
+            srcT, srcY);
     }
     const double DtT = diffT + srcT;
     double DtY[NSP], invWs = 0.0;
+#pragma unroll
     for (int k = 0; k < NSP; ++k) {
         DtY[k] = diffY[k] + srcY[k];
         invWs += Y[0][k] * P.invW[k];
     }
     const double Wm = 1.0 / invWs;
     double Lam = DtT / T[0];
+#pragma unroll
     for (int k = 0; k < NSP; ++k) Lam += (Wm * P.invW[k]) * DtY[k];
 
+    // xi_i = cs2 (feq_i - w_i) proj_i + w_i rho cs2 Lam, feq_i / w_i and proj_i
+    // from u and grad (recomputed in the reverse)
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    double xi[Q], feq[Q], proj[Q], h0[Q], pi = 0.0;
-    const double half_inv = 0.5 * inv_rc;
-    for (int i = 0; i < Q; ++i) {
+    auto xi_of = [&](int i, double &feq, double &proj) {
         const double wi = L::w(i);
         const double cu = L::cx(i) * u[0] + L::cy(i) * u[1] + L::cz(i) * u[2];
-        feq[i] = wi * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        proj[i] = (L::cx(i) - u[0]) * grad[0] + (L::cy(i) - u[1]) * grad[1] + (L::cz(i) - u[2]) * grad[2];
-        xi[i] = kCs2 * (feq[i] - wi) * proj[i] + wi * rho * kCs2 * Lam;
-        h0[i] = g[i] * inv_rc + xi[i] * half_inv;
-        pi += h0[i];
+        feq = wi * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        proj = (L::cx(i) - u[0]) * grad[0] + (L::cy(i) - u[1]) * grad[1] + (L::cz(i) - u[2]) * grad[2];
+        return kCs2 * (feq - wi) * proj + wi * rho * kCs2 * Lam;
+    };
+    const double half_inv = 0.5 * inv_rc;
+    double hx[Q], pi = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        double feq, proj;
+        hx[i] = g[i] * inv_rc + xi_of(i, feq, proj) * half_inv;
+        pi += hx[i];
     }
     const double sh = 1.0 - pi;
-    // the transforms, keeping the input of every pass
-    double hx[Q], hy[Q], hz[Q], kr[Q], iz[Q], iy[Q];
-    for (int i = 0; i < Q; ++i) hx[i] = h0[i] + L::w(i) * sh;
-    for (int i = 0; i < Q; ++i) hy[i] = hx[i];
-    for (int l = 0; l < Q / 3; ++l) cm_fwd_line(hy[3 * l], hy[3 * l + 1], hy[3 * l + 2], u[0]);
-    for (int i = 0; i < Q; ++i) hz[i] = hy[i];
-    for (int zp = 0; zp < Q / 9; ++zp)
-        for (int p = 0; p < 3; ++p) cm_fwd_line(hz[9 * zp + p], hz[9 * zp + p + 3], hz[9 * zp + p + 6], u[1]);
-    for (int i = 0; i < Q; ++i) kr[i] = hz[i];
-    if constexpr (Q == 27)
-        for (int r = 0; r < 9; ++r) cm_fwd_line(kr[r], kr[r + 9], kr[r + 18], u[2]);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) hx[i] += L::w(i) * sh;
+    // moments (kept: kr, the relaxed central moments; the passes' other
+    // inputs are recomputed in the reverse)
+    double kr[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) kr[i] = hx[i];
+    central_fwd<Q>(kr, u);
     relax<Q>(kr, P.omega2, P.omega3, P.omega4);
-    for (int i = 0; i < Q; ++i) iz[i] = kr[i];
-    if constexpr (Q == 27)
-        for (int r = 0; r < 9; ++r) cm_inv_line(iz[r], iz[r + 9], iz[r + 18], u[2]);
-    for (int i = 0; i < Q; ++i) iy[i] = iz[i];
-    for (int zp = 0; zp < Q / 9; ++zp)
-        for (int p = 0; p < 3; ++p) cm_inv_line(iy[9 * zp + p], iy[9 * zp + p + 3], iy[9 * zp + p + 6], u[1]);
-    double h3[Q];
-    for (int i = 0; i < Q; ++i) h3[i] = iy[i];
-    for (int l = 0; l < Q / 3; ++l) cm_inv_line(h3[3 * l], h3[3 * l + 1], h3[3 * l + 2], u[0]);
     const double rc = rho * kCs2;
 
     // ------------------------------------------------------ reverse
-    for (int i = 0; i < Q; ++i) a.g[i] = 0.0;
-    for (int s = 0; s < kSlots; ++s) {
-        a.T[s] = 0.0;
-        a.Tw[s] = 0.0;
-        for (int k = 0; k < NSP; ++k) a.Y[s][k] = 0.0;
-    }
-    double lR[kSlots];
-    for (int s = 0; s < kSlots; ++s) lR[s] = 0.0;
+    const long long c_self = in.cell[0];
+    double lo[Q + 1 + NSP];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lo[i] = out.lo_pop[(long long)i * P.N + c_self];
+#pragma unroll
+    for (int k = 0; k < 1 + NSP; ++k) lo[Q + k] = out.lo_sc[(long long)k * P.N + c_self];
+    double ag[Q];
+    double aT0 = 0.0, aY0[NSP], lR0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) aY0[k] = 0.0;
     double lu[3] = {0.0, 0.0, 0.0}, lrho = 0.0, linv_rc = 0.0, linv_rho = 0.0;
 
-    // out[i] = rc (h3[i] - w_i sh) + xi[i] / 2
-    double lh[Q], lxi[Q], lrc = 0.0, lsh = 0.0;
-    for (int i = 0; i < Q; ++i) {
-        lh[i] = rc * lo[i];
-        lrc += lo[i] * (h3[i] - L::w(i) * sh);
-        lsh -= rc * L::w(i) * lo[i];
-        lxi[i] = 0.5 * lo[i];
-    }
-    // central_inv, reversed
-    for (int l = 0; l < Q / 3; ++l)
-        lu[0] += cm_inv_line_adj(iy[3 * l], iy[3 * l + 1], iy[3 * l + 2], u[0], lh[3 * l], lh[3 * l + 1], lh[3 * l + 2]);
-    for (int zp = 0; zp < Q / 9; ++zp)
-        for (int p = 0; p < 3; ++p) {
-            const int i0 = 9 * zp + p, i1 = i0 + 3, i2 = i0 + 6;
-            lu[1] += cm_inv_line_adj(iz[i0], iz[i1], iz[i2], u[1], lh[i0], lh[i1], lh[i2]);
+    // out_i = rc (h3_i - w_i sh) + xi_i / 2, h3 = central_inv(kr)
+    double lh[Q], lrc = 0.0, lsh = 0.0;
+    {
+        double iz[Q], iy[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) iz[i] = kr[i];
+        if constexpr (Q == 27) {
+#pragma unroll
+            for (int r = 0; r < 9; ++r) cm_inv_line(iz[r], iz[r + 9], iz[r + 18], u[2]);
         }
-    if constexpr (Q == 27)
-        for (int r = 0; r < 9; ++r) lu[2] += cm_inv_line_adj(kr[r], kr[r + 9], kr[r + 18], u[2], lh[r], lh[r + 9], lh[r + 18]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) iy[i] = iz[i];
+#pragma unroll
+        for (int zp = 0; zp < Q / 9; ++zp)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) cm_inv_line(iy[9 * zp + p], iy[9 * zp + p + 3], iy[9 * zp + p + 6], u[1]);
+        double h3[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) h3[i] = iy[i];
+#pragma unroll
+        for (int l = 0; l < Q / 3; ++l) cm_inv_line(h3[3 * l], h3[3 * l + 1], h3[3 * l + 2], u[0]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            lh[i] = rc * lo[i];
+            lrc += lo[i] * (h3[i] - L::w(i) * sh);
+            lsh -= rc * L::w(i) * lo[i];
+        }
+        // central_inv, reversed
+#pragma unroll
+        for (int l = 0; l < Q / 3; ++l)
+            lu[0] += cm_inv_line_adj(iy[3 * l], iy[3 * l + 1], iy[3 * l + 2], u[0], lh[3 * l], lh[3 * l + 1],
+                                     lh[3 * l + 2]);
+#pragma unroll
+        for (int zp = 0; zp < Q / 9; ++zp)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const int i0 = 9 * zp + p, i1 = i0 + 3, i2 = i0 + 6;
+                lu[1] += cm_inv_line_adj(iz[i0], iz[i1], iz[i2], u[1], lh[i0], lh[i1], lh[i2]);
+            }
+        if constexpr (Q == 27) {
+#pragma unroll
+            for (int r = 0; r < 9; ++r)
+                lu[2] += cm_inv_line_adj(kr[r], kr[r + 9], kr[r + 18], u[2], lh[r], lh[r + 9], lh[r + 18]);
+        }
+    }
     relax_adj<Q>(lh, P.omega2, P.omega3, P.omega4);
     // central_fwd, reversed
-    if constexpr (Q == 27)
-        for (int r = 0; r < 9; ++r) lu[2] += cm_fwd_line_adj(hz[r], hz[r + 9], hz[r + 18], u[2], lh[r], lh[r + 9], lh[r + 18]);
-    for (int zp = 0; zp < Q / 9; ++zp)
-        for (int p = 0; p < 3; ++p) {
-            const int i0 = 9 * zp + p, i1 = i0 + 3, i2 = i0 + 6;
-            lu[1] += cm_fwd_line_adj(hy[i0], hy[i1], hy[i2], u[1], lh[i0], lh[i1], lh[i2]);
+    {
+        double hy[Q], hz[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) hy[i] = hx[i];
+#pragma unroll
+        for (int l = 0; l < Q / 3; ++l) cm_fwd_line(hy[3 * l], hy[3 * l + 1], hy[3 * l + 2], u[0]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) hz[i] = hy[i];
+#pragma unroll
+        for (int zp = 0; zp < Q / 9; ++zp)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) cm_fwd_line(hz[9 * zp + p], hz[9 * zp + p + 3], hz[9 * zp + p + 6], u[1]);
+        if constexpr (Q == 27) {
+#pragma unroll
+            for (int r = 0; r < 9; ++r)
+                lu[2] += cm_fwd_line_adj(hz[r], hz[r + 9], hz[r + 18], u[2], lh[r], lh[r + 9], lh[r + 18]);
         }
-    for (int l = 0; l < Q / 3; ++l)
-        lu[0] += cm_fwd_line_adj(hx[3 * l], hx[3 * l + 1], hx[3 * l + 2], u[0], lh[3 * l], lh[3 * l + 1], lh[3 * l + 2]);
+#pragma unroll
+        for (int zp = 0; zp < Q / 9; ++zp)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const int i0 = 9 * zp + p, i1 = i0 + 3, i2 = i0 + 6;
+                lu[1] += cm_fwd_line_adj(hy[i0], hy[i1], hy[i2], u[1], lh[i0], lh[i1], lh[i2]);
+            }
+#pragma unroll
+        for (int l = 0; l < Q / 3; ++l)
+            lu[0] += cm_fwd_line_adj(hx[3 * l], hx[3 * l + 1], hx[3 * l + 2], u[0], lh[3 * l], lh[3 * l + 1],
+                                     lh[3 * l + 2]);
+    }
     // hx = h0 + w sh, sh = 1 - sum h0
+#pragma unroll
     for (int i = 0; i < Q; ++i) lsh += L::w(i) * lh[i];
     double lLam = 0.0, lgrad[3] = {0.0, 0.0, 0.0}, luu = 0.0;
+#pragma unroll
     for (int i = 0; i < Q; ++i) {
         const double lh0 = lh[i] - lsh;
+        double feq, proj;
+        const double xi = xi_of(i, feq, proj);
         // h0 = g inv_rc + xi inv_rc / 2
-        a.g[i] += inv_rc * lh0;
-        lxi[i] += half_inv * lh0;
-        linv_rc += lh0 * (g[i] + 0.5 * xi[i]);
+        ag[i] = inv_rc * lh0;
+        const double lxi = 0.5 * lo[i] + half_inv * lh0;
+        linv_rc += lh0 * (g[i] + 0.5 * xi);
         // xi = cs2 (feq - w) proj + w rho cs2 Lam
         const double wi = L::w(i);
-        const double lfeq = kCs2 * proj[i] * lxi[i];
-        const double lproj = kCs2 * (feq[i] - wi) * lxi[i];
-        lrho += wi * kCs2 * Lam * lxi[i];
-        lLam += wi * rho * kCs2 * lxi[i];
+        const double lfeq = kCs2 * proj * lxi;
+        const double lproj = kCs2 * (feq - wi) * lxi;
+        lrho += wi * kCs2 * Lam * lxi;
+        lLam += wi * rho * kCs2 * lxi;
         // proj = sum_d (c_d - u_d) grad_d
         const double cd[3] = {(double)L::cx(i), (double)L::cy(i), (double)L::cz(i)};
+#pragma unroll
         for (int d = 0; d < 3; ++d) {
             lgrad[d] += lproj * (cd[d] - u[d]);
             lu[d] -= lproj * grad[d];
@@ -727,99 +821,80 @@ __device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, const doubl
         const double cu = cd[0] * u[0] + cd[1] * u[1] + cd[2] * u[2];
         const double lcu = wi * (3.0 + 9.0 * cu) * lfeq;
         luu -= 1.5 * wi * lfeq;
+#pragma unroll
         for (int d = 0; d < 3; ++d) lu[d] += cd[d] * lcu;
     }
+#pragma unroll
     for (int d = 0; d < 3; ++d) lu[d] += 2.0 * u[d] * luu;
     lrho += kCs2 * lrc;
 
     // scalar outputs: T' = T0 - CT + DtT, Y' = Y0 - CY + DtY
     const double lTo = lo[Q];
-    a.T[0] += lTo + wT0;
+    aT0 += lTo + wT0;
     const double lCT = -lTo;
     double lDtT = lTo, lCY[NSP], lDtY[NSP];
+#pragma unroll
     for (int k = 0; k < NSP; ++k) {
-        a.Y[0][k] += lo[Q + 1 + k];
+        aY0[k] += lo[Q + 1 + k];
         lCY[k] = -lo[Q + 1 + k];
         lDtY[k] = lo[Q + 1 + k];
     }
     // Lam = DtT / T0 + sum_k Wm / W_k DtY_k, Wm = 1 / sum_k Y0_k / W_k
     lDtT += lLam / T[0];
-    a.T[0] -= lLam * DtT / (T[0] * T[0]);
+    aT0 -= lLam * DtT / (T[0] * T[0]);
     double lWm = 0.0;
+#pragma unroll
     for (int k = 0; k < NSP; ++k) {
         lDtY[k] += lLam * Wm * P.invW[k];
         lWm += lLam * P.invW[k] * DtY[k];
     }
     const double linvWs = -lWm * Wm * Wm;
-    for (int k = 0; k < NSP; ++k) a.Y[0][k] += linvWs * P.invW[k];
-    // Dt = alpha (diffusion) + source
-    {
-        double ls[NS];
-        ls[0] = lDtT;
-        for (int k = 0; k < NSP; ++k) ls[1 + k] = lDtY[k];
-        for (int i = 0; i < NS; ++i) {
-            double acc = 0.0;
-            for (int o = 0; o < NS; ++o) acc += Jc[o][i] * ls[o];
-            if (i == 0)
-                a.T[0] += acc;
-            else
-                a.Y[0][i - 1] += acc;
-        }
-        // (A_j, Ta_j): one forward-mode pass per reaction
-        using V = DualN<2>;
-        for (int jr = 0; jr < P.n_rx; ++jr) {
-            V T0(T[0]), Y0[NSP], sT, sY[NSP];
-            for (int k = 0; k < NSP; ++k) Y0[k] = V(Y[0][k]);
-            chem_source<NSP>(
-                P, T0, Y0,
-                [&](int j, V &Aj, V &Taj) {
-                    Aj = V(P.rx[j].A);
-                    Taj = V(P.rx[j].Ta);
-                    if (j == jr) {
-                        Aj.d[0] = 1.0;
-                        Taj.d[1] = 1.0;
-                    }
-                },
-                sT, sY);
-            double gA = ls[0] * sT.d[0], gTa = ls[0] * sT.d[1];
-            for (int k = 0; k < NSP; ++k) {
-                gA += ls[1 + k] * sY[k].d[0];
-                gTa += ls[1 + k] * sY[k].d[1];
-            }
-            atomicAdd(&lam_param[2 * jr], gA);
-            atomicAdd(&lam_param[2 * jr + 1], gTa);
-        }
-    }
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) aY0[k] += linvWs * P.invW[k];
     const double ldT = P.alpha * lDtT;
     double ldY[NSP];
+#pragma unroll
     for (int k = 0; k < NSP; ++k) ldY[k] = P.alpha * lDtY[k];
 
-    // the axes, reversed
+    // the axes, reversed; each axis's four slots finished and scattered
+    asm volatile("" ::: "memory");  // read the stencil again instead of keeping it
+    fill();
+#pragma unroll
     for (int d = 0; d < D; ++d) {
         const int sl[5] = {1 + 4 * d, 2 + 4 * d, 0, 3 + 4 * d, 4 + 4 * d};
-        bool near = false;
-        for (int j = 0; j < 5; ++j) near |= in.kind[sl[j]] != kFluid;
+        // adjoints of the stencil's T, Y, rho (index 2: the cell, accumulated
+        // into aT0, aY0, lR0 at the end of the axis)
+        double aT[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, aY[5][NSP], lR[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        double aTw[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) aY[j][k] = 0.0;
         // wall heat flux q += 2 alpha rho(Tw, Y0) (T0 - Tw), rho(Tw, Y0) = c0 / (Tw Sw0)
+#pragma unroll
         for (int j = 1; j <= 3; j += 2)
             if (in.kind[sl[j]] == kIso && wq != 0.0) {
-                const int s = sl[j];
-                const double Tw = in.Tw[s], rw = c0 / (Tw * Sw[0]), f = 2.0 * P.alpha * wq;
-                a.T[0] += f * rw;
-                a.Tw[s] += f * (-rw / Tw * (T[0] - Tw) - rw);
-                for (int k = 0; k < NSP; ++k) a.Y[0][k] += f * (T[0] - Tw) * (-rw * P.invW[k] / Sw[0]);
+                const double Tw = in.Tw[sl[j]], rw = c0 / (Tw * Sw[0]), f = 2.0 * P.alpha * wq;
+                aT0 += f * rw;
+                aTw[j] += f * (-rw / Tw * (T[0] - Tw) - rw);
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) aY0[k] += f * (T[0] - Tw) * (-rw * P.invW[k] / Sw[0]);
             }
         const double d1r = grad[d];
         double ld1r = lgrad[d];
         // diffusion: d2(phi) + d1r d1(phi) / rho
         {
             const double dT1 = d1(T[sl[0]], T[sl[1]], T[sl[2]], T[sl[3]], T[sl[4]]);
-            for (int j = 0; j < 5; ++j) a.T[sl[j]] += ldT * (c2[j] + d1r * inv_rho * c1[j]);
+#pragma unroll
+            for (int j = 0; j < 5; ++j) aT[j] += ldT * (c2[j] + d1r * inv_rho * c1[j]);
             ld1r += ldT * dT1 * inv_rho;
             linv_rho += ldT * d1r * dT1;
         }
+#pragma unroll
         for (int k = 0; k < NSP; ++k) {
             const double dY1 = d1(Y[sl[0]][k], Y[sl[1]][k], Y[sl[2]][k], Y[sl[3]][k], Y[sl[4]][k]);
-            for (int j = 0; j < 5; ++j) a.Y[sl[j]][k] += ldY[k] * (c2[j] + d1r * inv_rho * c1[j]);
+#pragma unroll
+            for (int j = 0; j < 5; ++j) aY[j][k] += ldY[k] * (c2[j] + d1r * inv_rho * c1[j]);
             ld1r += ldY[k] * dY1 * inv_rho;
             linv_rho += ldY[k] * d1r * dY1;
         }
@@ -827,78 +902,172 @@ __device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, const doubl
         lu[d] += lCT * cT[d];
         {
             const double lc = lCT * u[d];
-            double l5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            if (near) {
-                l5[3] += 0.5 * lc;
-                l5[1] -= 0.5 * lc;
+            if (near[d]) {
+                aT[3] += 0.5 * lc;
+                aT[1] -= 0.5 * lc;
             } else {
-                weno3_adj(T[sl[0]], T[sl[1]], T[sl[2]], T[sl[3]], T[sl[4]], u[d], lc, l5);
+                weno3_adj(T[sl[0]], T[sl[1]], T[sl[2]], T[sl[3]], T[sl[4]], u[d], lc, aT);
             }
-            for (int j = 0; j < 5; ++j) a.T[sl[j]] += l5[j];
         }
         // convection of Y: CY_k += u_d (cY_k - Y0_k sumc)
         double lsumc = 0.0;
+#pragma unroll
         for (int k = 0; k < NSP; ++k) {
             lu[d] += lCY[k] * (cY[d][k] - Y[0][k] * sumc[d]);
-            a.Y[0][k] -= lCY[k] * u[d] * sumc[d];
+            aY0[k] -= lCY[k] * u[d] * sumc[d];
             lsumc -= lCY[k] * u[d] * Y[0][k];
         }
+#pragma unroll
         for (int k = 0; k < NSP; ++k) {
             const double lc = lCY[k] * u[d] + lsumc;
-            double l5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            if (near) {
-                l5[3] += 0.5 * lc;
-                l5[1] -= 0.5 * lc;
+            if (near[d]) {
+                aY[3][k] += 0.5 * lc;
+                aY[1][k] -= 0.5 * lc;
             } else {
+                double l5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
                 weno3_adj(Y[sl[0]][k], Y[sl[1]][k], Y[sl[2]][k], Y[sl[3]][k], Y[sl[4]][k], u[d], lc, l5);
+#pragma unroll
+                for (int j = 0; j < 5; ++j) aY[j][k] += l5[j];
             }
-            for (int j = 0; j < 5; ++j) a.Y[sl[j]][k] += l5[j];
         }
         // d1r = d1(R)
-        for (int j = 0; j < 5; ++j) lR[sl[j]] += ld1r * c1[j];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) lR[j] += ld1r * c1[j];
+
+        // ghosts of this axis onto their images (the cell, j = 2, or a first
+        // neighbour, j = 1 or 3) and their wall temperatures
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            if (j == 2) continue;
+            const int s = sl[j], kd = in.kind[s];
+            if (kd == kFluid) continue;
+            const int im = in.img[s];
+            // local index of the image: slot img_lo(s) is j = 1, img_hi(s) is j = 3
+            const bool second = j == 0 || j == 4;
+            const bool ia = second && im == img_lo(s), ib = second && !ia && im == img_hi(s);
+            const int li = ia ? 1 : ib ? 3 : 2;
+            const double fa = ia ? 1.0 : 0.0, fb = ib ? 1.0 : 0.0;
+            const double Swi = fa * Sw[sl[1]] + fb * Sw[sl[3]] + (1.0 - fa - fb) * Sw[0];
+            double gT, gY[NSP], gR;  // what the image receives
+            if (kd == kIso) {
+                const double Tw = in.Tw[s], rw = c0 / (Tw * Swi);
+                aTw[j] += 2.0 * aT[j] + 2.0 * lR[j] * (-rw / Tw);
+                gT = -aT[j];
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) gY[k] = aY[j][k] + 2.0 * lR[j] * (-rw * P.invW[k] / Swi);
+                gR = -lR[j];
+            } else if (kd == kInflow) {
+                gT = -aT[j];
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) gY[k] = -aY[j][k];
+                gR = -lR[j];
+            } else {
+                gT = aT[j];
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) gY[k] = aY[j][k];
+                gR = lR[j];
+            }
+            aT[1] += li == 1 ? gT : 0.0;
+            aT[3] += li == 3 ? gT : 0.0;
+            aT[2] += li == 2 ? gT : 0.0;
+            lR[1] += li == 1 ? gR : 0.0;
+            lR[3] += li == 3 ? gR : 0.0;
+            lR[2] += li == 2 ? gR : 0.0;
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) {
+                aY[1][k] += li == 1 ? gY[k] : 0.0;
+                aY[3][k] += li == 3 ? gY[k] : 0.0;
+                aY[2][k] += li == 2 ? gY[k] : 0.0;
+            }
+            if (kd == kIso && in.wall[s] >= 0) atomicAdd(&out.dwallT[in.wall[s]], aTw[j]);
+        }
+        // the axis's fluid slots: densities R = c0 / (T Sw) onto T and Y, scatter
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            if (j == 2) continue;
+            const int s = sl[j];
+            if (in.kind[s] != kFluid) continue;
+            double t = aT[j] - lR[j] * R[s] / T[s];
+            const long long c = in.cell[s];
+            atomicAdd(&out.lam_sc[c], t);
+#pragma unroll
+            for (int k = 0; k < NSP; ++k)
+                atomicAdd(&out.lam_sc[(long long)(1 + k) * P.N + c], aY[j][k] - lR[j] * R[s] * P.invW[k] / Sw[s]);
+        }
+        aT0 += aT[2];
+        lR0 += lR[2];
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) aY0[k] += aY[2][k];
+        // the wall-heat-flux terms' wall temperatures (first neighbours)
     }
 
+    // the source, reversed (Dt = alpha (diffusion) + source)
+    {
+        double ls[NS];
+        ls[0] = lDtT;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) ls[1 + k] = lDtY[k];
+        // one forward-mode pass per input of the source: T0, Y0_k, then
+        // (A_j, Ta_j) of every reaction; each column of the Jacobian times ls
+        using V = DualN<1>;
+        const int ncol = NS + 2 * P.n_rx;
+        for (int col = 0; col < ncol; ++col) {
+            V T0(T[0]), Y0[NSP], sT, sY[NSP];
+            if (col == 0) T0.d[0] = 1.0;
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) {
+                Y0[k] = V(Y[0][k]);
+                if (col == 1 + k) Y0[k].d[0] = 1.0;
+            }
+            const int pj = col - NS;  // parameter column: reaction pj / 2, A (even) or Ta (odd)
+            chem_source<NSP>(
+                P, T0, Y0,
+                [&](int j, V &Aj, V &Taj) {
+                    Aj = V(P.rx[j].A);
+                    Taj = V(P.rx[j].Ta);
+                    if (pj == 2 * j) Aj.d[0] = 1.0;
+                    if (pj == 2 * j + 1) Taj.d[0] = 1.0;
+                },
+                sT, sY);
+            double acc = ls[0] * sT.d[0];
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) acc += ls[1 + k] * sY[k].d[0];
+            if (col == 0)
+                aT0 += acc;
+            else if (col < NS) {
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) aY0[k] += col == 1 + k ? acc : 0.0;
+            } else {
+                atomicAdd(&out.lam_param[pj], acc);
+            }
+        }
+    }
     // u = m / (rho cs2), inv_rho = 1 / rho
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double lm = lu[d] * inv_rc;
         linv_rc += lu[d] * m[d];
+#pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int c = d == 0 ? L::cx(i) : d == 1 ? L::cy(i) : L::cz(i);
-            if (c != 0) a.g[i] += c * lm;
+            if (c != 0) ag[i] += c * lm;
         }
     }
     lrho -= linv_rc * inv_rc / rho;
     lrho -= linv_rho * inv_rho * inv_rho;
-    lR[0] += lrho;
-
-    // ghosts onto their images and wall temperatures
-    for (int s = 0; s < kSlots; ++s) {
-        if (in.kind[s] == kFluid) continue;
-        const int im = in.img[s];
-        if (in.kind[s] == kIso) {
-            const double Tw = in.Tw[s], rw = c0 / (Tw * Sw[im]);
-            a.Tw[s] += 2.0 * a.T[s] + 2.0 * lR[s] * (-rw / Tw);
-            a.T[im] -= a.T[s];
-            for (int k = 0; k < NSP; ++k) a.Y[im][k] += a.Y[s][k] + 2.0 * lR[s] * (-rw * P.invW[k] / Sw[im]);
-            lR[im] -= lR[s];
-        } else if (in.kind[s] == kInflow) {
-            a.T[im] -= a.T[s];
-            for (int k = 0; k < NSP; ++k) a.Y[im][k] -= a.Y[s][k];
-            lR[im] -= lR[s];
-        } else {
-            a.T[im] += a.T[s];
-            for (int k = 0; k < NSP; ++k) a.Y[im][k] += a.Y[s][k];
-            lR[im] += lR[s];
-        }
-        a.T[s] = 0.0;
-        for (int k = 0; k < NSP; ++k) a.Y[s][k] = 0.0;
+    lR0 += lrho;
+    // the cell's own slot and its pulls
+    {
+        const long long c = in.cell[0];
+        atomicAdd(&out.lam_sc[c], aT0 - lR0 * R[0] / T[0]);
+#pragma unroll
+        for (int k = 0; k < NSP; ++k)
+            atomicAdd(&out.lam_sc[(long long)(1 + k) * P.N + c], aY0[k] - lR0 * R[0] * P.invW[k] / Sw[0]);
     }
-    // densities of the fluid slots: R = c0 / (T Sw)
-    for (int s = 0; s < kSlots; ++s) {
-        if (in.kind[s] != kFluid || lR[s] == 0.0) continue;
-        a.T[s] -= lR[s] * R[s] / T[s];
-        for (int k = 0; k < NSP; ++k) a.Y[s][k] -= lR[s] * R[s] * P.invW[k] / Sw[s];
-    }
+    // pull streaming reads every population entry at most once (the source
+    // cell's, or the cell's own opposite entry behind a wall)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out.lam_pop[(long long)in.tdir[i] * P.N + in.tcell[i]] = ag[i];
 }
 
 struct AdjParams {
@@ -925,27 +1094,10 @@ __global__ void __launch_bounds__(kBlock) adjoint_kernel(const AdjParams AP)
         const int x = (int)(idx % P.nx), y = (int)((idx / P.nx) % P.ny), z = (int)(idx / ((long long)P.nx * P.ny));
         CellIn<Q, NSP> in;
         gather_inputs<Q, NSP>(P, x, y, z, idx, in);
-        double lo[Q + 1 + NSP];
-        for (int i = 0; i < Q; ++i) lo[i] = AP.lam_pop_next[(long long)i * P.N + idx];
-        for (int k = 0; k < 1 + NSP; ++k) lo[Q + k] = AP.lam_sc_next[(long long)k * P.N + idx];
         const double wq = AP.obj_kind == LBFD_OBJ_WALL_HEAT_FLUX ? AP.obj_w : 0.0;
         const double wT0 = AP.obj_kind == LBFD_OBJ_FLAME_POSITION ? AP.obj_w : 0.0;
-        CellAdj<Q, NSP> a;
-        cell_vjp<Q, NSP>(P, in, lo, wq, wT0, a, red);
-        // pull streaming reads every population entry at most once (the
-        // source cell's, or the cell's own opposite entry behind a wall)
-        for (int i = 0; i < Q; ++i) AP.lam_pop[(long long)in.tdir[i] * P.N + in.tcell[i]] = a.g[i];
-        constexpr int D = Lat<Q>::D;
-        for (int s = 0; s < kSlots; ++s) {
-            if (s > 0 && (s - 1) / 4 >= D) continue;
-            if (in.kind[s] == kFluid) {
-                const long long c = in.cell[s];
-                atomicAdd(&AP.lam_sc[c], a.T[s]);
-                for (int k = 0; k < NSP; ++k) atomicAdd(&AP.lam_sc[(long long)(1 + k) * P.N + c], a.Y[s][k]);
-            } else if (in.kind[s] == kIso && in.wall[s] >= 0) {
-                atomicAdd(&AP.dwallT[in.wall[s]], a.Tw[s]);
-            }
-        }
+        AdjOut o{AP.lam_pop_next, AP.lam_sc_next, AP.lam_pop, AP.lam_sc, AP.dwallT, red};
+        cell_vjp<Q, NSP>(P, in, wq, wT0, o);
     }
     __syncthreads();
     for (int j = threadIdx.x; j < 2 * P.n_rx; j += blockDim.x)
@@ -977,7 +1129,7 @@ __global__ void __launch_bounds__(kBlock) tangent_kernel(const TanParams TP)
     gather_inputs<Q, NSP>(P, x, y, z, idx, in);
     double tan[S::param + 2 * LBFD_MAX_REACTIONS];
     for (int i = 0; i < Q; ++i) tan[S::pull + i] = TP.dpop[(long long)in.tdir[i] * P.N + in.tcell[i]];
-    for (int s = 0; s < kSlots; ++s) {
+    for (int s = 0; s < S::S; ++s) {
         const bool fl = in.kind[s] == kFluid;
         for (int v = 0; v < 1 + NSP; ++v)
             tan[S::scal + s * (1 + NSP) + v] = fl ? TP.dsc[(long long)v * P.N + in.cell[s]] : 0.0;
