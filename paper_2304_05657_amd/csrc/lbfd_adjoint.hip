@@ -10,17 +10,17 @@
 //   lambda^n = (dF/ds^n)^T lambda^{n+1} + (dq/ds^n)^T,
 //   dJ/dtheta = sum_n (dF/dtheta)^T lambda^{n+1} + dq^n/dtheta.
 // One thread per fluid cell c gathers the cell's inputs (pull sources,
-// the finite-difference stencil's scalars, ghost wall temperatures; in the
-// general geometry path: neighbours classified on the fly) and runs the
-// cell's update forward in FP64, then backward (cell_vjp): the reverse of
+// the finite-difference stencil's scalars, ghost wall temperatures; at
+// interior cells plain offsets, elsewhere neighbours classified on the fly)
+// and runs the cell's update forward in FP64, then backward: the reverse of
 // every operation, hand-derived, from the adjoint of the cell's outputs to
-// those of its inputs.  The sub-stepped Arrhenius source is differentiated
-// in forward mode instead (a 5 x 5 Jacobian carried through the sub-steps,
-// and one pass per reaction for A_j, Ta_j): its state is small and its
-// sub-step count data-dependent.  Each pulled population is read by exactly
-// one cell, so its adjoint is stored; the stencil scalars' and wall
-// temperatures' adjoints are added atomically.  Steps are recomputed from
-// checkpoints taken every K steps (host side, lbfd_api.hip).
+// those of its inputs, in two kernels (cell_vjp_collision,
+// cell_vjp_stencil).  The sub-stepped Arrhenius source is reversed sub-step
+// by sub-step, each sub-step's state recomputed from the cell's (chem_vjp).
+// Each pulled population is read by exactly one cell, so its adjoint is
+// stored; the stencil scalars' and wall temperatures' adjoints are added
+// atomically.  Steps are recomputed from checkpoints taken every K steps
+// (host side, lbfd_api.hip).
 //
 // tangent_kernel evaluates the same update in dual numbers with a given
 // tangent of every input (the Jacobian-vector product of one step); the
@@ -106,13 +106,14 @@ template <int N> __device__ inline bool operator<(const DualN<N> &a, const DualN
 template <int N> __device__ inline bool operator>(const DualN<N> &a, const DualN<N> &b) { return a.v > b.v; }
 template <int N> __device__ inline bool operator>=(const DualN<N> &a, const DualN<N> &b) { return a.v >= b.v; }
 template <int N> __device__ inline bool operator<=(const DualN<N> &a, const DualN<N> &b) { return a.v <= b.v; }
-// the exponential of the forward chemistry (exp_tab)
-template <int N> __device__ inline DualN<N> dexp(const DualN<N> &a)
+// the exponential of the forward chemistry (exp_tab; tab: its table, in
+// LDS or constant memory)
+template <int N> __device__ inline DualN<N> dexp(const DualN<N> &a, const double *tab)
 {
-    const double e = exp_tab(a.v, kExp2Tab);
+    const double e = exp_tab(a.v, tab);
     return chain(a, e, e);
 }
-__device__ inline double dexp(double a) { return exp_tab(a, kExp2Tab); }
+__device__ inline double dexp(double a, const double *tab) { return exp_tab(a, tab); }
 template <int N> __device__ inline DualN<N> dlog(const DualN<N> &a) { return chain(a, log(a.v), rcp(a.v)); }
 __device__ inline double dlog(double a) { return log(a); }
 template <int N> __device__ inline double val(const DualN<N> &a) { return a.v; }
@@ -142,14 +143,36 @@ struct CellIn {
     int wall[S];          // ghost slot behind an isothermal in-box solid: its cell, else -1
 };
 
-template <int Q, int NSP>
+// PULLS = false: the stencil's slots only.
+template <int Q, int NSP, bool PULLS = true>
 __device__ void gather_inputs(const KParams &P, int x, int y, int z, long long idx, CellIn<Q, NSP> &in)
 {
     using L = Lat<Q>;
     constexpr int D = L::D;
     const double *pop = (const double *)P.pop_in;
+    if (P.code[idx] == kCodeInterior) {
+        // every pull source and stencil point is an in-box fluid cell
+        const long long st[3] = {1, P.nx, (long long)P.nx * P.ny};
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+        for (int i = 0; i < (PULLS ? Q : 0); ++i) {
+            in.tdir[i] = i;
+            in.tcell[i] = (int)(idx - (L::cx(i) * st[0] + L::cy(i) * st[1] + L::cz(i) * st[2]));
+            in.g[i] = pop[(long long)i * P.N + in.tcell[i]];
+        }
+#pragma unroll
+        for (int s = 0; s < n_slots<Q>(); ++s) {
+            const int d = s == 0 ? 0 : (s - 1) / 4, j = s == 0 ? 0 : (s - 1) % 4;
+            const int mm = j == 0 ? -2 : j == 1 ? -1 : j == 2 ? 1 : 2;
+            in.cell[s] = (int)(s == 0 ? idx : idx + mm * st[d]);
+            in.kind[s] = kFluid;
+            in.img[s] = -1;
+            in.Tw[s] = 0.0;
+            in.wall[s] = -1;
+        }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < (PULLS ? Q : 0); ++i) {
         const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = Q == 9 ? 0 : i / 9 - 1;
         const int opp = Q - 1 - i;
         double corr = 0.0;
@@ -245,14 +268,15 @@ __device__ A density_a(const KParams &P, A T, const A (&Y)[NSP])
 // the cell's T0, Y0 and the reactions' (A_j, Ta_j) = par(j) to (srcT, srcY).
 // The sub-step count and the limiter's choice follow the values.
 template <int NSP, class A, class Par>
-__device__ void chem_source(const KParams &P, const A &T0, const A (&Y0)[NSP], Par par, A &srcT, A (&srcY)[NSP])
+__device__ void chem_source(const KParams &P, const double *tab, const A &T0, const A (&Y0)[NSP], Par par, A &srcT,
+                            A (&srcY)[NSP])
 {
     const bool anyb = P.chem_anyb != 0;
     int nsub = 1;
     if (P.chem_substeps_max > 1) {
         const double lnT = anyb ? log(val(T0)) : 0.0, invT = rcp(val(T0));
         double kmax = 0.0;
-        for (int j = 0; j < P.n_rx; ++j) kmax = fmax(kmax, rate_coeff_l(P.rxk[j], lnT, invT, kExp2Tab));
+        for (int j = 0; j < P.n_rx; ++j) kmax = fmax(kmax, rate_coeff_l(P.rxk[j], lnT, invT, tab));
         const double want = ceil(kmax / 0.1);
         nsub = want < 1.0 ? 1 : want > (double)P.chem_substeps_max ? P.chem_substeps_max : (int)want;
     }
@@ -271,7 +295,7 @@ __device__ void chem_source(const KParams &P, const A &T0, const A (&Y0)[NSP], P
             const lbfd_reaction &r = P.rx[j];
             A Aj, Taj;
             par(j, Aj, Taj);
-            A rr = Aj * A(P.dt_phys) * dexp(A(r.b) * lnTc - Taj * invTc) * A(inv_nsub);
+            A rr = Aj * A(P.dt_phys) * dexp(A(r.b) * lnTc - Taj * invTc, tab) * A(inv_nsub);
             // four reactant factors, Y of the reactant or 1 (react[m] = NSP)
 #pragma unroll
             for (int mm = 0; mm < 4; ++mm) {
@@ -296,6 +320,149 @@ __device__ void chem_source(const KParams &P, const A &T0, const A (&Y0)[NSP], P
     }
     srcT = dT;
     for (int k = 0; k < NSP; ++k) srcY[k] = dY[k];
+}
+
+// One sub-step of chem_source in FP64 from the state (Tc, Yc): the
+// increments, the limiter's scale lam and the species that set it (kstar,
+// -1 when lam = 1), with the same arithmetic as chem_source.
+template <int NSP>
+__device__ __forceinline__ void chem_substep(const KParams &P, const double *tab, bool anyb, double inv_nsub,
+                                             double Tc, const double (&Yc)[NSP], double &incT, double (&incY)[NSP],
+                                             double &lam, int &kstar)
+{
+    const double lnTc = anyb ? log(Tc) : 0.0, invTc = rcp(Tc);
+    incT = 0.0;
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) incY[k] = 0.0;
+    for (int j = 0; j < P.n_rx; ++j) {
+        const lbfd_reaction &r = P.rx[j];
+        double rr = r.A * P.dt_phys * dexp(r.b * lnTc - r.Ta * invTc, tab) * inv_nsub;
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm) {
+            const int sp = P.rxk[j].react[mm];
+            double f = 1.0;
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) f = sp == k ? Yc[k] : f;
+            rr *= f;
+        }
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) incY[k] += r.nu_mass[k] * rr;
+        incT += r.q_over_cp * rr;
+    }
+    lam = 1.0;
+    kstar = -1;
+#pragma unroll
+    for (int k = 0; k < NSP; ++k)
+        if (incY[k] < 0.0 && Yc[k] + incY[k] < 0.0) {
+            const double l = (Yc[k] > 0.0 ? Yc[k] : 0.0) / (-incY[k]);
+            if (l < lam) {
+                lam = l;
+                kstar = k;
+            }
+        }
+}
+
+// Reverse of chem_source (FP64): given ls, the adjoint of (srcT, srcY),
+// adds ls^T d src / d (T0, Y0) to aT0, aY0 and ls^T d src / d (A_j, Ta_j) to
+// lam_param[2 j], lam_param[2 j + 1] (LDS).  The sub-steps are reversed
+// from the last; the state of each is recomputed from (T0, Y0), so the cost
+// grows with the square of the sub-step count (one sub-step: one forward
+// and one reverse evaluation).
+template <int NSP>
+__device__ void chem_vjp(const KParams &P, const double *tab, double T0, const double (&Y0)[NSP],
+                         const double (&ls)[1 + NSP], double &aT0, double (&aY0)[NSP], double *lam_param)
+{
+    const bool anyb = P.chem_anyb != 0;
+    int nsub = 1;
+    if (P.chem_substeps_max > 1) {
+        const double lnT = anyb ? log(T0) : 0.0, invT = rcp(T0);
+        double kmax = 0.0;
+        for (int j = 0; j < P.n_rx; ++j) kmax = fmax(kmax, rate_coeff_l(P.rxk[j], lnT, invT, tab));
+        const double want = ceil(kmax / 0.1);
+        nsub = want < 1.0 ? 1 : want > (double)P.chem_substeps_max ? P.chem_substeps_max : (int)want;
+    }
+    const double inv_nsub = nsub == 1 ? 1.0 : rcp((double)nsub);
+    // adjoint of the accumulated increments (dT, dY) after sub-step s
+    double LdT = ls[0], LdY[NSP];
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) LdY[k] = ls[1 + k];
+    for (int s = nsub - 1; s >= 0; --s) {
+        double dT = 0.0, dY[NSP];
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) dY[k] = 0.0;
+        double Yc[NSP], incT, incY[NSP], lam;
+        int kstar;
+        for (int t = 0; t < s; ++t) {
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) Yc[k] = Y0[k] + dY[k];
+            chem_substep<NSP>(P, tab, anyb, inv_nsub, T0 + dT, Yc, incT, incY, lam, kstar);
+            dT += lam * incT;
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) dY[k] += lam * incY[k];
+        }
+        const double Tc = T0 + dT;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) Yc[k] = Y0[k] + dY[k];
+        chem_substep<NSP>(P, tab, anyb, inv_nsub, Tc, Yc, incT, incY, lam, kstar);
+        // (dT, dY) += lam (incT, incY)
+        double llam = LdT * incT, lincY[NSP], lYc[NSP];
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) {
+            llam += LdY[k] * incY[k];
+            lincY[k] = lam * LdY[k];
+            lYc[k] = 0.0;
+        }
+        const double lincT = lam * LdT;
+        // lam = Yc_k / (-incY_k) for the limiting species k (0 if Yc_k <= 0)
+#pragma unroll
+        for (int k = 0; k < NSP; ++k)
+            if (k == kstar && Yc[k] > 0.0) {
+                lYc[k] += llam / (-incY[k]);
+                lincY[k] += llam * Yc[k] / (incY[k] * incY[k]);
+            }
+        // the rates rr_j = A_j dt exp(b_j ln Tc - Ta_j / Tc) / nsub prod_m F_jm
+        const double lnTc = anyb ? log(Tc) : 0.0, invTc = rcp(Tc);
+        double lTc = 0.0;
+        for (int j = 0; j < P.n_rx; ++j) {
+            const lbfd_reaction &r = P.rx[j];
+            const double e = dexp(r.b * lnTc - r.Ta * invTc, tab);
+            const double base = r.A * P.dt_phys * e * inv_nsub;
+            double F[4];
+            int sp[4];
+#pragma unroll
+            for (int mm = 0; mm < 4; ++mm) {
+                sp[mm] = P.rxk[j].react[mm];
+                double f = 1.0;
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) f = sp[mm] == k ? Yc[k] : f;
+                F[mm] = f;
+            }
+            const double pr = F[0] * F[1] * F[2] * F[3];
+            const double rr = base * pr;
+            double lrr = r.q_over_cp * lincT;
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) lrr += r.nu_mass[k] * lincY[k];
+            lTc += lrr * rr * (r.b * invTc + r.Ta * invTc * invTc);
+            atomicAdd(&lam_param[2 * j], lrr * P.dt_phys * e * inv_nsub * pr);
+            atomicAdd(&lam_param[2 * j + 1], -lrr * rr * invTc);
+            // each factor: the product of the other three
+            const double other[4] = {F[1] * F[2] * F[3], F[0] * F[2] * F[3], F[0] * F[1] * F[3], F[0] * F[1] * F[2]};
+#pragma unroll
+            for (int mm = 0; mm < 4; ++mm) {
+                const double g = lrr * base * other[mm];
+#pragma unroll
+                for (int k = 0; k < NSP; ++k) lYc[k] += sp[mm] == k ? g : 0.0;
+            }
+        }
+        // Tc = T0 + dT, Yc = Y0 + dY
+        aT0 += lTc;
+        LdT += lTc;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) {
+            aY0[k] += lYc[k];
+            LdY[k] += lYc[k];
+        }
+    }
 }
 
 // The cell's update in dual numbers with the tangent tan[slot] of every
@@ -403,7 +570,7 @@ __device__ void cell_eval(const KParams &P, const CellIn<Q, NSP> &in, const doub
     A srcT, srcY[NSP], Y0[NSP];
     for (int k = 0; k < NSP; ++k) Y0[k] = Y[0][k];
     chem_source<NSP>(
-        P, T[0], Y0,
+        P, kExp2Tab, T[0], Y0,
         [&](int j, A &Aj, A &Taj) {
             Aj = mk(P.rx[j].A, S::param + 2 * j);
             Taj = mk(P.rx[j].Ta, S::param + 2 * j + 1);
@@ -498,7 +665,7 @@ __device__ __forceinline__ void weno3_adj(double m2, double m1, double c0, doubl
     const double eA = eps + dA * dA, eB = eps + dB * dB, eE = eps + dE * dE;
     const double eA2 = eA * eA, eB2 = eB * eB, eE2 = eE * eE;
     const double den_p = eE2 + 2.0 * eB2, den_m = eB2 + 2.0 * eA2;
-    const double ip = 1.0 / den_p, im = 1.0 / den_m;
+    const double ip = rcp(den_p), im = rcp(den_m);
     const double w_p = eE2 * ip, w_m = eB2 * im;
     const double q0p = 1.5 * c0 - 0.5 * B, q1p = 0.5 * (c0 + E);
     const double q0m = 1.5 * B - 0.5 * A, q1m = 0.5 * (B + c0);
@@ -522,6 +689,24 @@ __device__ __forceinline__ void weno3_adj(double m2, double m1, double c0, doubl
     l[4] += neg ? lA : 0.0;
 }
 
+// The backward step runs as two kernels per level.  The first
+// (adjoint_collision_kernel) evaluates the cell's update forward and reverses
+// the collision, the moments and the velocity's part of the convection: it
+// finishes the adjoints of the pulled populations and leaves, per cell, the
+// few adjoints the rest needs (AdjMid).  The second (adjoint_stencil_kernel)
+// reverses the finite-difference stencils, the ghosts and densities, and the
+// Arrhenius source, and scatters the stencil scalars' adjoints.  Split so
+// that each kernel's registers leave room for more than one wave per SIMD.
+
+// Fields of the per-cell state between the two kernels, [field][N]:
+// lDtT, lDtY_k (adjoints of the increments Dt), lgrad_d (of d1 rho), u_d,
+// aT0, aY0_k (partial adjoints of the cell's own T, Y), lR0 (of its rho).
+template <int D, int NSP>
+struct AdjMid {
+    static constexpr int ls = 0, lgrad = 1 + NSP, u = lgrad + D, aT0 = u + D, aY0 = aT0 + 1,
+                         lR0 = aY0 + NSP, n = lR0 + 1;
+};
+
 // Where the reverse sweep puts the adjoints of a cell's inputs.
 struct AdjOut {
     const double *lo_pop;  // [Q][N] adjoint of the populations the step writes
@@ -530,83 +715,87 @@ struct AdjOut {
     double *lam_sc;     // [1+NSP][N]: accumulated atomically
     double *dwallT;     // [N]: accumulated atomically
     double *lam_param;  // [2 n_rx] in LDS: accumulated atomically
+    double *mid;        // [AdjMid::n][N]
 };
 
-// The cell's update forward in FP64, then its reverse: from the adjoint lo
-// of the outputs (g*, T^{n+1}, Y^{n+1}; read from out), the weight wq of the cell's
-// wall-heat-flux term and the weight wT0 of its own T (the flame position's
-// linear term) to the adjoints of the inputs, added to out.  The slots of
-// each axis are finished (ghosts onto their images, densities onto T and
-// Y) and scattered as soon as the axis's finite differences are reversed;
-// the cell's own slot last.
+// The stencil's T, Y, rho and sum_k Y_k / W_k, ghosts from their images
+// (fluid slots: the cell or a first neighbour).  Reciprocals of these
+// positive normal values by rcp() (the divisions here and in the stencil's
+// reverse: about one ulp).
 template <int Q, int NSP>
-__device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, double wq, double wT0, const AdjOut &out)
+__device__ __forceinline__ void fill_stencil(const KParams &P, const CellIn<Q, NSP> &in, double (&T)[n_slots<Q>()],
+                                             double (&Y)[n_slots<Q>()][NSP], double (&R)[n_slots<Q>()],
+                                             double (&Sw)[n_slots<Q>()])
+{
+    constexpr int S = n_slots<Q>();
+    const double c0 = P.T_ref_over_W_ref;
+    slot_scalars<Q, NSP>(P, in, T, Y);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        double sw = 0.0;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) sw += Y[s][k] * P.invW[k];
+        const bool fl = in.kind[s] == kFluid;
+        Sw[s] = fl ? sw : 1.0;
+        R[s] = fl ? c0 * rcp(T[s] * Sw[s]) : 0.0;
+    }
+#pragma unroll
+    for (int s = 1; s < S; ++s) {
+        const int kd = in.kind[s];
+        if (kd == kFluid) continue;
+        const int im = in.img[s];
+        const int ca = img_lo(s), cb = img_hi(s);
+        const bool ia = im == ca, ib = !ia && im == cb;
+        // the image's values as an exact 0/1 blend of the three candidates
+        // (a select between array elements would become an indexed load and
+        // keep the arrays in scratch memory)
+        const double fa = ia ? 1.0 : 0.0, fb = ib ? 1.0 : 0.0, f0 = 1.0 - fa - fb;
+        auto blend = [&](double va, double vb, double v0) { return fa * va + fb * vb + f0 * v0; };
+        const double Ti = blend(T[ca], T[cb], T[0]);
+        const double Ri = blend(R[ca], R[cb], R[0]);
+        const double Swi = blend(Sw[ca], Sw[cb], Sw[0]);
+        double Yi[NSP];
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) Yi[k] = blend(Y[ca][k], Y[cb][k], Y[0][k]);
+        Sw[s] = Swi;
+        if (kd == kIso) {
+            T[s] = 2.0 * in.Tw[s] - Ti;
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) Y[s][k] = Yi[k];
+            R[s] = 2.0 * (c0 * rcp(in.Tw[s] * Swi)) - Ri;
+        } else if (kd == kInflow) {
+            T[s] = 2.0 * P.T_in - Ti;
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) Y[s][k] = 2.0 * P.Y_in[k] - Yi[k];
+            R[s] = 2.0 * P.rho_in - Ri;
+        } else {
+            T[s] = Ti;
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) Y[s][k] = Yi[k];
+            R[s] = Ri;
+        }
+    }
+}
+
+// First half: the cell's update forward in FP64, then the reverse of the
+// collision (central moments and their transforms, the forcing Xi, the
+// equilibrium), of the scalars' increments up to Dt, of the convection's
+// dependence on u and of the moments (u = m / (rho cs2)).  From the adjoint
+// of the outputs (g*, T^{n+1}, Y^{n+1}; read from out) and the weight wT0 of
+// the cell's own T (the flame position's linear term): the adjoints of the
+// pulled populations (stored) and the cell's AdjMid.
+template <int Q, int NSP>
+__device__ void cell_vjp_collision(const KParams &P, const CellIn<Q, NSP> &in, double wT0, const double *tab,
+                                   const AdjOut &out)
 {
     using L = Lat<Q>;
+    using M = AdjMid<Lat<Q>::D, NSP>;
     constexpr int D = L::D, S = n_slots<Q>(), NS = 1 + NSP;
-    constexpr double c1[5] = {1.0 / 12.0, -8.0 / 12.0, 0.0, 8.0 / 12.0, -1.0 / 12.0};
-    constexpr double c2[5] = {-1.0 / 12.0, 16.0 / 12.0, -30.0 / 12.0, 16.0 / 12.0, -1.0 / 12.0};
-    const double c0 = P.T_ref_over_W_ref;
 
     // ------------------------------------------------ forward (values)
     double g[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) g[i] = in.g[i];
-    // the stencil's T, Y, rho and sum_k Y_k / W_k, ghosts from their images
-    // (fluid slots: the cell or a first neighbour); filled for the forward
-    // finite differences and again for their reverse, so that the values are
-    // not held through the collision
-    double T[S], Y[S][NSP], R[S], Sw[S];
-    auto fill = [&]() {
-        slot_scalars<Q, NSP>(P, in, T, Y);
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            double sw = 0.0;
-#pragma unroll
-            for (int k = 0; k < NSP; ++k) sw += Y[s][k] * P.invW[k];
-            const bool fl = in.kind[s] == kFluid;
-            Sw[s] = fl ? sw : 1.0;
-            R[s] = fl ? c0 / (T[s] * Sw[s]) : 0.0;
-        }
-#pragma unroll
-        for (int s = 1; s < S; ++s) {
-            const int kd = in.kind[s];
-            if (kd == kFluid) continue;
-            const int im = in.img[s];
-            const int ca = img_lo(s), cb = img_hi(s);
-            const bool ia = im == ca, ib = !ia && im == cb;
-            // the image's values as an exact 0/1 blend of the three candidates
-            // (a select between array elements would become an indexed load
-            // and keep the arrays in scratch memory)
-            const double fa = ia ? 1.0 : 0.0, fb = ib ? 1.0 : 0.0, f0 = 1.0 - fa - fb;
-            auto blend = [&](double va, double vb, double v0) { return fa * va + fb * vb + f0 * v0; };
-            const double Ti = blend(T[ca], T[cb], T[0]);
-            const double Ri = blend(R[ca], R[cb], R[0]);
-            const double Swi = blend(Sw[ca], Sw[cb], Sw[0]);
-            double Yi[NSP];
-#pragma unroll
-            for (int k = 0; k < NSP; ++k) Yi[k] = blend(Y[ca][k], Y[cb][k], Y[0][k]);
-            Sw[s] = Swi;
-            if (kd == kIso) {
-                T[s] = 2.0 * in.Tw[s] - Ti;
-#pragma unroll
-                for (int k = 0; k < NSP; ++k) Y[s][k] = Yi[k];
-                R[s] = 2.0 * (c0 / (in.Tw[s] * Swi)) - Ri;
-            } else if (kd == kInflow) {
-                T[s] = 2.0 * P.T_in - Ti;
-#pragma unroll
-                for (int k = 0; k < NSP; ++k) Y[s][k] = 2.0 * P.Y_in[k] - Yi[k];
-                R[s] = 2.0 * P.rho_in - Ri;
-            } else {
-                T[s] = Ti;
-#pragma unroll
-                for (int k = 0; k < NSP; ++k) Y[s][k] = Yi[k];
-                R[s] = Ri;
-            }
-        }
-    };
-    fill();
-    const double rho = R[0];
     double m[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -614,65 +803,70 @@ __device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, double wq, 
         m[1] += L::cy(i) * g[i];
         m[2] += L::cz(i) * g[i];
     }
-    const double inv_rc = 1.0 / (rho * kCs2);
-    const double u[3] = {m[0] * inv_rc, m[1] * inv_rc, m[2] * inv_rc};
-    const double inv_rho = 1.0 / rho;
+    double T0, Y0[NSP], rho;
     double diffT = 0.0, grad[3] = {0.0, 0.0, 0.0}, diffY[NSP];
     double cT[3] = {0.0, 0.0, 0.0}, cY[3][NSP], sumc[3] = {0.0, 0.0, 0.0};
-    bool near[3] = {false, false, false};
+    double u[3], inv_rc, inv_rho;
+    {
+        double T[S], Y[S][NSP], R[S], Sw[S];
+        fill_stencil<Q, NSP>(P, in, T, Y, R, Sw);
+        T0 = T[0];
 #pragma unroll
-    for (int k = 0; k < NSP; ++k) diffY[k] = 0.0;
+        for (int k = 0; k < NSP; ++k) Y0[k] = Y[0][k];
+        rho = R[0];
+        inv_rc = rcp(rho * kCs2);
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-        const int sl[5] = {1 + 4 * d, 2 + 4 * d, 0, 3 + 4 * d, 4 + 4 * d};
+        for (int d = 0; d < 3; ++d) u[d] = m[d] * inv_rc;
+        inv_rho = rcp(rho);
 #pragma unroll
-        for (int j = 0; j < 5; ++j) near[d] |= in.kind[sl[j]] != kFluid;
-        const double d1r = d1(R[sl[0]], R[sl[1]], R[sl[2]], R[sl[3]], R[sl[4]]);
-        {
-            const double p = T[sl[0]], b = T[sl[1]], c = T[sl[2]], e = T[sl[3]], f = T[sl[4]];
-            diffT += d2(p, b, c, e, f) + d1r * d1(p, b, c, e, f) * inv_rho;
-            cT[d] = near[d] ? 0.5 * (e - b) : weno3(p, b, c, e, f, u[d]);
+        for (int k = 0; k < NSP; ++k) diffY[k] = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int sl[5] = {1 + 4 * d, 2 + 4 * d, 0, 3 + 4 * d, 4 + 4 * d};
+            bool near = false;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) near |= in.kind[sl[j]] != kFluid;
+            const double d1r = d1(R[sl[0]], R[sl[1]], R[sl[2]], R[sl[3]], R[sl[4]]);
+            {
+                const double p = T[sl[0]], b = T[sl[1]], c = T[sl[2]], e = T[sl[3]], f = T[sl[4]];
+                diffT += d2(p, b, c, e, f) + d1r * d1(p, b, c, e, f) * inv_rho;
+                cT[d] = near ? 0.5 * (e - b) : weno3(p, b, c, e, f, u[d]);
+            }
+#pragma unroll
+            for (int k = 0; k < NSP; ++k) {
+                const double p = Y[sl[0]][k], b = Y[sl[1]][k], c = Y[sl[2]][k], e = Y[sl[3]][k], f = Y[sl[4]][k];
+                diffY[k] += d2(p, b, c, e, f) + d1r * d1(p, b, c, e, f) * inv_rho;
+                cY[d][k] = near ? 0.5 * (e - b) : weno3(p, b, c, e, f, u[d]);
+                sumc[d] += cY[d][k];
+            }
+            grad[d] = d1r;
         }
-#pragma unroll
-        for (int k = 0; k < NSP; ++k) {
-            const double p = Y[sl[0]][k], b = Y[sl[1]][k], c = Y[sl[2]][k], e = Y[sl[3]][k], f = Y[sl[4]][k];
-            diffY[k] += d2(p, b, c, e, f) + d1r * d1(p, b, c, e, f) * inv_rho;
-            cY[d][k] = near[d] ? 0.5 * (e - b) : weno3(p, b, c, e, f, u[d]);
-            sumc[d] += cY[d][k];
-        }
-        grad[d] = d1r;
     }
     diffT *= P.alpha;
 #pragma unroll
     for (int k = 0; k < NSP; ++k) diffY[k] *= P.alpha;
-
-    // the source (its derivatives are taken in the reverse, by forward mode)
     double srcT, srcY[NSP];
-    {
-        double Y0[NSP];
-#pragma unroll
-        for (int k = 0; k < NSP; ++k) Y0[k] = Y[0][k];
-        chem_source<NSP>(
-            P, T[0], Y0,
-            [&](int j, double &Aj, double &Taj) {
-                Aj = P.rx[j].A;
-                Taj = P.rx[j].Ta;
-            },
-            srcT, srcY);
-    }
+    chem_source<NSP>(
+        P, tab, T0, Y0,
+        [&](int j, double &Aj, double &Taj) {
+            Aj = P.rx[j].A;
+            Taj = P.rx[j].Ta;
+        },
+        srcT, srcY);
     const double DtT = diffT + srcT;
     double DtY[NSP], invWs = 0.0;
 #pragma unroll
     for (int k = 0; k < NSP; ++k) {
         DtY[k] = diffY[k] + srcY[k];
-        invWs += Y[0][k] * P.invW[k];
+        invWs += Y0[k] * P.invW[k];
     }
-    const double Wm = 1.0 / invWs;
-    double Lam = DtT / T[0];
+    const double Wm = rcp(invWs);
+    const double inv_T0 = rcp(T0);
+    double Lam = DtT * inv_T0;
 #pragma unroll
     for (int k = 0; k < NSP; ++k) Lam += (Wm * P.invW[k]) * DtY[k];
 
-    // xi_i = cs2 (feq_i - w_i) proj_i + w_i rho cs2 Lam, feq_i / w_i and proj_i
+    // xi_i = cs2 (feq_i - w_i) proj_i + w_i rho cs2 Lam, feq_i and proj_i
     // from u and grad (recomputed in the reverse)
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     auto xi_of = [&](int i, double &feq, double &proj) {
@@ -709,11 +903,7 @@ __device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, double wq, 
     for (int i = 0; i < Q; ++i) lo[i] = out.lo_pop[(long long)i * P.N + c_self];
 #pragma unroll
     for (int k = 0; k < 1 + NSP; ++k) lo[Q + k] = out.lo_sc[(long long)k * P.N + c_self];
-    double ag[Q];
-    double aT0 = 0.0, aY0[NSP], lR0 = 0.0;
-#pragma unroll
-    for (int k = 0; k < NSP; ++k) aY0[k] = 0.0;
-    double lu[3] = {0.0, 0.0, 0.0}, lrho = 0.0, linv_rc = 0.0, linv_rho = 0.0;
+    double lu[3] = {0.0, 0.0, 0.0}, lrho = 0.0, linv_rc = 0.0;
 
     // out_i = rc (h3_i - w_i sh) + xi_i / 2, h3 = central_inv(kr)
     double lh[Q], lrc = 0.0, lsh = 0.0;
@@ -794,6 +984,7 @@ __device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, double wq, 
     // hx = h0 + w sh, sh = 1 - sum h0
 #pragma unroll
     for (int i = 0; i < Q; ++i) lsh += L::w(i) * lh[i];
+    double ag[Q];
     double lLam = 0.0, lgrad[3] = {0.0, 0.0, 0.0}, luu = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -830,18 +1021,18 @@ __device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, double wq, 
 
     // scalar outputs: T' = T0 - CT + DtT, Y' = Y0 - CY + DtY
     const double lTo = lo[Q];
-    aT0 += lTo + wT0;
+    double aT0 = lTo + wT0, aY0[NSP];
     const double lCT = -lTo;
     double lDtT = lTo, lCY[NSP], lDtY[NSP];
 #pragma unroll
     for (int k = 0; k < NSP; ++k) {
-        aY0[k] += lo[Q + 1 + k];
+        aY0[k] = lo[Q + 1 + k];
         lCY[k] = -lo[Q + 1 + k];
         lDtY[k] = lo[Q + 1 + k];
     }
     // Lam = DtT / T0 + sum_k Wm / W_k DtY_k, Wm = 1 / sum_k Y0_k / W_k
-    lDtT += lLam / T[0];
-    aT0 -= lLam * DtT / (T[0] * T[0]);
+    lDtT += lLam * inv_T0;
+    aT0 -= lLam * DtT * inv_T0 * inv_T0;
     double lWm = 0.0;
 #pragma unroll
     for (int k = 0; k < NSP; ++k) {
@@ -851,17 +1042,107 @@ __device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, double wq, 
     const double linvWs = -lWm * Wm * Wm;
 #pragma unroll
     for (int k = 0; k < NSP; ++k) aY0[k] += linvWs * P.invW[k];
-    const double ldT = P.alpha * lDtT;
+    // the convection's dependence on u (CT = sum_d u_d cT_d, CY_k = sum_d
+    // u_d (cY_k - Y0_k sumc)) and on Y0 through sumc's factor
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lu[d] += lCT * cT[d];
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) {
+            lu[d] += lCY[k] * (cY[d][k] - Y0[k] * sumc[d]);
+            aY0[k] -= lCY[k] * u[d] * sumc[d];
+        }
+    }
+    // u = m / (rho cs2)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double lm = lu[d] * inv_rc;
+        linv_rc += lu[d] * m[d];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int c = d == 0 ? L::cx(i) : d == 1 ? L::cy(i) : L::cz(i);
+            if (c != 0) ag[i] += c * lm;
+        }
+    }
+    lrho -= linv_rc * inv_rc * inv_rho;
+
+    // pull streaming reads every population entry at most once (the source
+    // cell's, or the cell's own opposite entry behind a wall)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out.lam_pop[(long long)in.tdir[i] * P.N + in.tcell[i]] = ag[i];
+    // the source, reversed
+    {
+        double ls[NS];
+        ls[0] = lDtT;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) ls[1 + k] = lDtY[k];
+        chem_vjp<NSP>(P, tab, T0, Y0, ls, aT0, aY0, out.lam_param);
+    }
+    double *mid = out.mid + c_self;
+    mid[(long long)M::ls * P.N] = lDtT;
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) mid[(long long)(M::ls + 1 + k) * P.N] = lDtY[k];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        mid[(long long)(M::lgrad + d) * P.N] = lgrad[d];
+        mid[(long long)(M::u + d) * P.N] = u[d];
+    }
+    mid[(long long)M::aT0 * P.N] = aT0;
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) mid[(long long)(M::aY0 + k) * P.N] = aY0[k];
+    mid[(long long)M::lR0 * P.N] = lrho;
+}
+
+// Second half: the reverse of the finite-difference stencils (diffusion,
+// the convection's dependence on the stencil values, d1 rho), the ghosts
+// and densities, the wall-heat-flux term (weight wq) and the Arrhenius
+// source, from the cell's AdjMid; scatters the adjoints of the stencil's T,
+// Y (atomically, per axis as soon as its slots are finished), of the wall
+// temperatures and of A_j, Ta_j.
+template <int Q, int NSP>
+__device__ void cell_vjp_stencil(const KParams &P, const CellIn<Q, NSP> &in, double wq, const AdjOut &out)
+{
+    using L = Lat<Q>;
+    using M = AdjMid<Lat<Q>::D, NSP>;
+    constexpr int D = L::D, S = n_slots<Q>(), NS = 1 + NSP;
+    constexpr double c1[5] = {1.0 / 12.0, -8.0 / 12.0, 0.0, 8.0 / 12.0, -1.0 / 12.0};
+    constexpr double c2[5] = {-1.0 / 12.0, 16.0 / 12.0, -30.0 / 12.0, 16.0 / 12.0, -1.0 / 12.0};
+    const double c0 = P.T_ref_over_W_ref;
+    const long long c_self = in.cell[0];
+    const double *mid = out.mid + c_self;
+    double ls[NS], u[3] = {0.0, 0.0, 0.0}, lgrad[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int o = 0; o < NS; ++o) ls[o] = mid[(long long)(M::ls + o) * P.N];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lgrad[d] = mid[(long long)(M::lgrad + d) * P.N];
+        u[d] = mid[(long long)(M::u + d) * P.N];
+    }
+    double aT0 = mid[(long long)M::aT0 * P.N], aY0[NSP];
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) aY0[k] = mid[(long long)(M::aY0 + k) * P.N];
+    double lR0 = mid[(long long)M::lR0 * P.N];
+    const double lCT = -out.lo_sc[c_self];
+    double lCY[NSP];
+#pragma unroll
+    for (int k = 0; k < NSP; ++k) lCY[k] = -out.lo_sc[(long long)(1 + k) * P.N + c_self];
+
+    double T[S], Y[S][NSP], R[S], Sw[S];
+    fill_stencil<Q, NSP>(P, in, T, Y, R, Sw);
+    const double inv_rho = rcp(R[0]);
+    const double ldT = P.alpha * ls[0];
     double ldY[NSP];
 #pragma unroll
-    for (int k = 0; k < NSP; ++k) ldY[k] = P.alpha * lDtY[k];
+    for (int k = 0; k < NSP; ++k) ldY[k] = P.alpha * ls[1 + k];
+    double linv_rho = 0.0;
 
     // the axes, reversed; each axis's four slots finished and scattered
-    asm volatile("" ::: "memory");  // read the stencil again instead of keeping it
-    fill();
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         const int sl[5] = {1 + 4 * d, 2 + 4 * d, 0, 3 + 4 * d, 4 + 4 * d};
+        bool near = false;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) near |= in.kind[sl[j]] != kFluid;
         // adjoints of the stencil's T, Y, rho (index 2: the cell, accumulated
         // into aT0, aY0, lR0 at the end of the axis)
         double aT[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, aY[5][NSP], lR[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -874,13 +1155,14 @@ __device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, double wq, 
 #pragma unroll
         for (int j = 1; j <= 3; j += 2)
             if (in.kind[sl[j]] == kIso && wq != 0.0) {
-                const double Tw = in.Tw[sl[j]], rw = c0 / (Tw * Sw[0]), f = 2.0 * P.alpha * wq;
+                const double Tw = in.Tw[sl[j]], rw = c0 * rcp(Tw * Sw[0]), f = 2.0 * P.alpha * wq;
                 aT0 += f * rw;
-                aTw[j] += f * (-rw / Tw * (T[0] - Tw) - rw);
+                aTw[j] += f * (-rw * rcp(Tw) * (T[0] - Tw) - rw);
+                const double rwS = rw * rcp(Sw[0]);
 #pragma unroll
-                for (int k = 0; k < NSP; ++k) aY0[k] += f * (T[0] - Tw) * (-rw * P.invW[k] / Sw[0]);
+                for (int k = 0; k < NSP; ++k) aY0[k] += f * (T[0] - Tw) * (-rwS * P.invW[k]);
             }
-        const double d1r = grad[d];
+        const double d1r = d1(R[sl[0]], R[sl[1]], R[sl[2]], R[sl[3]], R[sl[4]]);
         double ld1r = lgrad[d];
         // diffusion: d2(phi) + d1r d1(phi) / rho
         {
@@ -898,29 +1180,24 @@ __device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, double wq, 
             ld1r += ldY[k] * dY1 * inv_rho;
             linv_rho += ldY[k] * d1r * dY1;
         }
-        // convection of T: CT += u_d cT_d
-        lu[d] += lCT * cT[d];
+        // convection of T: CT += u_d cT_d, cT_d from the stencil
         {
             const double lc = lCT * u[d];
-            if (near[d]) {
+            if (near) {
                 aT[3] += 0.5 * lc;
                 aT[1] -= 0.5 * lc;
             } else {
                 weno3_adj(T[sl[0]], T[sl[1]], T[sl[2]], T[sl[3]], T[sl[4]], u[d], lc, aT);
             }
         }
-        // convection of Y: CY_k += u_d (cY_k - Y0_k sumc)
+        // convection of Y: CY_k += u_d (cY_k - Y0_k sumc), sumc = sum_k cY_k
         double lsumc = 0.0;
 #pragma unroll
-        for (int k = 0; k < NSP; ++k) {
-            lu[d] += lCY[k] * (cY[d][k] - Y[0][k] * sumc[d]);
-            aY0[k] -= lCY[k] * u[d] * sumc[d];
-            lsumc -= lCY[k] * u[d] * Y[0][k];
-        }
+        for (int k = 0; k < NSP; ++k) lsumc -= lCY[k] * u[d] * Y[0][k];
 #pragma unroll
         for (int k = 0; k < NSP; ++k) {
             const double lc = lCY[k] * u[d] + lsumc;
-            if (near[d]) {
+            if (near) {
                 aY[3][k] += 0.5 * lc;
                 aY[1][k] -= 0.5 * lc;
             } else {
@@ -950,11 +1227,11 @@ __device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, double wq, 
             const double Swi = fa * Sw[sl[1]] + fb * Sw[sl[3]] + (1.0 - fa - fb) * Sw[0];
             double gT, gY[NSP], gR;  // what the image receives
             if (kd == kIso) {
-                const double Tw = in.Tw[s], rw = c0 / (Tw * Swi);
-                aTw[j] += 2.0 * aT[j] + 2.0 * lR[j] * (-rw / Tw);
+                const double Tw = in.Tw[s], rw = c0 * rcp(Tw * Swi), rwS = rw * rcp(Swi);
+                aTw[j] += 2.0 * aT[j] + 2.0 * lR[j] * (-rw * rcp(Tw));
                 gT = -aT[j];
 #pragma unroll
-                for (int k = 0; k < NSP; ++k) gY[k] = aY[j][k] + 2.0 * lR[j] * (-rw * P.invW[k] / Swi);
+                for (int k = 0; k < NSP; ++k) gY[k] = aY[j][k] + 2.0 * lR[j] * (-rwS * P.invW[k]);
                 gR = -lR[j];
             } else if (kd == kInflow) {
                 gT = -aT[j];
@@ -987,121 +1264,76 @@ __device__ void cell_vjp(const KParams &P, const CellIn<Q, NSP> &in, double wq, 
             if (j == 2) continue;
             const int s = sl[j];
             if (in.kind[s] != kFluid) continue;
-            double t = aT[j] - lR[j] * R[s] / T[s];
             const long long c = in.cell[s];
-            atomicAdd(&out.lam_sc[c], t);
+            const double rT = R[s] * rcp(T[s]), rS = R[s] * rcp(Sw[s]);
+            atomicAdd(&out.lam_sc[c], aT[j] - lR[j] * rT);
 #pragma unroll
             for (int k = 0; k < NSP; ++k)
-                atomicAdd(&out.lam_sc[(long long)(1 + k) * P.N + c], aY[j][k] - lR[j] * R[s] * P.invW[k] / Sw[s]);
+                atomicAdd(&out.lam_sc[(long long)(1 + k) * P.N + c], aY[j][k] - lR[j] * rS * P.invW[k]);
         }
         aT0 += aT[2];
         lR0 += lR[2];
 #pragma unroll
         for (int k = 0; k < NSP; ++k) aY0[k] += aY[2][k];
-        // the wall-heat-flux terms' wall temperatures (first neighbours)
     }
 
-    // the source, reversed (Dt = alpha (diffusion) + source)
-    {
-        double ls[NS];
-        ls[0] = lDtT;
+    // inv_rho = 1 / rho; the cell's own slot
+    lR0 -= linv_rho * inv_rho * inv_rho;
+    const double rT0 = R[0] * rcp(T[0]), rS0 = R[0] * rcp(Sw[0]);
+    atomicAdd(&out.lam_sc[c_self], aT0 - lR0 * rT0);
 #pragma unroll
-        for (int k = 0; k < NSP; ++k) ls[1 + k] = lDtY[k];
-        // one forward-mode pass per input of the source: T0, Y0_k, then
-        // (A_j, Ta_j) of every reaction; each column of the Jacobian times ls
-        using V = DualN<1>;
-        const int ncol = NS + 2 * P.n_rx;
-        for (int col = 0; col < ncol; ++col) {
-            V T0(T[0]), Y0[NSP], sT, sY[NSP];
-            if (col == 0) T0.d[0] = 1.0;
-#pragma unroll
-            for (int k = 0; k < NSP; ++k) {
-                Y0[k] = V(Y[0][k]);
-                if (col == 1 + k) Y0[k].d[0] = 1.0;
-            }
-            const int pj = col - NS;  // parameter column: reaction pj / 2, A (even) or Ta (odd)
-            chem_source<NSP>(
-                P, T0, Y0,
-                [&](int j, V &Aj, V &Taj) {
-                    Aj = V(P.rx[j].A);
-                    Taj = V(P.rx[j].Ta);
-                    if (pj == 2 * j) Aj.d[0] = 1.0;
-                    if (pj == 2 * j + 1) Taj.d[0] = 1.0;
-                },
-                sT, sY);
-            double acc = ls[0] * sT.d[0];
-#pragma unroll
-            for (int k = 0; k < NSP; ++k) acc += ls[1 + k] * sY[k].d[0];
-            if (col == 0)
-                aT0 += acc;
-            else if (col < NS) {
-#pragma unroll
-                for (int k = 0; k < NSP; ++k) aY0[k] += col == 1 + k ? acc : 0.0;
-            } else {
-                atomicAdd(&out.lam_param[pj], acc);
-            }
-        }
-    }
-    // u = m / (rho cs2), inv_rho = 1 / rho
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const double lm = lu[d] * inv_rc;
-        linv_rc += lu[d] * m[d];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int c = d == 0 ? L::cx(i) : d == 1 ? L::cy(i) : L::cz(i);
-            if (c != 0) ag[i] += c * lm;
-        }
-    }
-    lrho -= linv_rc * inv_rc / rho;
-    lrho -= linv_rho * inv_rho * inv_rho;
-    lR0 += lrho;
-    // the cell's own slot and its pulls
-    {
-        const long long c = in.cell[0];
-        atomicAdd(&out.lam_sc[c], aT0 - lR0 * R[0] / T[0]);
-#pragma unroll
-        for (int k = 0; k < NSP; ++k)
-            atomicAdd(&out.lam_sc[(long long)(1 + k) * P.N + c], aY0[k] - lR0 * R[0] * P.invW[k] / Sw[0]);
-    }
-    // pull streaming reads every population entry at most once (the source
-    // cell's, or the cell's own opposite entry behind a wall)
-#pragma unroll
-    for (int i = 0; i < Q; ++i) out.lam_pop[(long long)in.tdir[i] * P.N + in.tcell[i]] = ag[i];
+    for (int k = 0; k < NSP; ++k)
+        atomicAdd(&out.lam_sc[(long long)(1 + k) * P.N + c_self], aY0[k] - lR0 * rS0 * P.invW[k]);
 }
 
 struct AdjParams {
     KParams k;              // pop_in / sc_in: the state of level n
     const double *lam_pop_next;  // [Q][N] adjoint of the populations written by step n
     const double *lam_sc_next;   // [1+NSP][N]
-    double *lam_pop;        // [Q][N] adjoint of level n (cleared by the caller; stored)
+    double *lam_pop;        // [Q][N] adjoint of level n (stored at every fluid cell's entries)
     double *lam_sc;         // [1+NSP][N] (cleared by the caller; accumulated)
     double *dwallT;         // [N] dJ/d wall_T (accumulated)
     double *dparam;         // [2 n_rx]: dJ/dA_j, dJ/dTa_j (accumulated)
+    double *mid;            // [AdjMid::n][N] between the two kernels
     int obj_kind;           // LBFD_OBJ_*
     double obj_w;           // weight of this level's q (flame position: times dq/dT of a cell)
 };
 
 template <int Q, int NSP>
-__global__ void __launch_bounds__(kBlock) adjoint_kernel(const AdjParams AP)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) adjoint_collision_kernel(const AdjParams AP)
 {
     const KParams &P = AP.k;
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     __shared__ double red[2 * LBFD_MAX_REACTIONS];
+    __shared__ double tab[64];
     for (int j = threadIdx.x; j < 2 * LBFD_MAX_REACTIONS; j += blockDim.x) red[j] = 0.0;
+    if (threadIdx.x < 64) tab[threadIdx.x] = kExp2Tab[threadIdx.x];
     __syncthreads();
     if (idx < P.N && P.mask[idx] == LBFD_FLUID) {
         const int x = (int)(idx % P.nx), y = (int)((idx / P.nx) % P.ny), z = (int)(idx / ((long long)P.nx * P.ny));
         CellIn<Q, NSP> in;
         gather_inputs<Q, NSP>(P, x, y, z, idx, in);
-        const double wq = AP.obj_kind == LBFD_OBJ_WALL_HEAT_FLUX ? AP.obj_w : 0.0;
         const double wT0 = AP.obj_kind == LBFD_OBJ_FLAME_POSITION ? AP.obj_w : 0.0;
-        AdjOut o{AP.lam_pop_next, AP.lam_sc_next, AP.lam_pop, AP.lam_sc, AP.dwallT, red};
-        cell_vjp<Q, NSP>(P, in, wq, wT0, o);
+        AdjOut o{AP.lam_pop_next, AP.lam_sc_next, AP.lam_pop, AP.lam_sc, AP.dwallT, red, AP.mid};
+        cell_vjp_collision<Q, NSP>(P, in, wT0, tab, o);
     }
     __syncthreads();
     for (int j = threadIdx.x; j < 2 * P.n_rx; j += blockDim.x)
         if (red[j] != 0.0) atomicAdd(&AP.dparam[j], red[j]);
+}
+
+template <int Q, int NSP>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) adjoint_stencil_kernel(const AdjParams AP)
+{
+    const KParams &P = AP.k;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= P.N || P.mask[idx] != LBFD_FLUID) return;
+    const int x = (int)(idx % P.nx), y = (int)((idx / P.nx) % P.ny), z = (int)(idx / ((long long)P.nx * P.ny));
+    CellIn<Q, NSP> in;
+    gather_inputs<Q, NSP, false>(P, x, y, z, idx, in);
+    const double wq = AP.obj_kind == LBFD_OBJ_WALL_HEAT_FLUX ? AP.obj_w : 0.0;
+    AdjOut o{AP.lam_pop_next, AP.lam_sc_next, AP.lam_pop, AP.lam_sc, AP.dwallT, nullptr, AP.mid};
+    cell_vjp_stencil<Q, NSP>(P, in, wq, o);
 }
 
 struct TanParams {
@@ -1151,8 +1383,14 @@ __global__ void accumulate_kernel(double *acc, const double *diag, int slot, dou
 
 bool adjoint_supported(int Q, int nsp) { return (Q == 9 && nsp == 4) || (Q == 27 && nsp == 4); }
 
+int adjoint_mid_fields(int Q, int nsp)
+{
+    if (nsp != 4) return 0;
+    return Q == 9 ? AdjMid<2, 4>::n : Q == 27 ? AdjMid<3, 4>::n : 0;
+}
+
 hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_pop_next, const double *lam_sc_next,
-                          double *lam_pop, double *lam_sc, double *dwallT, double *dparam, int obj_kind,
+                          double *lam_pop, double *lam_sc, double *dwallT, double *dparam, double *mid, int obj_kind,
                           double obj_w, hipStream_t s)
 {
     AdjParams ap;
@@ -1163,15 +1401,19 @@ hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_p
     ap.lam_sc = lam_sc;
     ap.dwallT = dwallT;
     ap.dparam = dparam;
+    ap.mid = mid;
     ap.obj_kind = obj_kind;
     ap.obj_w = obj_w;
     const unsigned nb = (unsigned)((kp.N + kBlock - 1) / kBlock);
-    if (Q == 9 && nsp == 4)
-        adjoint_kernel<9, 4><<<nb, kBlock, 0, s>>>(ap);
-    else if (Q == 27 && nsp == 4)
-        adjoint_kernel<27, 4><<<nb, kBlock, 0, s>>>(ap);
-    else
+    if (Q == 9 && nsp == 4) {
+        adjoint_collision_kernel<9, 4><<<nb, kBlock, 0, s>>>(ap);
+        adjoint_stencil_kernel<9, 4><<<nb, kBlock, 0, s>>>(ap);
+    } else if (Q == 27 && nsp == 4) {
+        adjoint_collision_kernel<27, 4><<<nb, kBlock, 0, s>>>(ap);
+        adjoint_stencil_kernel<27, 4><<<nb, kBlock, 0, s>>>(ap);
+    } else {
         return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

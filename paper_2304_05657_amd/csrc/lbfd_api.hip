@@ -1544,7 +1544,8 @@ int lbfd_step_adjoint(lbfd_ctx *c, const double *lam_pop, const double *lam_sc, 
     double *l_out = (double *)mem.get(pop_b), *s_out = (double *)mem.get(sc_b);
     double *dW = (double *)mem.get(N * sizeof(double));
     double *dP = (double *)mem.get(2 * LBFD_MAX_REACTIONS * sizeof(double));
-    if (!l_next || !s_next || !l_out || !s_out || !dW || !dP)
+    double *mid = (double *)mem.get((size_t)adjoint_mid_fields(c->Q, c->nsp) * N * sizeof(double));
+    if (!l_next || !s_next || !l_out || !s_out || !dW || !dP || !mid)
         return fail(LBFD_ENOMEM, "adjoint step: device allocation failed");
     HIP_TRY(hipMemcpy(l_next, lam_pop, pop_b, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s_next, lam_sc, sc_b, hipMemcpyHostToDevice));
@@ -1555,7 +1556,7 @@ int lbfd_step_adjoint(lbfd_ctx *c, const double *lam_pop, const double *lam_sc, 
     KParams k = c->base;
     k.pop_in = c->pop[c->cur];
     k.sc_in = c->sc[c->cur];
-    HIP_TRY(launch_adjoint(c->Q, c->nsp, k, l_next, s_next, l_out, s_out, dW, dP, c->obj_kind,
+    HIP_TRY(launch_adjoint(c->Q, c->nsp, k, l_next, s_next, l_out, s_out, dW, dP, mid, c->obj_kind,
                            wq * objective_cell_weight(c), c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipMemcpy(lam_pop_in, l_out, pop_b, hipMemcpyDeviceToHost));
@@ -1593,7 +1594,8 @@ static int adjoint_impl(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *d
     double *dW = (double *)mem.get(N * sizeof(double));
     double *dP = (double *)mem.get(2 * LBFD_MAX_REACTIONS * sizeof(double));
     double *Jd = (double *)mem.get(sizeof(double));
-    if (!ckpt || !segs || !lam[0] || !lam[1] || !lsc[0] || !lsc[1] || !dW || !dP || !Jd)
+    double *mid = (double *)mem.get((size_t)adjoint_mid_fields(Q, ns) * N * sizeof(double));
+    if (!ckpt || !segs || !lam[0] || !lam[1] || !lsc[0] || !lsc[1] || !dW || !dP || !Jd || !mid)
         return fail(LBFD_ENOMEM, "adjoint: device allocation failed");
     auto ck_pop = [&](int64_t s) { return ckpt + (size_t)s * (pop_b + sc_b); };
     auto ck_sc = [&](int64_t s) { return ckpt + (size_t)s * (pop_b + sc_b) + pop_b; };
@@ -1623,7 +1625,12 @@ static int adjoint_impl(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *d
     }
 
     // backward sweep over segments, each recomputed from its checkpoint
+    // Every population entry of a fluid cell is pulled by exactly one cell,
+    // whose backward step stores its adjoint there; entries of solid cells
+    // are never pulled and keep the zeros of this clear.  The scalars'
+    // adjoints are sums over neighbours and are cleared before every step.
     HIP_TRY(hipMemsetAsync(lam[0], 0, pop_b, c->stream));
+    HIP_TRY(hipMemsetAsync(lam[1], 0, pop_b, c->stream));
     HIP_TRY(hipMemsetAsync(lsc[0], 0, sc_b, c->stream));
     HIP_TRY(hipMemsetAsync(dW, 0, N * sizeof(double), c->stream));
     HIP_TRY(hipMemsetAsync(dP, 0, 2 * LBFD_MAX_REACTIONS * sizeof(double), c->stream));
@@ -1642,13 +1649,12 @@ static int adjoint_impl(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *d
         }
         for (int64_t n = n1 - 1; n >= n0; --n) {
             const int cu = 1 - nxt;
-            HIP_TRY(hipMemsetAsync(lam[cu], 0, pop_b, c->stream));
             HIP_TRY(hipMemsetAsync(lsc[cu], 0, sc_b, c->stream));
             KParams k = c->base;
             k.pop_in = sg_pop(n - n0);
             k.sc_in = sg_sc(n - n0);
             const ObjTerm o = objective_term(c, n);
-            HIP_TRY(launch_adjoint(c->Q, c->nsp, k, lam[nxt], lsc[nxt], lam[cu], lsc[cu], dW, dP, c->obj_kind,
+            HIP_TRY(launch_adjoint(c->Q, c->nsp, k, lam[nxt], lsc[nxt], lam[cu], lsc[cu], dW, dP, mid, c->obj_kind,
                                    o.w, c->stream));
             nxt = cu;
         }

@@ -154,8 +154,11 @@ bool adjoint_supported(int Q, int nsp);
 // The objective's share of one level: kind LBFD_OBJ_*, weight w (0 outside
 // the objective's window; for the flame position w carries d x_f / d T of
 // one cell, -nx / (n_fluid (T_b - T_u))).
+// mid: adjoint_mid_fields(Q, nsp) x N doubles of scratch between the
+// backward step's two kernels.
+int adjoint_mid_fields(int Q, int nsp);
 hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_pop_next, const double *lam_sc_next,
-                          double *lam_pop, double *lam_sc, double *dwallT, double *dparam, int obj_kind,
+                          double *lam_pop, double *lam_sc, double *dwallT, double *dparam, double *mid, int obj_kind,
                           double obj_w, hipStream_t s);
 // One forward-mode (Jacobian-vector) evaluation of the FP64 step at the
 // state kp.pop_in / kp.sc_in: tangents of the inputs in, tangents of the
