@@ -18,8 +18,9 @@
 // cell_vjp_stencil).  The sub-stepped Arrhenius source is reversed sub-step
 // by sub-step, each sub-step's state recomputed from the cell's (chem_vjp).
 // Each pulled population is read by exactly one cell, so its adjoint is
-// stored; the stencil scalars' and wall temperatures' adjoints are added
-// atomically.  Steps are recomputed from checkpoints taken every K steps
+// stored; each stencil slot's share of a scalar's adjoint is stored per slot
+// and gathered by the slot's cell in a third kernel; the wall temperatures'
+// adjoints are added atomically.  Steps are recomputed from checkpoints taken every K steps
 // (host side, lbfd_api.hip).
 //
 // tangent_kernel evaluates the same update in dual numbers with a given
@@ -716,6 +717,7 @@ struct AdjOut {
     double *dwallT;     // [N]: accumulated atomically
     double *lam_param;  // [2 n_rx] in LDS: accumulated atomically
     double *mid;        // [AdjMid::n][N]
+    double *nb;         // [S - 1][1+NSP][N]: what each stencil slot's cell receives
 };
 
 // The stencil's T, Y, rho and sum_k Y_k / W_k, ghosts from their images
@@ -1258,18 +1260,18 @@ __device__ void cell_vjp_stencil(const KParams &P, const CellIn<Q, NSP> &in, dou
             }
             if (kd == kIso && in.wall[s] >= 0) atomicAdd(&out.dwallT[in.wall[s]], aTw[j]);
         }
-        // the axis's fluid slots: densities R = c0 / (T Sw) onto T and Y, scatter
+        // the axis's fluid slots: densities R = c0 / (T Sw) onto T and Y; what
+        // each slot's cell receives, stored for the gather (0 at ghost slots)
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
             if (j == 2) continue;
             const int s = sl[j];
-            if (in.kind[s] != kFluid) continue;
-            const long long c = in.cell[s];
-            const double rT = R[s] * rcp(T[s]), rS = R[s] * rcp(Sw[s]);
-            atomicAdd(&out.lam_sc[c], aT[j] - lR[j] * rT);
+            const bool fl = in.kind[s] == kFluid;
+            const double rT = fl ? R[s] * rcp(T[s]) : 0.0, rS = fl ? R[s] * rcp(Sw[s]) : 0.0;
+            double *nb = out.nb + (long long)(s - 1) * NS * P.N + c_self;
+            nb[0] = fl ? aT[j] - lR[j] * rT : 0.0;
 #pragma unroll
-            for (int k = 0; k < NSP; ++k)
-                atomicAdd(&out.lam_sc[(long long)(1 + k) * P.N + c], aY[j][k] - lR[j] * rS * P.invW[k]);
+            for (int k = 0; k < NSP; ++k) nb[(long long)(1 + k) * P.N] = fl ? aY[j][k] - lR[j] * rS * P.invW[k] : 0.0;
         }
         aT0 += aT[2];
         lR0 += lR[2];
@@ -1280,10 +1282,9 @@ __device__ void cell_vjp_stencil(const KParams &P, const CellIn<Q, NSP> &in, dou
     // inv_rho = 1 / rho; the cell's own slot
     lR0 -= linv_rho * inv_rho * inv_rho;
     const double rT0 = R[0] * rcp(T[0]), rS0 = R[0] * rcp(Sw[0]);
-    atomicAdd(&out.lam_sc[c_self], aT0 - lR0 * rT0);
+    out.lam_sc[c_self] = aT0 - lR0 * rT0;
 #pragma unroll
-    for (int k = 0; k < NSP; ++k)
-        atomicAdd(&out.lam_sc[(long long)(1 + k) * P.N + c_self], aY0[k] - lR0 * rS0 * P.invW[k]);
+    for (int k = 0; k < NSP; ++k) out.lam_sc[(long long)(1 + k) * P.N + c_self] = aY0[k] - lR0 * rS0 * P.invW[k];
 }
 
 struct AdjParams {
@@ -1291,10 +1292,11 @@ struct AdjParams {
     const double *lam_pop_next;  // [Q][N] adjoint of the populations written by step n
     const double *lam_sc_next;   // [1+NSP][N]
     double *lam_pop;        // [Q][N] adjoint of level n (stored at every fluid cell's entries)
-    double *lam_sc;         // [1+NSP][N] (cleared by the caller; accumulated)
+    double *lam_sc;         // [1+NSP][N] (stored at every fluid cell)
     double *dwallT;         // [N] dJ/d wall_T (accumulated)
     double *dparam;         // [2 n_rx]: dJ/dA_j, dJ/dTa_j (accumulated)
-    double *mid;            // [AdjMid::n][N] between the two kernels
+    double *mid;            // [AdjMid::n][N] between the first two kernels
+    double *nb;             // [S - 1][1+NSP][N] from the stencil kernel to the gather
     int obj_kind;           // LBFD_OBJ_*
     double obj_w;           // weight of this level's q (flame position: times dq/dT of a cell)
 };
@@ -1314,7 +1316,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
         CellIn<Q, NSP> in;
         gather_inputs<Q, NSP>(P, x, y, z, idx, in);
         const double wT0 = AP.obj_kind == LBFD_OBJ_FLAME_POSITION ? AP.obj_w : 0.0;
-        AdjOut o{AP.lam_pop_next, AP.lam_sc_next, AP.lam_pop, AP.lam_sc, AP.dwallT, red, AP.mid};
+        AdjOut o{AP.lam_pop_next, AP.lam_sc_next, AP.lam_pop, AP.lam_sc, AP.dwallT, red, AP.mid, AP.nb};
         cell_vjp_collision<Q, NSP>(P, in, wT0, tab, o);
     }
     __syncthreads();
@@ -1332,8 +1334,45 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     CellIn<Q, NSP> in;
     gather_inputs<Q, NSP, false>(P, x, y, z, idx, in);
     const double wq = AP.obj_kind == LBFD_OBJ_WALL_HEAT_FLUX ? AP.obj_w : 0.0;
-    AdjOut o{AP.lam_pop_next, AP.lam_sc_next, AP.lam_pop, AP.lam_sc, AP.dwallT, nullptr, AP.mid};
+    AdjOut o{AP.lam_pop_next, AP.lam_sc_next, AP.lam_pop, AP.lam_sc, AP.dwallT, nullptr, AP.mid, AP.nb};
     cell_vjp_stencil<Q, NSP>(P, in, wq, o);
+}
+
+// The stencil scalars' adjoints: each fluid cell adds to its own share (in
+// lam_sc) what the cells whose stencils hold it stored for it, slot by slot
+// in a fixed order (so the sums do not depend on scheduling).  The cell
+// whose slot s (offset m along axis d) is this cell sits at -m along d;
+// at a wall or outside the box nothing is added, and a ghost slot stored 0.
+template <int Q, int NSP>
+__global__ void __launch_bounds__(kBlock) adjoint_gather_kernel(const AdjParams AP)
+{
+    constexpr int S = n_slots<Q>(), NS = 1 + NSP;
+    const KParams &P = AP.k;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= P.N || P.mask[idx] != LBFD_FLUID) return;
+    const int x = (int)(idx % P.nx), y = (int)((idx / P.nx) % P.ny), z = (int)(idx / ((long long)P.nx * P.ny));
+    const bool interior = P.code[idx] == kCodeInterior;
+    const long long st[3] = {1, P.nx, (long long)P.nx * P.ny};
+    double acc[NS];
+#pragma unroll
+    for (int v = 0; v < NS; ++v) acc[v] = AP.lam_sc[(long long)v * P.N + idx];
+#pragma unroll
+    for (int s = 1; s < S; ++s) {
+        const int d = (s - 1) / 4, j = (s - 1) % 4;
+        const int mm = j == 0 ? -2 : j == 1 ? -1 : j == 2 ? 1 : 2;
+        long long src = idx - mm * st[d];
+        bool ok = true;
+        if (!interior) {
+            const Nb c = classify(P, x - (d == 0 ? mm : 0), y - (d == 1 ? mm : 0), z - (d == 2 ? mm : 0));
+            ok = c.kind == kFluid;
+            src = ok ? c.idx : idx;
+        }
+        const double *nb = AP.nb + (long long)(s - 1) * NS * P.N + src;
+#pragma unroll
+        for (int v = 0; v < NS; ++v) acc[v] += ok ? nb[(long long)v * P.N] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < NS; ++v) AP.lam_sc[(long long)v * P.N + idx] = acc[v];
 }
 
 struct TanParams {
@@ -1376,17 +1415,14 @@ __global__ void __launch_bounds__(kBlock) tangent_kernel(const TanParams TP)
     if (dq != 0.0) atomicAdd(TP.dq, dq);
 }
 
-__global__ void accumulate_kernel(double *acc, const double *diag, int slot, double a, double b)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) *acc += a * diag[slot] + b;
-}
-
 bool adjoint_supported(int Q, int nsp) { return (Q == 9 && nsp == 4) || (Q == 27 && nsp == 4); }
 
 int adjoint_mid_fields(int Q, int nsp)
 {
     if (nsp != 4) return 0;
-    return Q == 9 ? AdjMid<2, 4>::n : Q == 27 ? AdjMid<3, 4>::n : 0;
+    const int mid = Q == 9 ? AdjMid<2, 4>::n : Q == 27 ? AdjMid<3, 4>::n : 0;
+    const int nb = Q == 9 ? (n_slots<9>() - 1) * 5 : Q == 27 ? (n_slots<27>() - 1) * 5 : 0;
+    return mid + nb;
 }
 
 hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_pop_next, const double *lam_sc_next,
@@ -1402,15 +1438,18 @@ hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_p
     ap.dwallT = dwallT;
     ap.dparam = dparam;
     ap.mid = mid;
+    ap.nb = mid + (size_t)(Q == 9 ? AdjMid<2, 4>::n : AdjMid<3, 4>::n) * kp.N;
     ap.obj_kind = obj_kind;
     ap.obj_w = obj_w;
     const unsigned nb = (unsigned)((kp.N + kBlock - 1) / kBlock);
     if (Q == 9 && nsp == 4) {
         adjoint_collision_kernel<9, 4><<<nb, kBlock, 0, s>>>(ap);
         adjoint_stencil_kernel<9, 4><<<nb, kBlock, 0, s>>>(ap);
+        adjoint_gather_kernel<9, 4><<<nb, kBlock, 0, s>>>(ap);
     } else if (Q == 27 && nsp == 4) {
         adjoint_collision_kernel<27, 4><<<nb, kBlock, 0, s>>>(ap);
         adjoint_stencil_kernel<27, 4><<<nb, kBlock, 0, s>>>(ap);
+        adjoint_gather_kernel<27, 4><<<nb, kBlock, 0, s>>>(ap);
     } else {
         return hipErrorInvalidValue;
     }
@@ -1452,12 +1491,6 @@ hipError_t launch_fill(double *dst, int n, double v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     fill_kernel<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(dst, n, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_accumulate(double *acc, const double *diag, int slot, double a, double b, hipStream_t s)
-{
-    accumulate_kernel<<<1, 1, 0, s>>>(acc, diag, slot, a, b);
     return hipGetLastError();
 }
 

@@ -1414,8 +1414,8 @@ int lbfd_objective(lbfd_ctx *c, int64_t nsteps, double *J)
         const ObjTerm o = objective_term(c, n);
         e = launch_step(c->Q, c->nsp, c->prec, o.on ? kModeStepDiag : kModeStep, k, c->streams);
         if (e == hipSuccess && o.on)
-            e = launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream);
-        if (e == hipSuccess && o.on) e = launch_accumulate(Jd, c->diag_dev, o.slot, o.a, o.b, c->stream);
+            e = launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream, Jd, o.slot,
+                                o.a, o.b);
         c->cur ^= 1;
         c->level += 1;
     }
@@ -1447,8 +1447,8 @@ int lbfd_objective_static(lbfd_ctx *c, int64_t nsteps, double *J)
         k.partials = partials;
         const ObjTerm o = objective_term(c, n);
         e = launch_step(c->Q, c->nsp, c->prec, o.on ? kModeStepDiag : kModeStep, k, c->streams);
-        if (e == hipSuccess && o.on) e = launch_finalize(partials, c->nblocks, diag, c->bad_dev, c->level, c->stream);
-        if (e == hipSuccess && o.on) e = launch_accumulate(acc, diag, o.slot, o.a, o.b, c->stream);
+        if (e == hipSuccess && o.on)
+            e = launch_finalize(partials, c->nblocks, diag, c->bad_dev, c->level, c->stream, acc, o.slot, o.a, o.b);
         c->cur ^= 1;
         c->level += 1;
     }
@@ -1617,21 +1617,21 @@ static int adjoint_impl(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *d
         const ObjTerm o = objective_term(c, n);
         HIP_TRY(launch_step(c->Q, c->nsp, c->prec, o.on ? kModeStepDiag : kModeStep, k, c->streams));
         if (o.on) {
-            HIP_TRY(launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream));
-            HIP_TRY(launch_accumulate(Jd, c->diag_dev, o.slot, o.a, o.b, c->stream));
+            HIP_TRY(launch_finalize(c->partials, c->nblocks, c->diag_dev, c->bad_dev, c->level, c->stream, Jd, o.slot,
+                                    o.a, o.b));
         }
         c->cur ^= 1;
         c->level += 1;
     }
 
     // backward sweep over segments, each recomputed from its checkpoint
-    // Every population entry of a fluid cell is pulled by exactly one cell,
-    // whose backward step stores its adjoint there; entries of solid cells
-    // are never pulled and keep the zeros of this clear.  The scalars'
-    // adjoints are sums over neighbours and are cleared before every step.
-    HIP_TRY(hipMemsetAsync(lam[0], 0, pop_b, c->stream));
-    HIP_TRY(hipMemsetAsync(lam[1], 0, pop_b, c->stream));
-    HIP_TRY(hipMemsetAsync(lsc[0], 0, sc_b, c->stream));
+    // Every backward step stores the adjoints of every fluid cell's
+    // populations and scalars; entries of solid cells are never written and
+    // keep the zeros of this clear.
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(hipMemsetAsync(lam[b], 0, pop_b, c->stream));
+        HIP_TRY(hipMemsetAsync(lsc[b], 0, sc_b, c->stream));
+    }
     HIP_TRY(hipMemsetAsync(dW, 0, N * sizeof(double), c->stream));
     HIP_TRY(hipMemsetAsync(dP, 0, 2 * LBFD_MAX_REACTIONS * sizeof(double), c->stream));
     int nxt = 0;  // lam[nxt], lsc[nxt]: adjoint of level n+1
@@ -1649,7 +1649,6 @@ static int adjoint_impl(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *d
         }
         for (int64_t n = n1 - 1; n >= n0; --n) {
             const int cu = 1 - nxt;
-            HIP_TRY(hipMemsetAsync(lsc[cu], 0, sc_b, c->stream));
             KParams k = c->base;
             k.pop_in = sg_pop(n - n0);
             k.sc_in = sg_sc(n - n0);

@@ -12,9 +12,12 @@ LBFD_FOR_CONFIGS(X)
 #undef X
 
 // Deterministic final reduction of the block partials (one block); records
-// the first level whose check saw a non-finite value.
+// the first level whose check saw a non-finite value and, with acc, adds
+// coef * out[slot] + shift to *acc.  (A 1024-thread block with wave
+// butterflies measured slower: 13.6 against 7.9 us for 1024 partials.)
 __global__ void __launch_bounds__(kBlock) finalize_kernel(const double *partials, int nblocks, double *out,
-                                                          long long *first_bad, long long level)
+                                                          long long *first_bad, long long level, double *acc,
+                                                          int slot, double coef, double shift)
 {
     __shared__ double red[kBlock][kNDiag];
     double a[kNDiag];
@@ -37,6 +40,7 @@ __global__ void __launch_bounds__(kBlock) finalize_kernel(const double *partials
 #pragma unroll
         for (int s = 0; s < kNDiag; ++s) out[s] = red[0][s];
         if (first_bad && red[0][kNonfinite] > 0.0 && *first_bad < 0) *first_bad = level;
+        if (acc) *acc += coef * red[0][slot] + shift;
     }
 }
 
@@ -114,9 +118,9 @@ hipError_t launch_inflow_shift(int Q, int prec, const KParams &kp, int face, con
 }
 
 hipError_t launch_finalize(const double *partials, int nblocks, double *out, long long *first_bad,
-                           long long level, hipStream_t s)
+                           long long level, hipStream_t s, double *acc, int slot, double a, double b)
 {
-    finalize_kernel<<<1, kBlock, 0, s>>>(partials, nblocks, out, first_bad, level);
+    finalize_kernel<<<1, kBlock, 0, s>>>(partials, nblocks, out, first_bad, level, acc, slot, a, b);
     return hipGetLastError();
 }
 

@@ -145,8 +145,11 @@ hipError_t launch_init(int Q, int nsp, int prec, const KParams &kp, const double
 // Keep the populations entering through inflow face `face` at the current
 // level when its profile changes by -du (lbfd_dispatch.hip).
 hipError_t launch_inflow_shift(int Q, int prec, const KParams &kp, int face, const double *du, hipStream_t s);
+// The final diagnostics from the per-block partials (one block); with acc,
+// also *acc += a * out[slot] + b (an objective's term).
 hipError_t launch_finalize(const double *partials, int nblocks, double *out,
-                           long long *first_bad, long long level, hipStream_t s);
+                           long long *first_bad, long long level, hipStream_t s, double *acc = nullptr,
+                           int slot = 0, double a = 0.0, double b = 0.0);
 bool supported(int Q, int nsp, int prec);
 
 // Adjoint (lbfd_adjoint.hip): one backward step of the FP64 coupled step.
@@ -155,7 +158,8 @@ bool adjoint_supported(int Q, int nsp);
 // the objective's window; for the flame position w carries d x_f / d T of
 // one cell, -nx / (n_fluid (T_b - T_u))).
 // mid: adjoint_mid_fields(Q, nsp) x N doubles of scratch between the
-// backward step's two kernels.
+// backward step's kernels.  lam_sc is written at every fluid cell (its
+// entries at solid cells are left as they are).
 int adjoint_mid_fields(int Q, int nsp);
 hipError_t launch_adjoint(int Q, int nsp, const KParams &kp, const double *lam_pop_next, const double *lam_sc_next,
                           double *lam_pop, double *lam_sc, double *dwallT, double *dparam, double *mid, int obj_kind,
@@ -168,8 +172,6 @@ hipError_t launch_tangent(int Q, int nsp, const KParams &kp, const double *dpop,
                           int obj_kind, double obj_w, hipStream_t s);
 // dst[i] = src[i] for i < n (float to double, on the stream).
 hipError_t launch_widen(const float *src, double *dst, size_t n, hipStream_t s);
-// *acc += a * diag[slot] + b (one thread).
-hipError_t launch_accumulate(double *acc, const double *diag, int slot, double a, double b, hipStream_t s);
 // dst[i] = v for i < n (a fill kernel, so that callers capturing a graph
 // record no memset node).
 hipError_t launch_fill(double *dst, int n, double v, hipStream_t s);
