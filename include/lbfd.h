@@ -368,8 +368,8 @@ int lbfd_objective_static(lbfd_ctx *c, int64_t nsteps, double *J);
  * context is at level L + nsteps, as after lbfd_step(nsteps).  Requires FP64
  * precision, no OUTFLOW face, and a lattice/species combination with an
  * adjoint kernel (D2Q9 or D3Q27 with 4 species); LBFD_EINVAL otherwise.
- * Contributions are accumulated with atomic adds, so results may differ in
- * the last bits between runs. */
+ * The wall-temperature and Arrhenius derivatives are accumulated with
+ * atomic adds, so they may differ in the last bits between runs. */
 int lbfd_adjoint(lbfd_ctx *c, int64_t nsteps, int K, double *J, double *dJ_dwallT, double *dJ_dA,
                  double *dJ_dTa);
 
