@@ -364,7 +364,7 @@ int lbfd_objective_static(lbfd_ctx *c, int64_t nsteps, double *J);
  * be NULL; zero at other cells) and the Arrhenius A and Ta of every reaction
  * (dJ_dA, dJ_dTa [n_reactions], host, may be NULL).  Checkpoints are taken
  * every K steps and each segment is recomputed once during the backward
- * sweep (device memory: about (nsteps/K + K + 4) states).  On return the
+ * sweep (device memory: about (nsteps/K + K + 8) states).  On return the
  * context is at level L + nsteps, as after lbfd_step(nsteps).  Requires FP64
  * precision, no OUTFLOW face, and a lattice/species combination with an
  * adjoint kernel (D2Q9 or D3Q27 with 4 species); LBFD_EINVAL otherwise.
