@@ -289,6 +289,46 @@ def run_cpu_baseline(prob, budget_s: float) -> dict:
     return res
 
 
+def bench_adjoint(args, W):
+    """Cost of the discrete adjoint against the forward step on one workload:
+    us per step of lbfd_adjoint (forward pass with checkpoints every K steps,
+    the backward sweep with each segment recomputed), of lbfd_objective (the
+    steps with the objective's diagnostics) and of plain steps."""
+    import time
+    import torch
+    from paper_2304_05657_amd.lbfd import Solver
+    prob = W.named(args.workload)
+    s = Solver(prob, "fp64")
+    state = s.save_state()
+    n, K = args.steps, args.adjoint
+    s.objective(min(n, 10))
+    s.load_state(state)
+    t0 = time.perf_counter()
+    s.step(n)
+    s.sync()
+    plain = (time.perf_counter() - t0) / n * 1e6
+    s.load_state(state)
+    t0 = time.perf_counter()
+    J = s.objective(n)
+    obj = (time.perf_counter() - t0) / n * 1e6
+    s.load_state(state)
+    s.adjoint(min(n, 2 * K), K)
+    s.load_state(state)
+    t0 = time.perf_counter()
+    Ja, gW, gA, gTa = s.adjoint(n, K)
+    adj = (time.perf_counter() - t0) / n * 1e6
+    torch.cuda.synchronize()
+    line = {"metric": "discrete adjoint cost per step", "value": adj, "unit": "us", "higher_is_better": False,
+            "steps": n, "checkpoint_every": K, "plain_step_us": plain, "objective_step_us": obj,
+            "ratio_to_plain_step": adj / plain, "ratio_to_objective_step": adj / obj, "J": Ja,
+            "J_objective": J, "dJ_dA": list(map(float, gA)), "dJ_dTa": list(map(float, gTa)),
+            "dtype": "f64", "data": "synthetic", "n_gpus": 1,
+            "config": {"workload": prob.name, "lattice": "D%dQ%d" % (2 if prob.lattice == 9 else 3, prob.lattice),
+                       "cells": int(prob.mask.size), "objective": "wall_q"}}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +360,11 @@ def main():
                     help="also run one plain 512 MiB device copy (calibrates the HBM byte counters)")
     ap.add_argument("--also", default="porous:fp64,fp16",
                     help="further workloads on the same line, 'name:prec,prec;name:...' ('none' for none)")
+    ap.add_argument("--adjoint", type=int, default=0, metavar="K",
+                    help="instead of the step benchmark: time lbfd_adjoint (FP64, wall heat flux over every "
+                         "level) over --steps steps with checkpoints every K steps on --workload "
+                         "(channel_adjoint: the 1024 x 256 channel), against lbfd_objective and plain steps "
+                         "over the same steps; prints one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU slab sharding is a design note, "
@@ -330,6 +375,9 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(3)
     from paper_2304_05657_amd import workloads as W
+
+    if args.adjoint:
+        sys.exit(bench_adjoint(args, W))
 
     default_acc = {"porous_mech": 200, "burner": 20000, "porous": 5000, "channel": 2000}
 
