@@ -1005,7 +1005,6 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
 {
     using L = Lat<Q>;
     using C = typename Prec<PREC>::calc;
-    using S = typename Prec<PREC>::scal;
     constexpr int D = L::D;
     constexpr bool DIAG = MODE != kModeStep;
     using TS = TileShape<D>;
@@ -1200,24 +1199,21 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
                 for (int m = 0; m < 5; ++m) r5[m] = tile[kNP + ic + (m - 2) * sd];
                 d1r = axis_terms([&](int f, int m) -> C { return tile[f * kNP + ic + m * sd]; }, r5, false, ud);
             } else if constexpr (FAST) {
+                // the four points' T and Y, read once for their densities and
+                // kept for the finite differences
                 const long long sd = d == 0 ? 1 : d == 1 ? sy : sz;
+                Pt<NSP, C> pv[4];
                 C r5[5];
+                r5[2] = rho;
 #pragma unroll
-                for (int m = 0; m < 5; ++m) {
-                    if (m == 2) {
-                        r5[m] = rho;
-                    } else {
-                        Pt<NSP, C> pt;
-                        load_point<NSP, PREC>(P, idx + (m - 2) * sd, pt);
-                        r5[m] = pt.rho;
-                    }
+                for (int j = 0; j < 4; ++j) {
+                    load_point<NSP, PREC>(P, idx + (j < 2 ? j - 2 : j - 1) * sd, pv[j]);
+                    r5[j < 2 ? j : j + 1] = pv[j].rho;
                 }
-                const char *sc = (const char *)P.sc_in;
-                const size_t fstride = (size_t)P.N * sizeof(S);
                 d1r = axis_terms(
                     [&](int f, int m) -> C {
-                        const size_t fo = f == 0 ? 0 : (size_t)(f - 1) * fstride;
-                        return (C)ldo<S>(sc + fo, (uint32_t)(idx + m * sd) * (uint32_t)sizeof(S));
+                        const int j = m < 0 ? m + 2 : m + 1;
+                        return f == 0 ? pv[j].T : pv[j].Y[f - 2];
                     },
                     r5, false, ud);
             } else if constexpr (D == 2) {
@@ -1244,10 +1240,11 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
                 const bool near = (wks[0] | wks[1] | wks[2] | wks[3]) != kFluid;
                 C r5[5];
                 r5[2] = rho;
+                Pt<NSP, C> pv[4];  // the points' (or images') values, kept for the differences
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int slot = j < 2 ? j : j + 1;
-                    Pt<NSP, C> pt;
+                    Pt<NSP, C> &pt = pv[j];
                     if (CW && lis[j] >= 0)
                         image_value<NSP>(P, lis[j], pt);
                     else
@@ -1265,14 +1262,10 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
                         r5[slot] = (C)2 * (C)P.rho_in - pt.rho;
                     }
                 }
-                const char *sc = (const char *)P.sc_in;
-                const size_t fstride = (size_t)P.N * sizeof(S);
                 d1r = axis_terms(
                     [&](int f, int m) -> C {
                         const int j = m < 0 ? m + 2 : m + 1;
-                        const size_t fo = f == 0 ? 0 : (size_t)(f - 1) * fstride;
-                        const C v = CW && lis[j] >= 0 ? (C)P.img_val[(size_t)f * P.n_img + lis[j]]
-                                                      : (C)ldo<S>(sc + fo, (uint32_t)pts[j] * (uint32_t)sizeof(S));
+                        const C v = f == 0 ? pv[j].T : pv[j].Y[f - 2];
                         if (wks[j] == kFluid) return v;
                         if (f == 0) {
                             if (wks[j] == kIso) return (C)2 * (C)P.btw[(d * 4 + j) * nbd + tb] - v;
