@@ -118,6 +118,8 @@ struct lbfd_ctx {
     int *bsrc = nullptr, *bpt = nullptr;
     uint8_t *bwk = nullptr;
     double *btw = nullptr;
+    unsigned long long *bcode_pull = nullptr, *bcode_st = nullptr;  // compact codes of the same descriptors
+    double *face_Td = nullptr;                                         // face_T in device memory
     int nblocks_interior = 0;
     double *wall_T = nullptr;
     double *outlet = nullptr;
@@ -158,7 +160,7 @@ static void free_ctx(lbfd_ctx *c)
                     c->btw, c->wall_T, c->outlet, c->outlet_un, c->inflow_u, c->inflow_du, c->bq,
                     c->bimg, c->img_rng, c->img_idx, c->img_w, c->img_val, c->sup_idx, c->sup_val,
                     c->fields, c->partials, c->diag_dev, c->bad_dev, c->rx_dev, c->rxk_dev, c->fluid,
-                    c->chem_order, c->chem_heavy, c->chem_count};
+                    c->chem_order, c->chem_heavy, c->chem_count, c->bcode_pull, c->bcode_st, c->face_Td};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete c;
@@ -347,6 +349,14 @@ static HostNb host_classify(const lbfd_params &p, const uint8_t *mask, const dou
 // cell on the other side for m = +-2, clamped to the cell when not fluid,
 // or the first neighbour when the wall is the second), the kind of the wall
 // behind a ghost and its temperature.
+// bit f set for a periodic face f
+static unsigned periodic_bits(const lbfd_params &p)
+{
+    unsigned b = 0;
+    for (int f = 0; f < 6; ++f) b |= p.face[f] == LBFD_FACE_PERIODIC ? 1u << f : 0u;
+    return b;
+}
+
 static int build_descriptors(lbfd_ctx *c)
 {
     const lbfd_params &p = c->p;
@@ -406,6 +416,50 @@ static int build_descriptors(lbfd_ctx *c)
             }
         }
     }
+    // the compact codes of the same descriptors (what the kernels without
+    // curved-wall links read), each decoded entry checked against them
+    std::vector<unsigned long long> pcode((size_t)nb, 0ull), scode((size_t)nb, 0ull);
+    for (long long t = 0; t < nb; ++t) {
+        const long long idx = c->boundary_host[t];
+        const int x = (int)(idx % p.nx), y = (int)((idx / p.nx) % p.ny), z = (int)(idx / ((long long)p.nx * p.ny));
+        unsigned long long pc = 0;
+        int i = 0;
+        for (int cz = -zr; cz <= zr; ++cz)
+            for (int cy = -1; cy <= 1; ++cy)
+                for (int cx = -1; cx <= 1; ++cx, ++i) {
+                    const int v = src[(size_t)i * nb + t];
+                    const int kind = v >= 0 ? kPullFluid : v == kSrcBounce ? kPullBounce
+                                   : v == kSrcInflow ? kPullInflow : kPullOutlet;
+                    pc |= (unsigned long long)kind << (2 * i);
+                    if (kind == kPullFluid && cell_at(x, y, z, -cx, -cy, -cz, p.nx, p.ny, p.nz) != v)
+                        return fail(LBFD_EINVAL, "internal: pull code of boundary cell %lld, direction %d", idx, i);
+                }
+        unsigned long long sc = 0;
+        for (int d = 0; d < D; ++d)
+            for (int j = 0; j < 4; ++j) {
+                const size_t sl = (size_t)(d * 4 + j) * nb + t;
+                const int w = wk[sl], w1 = wk[(size_t)(d * 4 + (j < 2 ? 1 : 2)) * nb + t];
+                const bool second = j == 0 || j == 3;
+                const int img = !second ? (w == kFluid ? kImgSelf : kImgCell)
+                              : w1 != kFluid ? (pt[sl] == idx ? kImgCell : kImgMirror)
+                              : w != kFluid ? kImgSame : kImgSelf;
+                sc |= (unsigned long long)(w | img << 3) << (5 * (4 * d + j));
+            }
+        for (int d = 0; d < D; ++d)
+            for (int j = 0; j < 4; ++j) {
+                const size_t sl = (size_t)(d * 4 + j) * nb + t;
+                const bool ok = decode_kind(sc, d, j) == wk[sl] &&
+                                decode_point(sc, d, j, idx, x, y, z, p.nx, p.ny, p.nz) == pt[sl] &&
+                                (wk[sl] != kIso ||
+                                 decode_wall_T(sc, d, j, x, y, z, p.nx, p.ny, p.nz, periodic_bits(p), p.face_T, wT) == tw[sl]);
+                if (!ok) return fail(LBFD_EINVAL, "internal: stencil code of boundary cell %lld, axis %d, slot %d", idx, d, j);
+            }
+        pcode[t] = pc;
+        scode[t] = sc;
+    }
+    HIP_TRY(hipMemcpy(c->bcode_pull, pcode.data(), pcode.size() * sizeof(unsigned long long), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->bcode_st, scode.data(), scode.size() * sizeof(unsigned long long), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->face_Td, p.face_T, sizeof(p.face_T), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->bsrc, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->bpt, pt.data(), pt.size() * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->bwk, wk.data(), wk.size(), hipMemcpyHostToDevice));
@@ -442,6 +496,10 @@ static KParams make_kparams(const lbfd_ctx *c)
     k.tiles_x = (int)c->grid.x;
     k.tiles_y = (int)c->grid.y;
     k.bsrc = c->bsrc;
+    k.bcode_pull = c->bcode_pull;
+    k.bcode_st = c->bcode_st;
+    k.face_Td = c->face_Td;
+    k.periodic_bits = periodic_bits(c->p);
     k.bpt = c->bpt;
     k.bwk = c->bwk;
     k.btw = c->btw;
@@ -605,6 +663,9 @@ int lbfd_init(const lbfd_params *p, const uint8_t *mask, const double *wall_T, c
         ALLOC(c->bpt, sizeof(int) * 12 * nbd);
         ALLOC(c->bwk, 12 * nbd);
         ALLOC(c->btw, sizeof(double) * 12 * nbd);
+        ALLOC(c->bcode_pull, sizeof(unsigned long long) * nbd);
+        ALLOC(c->bcode_st, sizeof(unsigned long long) * nbd);
+        ALLOC(c->face_Td, sizeof(double) * 6);
     }
     ALLOC(c->wall_T, N * sizeof(double));
     ALLOC(c->outlet, c->outlet_n * sizeof(double));

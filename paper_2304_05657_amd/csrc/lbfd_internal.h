@@ -44,6 +44,66 @@ struct ChemRx {
 // evaluate it inside the step kernel.
 constexpr bool chem_pass(int nsp) { return nsp > 4; }
 
+// Compact per-boundary-cell codes, decoded by the kernels and checked
+// against the full descriptors on the host when they are built (the same
+// functions on both sides).  Pull: 2 bits per direction I (bits 2 I ..);
+// the source of a fluid pull is the neighbour x - c_I, wrapped across
+// periodic faces.  Stencil: 5 bits per axis d and offset m = -2, -1, 1, 2
+// (slot 4 d + j, bits 5 (4 d + j) ..): the point's kind (kFluid, or the kind
+// of the wall behind its ghost; 3 bits) and where its value, or its ghost's
+// image, sits (2 bits): the point itself, the cell, the first neighbour on
+// the other side, the first neighbour on the same side.
+enum { kPullFluid = 0, kPullBounce = 1, kPullInflow = 2, kPullOutlet = 3 };
+enum { kImgSelf = 0, kImgCell = 1, kImgMirror = 2, kImgSame = 3 };
+
+// v wrapped once into [0, n) (offsets of at most 2 from an in-box point)
+__host__ __device__ inline int wrap_once(int v, int n) { return v < 0 ? v + n : v >= n ? v - n : v; }
+
+__host__ __device__ inline long long cell_at(int x, int y, int z, int dx, int dy, int dz, int nx, int ny, int nz)
+{
+    return ((long long)wrap_once(z + dz, nz) * ny + wrap_once(y + dy, ny)) * nx + wrap_once(x + dx, nx);
+}
+
+__host__ __device__ inline int decode_pull_kind(unsigned long long pc, int I) { return (int)(pc >> (2 * I)) & 3; }
+
+__host__ __device__ inline int decode_kind(unsigned long long sc, int d, int j)
+{
+    return (int)(sc >> (5 * (4 * d + j))) & 7;
+}
+
+__host__ __device__ inline int slot_offset(int j) { return j == 0 ? -2 : j == 1 ? -1 : j == 2 ? 1 : 2; }
+
+// The cell holding the value of stencil slot (d, j), or its ghost's image.
+__host__ __device__ inline long long decode_point(unsigned long long sc, int d, int j, long long idx, int x, int y,
+                                                  int z, int nx, int ny, int nz)
+{
+    const int img = (int)(sc >> (5 * (4 * d + j) + 3)) & 3;
+    const int m = slot_offset(j), sg = m < 0 ? -1 : 1;
+    const int o = img == kImgSelf ? m : img == kImgMirror ? -sg : img == kImgSame ? sg : 0;
+    if (o == 0) return idx;
+    return cell_at(x, y, z, d == 0 ? o : 0, d == 1 ? o : 0, d == 2 ? o : 0, nx, ny, nz);
+}
+
+// Temperature of the isothermal wall behind the ghost of slot (d, j): the
+// wall is the first non-fluid point from the cell along the slot's side
+// (the first neighbour when that is a ghost, else the point itself), an
+// in-box solid cell (wrapped across a periodic face) or a domain face.
+// periodic_bits has bit f set for a periodic face f; face_T holds the six
+// face temperatures (in device memory on the device: a read of the kernel's
+// argument block at a computed index would copy the block to scratch).
+__host__ __device__ inline double decode_wall_T(unsigned long long sc, int d, int j, int x, int y, int z, int nx,
+                                                int ny, int nz, unsigned periodic_bits, const double *face_T,
+                                                const double *wall_T)
+{
+    const int m = slot_offset(j), sg = m < 0 ? -1 : 1;
+    const int j1 = sg < 0 ? 1 : 2;
+    const int mw = (j == j1 || decode_kind(sc, d, j1) != kFluid) ? sg : m;
+    const int c = d == 0 ? x : d == 1 ? y : z, n = d == 0 ? nx : d == 1 ? ny : nz;
+    const int f = 2 * d + (mw > 0 ? 1 : 0);
+    if ((c + mw < 0 || c + mw >= n) && !((periodic_bits >> f) & 1u)) return face_T[f];
+    return wall_T[cell_at(x, y, z, d == 0 ? mw : 0, d == 1 ? mw : 0, d == 2 ? mw : 0, nx, ny, nz)];
+}
+
 // Everything a step kernel reads; passed by value (kernarg segment, read
 // through the scalar cache).
 struct KParams {
@@ -66,6 +126,10 @@ struct KParams {
     const int *bpt;             // [3*4][nb] finite-difference point (or ghost image) index, axis-major, m = -2,-1,1,2
     const uint8_t *bwk;         // [3*4][nb] kind of the wall behind a ghost point, kFluid for a plain point
     const double *btw;          // [3*4][nb] wall temperature of isothermal ghost walls
+    const unsigned long long *bcode_pull;  // [nb] compact pull codes (decode_pull_kind below)
+    const unsigned long long *bcode_st;    // [nb] compact stencil codes (decode_point below)
+    const double *face_Td;      // [6] face_T in device memory (read at a computed face index)
+    unsigned periodic_bits;     // bit f: face f periodic
     const float *bq;            // [Q][nb] wall distance of the bounced link of population I, NaN: half-way
                                 // (nullptr: every link half-way)
     const int *bimg;            // [3*4][nb] a ghost's image point in img_val, -1: axis mirror

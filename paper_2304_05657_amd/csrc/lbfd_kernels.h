@@ -329,7 +329,8 @@ static __constant__ double kZeroEntry[1] = {0.0};
 // that the other side's lanes later read stale registers.)
 template <int Q, int PREC, int I, bool CW>
 __device__ __forceinline__ typename Prec<PREC>::calc desc_pull(const KParams &P, long long t, long long nb,
-                                                               long long idx, int x, int y, int z)
+                                                               long long idx, int x, int y, int z,
+                                                               unsigned long long pcode)
 {
     using C = typename Prec<PREC>::calc;
     using L = Lat<Q>;
@@ -337,7 +338,18 @@ __device__ __forceinline__ typename Prec<PREC>::calc desc_pull(const KParams &P,
     if constexpr (I == (Q - 1) / 2) {
         return pop_load<Q, PREC, I>(P.pop_in, P.N, (uint32_t)idx);
     } else {
-        const int src = P.bsrc[I * nb + t];
+        // the source: the full descriptor with curved-wall links (whose
+        // rule also reads the opposite direction's), else the compact code
+        int src;
+        if constexpr (CW) {
+            src = P.bsrc[I * nb + t];
+        } else {
+            const int kind = decode_pull_kind(pcode, I);
+            src = kind == kPullFluid    ? (int)cell_at(x, y, z, -L::cx(I), -L::cy(I), -L::cz(I), P.nx, P.ny, P.nz)
+                  : kind == kPullBounce ? kSrcBounce
+                  : kind == kPullInflow ? kSrcInflow
+                                        : kSrcOutlet;
+        }
         const bool fluid = src >= 0;
         // the source cell's population I, or this cell's opposite one
         // (half-way bounce-back, and the base of the inlet rule)
@@ -1010,6 +1022,7 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
     using TS = TileShape<D>;
     int x, y, z;
     long long idx, tb = 0;
+    unsigned long long pcode = 0, scode = 0;  // a boundary cell's compact codes
     bool active, inbox;
     if constexpr (FAST) {
         x = bx * TS::X + tx;
@@ -1023,6 +1036,10 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
         inbox = false;
         active = tb < P.n_boundary;
         idx = active ? (long long)P.boundary[tb] : 0;
+        if constexpr (!CW) {
+            pcode = P.bcode_pull[active ? tb : 0];
+            scode = P.bcode_st[active ? tb : 0];
+        }
         x = (int)(idx % P.nx);
         y = (int)((idx / P.nx) % P.ny);
         z = (int)(idx / ((long long)P.nx * P.ny));
@@ -1090,7 +1107,7 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
                 if constexpr (FAST)
                     g[i] = pop_load<Q, PREC, i>(P.pop_in, P.N, idx - (L::cx(i) + sy * L::cy(i) + sz * L::cz(i)));
                 else
-                    g[i] = desc_pull<Q, PREC, i, CW>(P, tb, P.n_boundary, idx, x, y, z);
+                    g[i] = desc_pull<Q, PREC, i, CW>(P, tb, P.n_boundary, idx, x, y, z, pcode);
             });
         Pt<NSP, C> ctr;
         if constexpr (TILE)
@@ -1233,10 +1250,24 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
                 int pts[4], wks[4], lis[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    pts[j] = P.bpt[(d * 4 + j) * nbd + tb];
-                    wks[j] = P.bwk[(d * 4 + j) * nbd + tb];
-                    lis[j] = CW && P.bimg != nullptr ? P.bimg[(d * 4 + j) * nbd + tb] : -1;
+                    if constexpr (CW) {
+                        pts[j] = P.bpt[(d * 4 + j) * nbd + tb];
+                        wks[j] = P.bwk[(d * 4 + j) * nbd + tb];
+                        lis[j] = P.bimg != nullptr ? P.bimg[(d * 4 + j) * nbd + tb] : -1;
+                    } else {
+                        pts[j] = (int)decode_point(scode, d, j, idx, x, y, z, P.nx, P.ny, P.nz);
+                        wks[j] = decode_kind(scode, d, j);
+                        lis[j] = -1;
+                    }
                 }
+                // the wall temperature behind an isothermal ghost at slot j
+                auto wall_temp = [&](int j) -> double {
+                    if constexpr (CW)
+                        return P.btw[(d * 4 + j) * nbd + tb];
+                    else
+                        return decode_wall_T(scode, d, j, x, y, z, P.nx, P.ny, P.nz, P.periodic_bits, P.face_Td,
+                                             P.wall_T);
+                };
                 const bool near = (wks[0] | wks[1] | wks[2] | wks[3]) != kFluid;
                 C r5[5];
                 r5[2] = rho;
@@ -1251,7 +1282,7 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
                         load_point<NSP, PREC>(P, pts[j], pt);
                     r5[slot] = pt.rho;
                     if (wks[j] == kIso) {
-                        const C Tw = (C)P.btw[(d * 4 + j) * nbd + tb];
+                        const C Tw = (C)wall_temp(j);
                         r5[slot] = (C)2 * density<NSP>(P, Tw, pt.Y) - pt.rho;
                         if constexpr (DIAG) {
                             if (j == 1 || j == 2)
@@ -1268,7 +1299,7 @@ __device__ __forceinline__ void step_block(const KParams &P, int bx, int by, int
                         const C v = f == 0 ? pv[j].T : pv[j].Y[f - 2];
                         if (wks[j] == kFluid) return v;
                         if (f == 0) {
-                            if (wks[j] == kIso) return (C)2 * (C)P.btw[(d * 4 + j) * nbd + tb] - v;
+                            if (wks[j] == kIso) return (C)2 * (C)wall_temp(j) - v;
                             if (wks[j] == kInflow) return (C)2 * (C)P.T_in - v;
                             return v;
                         }
