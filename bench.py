@@ -112,12 +112,12 @@ def step_flops_per_cell(prob) -> int:
 
 def chem_flops_per_substep(prob) -> int:
     """Flops of one chemistry sub-step of one cell (exp and log count 1):
-    per reaction the exponent b ln T - Ta/T (3), exp, prefactor and 1/N (2),
+    per reaction the exponent b ln T - Ta/T + ln(A dt) - ln N (5), exp,
     the reactant product (n_react), nu_k r for every species (2 N_sp) and
     q r (2); per sub-step the current state (1 + N_sp), ln T and 1/T (2), the
     limiter (3 N_sp) and the accumulation (2 + 2 N_sp)."""
     ns = prob.n_species
-    per_rx = sum(3 + 1 + 2 + len(r.reactants) + 2 * ns + 2 for r in prob.reactions)
+    per_rx = sum(5 + 1 + len(r.reactants) + 2 * ns + 2 for r in prob.reactions)
     return per_rx + (1 + ns) + 2 + 3 * ns + 2 + 2 * ns
 
 

@@ -1307,9 +1307,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     const KParams &P = AP.k;
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     __shared__ double red[2 * LBFD_MAX_REACTIONS];
-    __shared__ double tab[64];
+    __shared__ double tab[kExpTabN];
     for (int j = threadIdx.x; j < 2 * LBFD_MAX_REACTIONS; j += blockDim.x) red[j] = 0.0;
-    if (threadIdx.x < 64) tab[threadIdx.x] = kExp2Tab[threadIdx.x];
+    for (int j = threadIdx.x; j < kExpTabN; j += blockDim.x) tab[j] = kExp2Tab[j];
     __syncthreads();
     if (idx < P.N && P.mask[idx] == LBFD_FLUID) {
         const int x = (int)(idx % P.nx), y = (int)((idx / P.nx) % P.ny), z = (int)(idx / ((long long)P.nx * P.ny));

@@ -558,10 +558,11 @@ static int upload_reactions(lbfd_ctx *c)
     const lbfd_params &p = c->p;
     ChemRx h[LBFD_MAX_REACTIONS];
     memset(h, 0, sizeof(h));
-    int anyb = 0;
+    int anyb = 0, nreact = 0;
     for (int j = 0; j < p.n_reactions; ++j) {
         const lbfd_reaction &r = c->rx[j];
         h[j].adt = r.A * p.dt_phys;
+        h[j].lnadt = h[j].adt > 0.0 ? std::log(h[j].adt) : -HUGE_VAL;
         h[j].b = r.b;
         h[j].ta = r.Ta;
         h[j].q = r.q_over_cp;
@@ -570,12 +571,14 @@ static int upload_reactions(lbfd_ctx *c)
         for (int m = 0; m < 4; ++m) h[j].react[m] = m < r.n_react ? r.react[m] : c->nsp;
         for (int k = 0; k < c->nsp; ++k) h[j].nu[k] = r.nu_mass[k];
         anyb |= r.b != 0.0;
+        nreact = std::max(nreact, r.n_react);
     }
     if (p.n_reactions > 0) {
         HIP_TRY(hipMemcpy(c->rx_dev, c->rx, sizeof(lbfd_reaction) * p.n_reactions, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(c->rxk_dev, h, sizeof(ChemRx) * p.n_reactions, hipMemcpyHostToDevice));
     }
     c->base.chem_anyb = anyb;
+    c->base.chem_nreact = nreact;
     return LBFD_OK;
 }
 

@@ -34,6 +34,7 @@ enum NbKind { kFluid = 0, kIso = 1, kAdia = 2, kInflow = 3, kOutflow = 4 };
 // reactant indices and the mass coefficients.
 struct ChemRx {
     double adt, b, ta, q;
+    double lnadt;           // ln(A dt) (-inf for A = 0)
     int n_react, react[4];  // react[m >= n_react] = n_species (a factor 1)
     double nu[kMaxSp];
 };
@@ -161,6 +162,7 @@ struct KParams {
     const ChemRx *rxk;  // the same reactions as the chemistry reads them
     int n_rx;
     int chem_anyb;      // some reaction has a temperature exponent b != 0
+    int chem_nreact;    // the largest reactant count of a reaction (0..4)
     int chem_substeps_max;
     double omega2, omega3, omega4, alpha;
     double dt_phys;

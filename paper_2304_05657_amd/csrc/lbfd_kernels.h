@@ -521,52 +521,104 @@ __device__ __forceinline__ void axis5(C m2, C m1, C c0, C p1, C p2, C u, bool ne
 }
 
 // ------------------------------------------------------------ exponential
-// 2^(j/64), j = 0..63, each the double nearest to the exact value (computed
-// with 60-digit decimal arithmetic).
-static __constant__ double kExp2Tab[64] = {
-    0x1.0000000000000p+0, 0x1.02c9a3e778061p+0, 0x1.059b0d3158574p+0, 0x1.0874518759bc8p+0,
-    0x1.0b5586cf9890fp+0, 0x1.0e3ec32d3d1a2p+0, 0x1.11301d0125b51p+0, 0x1.1429aaea92de0p+0,
-    0x1.172b83c7d517bp+0, 0x1.1a35beb6fcb75p+0, 0x1.1d4873168b9aap+0, 0x1.2063b88628cd6p+0,
-    0x1.2387a6e756238p+0, 0x1.26b4565e27cddp+0, 0x1.29e9df51fdee1p+0, 0x1.2d285a6e4030bp+0,
-    0x1.306fe0a31b715p+0, 0x1.33c08b26416ffp+0, 0x1.371a7373aa9cbp+0, 0x1.3a7db34e59ff7p+0,
-    0x1.3dea64c123422p+0, 0x1.4160a21f72e2ap+0, 0x1.44e086061892dp+0, 0x1.486a2b5c13cd0p+0,
-    0x1.4bfdad5362a27p+0, 0x1.4f9b2769d2ca7p+0, 0x1.5342b569d4f82p+0, 0x1.56f4736b527dap+0,
-    0x1.5ab07dd485429p+0, 0x1.5e76f15ad2148p+0, 0x1.6247eb03a5585p+0, 0x1.6623882552225p+0,
-    0x1.6a09e667f3bcdp+0, 0x1.6dfb23c651a2fp+0, 0x1.71f75e8ec5f74p+0, 0x1.75feb564267c9p+0,
-    0x1.7a11473eb0187p+0, 0x1.7e2f336cf4e62p+0, 0x1.82589994cce13p+0, 0x1.868d99b4492edp+0,
-    0x1.8ace5422aa0dbp+0, 0x1.8f1ae99157736p+0, 0x1.93737b0cdc5e5p+0, 0x1.97d829fde4e50p+0,
-    0x1.9c49182a3f090p+0, 0x1.a0c667b5de565p+0, 0x1.a5503b23e255dp+0, 0x1.a9e6b5579fdbfp+0,
-    0x1.ae89f995ad3adp+0, 0x1.b33a2b84f15fbp+0, 0x1.b7f76f2fb5e47p+0, 0x1.bcc1e904bc1d2p+0,
-    0x1.c199bdd85529cp+0, 0x1.c67f12e57d14bp+0, 0x1.cb720dcef9069p+0, 0x1.d072d4a07897cp+0,
-    0x1.d5818dcfba487p+0, 0x1.da9e603db3285p+0, 0x1.dfc97337b9b5fp+0, 0x1.e502ee78b3ff6p+0,
-    0x1.ea4afa2a490dap+0, 0x1.efa1bee615a27p+0, 0x1.f50765b6e4540p+0, 0x1.fa7c1819e90d8p+0,
+// 2^(j/256), j = 0..255, each the double nearest to the exact value
+// (computed with 60-digit decimal arithmetic).
+constexpr int kExpTabN = 256;
+static __constant__ double kExp2Tab[kExpTabN] = {
+    0x1.0000000000000p+0, 0x1.00b1afa5abcbfp+0, 0x1.0163da9fb3335p+0, 0x1.02168143b0281p+0,
+    0x1.02c9a3e778061p+0, 0x1.037d42e11bbccp+0, 0x1.04315e86e7f85p+0, 0x1.04e5f72f654b1p+0,
+    0x1.059b0d3158574p+0, 0x1.0650a0e3c1f89p+0, 0x1.0706b29ddf6dep+0, 0x1.07bd42b72a836p+0,
+    0x1.0874518759bc8p+0, 0x1.092bdf66607e0p+0, 0x1.09e3ecac6f383p+0, 0x1.0a9c79b1f3919p+0,
+    0x1.0b5586cf9890fp+0, 0x1.0c0f145e46c85p+0, 0x1.0cc922b7247f7p+0, 0x1.0d83b23395decp+0,
+    0x1.0e3ec32d3d1a2p+0, 0x1.0efa55fdfa9c5p+0, 0x1.0fb66affed31bp+0, 0x1.1073028d7233ep+0,
+    0x1.11301d0125b51p+0, 0x1.11edbab5e2ab6p+0, 0x1.12abdc06c31ccp+0, 0x1.136a814f204abp+0,
+    0x1.1429aaea92de0p+0, 0x1.14e95934f312ep+0, 0x1.15a98c8a58e51p+0, 0x1.166a45471c3c2p+0,
+    0x1.172b83c7d517bp+0, 0x1.17ed48695bbc0p+0, 0x1.18af9388c8deap+0, 0x1.1972658375d2fp+0,
+    0x1.1a35beb6fcb75p+0, 0x1.1af99f8138a1cp+0, 0x1.1bbe084045cd4p+0, 0x1.1c82f95281c6bp+0,
+    0x1.1d4873168b9aap+0, 0x1.1e0e75eb44027p+0, 0x1.1ed5022fcd91dp+0, 0x1.1f9c18438ce4dp+0,
+    0x1.2063b88628cd6p+0, 0x1.212be3578a819p+0, 0x1.21f49917ddc96p+0, 0x1.22bdda27912d1p+0,
+    0x1.2387a6e756238p+0, 0x1.2451ffb82140ap+0, 0x1.251ce4fb2a63fp+0, 0x1.25e85711ece75p+0,
+    0x1.26b4565e27cddp+0, 0x1.2780e341ddf29p+0, 0x1.284dfe1f56381p+0, 0x1.291ba7591bb70p+0,
+    0x1.29e9df51fdee1p+0, 0x1.2ab8a66d10f13p+0, 0x1.2b87fd0dad990p+0, 0x1.2c57e39771b2fp+0,
+    0x1.2d285a6e4030bp+0, 0x1.2df961f641589p+0, 0x1.2ecafa93e2f56p+0, 0x1.2f9d24abd886bp+0,
+    0x1.306fe0a31b715p+0, 0x1.31432edeeb2fdp+0, 0x1.32170fc4cd831p+0, 0x1.32eb83ba8ea32p+0,
+    0x1.33c08b26416ffp+0, 0x1.3496266e3fa2dp+0, 0x1.356c55f929ff1p+0, 0x1.36431a2de883bp+0,
+    0x1.371a7373aa9cbp+0, 0x1.37f26231e754ap+0, 0x1.38cae6d05d866p+0, 0x1.39a401b7140efp+0,
+    0x1.3a7db34e59ff7p+0, 0x1.3b57fbfec6cf4p+0, 0x1.3c32dc313a8e5p+0, 0x1.3d0e544ede173p+0,
+    0x1.3dea64c123422p+0, 0x1.3ec70df1c5175p+0, 0x1.3fa4504ac801cp+0, 0x1.40822c367a024p+0,
+    0x1.4160a21f72e2ap+0, 0x1.423fb2709468ap+0, 0x1.431f5d950a897p+0, 0x1.43ffa3f84b9d4p+0,
+    0x1.44e086061892dp+0, 0x1.45c2042a7d232p+0, 0x1.46a41ed1d0057p+0, 0x1.4786d668b3237p+0,
+    0x1.486a2b5c13cd0p+0, 0x1.494e1e192aed2p+0, 0x1.4a32af0d7d3dep+0, 0x1.4b17dea6db7d7p+0,
+    0x1.4bfdad5362a27p+0, 0x1.4ce41b817c114p+0, 0x1.4dcb299fddd0dp+0, 0x1.4eb2d81d8abffp+0,
+    0x1.4f9b2769d2ca7p+0, 0x1.508417f4531eep+0, 0x1.516daa2cf6642p+0, 0x1.5257de83f4eefp+0,
+    0x1.5342b569d4f82p+0, 0x1.542e2f4f6ad27p+0, 0x1.551a4ca5d920fp+0, 0x1.56070dde910d2p+0,
+    0x1.56f4736b527dap+0, 0x1.57e27dbe2c4cfp+0, 0x1.58d12d497c7fdp+0, 0x1.59c0827ff07ccp+0,
+    0x1.5ab07dd485429p+0, 0x1.5ba11fba87a03p+0, 0x1.5c9268a5946b7p+0, 0x1.5d84590998b93p+0,
+    0x1.5e76f15ad2148p+0, 0x1.5f6a320dceb71p+0, 0x1.605e1b976dc09p+0, 0x1.6152ae6cdf6f4p+0,
+    0x1.6247eb03a5585p+0, 0x1.633dd1d1929fdp+0, 0x1.6434634ccc320p+0, 0x1.652b9febc8fb7p+0,
+    0x1.6623882552225p+0, 0x1.671c1c70833f6p+0, 0x1.68155d44ca973p+0, 0x1.690f4b19e9538p+0,
+    0x1.6a09e667f3bcdp+0, 0x1.6b052fa75173ep+0, 0x1.6c012750bdabfp+0, 0x1.6cfdcddd47645p+0,
+    0x1.6dfb23c651a2fp+0, 0x1.6ef9298593ae5p+0, 0x1.6ff7df9519484p+0, 0x1.70f7466f42e87p+0,
+    0x1.71f75e8ec5f74p+0, 0x1.72f8286ead08ap+0, 0x1.73f9a48a58174p+0, 0x1.74fbd35d7cbfdp+0,
+    0x1.75feb564267c9p+0, 0x1.77024b1ab6e09p+0, 0x1.780694fde5d3fp+0, 0x1.790b938ac1cf6p+0,
+    0x1.7a11473eb0187p+0, 0x1.7b17b0976cfdbp+0, 0x1.7c1ed0130c132p+0, 0x1.7d26a62ff86f0p+0,
+    0x1.7e2f336cf4e62p+0, 0x1.7f3878491c491p+0, 0x1.80427543e1a12p+0, 0x1.814d2add106d9p+0,
+    0x1.82589994cce13p+0, 0x1.8364c1eb941f7p+0, 0x1.8471a4623c7adp+0, 0x1.857f4179f5b21p+0,
+    0x1.868d99b4492edp+0, 0x1.879cad931a436p+0, 0x1.88ac7d98a6699p+0, 0x1.89bd0a478580fp+0,
+    0x1.8ace5422aa0dbp+0, 0x1.8be05bad61778p+0, 0x1.8cf3216b5448cp+0, 0x1.8e06a5e0866d9p+0,
+    0x1.8f1ae99157736p+0, 0x1.902fed0282c8ap+0, 0x1.9145b0b91ffc6p+0, 0x1.925c353aa2fe2p+0,
+    0x1.93737b0cdc5e5p+0, 0x1.948b82b5f98e5p+0, 0x1.95a44cbc8520fp+0, 0x1.96bdd9a7670b3p+0,
+    0x1.97d829fde4e50p+0, 0x1.98f33e47a22a2p+0, 0x1.9a0f170ca07bap+0, 0x1.9b2bb4d53fe0dp+0,
+    0x1.9c49182a3f090p+0, 0x1.9d674194bb8d5p+0, 0x1.9e86319e32323p+0, 0x1.9fa5e8d07f29ep+0,
+    0x1.a0c667b5de565p+0, 0x1.a1e7aed8eb8bbp+0, 0x1.a309bec4a2d33p+0, 0x1.a42c980460ad8p+0,
+    0x1.a5503b23e255dp+0, 0x1.a674a8af46052p+0, 0x1.a799e1330b358p+0, 0x1.a8bfe53c12e59p+0,
+    0x1.a9e6b5579fdbfp+0, 0x1.ab0e521356ebap+0, 0x1.ac36bbfd3f37ap+0, 0x1.ad5ff3a3c2774p+0,
+    0x1.ae89f995ad3adp+0, 0x1.afb4ce622f2ffp+0, 0x1.b0e07298db666p+0, 0x1.b20ce6c9a8952p+0,
+    0x1.b33a2b84f15fbp+0, 0x1.b468415b749b1p+0, 0x1.b59728de5593ap+0, 0x1.b6c6e29f1c52ap+0,
+    0x1.b7f76f2fb5e47p+0, 0x1.b928cf22749e4p+0, 0x1.ba5b030a1064ap+0, 0x1.bb8e0b79a6f1fp+0,
+    0x1.bcc1e904bc1d2p+0, 0x1.bdf69c3f3a207p+0, 0x1.bf2c25bd71e09p+0, 0x1.c06286141b33dp+0,
+    0x1.c199bdd85529cp+0, 0x1.c2d1cd9fa652cp+0, 0x1.c40ab5fffd07ap+0, 0x1.c544778fafb22p+0,
+    0x1.c67f12e57d14bp+0, 0x1.c7ba88988c933p+0, 0x1.c8f6d9406e7b5p+0, 0x1.ca3405751c4dbp+0,
+    0x1.cb720dcef9069p+0, 0x1.ccb0f2e6d1675p+0, 0x1.cdf0b555dc3fap+0, 0x1.cf3155b5bab74p+0,
+    0x1.d072d4a07897cp+0, 0x1.d1b532b08c968p+0, 0x1.d2f87080d89f2p+0, 0x1.d43c8eacaa1d6p+0,
+    0x1.d5818dcfba487p+0, 0x1.d6c76e862e6d3p+0, 0x1.d80e316c98398p+0, 0x1.d955d71ff6075p+0,
+    0x1.da9e603db3285p+0, 0x1.dbe7cd63a8315p+0, 0x1.dd321f301b460p+0, 0x1.de7d5641c0658p+0,
+    0x1.dfc97337b9b5fp+0, 0x1.e11676b197d17p+0, 0x1.e264614f5a129p+0, 0x1.e3b333b16ee12p+0,
+    0x1.e502ee78b3ff6p+0, 0x1.e653924676d76p+0, 0x1.e7a51fbc74c83p+0, 0x1.e8f7977cdb740p+0,
+    0x1.ea4afa2a490dap+0, 0x1.eb9f4867cca6ep+0, 0x1.ecf482d8e67f1p+0, 0x1.ee4aaa2188510p+0,
+    0x1.efa1bee615a27p+0, 0x1.f0f9c1cb6412ap+0, 0x1.f252b376bba97p+0, 0x1.f3ac948dd7274p+0,
+    0x1.f50765b6e4540p+0, 0x1.f6632798844f8p+0, 0x1.f7bfdad9cbe14p+0, 0x1.f91d802243c89p+0,
+    0x1.fa7c1819e90d8p+0, 0x1.fbdba3692d514p+0, 0x1.fd3c22b8f71f1p+0, 0x1.fe9d96b2a23d9p+0,
 };
 
 // exp(x) by table-driven argument reduction (P. T. P. Tang, Table-driven
 // implementation of the exponential function in IEEE floating-point
-// arithmetic, ACM TOMS 15, 1989): x = (64 m + j) ln2/64 + r, |r| <= ln2/128,
-// with ln2/64 split into a 32-bit head (n times it is exact) and a tail;
-// exp(x) = 2^m 2^(j/64) (1 + p(r)), p the degree-5 Taylor polynomial of
-// exp(r) - 1 (truncation below 4e-17 relative).  About one ulp from the
-// correctly rounded value; x is clamped to [-1000, 1000] (exp underflows to
-// 0 and overflows to infinity well inside it).  `tab` holds kExp2Tab (in
-// LDS in the chemistry launch, the constant table elsewhere).
+// arithmetic, ACM TOMS 15, 1989): x = (256 m + j) ln2/256 + r,
+// |r| <= ln2/512, with ln2/256 split into a 33-bit head (n times it is exact
+// for |n| < 2^20) and a tail; exp(x) = 2^m 2^(j/256) (1 + p(r)), p the
+// degree-4 Taylor polynomial of exp(r) - 1 (truncation below 4e-17
+// relative).  About one ulp from the correctly rounded value; x is clamped
+// to [-1000, 1000] (exp underflows to 0 and overflows to infinity well
+// inside it).  `tab` holds kExp2Tab (in LDS in the chemistry launches, the
+// constant table elsewhere).  HI = false drops the upper clamp, for
+// arguments known to stay far below it.
+template <bool HI = true>
 __device__ __forceinline__ double exp_tab(double x, const double *tab)
 {
-    constexpr double kInvLn2_64 = 0x1.71547652b82fep+6;   // 64 / ln 2
-    constexpr double kLn2_64_hi = 0x1.62e42fee00000p-7;   // ln 2 / 64, head
-    constexpr double kLn2_64_lo = 0x1.a39ef35793c76p-39;  // and tail
-    x = fmin(fmax(x, -1000.0), 1000.0);
-    const double n = __builtin_rint(x * kInvLn2_64);
-    const double r = fma(-n, kLn2_64_lo, fma(-n, kLn2_64_hi, x));
+    constexpr double kInvLn2_256 = 0x1.71547652b82fep+8;   // 256 / ln 2
+    constexpr double kLn2_256_hi = 0x1.62e42fee00000p-9;   // ln 2 / 256, head
+    constexpr double kLn2_256_lo = 0x1.a39ef35793c76p-41;  // and tail
+    x = fmax(x, -1000.0);
+    if constexpr (HI) x = fmin(x, 1000.0);
+    const double n = __builtin_rint(x * kInvLn2_256);
+    const double r = fma(-n, kLn2_256_lo, fma(-n, kLn2_256_hi, x));
     const int ni = (int)n;
-    double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
-    p = fma(r, p, 1.0 / 6.0);
+    double p = fma(r, 1.0 / 24.0, 1.0 / 6.0);
     p = fma(r, p, 0.5);
     p = fma(r, p, 1.0);
     p *= r;
-    const double t = tab[ni & 63];
-    return __builtin_ldexp(fma(t, p, t), ni >> 6);
+    const double t = tab[ni & (kExpTabN - 1)];
+    return __builtin_ldexp(fma(t, p, t), ni >> 8);
 }
 
 // ------------------------------------------------------------ chemistry
@@ -583,8 +635,21 @@ __device__ __forceinline__ double rate_coeff_l(const ChemRx &r, double lnT, doub
     return r.adt * exp_tab(r.b * lnT - r.ta * invT, tab);
 }
 
-// Returns the number of sub-steps taken.
-template <int NSP, bool LE = false>
+// The same coefficient divided by the sub-step count N, with ln(A dt) and
+// ln N moved into the exponent: exp(b ln T - Ta/T + ln(A dt) - ln N).  The
+// argument is below ln(A dt) + b ln T, far under the exponential's overflow
+// for any temperature a double holds, so the upper clamp is left out.
+__device__ __forceinline__ double rate_coeff_sub(const ChemRx &r, double lnT, double invT, double lnN,
+                                                 const double *tab)
+{
+    // (each operation takes one per-reaction constant: an instruction reads
+    // at most one scalar register operand)
+    return exp_tab<false>(fma(r.b, lnT, fma(-r.ta, invT, -lnN)) + r.lnadt, tab);
+}
+
+// Returns the number of sub-steps taken.  NR: the largest reactant count
+// of a reaction (slots past a reaction's own count multiply by 1).
+template <int NSP, bool LE = false, int NR = 4>
 __device__ __forceinline__ int chemistry(const KParams &P, const double *tab, double T, const double (&Y)[NSP],
                                          double &srcT, double (&srcY)[NSP])
 {
@@ -598,7 +663,7 @@ __device__ __forceinline__ int chemistry(const KParams &P, const double *tab, do
         double want = ceil(kmax / 0.1);
         nsub = want < 1.0 ? 1 : want > (double)P.chem_substeps_max ? P.chem_substeps_max : (int)want;
     }
-    const double inv_nsub = nsub == 1 ? 1.0 : rcp((double)nsub);
+    const double lnN = nsub == 1 ? 0.0 : log((double)nsub);
     double dT = 0.0, dY[NSP];
 #pragma unroll
     for (int k = 0; k < NSP; ++k) dY[k] = 0.0;
@@ -621,9 +686,9 @@ __device__ __forceinline__ int chemistry(const KParams &P, const double *tab, do
         // scalar load ahead of the products instead of one dependent load
         // per reactant
         auto apply = [&](const ChemRx &r, double k) {
-            double rr = k * inv_nsub;
+            double rr = k;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) rr *= Yc[r.react[m]];
+            for (int m = 0; m < NR; ++m) rr *= Yc[r.react[m]];
 #pragma unroll
             for (int k2 = 0; k2 < NSP; ++k2) incY[k2] += r.nu[k2] * rr;
             incT += r.q * rr;
@@ -634,11 +699,11 @@ __device__ __forceinline__ int chemistry(const KParams &P, const double *tab, do
         for (; j + 4 <= P.n_rx; j += 4) {
             double k4[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) k4[u] = rate_coeff_l(P.rxk[j + u], lnTc, invTc, tab);
+            for (int u = 0; u < 4; ++u) k4[u] = rate_coeff_sub(P.rxk[j + u], lnTc, invTc, lnN, tab);
 #pragma unroll
             for (int u = 0; u < 4; ++u) apply(P.rxk[j + u], k4[u]);
         }
-        for (; j < P.n_rx; ++j) apply(P.rxk[j], rate_coeff_l(P.rxk[j], lnTc, invTc, tab));
+        for (; j < P.n_rx; ++j) apply(P.rxk[j], rate_coeff_sub(P.rxk[j], lnTc, invTc, lnN, tab));
         if constexpr (LE) {
             // q_over_cp is the rise at c_p,ref: divide by c_p(Y) / c_p,ref
             // at the sub-step's composition (Eq. 7: omega_T / (rho c_p))
@@ -1583,12 +1648,12 @@ __global__ void chem_count_clear_kernel(int *count)
     if (threadIdx.x < 2) count[threadIdx.x] = 0;
 }
 
-template <int NSP, int PREC, bool LE>
+template <int NSP, int PREC, bool LE, int NR>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) chem_kernel(const KParams P)
 {
     using S = typename Prec<PREC>::scal;
-    __shared__ double tab[64];
-    if (threadIdx.x < 64) tab[threadIdx.x] = kExp2Tab[threadIdx.x];
+    __shared__ double tab[kExpTabN];
+    for (int i = (int)threadIdx.x; i < kExpTabN; i += (int)blockDim.x) tab[i] = kExp2Tab[i];
     __syncthreads();
     const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= P.n_fluid) return;
@@ -1601,7 +1666,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     const double T = (double)ldo<S>(si, off);
 #pragma unroll
     for (int k = 0; k < NSP; ++k) Y[k] = (double)ldo<S>(si + (size_t)(1 + k) * fstride, off);
-    const int nsub = chemistry<NSP, LE>(P, tab, T, Y, srcT, srcY);
+    const int nsub = chemistry<NSP, LE, NR>(P, tab, T, Y, srcT, srcY);
     P.chem_heavy[idx] = nsub > kChemLight;
     sto<S>(so, off, (S)srcT);
 #pragma unroll
@@ -1618,10 +1683,20 @@ hipError_t launch_chem(const KParams &kp, hipStream_t s)
     chem_order_kernel<NSP><<<dim3((unsigned)((kp.n_fluid + per - 1) / per)), dim3(kBlock), 0, s>>>(kp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (kp.transport == LBFD_MIXTURE_AVERAGED)
-        chem_kernel<NSP, PREC, true><<<dim3(nb), dim3(kBlock), 0, s>>>(kp);
-    else
-        chem_kernel<NSP, PREC, false><<<dim3(nb), dim3(kBlock), 0, s>>>(kp);
+    // mechanisms of at most two reactants per reaction skip the two
+    // constant-1 slots
+    const bool two = kp.chem_nreact <= 2;
+    if (kp.transport == LBFD_MIXTURE_AVERAGED) {
+        if (two)
+            chem_kernel<NSP, PREC, true, 2><<<dim3(nb), dim3(kBlock), 0, s>>>(kp);
+        else
+            chem_kernel<NSP, PREC, true, 4><<<dim3(nb), dim3(kBlock), 0, s>>>(kp);
+    } else {
+        if (two)
+            chem_kernel<NSP, PREC, false, 2><<<dim3(nb), dim3(kBlock), 0, s>>>(kp);
+        else
+            chem_kernel<NSP, PREC, false, 4><<<dim3(nb), dim3(kBlock), 0, s>>>(kp);
+    }
     return hipGetLastError();
 }
 
