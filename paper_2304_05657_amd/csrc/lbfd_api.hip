@@ -562,7 +562,10 @@ static int upload_reactions(lbfd_ctx *c)
     for (int j = 0; j < p.n_reactions; ++j) {
         const lbfd_reaction &r = c->rx[j];
         h[j].adt = r.A * p.dt_phys;
-        h[j].lnadt = h[j].adt > 0.0 ? std::log(h[j].adt) : -HUGE_VAL;
+        constexpr double kScale = 0x1.71547652b82fep+8;  // 256 / ln 2
+        h[j].bs = r.b * kScale;
+        h[j].tas = r.Ta * kScale;
+        h[j].lnadts = h[j].adt > 0.0 ? std::log(h[j].adt) * kScale : -HUGE_VAL;
         h[j].b = r.b;
         h[j].ta = r.Ta;
         h[j].q = r.q_over_cp;

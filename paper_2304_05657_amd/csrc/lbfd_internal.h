@@ -34,7 +34,9 @@ enum NbKind { kFluid = 0, kIso = 1, kAdia = 2, kInflow = 3, kOutflow = 4 };
 // reactant indices and the mass coefficients.
 struct ChemRx {
     double adt, b, ta, q;
-    double lnadt;           // ln(A dt) (-inf for A = 0)
+    // b, Ta and ln(A dt) scaled by 256 / ln 2 (the sub-steps' exponent is
+    // formed in units of ln 2 / 256; ln(A dt) is -inf for A = 0)
+    double bs, tas, lnadts;
     int n_react, react[4];  // react[m >= n_react] = n_species (a factor 1)
     double nu[kMaxSp];
 };

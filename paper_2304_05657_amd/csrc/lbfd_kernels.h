@@ -600,16 +600,13 @@ static __constant__ double kExp2Tab[kExpTabN] = {
 // relative).  About one ulp from the correctly rounded value; x is clamped
 // to [-1000, 1000] (exp underflows to 0 and overflows to infinity well
 // inside it).  `tab` holds kExp2Tab (in LDS in the chemistry launches, the
-// constant table elsewhere).  HI = false drops the upper clamp, for
-// arguments known to stay far below it.
-template <bool HI = true>
+// constant table elsewhere).
 __device__ __forceinline__ double exp_tab(double x, const double *tab)
 {
     constexpr double kInvLn2_256 = 0x1.71547652b82fep+8;   // 256 / ln 2
     constexpr double kLn2_256_hi = 0x1.62e42fee00000p-9;   // ln 2 / 256, head
     constexpr double kLn2_256_lo = 0x1.a39ef35793c76p-41;  // and tail
-    x = fmax(x, -1000.0);
-    if constexpr (HI) x = fmin(x, 1000.0);
+    x = fmin(fmax(x, -1000.0), 1000.0);
     const double n = __builtin_rint(x * kInvLn2_256);
     const double r = fma(-n, kLn2_256_lo, fma(-n, kLn2_256_hi, x));
     const int ni = (int)n;
@@ -802,16 +799,41 @@ __device__ __forceinline__ double rate_coeff_l(const ChemRx &r, double lnT, doub
     return r.adt * exp_tab(r.b * lnT - r.ta * invT, tab);
 }
 
+// exp(x) from xs = x 256/ln 2 (the caller folds the scale into the
+// constants it forms xs from): n = rint(xs), s = xs - n (exact, |s| <= 1/2),
+// exp(x) = 2^(n/256) exp(s ln2/256), exp(s ln2/256) - 1 by the degree-4
+// Taylor polynomial in s with the coefficients (ln2/256)^i / i!.  The
+// argument needs no two-part reduction (s is exact); its own rounding, one
+// part in 2^53 of xs, is the same relative error the unscaled x carries.
+// xs is clamped below (exp underflows to 0); the arguments it serves stay
+// far below the overflow.
+__device__ __forceinline__ double exp_scaled_tab(double xs, const double *tab)
+{
+    constexpr double k1 = 0x1.62e42fefa39efp-9;   // ln 2 / 256
+    constexpr double k2 = 0x1.ebfbdff82c58fp-19;  // k1^2 / 2
+    constexpr double k3 = 0x1.c6b08d704a0c0p-29;  // k1^3 / 6
+    constexpr double k4 = 0x1.3b2ab6fba4e77p-39;  // k1^4 / 24
+    xs = fmax(xs, -370000.0);                     // x below -1000
+    const double n = __builtin_rint(xs);
+    const double sr = xs - n;
+    double p = fma(sr, k4, k3);
+    p = fma(sr, p, k2);
+    p = fma(sr, p, k1);
+    p *= sr;
+    const int ni = (int)n;
+    const double t = tab[ni & (kExpTabN - 1)];
+    return __builtin_ldexp(fma(t, p, t), ni >> 8);
+}
+
 // The same coefficient divided by the sub-step count N, with ln(A dt) and
-// ln N moved into the exponent: exp(b ln T - Ta/T + ln(A dt) - ln N).  The
-// argument is below ln(A dt) + b ln T, far under the exponential's overflow
-// for any temperature a double holds, so the upper clamp is left out.
-__device__ __forceinline__ double rate_coeff_sub(const ChemRx &r, double lnT, double invT, double lnN,
+// ln N moved into the exponent: exp(b ln T - Ta/T + ln(A dt) - ln N), formed
+// in units of ln 2 / 256 (lnNs = ln N 256/ln 2).  Each operation takes one
+// per-reaction constant: an instruction reads at most one scalar register
+// operand.
+__device__ __forceinline__ double rate_coeff_sub(const ChemRx &r, double lnT, double invT, double lnNs,
                                                  const double *tab)
 {
-    // (each operation takes one per-reaction constant: an instruction reads
-    // at most one scalar register operand)
-    return exp_tab<false>(fma(r.b, lnT, fma(-r.ta, invT, -lnN)) + r.lnadt, tab);
+    return exp_scaled_tab(fma(r.bs, lnT, fma(-r.tas, invT, -lnNs)) + r.lnadts, tab);
 }
 
 // Returns the number of sub-steps taken.  NR: the largest reactant count
@@ -831,7 +853,7 @@ __device__ __forceinline__ int chemistry(const KParams &P, const double *tab, co
         double want = ceil(kmax / 0.1);
         nsub = want < 1.0 ? 1 : want > (double)P.chem_substeps_max ? P.chem_substeps_max : (int)want;
     }
-    const double lnN = nsub == 1 ? 0.0 : log((double)nsub);
+    const double lnNs = nsub == 1 ? 0.0 : log((double)nsub) * 0x1.71547652b82fep+8;  // ln N 256/ln 2
     double dT = 0.0, dY[NSP];
 #pragma unroll
     for (int k = 0; k < NSP; ++k) dY[k] = 0.0;
@@ -867,11 +889,11 @@ __device__ __forceinline__ int chemistry(const KParams &P, const double *tab, co
         for (; j + 4 <= P.n_rx; j += 4) {
             double k4[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) k4[u] = rate_coeff_sub(P.rxk[j + u], lnTc, invTc, lnN, tab);
+            for (int u = 0; u < 4; ++u) k4[u] = rate_coeff_sub(P.rxk[j + u], lnTc, invTc, lnNs, tab);
 #pragma unroll
             for (int u = 0; u < 4; ++u) apply(P.rxk[j + u], k4[u]);
         }
-        for (; j < P.n_rx; ++j) apply(P.rxk[j], rate_coeff_sub(P.rxk[j], lnTc, invTc, lnN, tab));
+        for (; j < P.n_rx; ++j) apply(P.rxk[j], rate_coeff_sub(P.rxk[j], lnTc, invTc, lnNs, tab));
         if constexpr (LE) {
             // q_over_cp is the rise at c_p,ref: divide by c_p(Y) / c_p,ref
             // at the sub-step's composition (Eq. 7: omega_T / (rho c_p))

@@ -4,11 +4,12 @@ log_tab) against 60-digit decimal arithmetic.  Tables: every entry 2^(j/256),
 Constants: 256/ln 2 and ln 2 are the nearest doubles, the head of ln 2/256
 has at most 33 significant bits (n times it is exact for |n| < 2^20), and
 each two-part constant is exact to within its tail's rounding.  Algorithms:
-both functions re-run step by step in Python doubles from the header's own
-tables and constants (each fused multiply-add rounded once through exact
-decimal arithmetic) stay within 1.5 ulp of the exact values over the
-arguments the chemistry meets (log: 2 <= x <= 1e4 within 1.5 ulp, and
-1e-5 <= x < 2 within 1e-15 absolute; exp: -700 <= x <= 700)."""
+the three functions (with exp_scaled_tab, the exponential of a scaled
+argument xs = x 256/ln 2) re-run step by step in Python doubles from the
+header's own tables and constants (each fused multiply-add rounded once
+through exact decimal arithmetic) stay within 1.5 ulp of the exact values
+over the arguments the chemistry meets (log: 2 <= x <= 1e4 within 1.5 ulp,
+and 1e-5 <= x < 2 within 1e-15 absolute; exp: -700 <= x <= 700)."""
 import math
 import os
 import random
@@ -136,3 +137,33 @@ def test_log_and_exp_algorithms():
     for x in [rng.uniform(-700.0, 700.0) for _ in range(1500)] + [0.0, -1.0, 1e-20, -745.0 + 1.0]:
         exact = Decimal(x).exp()
         assert abs(Decimal(_exp_tab(x, etab, inv, hi, lo)) - exact) <= Decimal(1.5 * math.ulp(float(exact))), x
+
+
+def _exp_scaled_tab(xs, tab, k):
+    xs = max(xs, -370000.0)
+    n = float(round(xs))
+    sr = xs - n
+    p = _fma(sr, k[3], k[2])
+    p = _fma(sr, p, k[1])
+    p = _fma(sr, p, k[0])
+    p *= sr
+    ni = int(n)
+    t = tab[ni & 255]
+    return math.ldexp(_fma(t, p, t), ni >> 8)
+
+
+def test_scaled_exponential():
+    s = _source()
+    etab = _table(s, "kExp2Tab[kExpTabN] = {")
+    getcontext().prec = 60
+    k1 = _ln2() / 256
+    k = [_const(s, "k%d" % i) for i in (1, 2, 3, 4)]
+    for i, f in enumerate((1, 2, 6, 24)):
+        assert k[i] == float(k1 ** (i + 1) / f)
+    assert float.fromhex("0x1.71547652b82fep+8") == float(1 / k1)  # the scale the host applies
+    rng = random.Random(11)
+    for x in [rng.uniform(-700.0, 700.0) for _ in range(1500)] + [0.0, -1.0, 1e-20]:
+        xs = x * float(1 / k1)
+        exact = (Decimal(xs) * k1).exp()  # exp of the argument as given
+        assert abs(Decimal(_exp_scaled_tab(xs, etab, k)) - exact) <= Decimal(1.5 * math.ulp(float(exact))), x
+    assert _exp_scaled_tab(-1e300, etab, k) == 0.0
