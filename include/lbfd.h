@@ -317,6 +317,18 @@ int lbfd_time_steps(lbfd_ctx *c, int64_t nsteps, double *ms);
 /* Replace the Arrhenius parameters of reaction j (A [1/s], b, Ta [K]). */
 int lbfd_set_reaction(lbfd_ctx *c, int j, double A, double b, double Ta);
 
+/* Which kernel computes the Arrhenius source of a mechanism of more than
+ * four species (Sec. II.A, Eq. 6-7; the launch ahead of the step): 1 when a
+ * kernel specialised to this mechanism's structure (its reactant lists and
+ * the zero pattern of its mass coefficients, written into HIP source and
+ * compiled for the device at lbfd_init) runs, 0 when the generic kernel
+ * does (smaller mechanisms, mixture-averaged transport, LBFD_CHEM_JIT=0 in
+ * the environment at lbfd_init, or a failed compile).  Both give the same
+ * values.  msg (len bytes, may be NULL) receives a NUL-terminated note: the
+ * kernel in use and, for the generic one, why.  LBFD_EINVAL for a null
+ * context. */
+int lbfd_chem_kernel(const lbfd_ctx *c, char *msg, size_t len);
+
 /* Objectives of lbfd_objective / lbfd_adjoint, per level n:
  *   LBFD_OBJ_WALL_HEAT_FLUX  q(n) = wall_q of lbfd_diag (Sec. III.B ghost
  *                            walls: per fluid cell and first-neighbour

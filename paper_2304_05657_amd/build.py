@@ -22,14 +22,15 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled (-packed-fp32-ops): plain float code
 # is kept on the scalar-lane VALU path.
+GEN = os.path.join(BUILD, "gen")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-I", os.path.join(ROOT, "include")]
+         "-I", os.path.join(ROOT, "include"), "-I", GEN]
 
 
 def sources() -> list[str]:
     return ([os.path.join(CSRC, "lbfd_api.hip"), os.path.join(CSRC, "lbfd_dispatch.hip"),
-             os.path.join(CSRC, "lbfd_adjoint.hip")]
+             os.path.join(CSRC, "lbfd_adjoint.hip"), os.path.join(CSRC, "lbfd_chemjit.hip")]
             + sorted(glob.glob(os.path.join(CSRC, "inst", "*.hip"))))
 
 
@@ -67,8 +68,24 @@ def _compile(src: str) -> tuple[str, int, str]:
     return src, r.returncode, out
 
 
+def _gen_math_text() -> None:
+    """The text of lbfd_math.h as a C++ raw string literal (the run-time
+    compile of the specialised chemistry kernel is given it), rewritten
+    only when it changes."""
+    os.makedirs(GEN, exist_ok=True)
+    with open(os.path.join(CSRC, "lbfd_math.h")) as f:
+        text = f.read()
+    assert ")LBFDMATH\"" not in text
+    out = 'R"LBFDMATH(' + text + ')LBFDMATH"\n'
+    path = os.path.join(GEN, "lbfd_math_text.inc")
+    if not os.path.exists(path) or open(path).read() != out:
+        with open(path, "w") as f:
+            f.write(out)
+
+
 def build(force: bool = False, jobs: int | None = None, verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    _gen_math_text()
     hdr_mtime = max(os.path.getmtime(h) for h in _headers())
     todo = []
     for s in sources():
@@ -107,7 +124,8 @@ def build(force: bool = False, jobs: int | None = None, verbose: bool = True) ->
     objs = [_obj(s) for s in sources()]
     if force or todo or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(o) for o in objs):
         tmp = LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+        subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs +
+                              ["-L/opt/rocm/lib", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"])
         os.replace(tmp, LIB)
         if verbose:
             print("[lbfd build] linked %s" % os.path.relpath(LIB, ROOT), flush=True)

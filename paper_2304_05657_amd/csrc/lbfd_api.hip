@@ -8,8 +8,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <string>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -120,6 +122,7 @@ struct lbfd_ctx {
     double *btw = nullptr;
     unsigned long long *bcode_pull = nullptr, *bcode_st = nullptr;  // compact codes of the same descriptors
     double *face_Td = nullptr;                                         // face_T in device memory
+    char chem_msg[512] = "";  // which chemistry kernel runs, or why the specialised one does not
     int nblocks_interior = 0;
     double *wall_T = nullptr;
     double *outlet = nullptr;
@@ -582,6 +585,25 @@ static int upload_reactions(lbfd_ctx *c)
     }
     c->base.chem_anyb = anyb;
     c->base.chem_nreact = nreact;
+    // the chemistry launch specialised to the mechanism's structure
+    // (LBFD_CHEM_JIT=0 in the environment keeps the generic kernel); a
+    // failed compile leaves the generic kernel and says why
+    c->base.chem_jit = nullptr;
+    if (!chem_pass(c->nsp) || p.n_reactions == 0 || p.transport != LBFD_UNITY_LEWIS) {
+        snprintf(c->chem_msg, sizeof c->chem_msg, "generic (the chemistry runs inside the step, or "
+                 "mixture-averaged transport)");
+    } else if (const char *env = getenv("LBFD_CHEM_JIT"); env && strcmp(env, "0") == 0) {
+        snprintf(c->chem_msg, sizeof c->chem_msg, "generic (LBFD_CHEM_JIT=0)");
+    } else {
+        std::string err;
+        const void *fn = nullptr;
+        if (chem_jit_build(h, p.n_reactions, c->nsp, c->prec == LBFD_FP64, &fn, err) == 0) {
+            c->base.chem_jit = fn;
+            snprintf(c->chem_msg, sizeof c->chem_msg, "specialised");
+        } else {
+            snprintf(c->chem_msg, sizeof c->chem_msg, "generic (%s)", err.c_str());
+        }
+    }
     return LBFD_OK;
 }
 
@@ -1399,6 +1421,13 @@ int lbfd_time_kernels(lbfd_ctx *c, int64_t nsteps, double *ms_interior, double *
     *ms_boundary = tb;
     if (ms_chemistry) *ms_chemistry = tc;
     return LBFD_OK;
+}
+
+int lbfd_chem_kernel(const lbfd_ctx *c, char *msg, size_t len)
+{
+    if (!c) return fail(LBFD_EINVAL, "null context");
+    if (msg && len) snprintf(msg, len, "%s", c->chem_msg);
+    return c->base.chem_jit != nullptr ? 1 : 0;
 }
 
 int lbfd_set_reaction(lbfd_ctx *c, int j, double A, double b, double Ta)

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/lbfd.h"
 
 namespace lbfd {
@@ -46,6 +48,10 @@ struct ChemRx {
 // the step's output scalars for the step kernel to read back; smaller ones
 // evaluate it inside the step kernel.
 constexpr bool chem_pass(int nsp) { return nsp > 4; }
+
+// A chemistry cell that took more than kChemLight sub-steps is "heavy": the
+// next launch's ordering puts it at the back of the list.
+constexpr int kChemLight = 8;
 
 // Compact per-boundary-cell codes, decoded by the kernels and checked
 // against the full descriptors on the host when they are built (the same
@@ -165,6 +171,7 @@ struct KParams {
     int n_rx;
     int chem_anyb;      // some reaction has a temperature exponent b != 0
     int chem_nreact;    // the largest reactant count of a reaction (0..4)
+    const void *chem_jit;  // host handle of the mechanism-specialised chemistry kernel, or nullptr
     int chem_substeps_max;
     double omega2, omega3, omega4, alpha;
     double dt_phys;
@@ -243,5 +250,14 @@ hipError_t launch_widen(const float *src, double *dst, size_t n, hipStream_t s);
 // dst[i] = v for i < n (a fill kernel, so that callers capturing a graph
 // record no memset node).
 hipError_t launch_fill(double *dst, int n, double v, hipStream_t s);
+
+// The chemistry kernel specialised to a mechanism's structure
+// (lbfd_chemjit.hip): its HIP source, its compile for the current device
+// (cached per device and source for the process; *fn the kernel handle, or
+// an error text), and its launch over kp's chemistry list (blocks of 256,
+// scalars of scal_bytes).
+std::string chem_jit_source(const ChemRx *rx, int n_rx, int nsp, bool fp64);
+int chem_jit_build(const ChemRx *rx, int n_rx, int nsp, bool fp64, const void **fn, std::string &err);
+hipError_t launch_chem_jit(const KParams &kp, unsigned blocks, size_t scal_bytes, hipStream_t s);
 
 }  // namespace lbfd

@@ -26,7 +26,7 @@ ERRORS = {0: "LBFD_OK", -1: "LBFD_EINVAL", -2: "LBFD_ENOMEM", -3: "LBFD_EDEVICE"
 EXPORTS = ("lbfd_init", "lbfd_step", "lbfd_sync", "lbfd_level", "lbfd_read_fields",
            "lbfd_diagnostics", "lbfd_set_wall_temperature", "lbfd_state_size",
            "lbfd_save_state", "lbfd_load_state", "lbfd_time_steps", "lbfd_time_kernels",
-           "lbfd_cell_counts", "lbfd_step_launches", "lbfd_set_reaction", "lbfd_set_objective",
+           "lbfd_cell_counts", "lbfd_step_launches", "lbfd_set_reaction", "lbfd_chem_kernel", "lbfd_set_objective",
            "lbfd_objective", "lbfd_adjoint", "lbfd_set_inflow", "lbfd_hold_flame", "lbfd_set_wall_links",
            "lbfd_set_image_points", "lbfd_init_dev", "lbfd_read_fields_dev", "lbfd_adjoint_dev",
            "lbfd_objective_static", "lbfd_step_tangent", "lbfd_step_adjoint",
@@ -115,6 +115,7 @@ def load_library():
     lib.lbfd_step_launches.argtypes = [vp]
     lib.lbfd_step_launches.restype = C.c_int
     lib.lbfd_set_reaction.argtypes = [vp, C.c_int, C.c_double, C.c_double, C.c_double]
+    lib.lbfd_chem_kernel.argtypes = [vp, C.c_char_p, C.c_size_t]
     lib.lbfd_set_objective.argtypes = [vp, C.c_int, C.c_int64, C.c_int64]
     lib.lbfd_set_inflow.argtypes = [vp, C.c_int, dp]
     lib.lbfd_set_wall_links.argtypes = [vp, C.c_int64, vp, vp, dp]
@@ -273,6 +274,16 @@ class Solver:
 
     def set_reaction(self, j: int, A: float, b: float, Ta: float):
         _check(self._lib, self._lib.lbfd_set_reaction(self._h, int(j), float(A), float(b), float(Ta)))
+
+    def chem_kernel(self):
+        """(specialised, note): whether the Arrhenius source of this
+        mechanism runs in the kernel specialised to its structure, and a
+        note on the kernel in use (lbfd_chem_kernel)."""
+        buf = C.create_string_buffer(512)
+        r = self._lib.lbfd_chem_kernel(self._h, buf, len(buf))
+        if r < 0:
+            _check(self._lib, r)
+        return bool(r), buf.value.decode()
 
     def set_objective(self, kind: str = "wall_q", t_begin: int = 0, t_end: int | None = None):
         """Objective of objective() / adjoint(): the sum of q(level) over the

@@ -1,4 +1,4 @@
-"""The device exponential and logarithm (lbfd_kernels.h, exp_tab and
+"""The device exponential and logarithm (lbfd_math.h, exp_tab and
 log_tab) against 60-digit decimal arithmetic.  Tables: every entry 2^(j/256),
 1/F_j and ln F_j (F_j = 1 + j/256) is the double nearest to the exact value.
 Constants: 256/ln 2 and ln 2 are the nearest doubles, the head of ln 2/256
@@ -18,7 +18,7 @@ import struct
 from decimal import Decimal, getcontext
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SRC = os.path.join(ROOT, "paper_2304_05657_amd", "csrc", "lbfd_kernels.h")
+SRC = os.path.join(ROOT, "paper_2304_05657_amd", "csrc", "lbfd_math.h")
 
 
 def _source():
