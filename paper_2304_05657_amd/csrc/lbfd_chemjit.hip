@@ -77,8 +77,9 @@ std::string generate(const ChemRx *rx, int n_rx, int nsp, bool fp64)
     w("using namespace lbfd;");
     w("struct ChemJitArgs { const char *sc_in; char *sc_out; const int *order; unsigned char *heavy;");
     w("    long long n_fluid; unsigned long long fstride; int substeps_max, anyb; };");
-    // three waves per SIMD (168 registers): the unrolled text holds more
-    // values at once than the 128 of four waves without spilling
+    // three waves per SIMD (168 registers): at four (128) the unrolled
+    // text spills (the compiler's schedule keeps more values live than in
+    // the generic kernel's loop over reaction groups)
     w("extern \"C\" __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))");
     w("lbfd_chem_jit(const ChemJitArgs a)");
     w("{");
@@ -99,7 +100,6 @@ std::string generate(const ChemRx *rx, int n_rx, int nsp, bool fp64)
     w("        const double lnT = anyb ? log(T) : 0.0, invT = rcp(T);");
     w("        double kmax = 0.0;");
     for (int j = 0; j < n_rx; ++j) {
-        if (j > 0 && j % kGroup == 0) w("        __builtin_amdgcn_sched_barrier(0);");
         f("        kmax = fmax(kmax, %s * exp_tab(%s * lnT - %s * invT, tab));", num(rx[j].adt).c_str(),
           num(rx[j].b).c_str(), num(rx[j].ta).c_str());
     }
@@ -120,10 +120,6 @@ std::string generate(const ChemRx *rx, int n_rx, int nsp, bool fp64)
     // increments)
     for (int j0 = 0; j0 < n_rx; j0 += kGroup) {
         const int j1 = n_rx - j0 >= kGroup ? j0 + kGroup : n_rx;
-        // (a scheduling barrier between groups: interleaving all the
-        // reactions of the unrolled text keeps more values live than the
-        // register budget of four waves per SIMD holds)
-        if (j0 > 0) w("        __builtin_amdgcn_sched_barrier(0);");
         for (int j = j0; j < j1; ++j)
             f("        const double k%d = exp_scaled_tab(fma(%s, lnTc, fma(-%s, invTc, -lnNs)) + %s, tab);", j,
               num(rx[j].bs).c_str(), num(rx[j].tas).c_str(),
