@@ -49,7 +49,7 @@ RIDGE = VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)  # flop per byte
 # sources that fix what the launches read and write (device code, the
 # host-side launch plan and the boundary-cell list)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_05657_amd", "csrc", f)
-                  for f in ("lbfd_kernels.h", "lbfd_internal.h", "lbfd_api.hip")]
+                  for f in ("lbfd_kernels.h", "lbfd_internal.h", "lbfd_api.hip", "lbfd_math.h", "lbfd_chemjit.hip")]
 # HBM bytes per launch of a kernel on a workload, from two rocprofv3 --pmc
 # runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) scaled by the same
 # counters on a plain device copy of known size, valid for the kernel
@@ -217,7 +217,12 @@ def run_gpu(prob, precision: str, steps: int, warmup: int, check_every: int, lin
     kernels = []
     if chem_pass(prob):
         nsc = (1 + prob.n_species) * SCALAR_BYTES[precision]
-        kernels.append(kernel_record("chem_kernel (FP64 Arrhenius source, one thread per cell)", n_fluid,
+        specialised, chem_note = s.chem_kernel()
+        if not specialised:
+            print("[bench] chemistry kernel: %s" % chem_note, file=sys.stderr, flush=True)
+        label = ("lbfd_chem_jit (FP64 Arrhenius source, kernel specialised to the mechanism, one thread per cell)"
+                 if specialised else "chem_kernel (FP64 Arrhenius source, one thread per cell)")
+        kernels.append(kernel_record(label, n_fluid,
                                      kms_c / steps, n_fluid * cfl, float(n_fluid * 2 * nsc + prob.N)))
         step_fl = sfl
     else:

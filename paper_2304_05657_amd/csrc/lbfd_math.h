@@ -1,10 +1,12 @@
 #pragma once
 // lbfd_math.h -- double-precision reciprocal, exponential and logarithm of
 // the chemistry (gfx950 device code).  Self-contained (it includes only the
-// HIP runtime header): the library's kernels include it, and the
-// mechanism-specialised chemistry kernels compiled at run time are given
-// its text.
+// HIP runtime header, which the run-time compiler does not need): the
+// library's kernels include it, and the mechanism-specialised chemistry
+// kernels compiled at run time are given its text.
+#ifndef __HIPCC_RTC__  // (the run-time compiler provides the HIP device API itself)
 #include <hip/hip_runtime.h>
+#endif
 
 namespace lbfd {
 
