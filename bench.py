@@ -59,9 +59,9 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_05657_amd", "csrc", f)
 # as), valid only for the kernel sources they were taken on
 # (profiles/traffic_porous_mech_512x256x256_and_porous_256.md)
 TRAFFIC = {
-    ("porous3d_mech_512x256x256", "fp64", "chem_kernel"): {
-        "bytes_per_launch": 6124.3e6,
-        "kernel_sha256": "5c73f4c7aa8888bd51f9c89d535b466313e59c7a395bb0865fc7f646ca858c84",
+    ("porous3d_mech_512x256x256", "fp64", "lbfd_chem_jit_f64"): {
+        "bytes_per_launch": 8461.2e6,
+        "kernel_sha256": "27fbf99ed77413136bb1fdf358683f116b1de33c7fc4d4a3969f541ba6f7e792",
     },
 }
 POP_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
@@ -220,7 +220,8 @@ def run_gpu(prob, precision: str, steps: int, warmup: int, check_every: int, lin
         specialised, chem_note = s.chem_kernel()
         if not specialised:
             print("[bench] chemistry kernel: %s" % chem_note, file=sys.stderr, flush=True)
-        label = ("lbfd_chem_jit (FP64 Arrhenius source, kernel specialised to the mechanism, one thread per cell)"
+        label = ("lbfd_chem_jit_%s (FP64 Arrhenius source, kernel specialised to the mechanism, one thread per cell)"
+                 % ("f64" if precision == "fp64" else "f32")
                  if specialised else "chem_kernel (FP64 Arrhenius source, one thread per cell)")
         kernels.append(kernel_record(label, n_fluid,
                                      kms_c / steps, n_fluid * cfl, float(n_fluid * 2 * nsc + prob.N)))

@@ -81,7 +81,8 @@ std::string generate(const ChemRx *rx, int n_rx, int nsp, bool fp64)
     // text spills (the compiler's schedule keeps more values live than in
     // the generic kernel's loop over reaction groups)
     w("extern \"C\" __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))");
-    w("lbfd_chem_jit(const ChemJitArgs a)");
+    // (named for its storage type, so that profiles tell the launches apart)
+    f("lbfd_chem_jit_%s(const ChemJitArgs a)", fp64 ? "f64" : "f32");
     w("{");
     w("    __shared__ double tab[kExpTabN], ltab[2 * kLogTabN];");
     w("    for (int i = (int)threadIdx.x; i < kExpTabN; i += (int)blockDim.x) tab[i] = kExp2Tab[i];");
@@ -198,7 +199,7 @@ int chem_jit_build(const ChemRx *rx, int n_rx, int nsp, bool fp64, const void **
     hipModule_t mod;
     hipFunction_t f;
     if (hipModuleLoadData(&mod, code.data()) != hipSuccess ||
-        hipModuleGetFunction(&f, mod, "lbfd_chem_jit") != hipSuccess) {
+        hipModuleGetFunction(&f, mod, fp64 ? "lbfd_chem_jit_f64" : "lbfd_chem_jit_f32") != hipSuccess) {
         err = "loading the compiled chemistry kernel failed";
         return -1;
     }
