@@ -24,7 +24,6 @@
 #include <hip/hiprtc.h>
 
 #include <cmath>
-#include <cstddef>
 #include <cstdio>
 #include <map>
 #include <mutex>
