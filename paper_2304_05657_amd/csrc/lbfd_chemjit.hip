@@ -125,11 +125,16 @@ std::string generate(const ChemRx *rx, int n_rx, int nsp, bool fp64)
     // increments)
     for (int j0 = 0; j0 < n_rx; j0 += kGroup) {
         const int j1 = n_rx - j0 >= kGroup ? j0 + kGroup : n_rx;
-        for (int j = j0; j < j1; ++j)
-            f("        const double k%d = exp_scaled_tab(fma(%s, lnTc, fma(-%s, invTc, -lnNs)) + %s, tab);", j,
-              num(rx[j].bs).c_str(), num(rx[j].tas).c_str(),
-              num(rx[j].lnadts).c_str());
+        // (a reaction with A = 0 adds exact zeros in the generic kernel and
+        // is left out; the others' arguments are finite, so the exponential
+        // needs no clamp)
         for (int j = j0; j < j1; ++j) {
+            if (!(rx[j].adt > 0.0)) continue;
+            f("        const double k%d = exp_scaled_tab<false>(fma(%s, lnTc, fma(-%s, invTc, -lnNs)) + %s, tab);", j,
+              num(rx[j].bs).c_str(), num(rx[j].tas).c_str(), num(rx[j].lnadts).c_str());
+        }
+        for (int j = j0; j < j1; ++j) {
+            if (!(rx[j].adt > 0.0)) continue;
             f("        double r%d = k%d;", j, j);
             for (int m = 0; m < rx[j].n_react; ++m) f("        r%d *= Yc%d;", j, rx[j].react[m]);
             for (int k = 0; k < nsp; ++k)

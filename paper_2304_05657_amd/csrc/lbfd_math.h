@@ -298,14 +298,18 @@ __device__ __forceinline__ double log_tab(double x, const double *ltab)
 // argument needs no two-part reduction (s is exact); its own rounding, one
 // part in 2^53 of xs, is the same relative error the unscaled x carries.
 // xs is clamped below (exp underflows to 0); the arguments it serves stay
-// far below the overflow.
+// far below the overflow.  CLAMP = false leaves the clamp out for finite
+// arguments: below it the result is 0 all the same (the exponent the table
+// entry is scaled by is then below -1445; a saturated conversion keeps it
+// there), but -inf and NaN give NaN.
+template <bool CLAMP = true>
 __device__ __forceinline__ double exp_scaled_tab(double xs, const double *tab)
 {
     constexpr double k1 = 0x1.62e42fefa39efp-9;   // ln 2 / 256
     constexpr double k2 = 0x1.ebfbdff82c58fp-19;  // k1^2 / 2
     constexpr double k3 = 0x1.c6b08d704a0c0p-29;  // k1^3 / 6
     constexpr double k4 = 0x1.3b2ab6fba4e77p-39;  // k1^4 / 24
-    xs = fmax(xs, -370000.0);                     // x below -1000
+    if constexpr (CLAMP) xs = fmax(xs, -370000.0);  // x below -1000
     const double n = __builtin_rint(xs);
     const double sr = xs - n;
     double p = fma(sr, k4, k3);

@@ -130,7 +130,7 @@ def test_generated_text_structure(harness):
     assert got == sorted(want)
     # the rate constants as the host forms them, each read back exactly
     for j, rj in enumerate(rx):
-        lit = re.search(r"const double k%d = exp_scaled_tab\(fma\(\(([^)]+)\), lnTc, fma\(-\(([^)]+)\), invTc, "
+        lit = re.search(r"const double k%d = exp_scaled_tab<false>\(fma\(\(([^)]+)\), lnTc, fma\(-\(([^)]+)\), invTc, "
                         r"-lnNs\)\) \+ \(([^)]+)\), tab\);" % j, text)
         assert lit is not None, j
         assert float.fromhex(lit.group(1)) == rj.b * SCALE
